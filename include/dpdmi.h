@@ -1,0 +1,164 @@
+/*
+ * dpdmi — TDNN digital predistorter cascaded with a GMP power-amplifier model,
+ * forward, NMSE and hand-written backward on AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2205.05158 (Wu, Gustavsson, Valkama, Graell i Amat, Wymeersch,
+ * "Frequency-domain digital predistortion for Massive MU-MIMO-OFDM Downlink").
+ *   - DPD: the time-domain DPD of eq. (8), u[n] = f_theta(x[n], ..., x[n-T+1]),
+ *     realised as the tapped-delay-line network of Sec. III-C: per tap the
+ *     features (Re, Im, |x|, |x|^2, |x|^3), fully connected tanh hidden layers,
+ *     two linear outputs (Re u, Im u).
+ *   - PA: the PA with memory of eq. (7), instantiated by the GMP of eq. (9)
+ *     (this header's K, M, L are the paper's K, L3, G).
+ *   - Target: the linear PA of Sec. II-B, y[n] = G x[n];  NMSE = sum|y-Gx|^2 / sum|Gx|^2.
+ *   - Training: MSE through the differentiable chain (Sec. V-A-2); the loss here
+ *     is the linear NMSE pooled over the streams that share one parameter set.
+ *
+ * Conventions for every entry point
+ *   - Pointers named *_host are host memory; every other array pointer is DEVICE
+ *     memory.  The caller allocates and owns every buffer, including the
+ *     workspace.  The library never allocates, never synchronises the device,
+ *     and enqueues all work on the caller's `stream` (in order).
+ *   - Complex sample streams are interleaved float32 (re, im), 8 bytes per sample,
+ *     8-byte aligned.  Streams are concatenated; stream s occupies samples
+ *     [offsets_host[s], offsets_host[s+1]).  Each stream is independent and
+ *     zero-padded on both ends (no state crosses a stream boundary).
+ *   - Arguments are validated on the host before any HIP call; on failure a
+ *     negative dpd_status is returned and nothing is enqueued.  A launch failure
+ *     reported by the runtime after enqueueing returns DPD_ERR_LAUNCH.
+ *   - Calls are thread-safe; the library keeps no mutable global state apart
+ *     from a lazily filled, mutex-guarded cache of device properties.
+ */
+#ifndef DPDMI_H
+#define DPDMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hipStream_t;
+
+typedef enum {
+    DPD_OK = 0,
+    DPD_ERR_NULL = -1,         /* a required pointer is NULL                          */
+    DPD_ERR_SHAPE = -2,        /* a size, offset table or descriptor value is invalid */
+    DPD_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement        */
+    DPD_ERR_WORKSPACE = -4,    /* workspace smaller than dpd_workspace_size() says    */
+    DPD_ERR_LAUNCH = -5,       /* the HIP runtime reported an error                   */
+    DPD_ERR_ALIGN = -6         /* a pointer is not aligned as documented              */
+} dpd_status;
+
+typedef enum { DPD_FP32 = 0, DPD_BF16 = 1 } dpd_precision;
+typedef enum { DPD_IMPL_TUNED = 0, DPD_IMPL_PLAIN = 1 } dpd_impl;
+
+enum { DPD_MAX_STREAMS = 128, DPD_MAX_TAPS = 32, DPD_MAX_HIDDEN = 256, DPD_MAX_LAYERS = 8,
+       DPD_MAX_GMP_K = 12, DPD_MAX_GMP_M = 15, DPD_MAX_GMP_L = 8 };
+
+/* TDNN DPD (eq. (8) slot, Sec. III-C network).  Features of tap t (t = 0..T-1) of
+ * sample n are (Re z, Im z, |z|, |z|^2, |z|^3) with z = x[n-t] (0 before the
+ * stream start), at input index 5t+j.  h_0 = features, h_i = tanh(W_i h_{i-1} + b_i),
+ * (o0, o1) = W_o h_nl + b_o, u = o0 + j o1 (+ x[n] if residual).
+ * Packed float32 weights (P = dpd_tdnn_param_count): W1[H][5T] b1[H]
+ * (W_i[H][H] b_i[H]) for i = 2..nl, W_o[2][H] b_o[2]; rows are output neurons. */
+typedef struct {
+    int32_t taps;       /* T, 1..DPD_MAX_TAPS                               */
+    int32_t n_hidden;   /* nl, 1..DPD_MAX_LAYERS                            */
+    int32_t hidden;     /* H, 1..DPD_MAX_HIDDEN                             */
+    int32_t residual;   /* 0 or 1                                           */
+    int32_t precision;  /* dpd_precision: arithmetic of the hidden layers   */
+    int32_t impl;       /* dpd_impl: tuned MFMA kernels or plain kernels    */
+} dpd_tdnn_desc;
+
+/* GMP PA, eq. (9): y[n] = sum_{k=0}^{K-1} sum_{l=0}^{M} a_{k,l} u[n-l] |u[n-l]|^k
+ *   + sum_{k=1}^{K-1} sum_{l=0}^{M} sum_{g=1}^{L} ( b_{k,l,g} u[n-l] |u[n-l-g]|^k
+ *                                                 + c_{k,l,g} u[n-l] |u[n-l+g]|^k ),
+ * u = 0 outside the stream.  Packed complex float32 coefficients
+ * (J = dpd_gmp_coeff_count): a[K][M+1], b[K-1][M+1][L], c[K-1][M+1][L],
+ * b and c indexed from k = 1 and g = 1. */
+typedef struct {
+    int32_t K;          /* nonlinear order, 1..DPD_MAX_GMP_K   */
+    int32_t M;          /* memory depth (paper L3), 0..DPD_MAX_GMP_M */
+    int32_t L;          /* cross-term length (paper G), 0..DPD_MAX_GMP_L */
+} dpd_gmp_desc;
+
+/* A batch of independent streams.  per_stream_params = 0: every stream uses the
+ * one parameter set (weights w, coefficients coef);  = 1: stream s uses set s,
+ * i.e. w + s*P and coef + s*2J.  The number of parameter sets is S or 1. */
+typedef struct {
+    int32_t n_streams;           /* S, 1..DPD_MAX_STREAMS                          */
+    int32_t per_stream_params;   /* 0 or 1                                         */
+    const int64_t* offsets_host; /* [S+1], offsets[0] = 0, strictly increasing     */
+} dpd_batch;
+
+/* Parameter counts (< 0 on an invalid descriptor). */
+int64_t dpd_tdnn_param_count(const dpd_tdnn_desc* tdnn);
+int64_t dpd_gmp_coeff_count(const dpd_gmp_desc* gmp);
+
+/* Bytes of device workspace every call below needs for this problem (an upper
+ * bound over the launch shapes the library may choose).  The same workspace may
+ * be reused by consecutive calls on one stream; concurrent calls need their own. */
+dpd_status dpd_workspace_size(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
+                              const dpd_batch* batch, size_t* bytes_host);
+
+/* DPD forward (eq. (8)): x [n_total][2] -> u [n_total][2]. */
+dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch,
+                       const float* x, const float* w, float* u,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* GMP PA forward (eq. (9)): u [n_total][2] -> y [n_total][2].  u and y must not overlap. */
+dpd_status pa_gmp_forward(const dpd_gmp_desc* gmp, const dpd_batch* batch,
+                          const float* u, const float* coef, float* y, hipStream_t stream);
+
+/* NMSE of y against the linear target G x (Sec. II-B), per stream and pooled per
+ * parameter set.  out: device float[3*(S+1)]: for s < S, (E_s, R_s, NMSE_dB_s);
+ * at s = S the triple pooled over all streams.  E = sum|y-Gx|^2, R = sum|Gx|^2,
+ * accumulated in float32 with compensated (Neumaier) sums. */
+dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x,
+                        float g_re, float g_im, float* out,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Direct-learning gradient (Sec. V-A-2): runs DPD -> GMP -> NMSE and the reverse
+ * mode through both, returning for each parameter set p the pooled loss
+ * loss[p] = sum_{s in p} E_s / sum_{s in p} R_s and dw[p] = d loss[p] / d w_p
+ * (same packed layout as w).  loss: device float[n_sets]; dw: device float[n_sets*P].
+ * d|u|/du is taken as 0 at u = 0.  Deterministic: identical inputs give bitwise
+ * identical results for a given launch shape. */
+dpd_status dpd_backward(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
+                        const dpd_batch* batch, const float* x, const float* w,
+                        const float* coef, float g_re, float g_im, float* dw, float* loss,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* The whole cascade in one call: optional u and y outputs (NULL to skip),
+ * per-stream NMSE triples as cascade_nmse (nmse: device float[3*(S+1)], may be
+ * NULL), and when dw is non-NULL the gradient and pooled loss as dpd_backward
+ * (loss required with dw). */
+dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
+                       const dpd_batch* batch, const float* x, const float* w,
+                       const float* coef, float g_re, float g_im,
+                       float* u, float* y, float* nmse, float* dw, float* loss,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Welch PSD of one stream y [n][2] (nfft-point segments, periodic Hann window,
+ * 50 % overlap, no detrending, scaled by 1/sum(w^2)), bins in natural FFT order,
+ * and the ACPR with main channel |k| <= half_bins, adjacent channels
+ * half_bins < |k| <= 3 half_bins.  nfft is a power of two in [64, 4096];
+ * n >= nfft; 3*half_bins < nfft/2.  psd: device float[nfft];
+ * acpr: device float[3] = (ACPR_L dB, ACPR_U dB, max). */
+dpd_status cascade_acpr(const float* y, int64_t n, int32_t nfft, int32_t half_bins,
+                        float* psd, float* acpr, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft);
+
+/* Human-readable name of a status code (static storage). */
+const char* dpd_status_string(dpd_status status);
+
+/* Library build identification (static storage). */
+const char* dpd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPDMI_H */

@@ -1,0 +1,188 @@
+"""ctypes binding of libdpdmi.so (include/dpdmi.h).
+
+Argument marshalling only: every entry point here has the name of the C function
+it calls, takes torch device tensors where the C function takes device pointers,
+and raises RuntimeError with the library's status string when the call fails.
+The library itself must be built (python -m paper_2205_05158_amd.build); there is
+no fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdpdmi.so")
+
+DPD_OK = 0
+DPD_ERR_NULL, DPD_ERR_SHAPE, DPD_ERR_UNSUPPORTED, DPD_ERR_WORKSPACE, DPD_ERR_LAUNCH, DPD_ERR_ALIGN = \
+    -1, -2, -3, -4, -5, -6
+DPD_FP32, DPD_BF16 = 0, 1
+DPD_IMPL_TUNED, DPD_IMPL_PLAIN = 0, 1
+DPD_MAX_STREAMS = 128
+
+
+class TdnnDesc(C.Structure):
+    _fields_ = [("taps", C.c_int32), ("n_hidden", C.c_int32), ("hidden", C.c_int32),
+                ("residual", C.c_int32), ("precision", C.c_int32), ("impl", C.c_int32)]
+
+
+class GmpDesc(C.Structure):
+    _fields_ = [("K", C.c_int32), ("M", C.c_int32), ("L", C.c_int32)]
+
+
+class Batch(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("per_stream_params", C.c_int32),
+                ("offsets_host", C.POINTER(C.c_int64))]
+
+
+_lib = None
+_lock = threading.Lock()
+
+_P = C.c_void_p
+_SIGS = {
+    "dpd_tdnn_param_count": (C.c_int64, [C.POINTER(TdnnDesc)]),
+    "dpd_gmp_coeff_count": (C.c_int64, [C.POINTER(GmpDesc)]),
+    "dpd_workspace_size": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch),
+                                     C.POINTER(C.c_size_t)]),
+    "dpd_forward": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(Batch), _P, _P, _P, _P, C.c_size_t, _P]),
+    "pa_gmp_forward": (C.c_int, [C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P, _P]),
+    "cascade_nmse": (C.c_int, [C.POINTER(Batch), _P, _P, C.c_float, C.c_float, _P, _P, C.c_size_t, _P]),
+    "dpd_backward": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
+                               C.c_float, C.c_float, _P, _P, _P, C.c_size_t, _P]),
+    "dpd_cascade": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
+                              C.c_float, C.c_float, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
+    "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
+    "dpd_status_string": (C.c_char_p, [C.c_int]),
+    "dpd_version": (C.c_char_p, []),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib():
+    """Load libdpdmi.so once; raise if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                                   "`python -m paper_2205_05158_amd.build`")
+            h = C.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(h, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = h
+        return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().dpd_status_string(code).decode()
+
+
+def _check(code: int, what: str):
+    if code != DPD_OK:
+        raise RuntimeError(f"{what}: {status_string(code)}")
+
+
+# ------------------------------------------------------------------ marshalling
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream if isinstance(stream, int) else stream.cuda_stream)
+
+
+def make_batch(offsets, per_stream_params: bool = False):
+    """Batch descriptor; the returned object keeps the host offsets alive."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    b = Batch(int(off.size - 1), int(bool(per_stream_params)),
+              off.ctypes.data_as(C.POINTER(C.c_int64)))
+    b._keep = off
+    return b
+
+
+def tdnn_desc(taps, n_hidden, hidden, residual=False, precision="fp32", impl="tuned"):
+    prec = {"fp32": DPD_FP32, "bf16": DPD_BF16}[precision] if isinstance(precision, str) else precision
+    im = {"tuned": DPD_IMPL_TUNED, "plain": DPD_IMPL_PLAIN}[impl] if isinstance(impl, str) else impl
+    return TdnnDesc(taps, n_hidden, hidden, int(bool(residual)), prec, im)
+
+
+def gmp_desc(K, M, L):
+    return GmpDesc(K, M, L)
+
+
+# ------------------------------------------------------------------ entry points
+def dpd_tdnn_param_count(tdnn: TdnnDesc) -> int:
+    return lib().dpd_tdnn_param_count(C.byref(tdnn))
+
+
+def dpd_gmp_coeff_count(gmp: GmpDesc) -> int:
+    return lib().dpd_gmp_coeff_count(C.byref(gmp))
+
+
+def dpd_workspace_size(tdnn, gmp, batch) -> int:
+    n = C.c_size_t(0)
+    _check(lib().dpd_workspace_size(C.byref(tdnn) if tdnn is not None else None,
+                                    C.byref(gmp) if gmp is not None else None,
+                                    C.byref(batch), C.byref(n)), "dpd_workspace_size")
+    return n.value
+
+
+def dpd_forward(tdnn, batch, x, w, u, workspace, stream=None):
+    _check(lib().dpd_forward(C.byref(tdnn), C.byref(batch), _ptr(x), _ptr(w), _ptr(u),
+                             _ptr(workspace), workspace.numel() * workspace.element_size(),
+                             _stream(stream)), "dpd_forward")
+
+
+def pa_gmp_forward(gmp, batch, u, coef, y, stream=None):
+    _check(lib().pa_gmp_forward(C.byref(gmp), C.byref(batch), _ptr(u), _ptr(coef), _ptr(y),
+                                _stream(stream)), "pa_gmp_forward")
+
+
+def cascade_nmse(batch, y, x, g, out, workspace, stream=None):
+    g = complex(g)
+    _check(lib().cascade_nmse(C.byref(batch), _ptr(y), _ptr(x), g.real, g.imag, _ptr(out),
+                              _ptr(workspace), workspace.numel() * workspace.element_size(),
+                              _stream(stream)), "cascade_nmse")
+
+
+def dpd_backward(tdnn, gmp, batch, x, w, coef, g, dw, loss, workspace, stream=None):
+    g = complex(g)
+    _check(lib().dpd_backward(C.byref(tdnn), C.byref(gmp), C.byref(batch), _ptr(x), _ptr(w),
+                              _ptr(coef), g.real, g.imag, _ptr(dw), _ptr(loss), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream)),
+           "dpd_backward")
+
+
+def dpd_cascade(tdnn, gmp, batch, x, w, coef, g, u, y, nmse, dw, loss, workspace, stream=None):
+    g = complex(g)
+    _check(lib().dpd_cascade(C.byref(tdnn), C.byref(gmp), C.byref(batch), _ptr(x), _ptr(w),
+                             _ptr(coef), g.real, g.imag, _ptr(u), _ptr(y), _ptr(nmse), _ptr(dw),
+                             _ptr(loss), _ptr(workspace),
+                             workspace.numel() * workspace.element_size(), _stream(stream)),
+           "dpd_cascade")
+
+
+def dpd_acpr_workspace_size(n: int, nfft: int) -> int:
+    return lib().dpd_acpr_workspace_size(n, nfft)
+
+
+def cascade_acpr(y, n, nfft, half_bins, psd, acpr, workspace, stream=None):
+    _check(lib().cascade_acpr(_ptr(y), n, nfft, half_bins, _ptr(psd), _ptr(acpr), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream)),
+           "cascade_acpr")
+
+
+def dpd_version() -> str:
+    return lib().dpd_version().decode()

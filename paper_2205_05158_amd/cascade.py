@@ -1,0 +1,112 @@
+"""Problem object and autograd boundary over the C ABI.
+
+`Cascade` holds the descriptors, the batch and a device workspace (allocated once
+through torch, the only allocator involved) and exposes the ABI calls on torch
+device tensors.  `CascadeFn` is the torch.autograd.Function of the direct-learning
+loss (Sec. V-A-2): its forward runs the hand-written reverse mode of the library
+(dpd_backward) together with the loss, so the backward only scales the stored
+gradient by the incoming grad.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class Cascade:
+    def __init__(self, taps, n_hidden, hidden, K, M, L_, offsets, per_stream_params=False,
+                 residual=False, precision="fp32", impl="tuned", gain=1.0 + 0.0j, device="cuda"):
+        self.tdnn = L.tdnn_desc(taps, n_hidden, hidden, residual, precision, impl)
+        self.gmp = L.gmp_desc(K, M, L_)
+        self.offsets = np.asarray(offsets, dtype=np.int64)
+        self.batch = L.make_batch(self.offsets, per_stream_params)
+        self.S = int(self.offsets.size - 1)
+        self.n_sets = self.S if per_stream_params else 1
+        self.n_total = int(self.offsets[-1])
+        self.P = L.dpd_tdnn_param_count(self.tdnn)
+        self.J = L.dpd_gmp_coeff_count(self.gmp)
+        self.gain = complex(gain)
+        self.device = torch.device(device)
+        nbytes = L.dpd_workspace_size(self.tdnn, self.gmp, self.batch)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    # -- shape checks on the host before handing pointers to the library
+    def _chk(self, t, shape, dtype=torch.float32):
+        if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"expected contiguous {dtype} cuda tensor of shape {shape}, got "
+                             f"{tuple(t.shape)} {t.dtype} {t.device}")
+        return t
+
+    def _w_shape(self):
+        return (self.n_sets, self.P) if self.n_sets > 1 else (self.P,)
+
+    def _c_shape(self):
+        return (self.n_sets, self.J, 2) if self.n_sets > 1 else (self.J, 2)
+
+    def forward_u(self, x, w):
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape())
+        u = torch.empty_like(x)
+        L.dpd_forward(self.tdnn, self.batch, x, w, u, self.workspace)
+        return u
+
+    def pa(self, u, coef):
+        self._chk(u, (self.n_total, 2)); self._chk(coef, self._c_shape())
+        y = torch.empty_like(u)
+        L.pa_gmp_forward(self.gmp, self.batch, u, coef, y)
+        return y
+
+    def nmse(self, y, x):
+        self._chk(y, (self.n_total, 2)); self._chk(x, (self.n_total, 2))
+        out = torch.empty(3 * (self.S + 1), dtype=torch.float32, device=self.device)
+        L.cascade_nmse(self.batch, y, x, self.gain, out, self.workspace)
+        return out.view(self.S + 1, 3)
+
+    def run(self, x, w, coef, want_u=True, want_y=True, want_nmse=True, want_grad=True):
+        """One pass of the whole cascade; returns dict of the requested outputs."""
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape()); self._chk(coef, self._c_shape())
+        dev = self.device
+        u = torch.empty_like(x) if want_u else None
+        y = torch.empty_like(x) if want_y else None
+        nm = torch.empty(3 * (self.S + 1), dtype=torch.float32, device=dev) if want_nmse else None
+        dw = torch.empty(self._w_shape(), dtype=torch.float32, device=dev) if want_grad else None
+        loss = torch.empty(self.n_sets, dtype=torch.float32, device=dev) if want_grad else None
+        L.dpd_cascade(self.tdnn, self.gmp, self.batch, x, w, coef, self.gain, u, y, nm, dw, loss,
+                      self.workspace)
+        return {"u": u, "y": y, "nmse": None if nm is None else nm.view(self.S + 1, 3),
+                "dw": dw, "loss": loss}
+
+    def backward(self, x, w, coef):
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape()); self._chk(coef, self._c_shape())
+        dw = torch.empty(self._w_shape(), dtype=torch.float32, device=self.device)
+        loss = torch.empty(self.n_sets, dtype=torch.float32, device=self.device)
+        L.dpd_backward(self.tdnn, self.gmp, self.batch, x, w, coef, self.gain, dw, loss, self.workspace)
+        return loss, dw
+
+
+class CascadeFn(torch.autograd.Function):
+    """loss[p] = pooled NMSE of parameter set p; differentiable w.r.t. the packed weights."""
+
+    @staticmethod
+    def forward(ctx, w, x, coef, cascade: Cascade):
+        if ctx.needs_input_grad[0]:
+            loss, dw = cascade.backward(x, w.detach(), coef)
+            ctx.save_for_backward(dw)
+        else:
+            nm = cascade.run(x, w, coef, want_u=False, want_y=False, want_nmse=True,
+                             want_grad=False)["nmse"]
+            if cascade.n_sets > 1:
+                loss = nm[:-1, 0] / nm[:-1, 1]
+            else:
+                loss = (nm[-1, 0] / nm[-1, 1]).reshape(1)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        (dw,) = ctx.saved_tensors
+        if dw.dim() == 1:
+            g = dw * grad_loss[0]
+        else:
+            g = dw * grad_loss[:, None]
+        return g, None, None, None

@@ -1,0 +1,467 @@
+// dpdmi C ABI: host-side validation, workspace layout and dispatch.  Every
+// argument is checked before the first HIP call; nothing is allocated; all work
+// goes onto the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "kernels.hpp"
+
+namespace dpdmi {
+void launch_plain_finalize_sets(const float* acc, int taps, int n_hidden, int hidden,
+                                int64_t acc_stride, int64_t P, int n_sets, const float* inv_r,
+                                float* dw, hipStream_t s);
+}
+
+using namespace dpdmi;
+
+namespace {
+
+constexpr int kNmseTile = 256;        // tile of the stand-alone NMSE pass
+constexpr int kPlainChunk = 1 << 17;  // samples per chunk of the plain path
+constexpr int kPlainDwBlock = 2048;   // samples per split-K block of the plain dW
+constexpr int kMaxGrid = 512;         // persistent workgroups (sizes the dW slots)
+constexpr int kBwdTile = 128;         // samples per workgroup tile of the tuned kernels
+
+struct Problem {
+  int S = 0, n_sets = 0, per_stream = 0;
+  int64_t n_total = 0, max_len = 0;
+  int64_t off[DPD_MAX_STREAMS + 1];
+};
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+dpd_status check_batch(const dpd_batch* b, Problem* p) {
+  if (!b || !b->offsets_host) return DPD_ERR_NULL;
+  if (b->n_streams < 1 || b->n_streams > DPD_MAX_STREAMS) return DPD_ERR_SHAPE;
+  if (b->per_stream_params != 0 && b->per_stream_params != 1) return DPD_ERR_SHAPE;
+  if (b->offsets_host[0] != 0) return DPD_ERR_SHAPE;
+  p->S = b->n_streams;
+  p->per_stream = b->per_stream_params;
+  p->n_sets = p->per_stream ? p->S : 1;
+  p->max_len = 0;
+  for (int s = 0; s <= p->S; ++s) {
+    p->off[s] = b->offsets_host[s];
+    if (s > 0) {
+      int64_t len = p->off[s] - p->off[s - 1];
+      if (len < 1) return DPD_ERR_SHAPE;
+      if (len > p->max_len) p->max_len = len;
+    }
+  }
+  p->n_total = p->off[p->S];
+  if (p->n_total > (int64_t)1 << 40) return DPD_ERR_SHAPE;
+  return DPD_OK;
+}
+
+dpd_status check_tdnn(const dpd_tdnn_desc* d) {
+  if (!d) return DPD_ERR_NULL;
+  if (d->taps < 1 || d->taps > DPD_MAX_TAPS) return DPD_ERR_SHAPE;
+  if (d->n_hidden < 1 || d->n_hidden > DPD_MAX_LAYERS) return DPD_ERR_SHAPE;
+  if (d->hidden < 1 || d->hidden > DPD_MAX_HIDDEN) return DPD_ERR_SHAPE;
+  if (d->residual != 0 && d->residual != 1) return DPD_ERR_SHAPE;
+  if (d->precision != DPD_FP32 && d->precision != DPD_BF16) return DPD_ERR_SHAPE;
+  if (d->impl != DPD_IMPL_TUNED && d->impl != DPD_IMPL_PLAIN) return DPD_ERR_SHAPE;
+  if (d->impl == DPD_IMPL_PLAIN && d->precision != DPD_FP32) return DPD_ERR_UNSUPPORTED;
+  if (d->impl == DPD_IMPL_TUNED && !tuned_supported(*d, nullptr)) return DPD_ERR_UNSUPPORTED;
+  return DPD_OK;
+}
+
+dpd_status check_gmp(const dpd_gmp_desc* g) {
+  if (!g) return DPD_ERR_NULL;
+  if (g->K < 1 || g->K > DPD_MAX_GMP_K) return DPD_ERR_SHAPE;
+  if (g->M < 0 || g->M > DPD_MAX_GMP_M) return DPD_ERR_SHAPE;
+  if (g->L < 0 || g->L > DPD_MAX_GMP_L) return DPD_ERR_SHAPE;
+  return DPD_OK;
+}
+
+int64_t param_count(const dpd_tdnn_desc& d) {
+  int64_t din = 5 * (int64_t)d.taps, H = d.hidden;
+  return H * din + H + (int64_t)(d.n_hidden - 1) * (H * H + H) + 2 * H + 2;
+}
+int64_t coeff_count(const dpd_gmp_desc& g) {
+  return (int64_t)g.K * (g.M + 1) + 2 * (int64_t)(g.K - 1) * (g.M + 1) * g.L;
+}
+
+StreamTable make_table(const Problem& p, int tile) {
+  StreamTable st;
+  memset(&st, 0, sizeof(st));
+  st.n = p.S;
+  st.per_stream = p.per_stream;
+  st.tile = tile;
+  int32_t t = 0;
+  for (int s = 0; s < p.S; ++s) {
+    st.off[s] = p.off[s];
+    st.tile0[s] = t;
+    t += (int32_t)ceil_div64(p.off[s + 1] - p.off[s], tile);
+  }
+  st.off[p.S] = p.off[p.S];
+  st.tile0[p.S] = t;
+  st.n_tiles = t;
+  return st;
+}
+
+int device_cus() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+
+// ------------------------------------------------------------ workspace layout
+struct Ws {
+  size_t tile_part = 0, inv_r = 0, loss_tmp = 0, u_buf = 0, y_buf = 0, gu_buf = 0;
+  size_t act = 0, part = 0, acc = 0, pack = 0, slots = 0, total = 0;
+  int64_t act_floats_per_sample = 0;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
+  (void)g;
+  Ws w;
+  size_t pos = 0;
+  auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
+  int64_t max_tiles = p.n_total / 32 + p.S + 1;   // any tile size >= 32
+  w.tile_part = take(sizeof(float2) * max_tiles);
+  w.inv_r = take(sizeof(float) * p.n_sets);
+  w.loss_tmp = take(sizeof(float) * p.n_sets);
+  w.u_buf = take(sizeof(float2) * p.n_total);
+  w.y_buf = take(sizeof(float2) * p.n_total);
+  if (d && d->impl == DPD_IMPL_PLAIN) {
+    int64_t H = d->hidden, din = 5 * (int64_t)d->taps;
+    int64_t ch = kPlainChunk;
+    w.gu_buf = take(sizeof(float2) * p.n_total);
+    w.act_floats_per_sample = din + H * d->n_hidden + 2 + 2 * std::max<int64_t>(H, 2);
+    w.act = take(sizeof(float) * ch * w.act_floats_per_sample);
+    int64_t maxl = std::max(H * (din + 1), std::max(H * (H + 1), 2 * (H + 1)));
+    w.part = take(sizeof(float) * (ch / kPlainDwBlock + 1) * maxl);
+    w.acc = take(sizeof(float) * p.n_sets * param_count(*d));
+  } else if (d) {
+    TdnnDims td;
+    tdnn_dims(*d, &td);
+    w.pack = take((size_t)td.pack_bytes * p.n_sets);
+    w.slots = take(sizeof(float) * (size_t)td.dw_slot * (kMaxGrid + p.S));
+  }
+  w.total = pos;
+  return w;
+}
+
+template <class T>
+T* at(void* base, size_t off) { return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off); }
+
+dpd_status launch_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? DPD_OK : DPD_ERR_LAUNCH;
+}
+
+// ------------------------------------------------------------ plain path pieces
+void plain_forward(const dpd_tdnn_desc& d, const Problem& p, const float* x, const float* w,
+                   float* u, const Ws& L, void* ws, hipStream_t s) {
+  int64_t P = param_count(d);
+  int H = d.hidden, din = 5 * d.taps;
+  float* act = at<float>(ws, L.act);
+  for (int st = 0; st < p.S; ++st) {
+    const float* wp = w + (p.per_stream ? st * P : 0);
+    for (int64_t c0 = p.off[st]; c0 < p.off[st + 1]; c0 += kPlainChunk) {
+      int cn = (int)std::min<int64_t>(kPlainChunk, p.off[st + 1] - c0);
+      float* F = act;
+      launch_plain_features(x, p.off[st], c0, cn, d.taps, F, s);
+      const float* in = F;
+      int k_in = din;
+      float* h = F + (int64_t)kPlainChunk * din;
+      const float* wl = wp;
+      for (int i = 0; i < d.n_hidden; ++i) {
+        launch_plain_dense(in, k_in, wl, wl + (int64_t)H * k_in, h, H, cn, 1, s);
+        wl += (int64_t)H * k_in + H;
+        in = h;
+        k_in = H;
+        h += (int64_t)kPlainChunk * H;
+      }
+      launch_plain_dense(in, k_in, wl, wl + 2 * (int64_t)k_in, h, 2, cn, 0, s);
+      launch_plain_u(h, x, c0, cn, d.residual, u, s);
+    }
+  }
+}
+
+void plain_gmp_forward(const dpd_gmp_desc& g, const Problem& p, const float* u, const float* coef,
+                       float* y, hipStream_t s) {
+  int64_t J = coeff_count(g);
+  for (int st = 0; st < p.S; ++st)
+    launch_plain_gmp_fwd(u, p.off[st], p.off[st + 1], coef + (p.per_stream ? st * 2 * J : 0), g.K,
+                         g.M, g.L, y, s);
+}
+
+void plain_backward(const dpd_tdnn_desc& d, const dpd_gmp_desc& g, const Problem& p,
+                    const float* x, const float* w, const float* coef, float g_re, float g_im,
+                    const float* u, const float* y, float* dw, const float* inv_r, const Ws& L,
+                    void* ws, hipStream_t s) {
+  int64_t P = param_count(d), J = coeff_count(g);
+  int H = d.hidden, din = 5 * d.taps, nl = d.n_hidden;
+  float* gu = at<float>(ws, L.gu_buf);
+  for (int st = 0; st < p.S; ++st)
+    launch_plain_gmp_bwd(u, y, x, p.off[st], p.off[st + 1], coef + (p.per_stream ? st * 2 * J : 0),
+                         g.K, g.M, g.L, g_re, g_im, gu, s);
+  float* acc = at<float>(ws, L.acc);
+  launch_fill(acc, (int64_t)p.n_sets * P, 0.f, s);
+  float* act = at<float>(ws, L.act);
+  float* part = at<float>(ws, L.part);
+  const int64_t ch = kPlainChunk;
+  for (int st = 0; st < p.S; ++st) {
+    int set = p.per_stream ? st : 0;
+    const float* wp = w + set * P;
+    float* accp = acc + set * P;
+    for (int64_t c0 = p.off[st]; c0 < p.off[st + 1]; c0 += ch) {
+      int cn = (int)std::min<int64_t>(ch, p.off[st + 1] - c0);
+      // forward, keeping every activation of the chunk
+      float* F = act;
+      launch_plain_features(x, p.off[st], c0, cn, d.taps, F, s);
+      const float* hs[DPD_MAX_LAYERS + 1];
+      const float* wls[DPD_MAX_LAYERS + 1];
+      int ins[DPD_MAX_LAYERS + 1];
+      hs[0] = F;
+      float* h = F + ch * din;
+      const float* wl = wp;
+      int k_in = din;
+      for (int i = 0; i < nl; ++i) {
+        wls[i] = wl;
+        ins[i] = k_in;
+        launch_plain_dense(hs[i], k_in, wl, wl + (int64_t)H * k_in, h, H, cn, 1, s);
+        hs[i + 1] = h;
+        wl += (int64_t)H * k_in + H;
+        k_in = H;
+        h += ch * H;
+      }
+      wls[nl] = wl;
+      ins[nl] = H;
+      float* dA = h;                       // ping-pong delta buffers
+      float* dB = h + ch * std::max(H, 2);
+      launch_plain_delta_out(gu, c0, cn, dA, s);
+      // layer offsets inside the packed/acc layout
+      int64_t loff[DPD_MAX_LAYERS + 1];
+      int64_t pos = 0;
+      for (int i = 0; i <= nl; ++i) {
+        loff[i] = pos;
+        int dout = i == nl ? 2 : H;
+        pos += (int64_t)dout * (ins[i] + 1);
+      }
+      int nblk = (cn + kPlainDwBlock - 1) / kPlainDwBlock;
+      for (int i = nl; i >= 0; --i) {
+        int dout = i == nl ? 2 : H;
+        launch_plain_dw(dA, dout, hs[i], ins[i], cn, kPlainDwBlock, part, s);
+        launch_plain_dw_accum(part, nblk, dout * (ins[i] + 1), accp + loff[i], s);
+        if (i > 0) {
+          launch_plain_dense_bwd(dA, dout, wls[i], hs[i], ins[i], dB, cn, s);
+          std::swap(dA, dB);
+        }
+      }
+    }
+  }
+  launch_plain_finalize_sets(acc, d.taps, nl, H, P, P, p.n_sets, inv_r, dw, s);
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+int64_t dpd_tdnn_param_count(const dpd_tdnn_desc* tdnn) {
+  if (!tdnn || tdnn->taps < 1 || tdnn->hidden < 1 || tdnn->n_hidden < 1) return -1;
+  return param_count(*tdnn);
+}
+
+int64_t dpd_gmp_coeff_count(const dpd_gmp_desc* gmp) {
+  if (check_gmp(gmp) != DPD_OK) return -1;
+  return coeff_count(*gmp);
+}
+
+dpd_status dpd_workspace_size(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
+                              const dpd_batch* batch, size_t* bytes_host) {
+  if (!bytes_host) return DPD_ERR_NULL;
+  Problem p;
+  dpd_status st = check_batch(batch, &p);
+  if (st != DPD_OK) return st;
+  if (tdnn && (st = check_tdnn(tdnn)) != DPD_OK) return st;
+  if (gmp && (st = check_gmp(gmp)) != DPD_OK) return st;
+  *bytes_host = ws_layout(tdnn, gmp, p).total;
+  return DPD_OK;
+}
+
+dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const float* x,
+                       const float* w, float* u, void* workspace, size_t workspace_bytes,
+                       hipStream_t stream) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_tdnn(tdnn)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!x || !w || !u || !workspace) return DPD_ERR_NULL;
+  if (!aligned(x, 8) || !aligned(u, 8) || !aligned(w, 4) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  Ws L = ws_layout(tdnn, nullptr, p);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  if (tdnn->impl == DPD_IMPL_PLAIN) {
+    plain_forward(*tdnn, p, x, w, u, L, workspace, stream);
+  } else {
+    TdnnDims td;
+    tdnn_dims(*tdnn, &td);
+    void* pack = at<void>(workspace, L.pack);
+    launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream);
+    StreamTable tab = make_table(p, kBwdTile);
+    int grid = std::min(tab.n_tiles, 4 * device_cus());
+    launch_tdnn_fwd(td, tab, x, pack, u, grid, stream);
+  }
+  return launch_status();
+}
+
+dpd_status pa_gmp_forward(const dpd_gmp_desc* gmp, const dpd_batch* batch, const float* u,
+                          const float* coef, float* y, hipStream_t stream) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_gmp(gmp)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!u || !coef || !y) return DPD_ERR_NULL;
+  if (!aligned(u, 8) || !aligned(y, 8) || !aligned(coef, 4)) return DPD_ERR_ALIGN;
+  if (u == y) return DPD_ERR_SHAPE;
+  StreamTable tab = make_table(p, kBwdTile);
+  launch_gmp_fwd(*gmp, tab, u, coef, y, stream);
+  return launch_status();
+}
+
+dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x, float g_re,
+                        float g_im, float* out, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!y || !x || !out || !workspace) return DPD_ERR_NULL;
+  if (!aligned(y, 8) || !aligned(x, 8) || !aligned(out, 4) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (!isfinite(g_re) || !isfinite(g_im) || (g_re == 0.f && g_im == 0.f)) return DPD_ERR_SHAPE;
+  Ws L = ws_layout(nullptr, nullptr, p);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  StreamTable tab = make_table(p, kNmseTile);
+  float2* part = at<float2>(workspace, L.tile_part);
+  launch_nmse_tiles(tab, y, x, g_re, g_im, part, stream);
+  launch_nmse_final(tab, part, out, nullptr, nullptr, stream);
+  return launch_status();
+}
+
+dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const dpd_batch* batch,
+                       const float* x, const float* w, const float* coef, float g_re, float g_im,
+                       float* u, float* y, float* nmse, float* dw, float* loss, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_tdnn(tdnn)) != DPD_OK) return st;
+  if ((st = check_gmp(gmp)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!x || !w || !coef || !workspace) return DPD_ERR_NULL;
+  if (dw && !loss) return DPD_ERR_NULL;
+  if (!aligned(x, 8) || (u && !aligned(u, 8)) || (y && !aligned(y, 8)) || !aligned(w, 4) ||
+      !aligned(coef, 4) || (dw && !aligned(dw, 4)) || (loss && !aligned(loss, 4)) ||
+      (nmse && !aligned(nmse, 4)) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (!isfinite(g_re) || !isfinite(g_im) || (g_re == 0.f && g_im == 0.f)) return DPD_ERR_SHAPE;
+  if (dw && tdnn->impl == DPD_IMPL_TUNED && !tuned_supported(*tdnn, gmp)) return DPD_ERR_UNSUPPORTED;
+  Ws L = ws_layout(tdnn, gmp, p);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  float* ubuf = u ? u : at<float>(workspace, L.u_buf);
+  float* inv_r = at<float>(workspace, L.inv_r);
+  float* lossp = loss ? loss : at<float>(workspace, L.loss_tmp);
+  float2* part = at<float2>(workspace, L.tile_part);
+  int64_t P = param_count(*tdnn);
+  if (tdnn->impl == DPD_IMPL_PLAIN) {
+    float* ybuf = y ? y : at<float>(workspace, L.y_buf);
+    plain_forward(*tdnn, p, x, w, ubuf, L, workspace, stream);
+    plain_gmp_forward(*gmp, p, ubuf, coef, ybuf, stream);
+    StreamTable tab = make_table(p, kNmseTile);
+    launch_nmse_tiles(tab, ybuf, x, g_re, g_im, part, stream);
+    launch_nmse_final(tab, part, nmse, lossp, inv_r, stream);
+    if (dw)
+      plain_backward(*tdnn, *gmp, p, x, w, coef, g_re, g_im, ubuf, ybuf, dw, inv_r, L, workspace,
+                     stream);
+    return launch_status();
+  }
+  TdnnDims td;
+  tdnn_dims(*tdnn, &td);
+  void* pack = at<void>(workspace, L.pack);
+  launch_pack(td, w, p.n_sets, P, pack, stream);
+  StreamTable tab = make_table(p, kBwdTile);
+  int fgrid = std::min(tab.n_tiles, 4 * device_cus());
+  launch_tdnn_fwd(td, tab, x, pack, ubuf, fgrid, stream);
+  if (y) launch_gmp_fwd(*gmp, tab, ubuf, coef, y, stream);
+  if (dw) {
+    int grid = std::min(tab.n_tiles, std::min(kMaxGrid, 2 * device_cus()));
+    float* slots = at<float>(workspace, L.slots);
+    launch_tdnn_bwd(td, *gmp, tab, x, ubuf, coef, g_re, g_im, pack, part, slots, grid, stream);
+    launch_nmse_final(tab, part, nmse, lossp, inv_r, stream);
+    launch_dw_finalize(td, tab, grid, slots, inv_r, dw, stream);
+  } else {
+    float* ybuf = y ? y : at<float>(workspace, L.y_buf);
+    if (!y) launch_gmp_fwd(*gmp, tab, ubuf, coef, ybuf, stream);
+    StreamTable nt = make_table(p, kNmseTile);
+    launch_nmse_tiles(nt, ybuf, x, g_re, g_im, part, stream);
+    launch_nmse_final(nt, part, nmse, lossp, inv_r, stream);
+  }
+  return launch_status();
+}
+
+dpd_status dpd_backward(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const dpd_batch* batch,
+                        const float* x, const float* w, const float* coef, float g_re, float g_im,
+                        float* dw, float* loss, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+  if (!dw || !loss) return DPD_ERR_NULL;
+  return dpd_cascade(tdnn, gmp, batch, x, w, coef, g_re, g_im, nullptr, nullptr, nullptr, dw, loss,
+                     workspace, workspace_bytes, stream);
+}
+
+size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft) {
+  if (nfft < 64 || nfft > 4096 || (nfft & (nfft - 1)) || n < nfft) return 0;
+  int64_t nseg = (n - nfft) / (nfft / 2) + 1;
+  int64_t groups = std::min<int64_t>(nseg, 1024);
+  return align_up(sizeof(float) * (size_t)groups * nfft);
+}
+
+dpd_status cascade_acpr(const float* y, int64_t n, int32_t nfft, int32_t half_bins, float* psd,
+                        float* acpr, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!y || !psd || !acpr || !workspace) return DPD_ERR_NULL;
+  if (nfft < 64 || nfft > 4096 || (nfft & (nfft - 1))) return DPD_ERR_SHAPE;
+  if (n < nfft || half_bins < 1 || 3 * half_bins >= nfft / 2) return DPD_ERR_SHAPE;
+  if (!aligned(y, 8) || !aligned(psd, 4) || !aligned(acpr, 4) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  size_t need = dpd_acpr_workspace_size(n, nfft);
+  if (workspace_bytes < need) return DPD_ERR_WORKSPACE;
+  int64_t nseg = (n - nfft) / (nfft / 2) + 1;
+  int groups = (int)std::min<int64_t>(nseg, 1024);
+  float* seg_part = static_cast<float*>(workspace);
+  launch_welch(y, n, nfft, seg_part, groups, stream);
+  launch_welch_final(seg_part, groups, (int)nseg, nfft, half_bins, psd, acpr, stream);
+  return launch_status();
+}
+
+const char* dpd_status_string(dpd_status status) {
+  switch (status) {
+    case DPD_OK: return "DPD_OK";
+    case DPD_ERR_NULL: return "DPD_ERR_NULL: a required pointer is NULL";
+    case DPD_ERR_SHAPE: return "DPD_ERR_SHAPE: invalid size, offset table or descriptor";
+    case DPD_ERR_UNSUPPORTED: return "DPD_ERR_UNSUPPORTED: request not implemented by this build";
+    case DPD_ERR_WORKSPACE: return "DPD_ERR_WORKSPACE: workspace too small";
+    case DPD_ERR_LAUNCH: return "DPD_ERR_LAUNCH: the HIP runtime reported an error";
+    case DPD_ERR_ALIGN: return "DPD_ERR_ALIGN: misaligned pointer";
+  }
+  return "unknown dpd_status";
+}
+
+const char* dpd_version(void) { return "dpdmi 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Host-side launchers of the dpdmi kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace dpdmi {
+
+// ------------------------------------------------------------------ shared
+// E/R partial per tile of the stream table (tile = table.tile samples).
+void launch_nmse_tiles(const StreamTable& st, const float* y, const float* x, float g_re,
+                       float g_im, float2* tile_part, hipStream_t s);
+// Per-stream and pooled (E, R, NMSE dB) from the tile partials; optional per-set
+// pooled loss and 1/R per set (inv_r may be null).
+void launch_nmse_final(const StreamTable& st, const float2* tile_part, float* out3, float* loss,
+                       float* inv_r, hipStream_t s);
+
+// ------------------------------------------------------------------ plain path
+void launch_plain_features(const float* x, int64_t lo, int64_t c0, int cn, int taps, float* F,
+                           hipStream_t s);
+void launch_plain_dense(const float* in, int din, const float* W, const float* b, float* out,
+                        int dout, int cn, int act, hipStream_t s);
+void launch_plain_u(const float* o2, const float* x, int64_t c0, int cn, int residual, float* u,
+                    hipStream_t s);
+void launch_plain_gmp_fwd(const float* u, int64_t lo, int64_t hi, const float* coef, int K, int M,
+                          int L, float* y, hipStream_t s);
+void launch_plain_gmp_bwd(const float* u, const float* y, const float* x, int64_t lo, int64_t hi,
+                          const float* coef, int K, int M, int L, float g_re, float g_im, float* gu,
+                          hipStream_t s);
+void launch_plain_delta_out(const float* gu, int64_t c0, int cn, float* d, hipStream_t s);
+void launch_plain_dense_bwd(const float* dout, int n_out, const float* W, const float* hin,
+                            int n_in, float* din, int cn, hipStream_t s);
+void launch_plain_dw(const float* dout, int n_out, const float* hin, int n_in, int cn, int blk,
+                     float* part, hipStream_t s);
+void launch_plain_dw_accum(const float* part, int nblk, int count, float* acc, hipStream_t s);
+void launch_plain_finalize_sets(const float* acc, int taps, int n_hidden, int hidden,
+                                int64_t acc_stride, int64_t P, int n_sets, const float* inv_r,
+                                float* dw, hipStream_t s);
+void launch_fill(float* p, int64_t n, float v, hipStream_t s);
+
+// ------------------------------------------------------------------ tuned path
+struct TdnnDims {
+  int taps, n_hidden, hidden, residual, prec;
+  int kin;          // 5 * taps
+  int hp;           // hidden padded to a multiple of 32
+  int kin_p;        // kin padded to the MFMA K step
+  int nks1;         // MFMA K steps of layer 1
+  int nksh;         // MFMA K steps of a hidden layer
+  int64_t pack_bytes;  // bytes of one packed parameter set
+  // packed offsets (bytes) inside one set
+  int64_t off_fwd1, off_fwdh, off_bwdh, off_bias, off_wo, off_bo;
+  // natural-layout dW (floats) per slot: layer rows x cols, bias in the last used column
+  int dw_cols1, dw_colsh, dw_colso;    // columns of layer 1, hidden, output blocks
+  int64_t dw_off[DPD_MAX_LAYERS + 2];  // float offset of each layer (index nl = output)
+  int64_t dw_slot;                     // floats per slot
+};
+bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out);
+bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g);
+
+void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack,
+                 hipStream_t s);
+// TDNN forward over the table's tiles.
+void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
+                     float* u, int grid, hipStream_t s);
+// GMP forward over the table's tiles.
+void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,
+                    float* y, hipStream_t s);
+// Fused GMP forward/backward + TDNN recompute/backward, dW partial slots and E/R tile partials.
+void launch_tdnn_bwd(const TdnnDims& td, const dpd_gmp_desc& g, const StreamTable& st,
+                     const float* x, const float* u, const float* coef, float g_re, float g_im,
+                     const void* pack, float2* tile_part, float* slots, int grid, hipStream_t s);
+void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
+                        const float* inv_r_set, float* dw, hipStream_t s);
+
+// ------------------------------------------------------------------ spectrum
+void launch_welch(const float* y, int64_t n, int nfft, float* seg_part, int n_groups,
+                  hipStream_t s);
+void launch_welch_final(const float* seg_part, int n_groups, int nseg, int nfft, int half_bins,
+                        float* psd, float* acpr, hipStream_t s);
+
+}  // namespace dpdmi

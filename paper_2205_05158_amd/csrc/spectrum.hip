@@ -1,0 +1,127 @@
+// Welch power spectral density of a PA output and its adjacent-channel power ratio
+// (the out-of-band metric named in Sec. I).  Segments of nfft samples, hop nfft/2,
+// periodic Hann window; each workgroup transforms a contiguous group of segments
+// with an in-LDS radix-2 decimation-in-time FFT and accumulates |X_k|^2 per bin;
+// a single-workgroup pass sums the group spectra in a fixed order (Neumaier) and
+// integrates the channel powers.
+#include "kernels.hpp"
+
+namespace dpdmi {
+
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kMaxFft = 4096;
+
+__global__ __launch_bounds__(kFftThreads) void k_welch(const float* __restrict__ y, int64_t n,
+                                                       int nfft, int log2n, int nseg,
+                                                       float* __restrict__ part) {
+  __shared__ float2 buf[kMaxFft];
+  __shared__ float2 tw[kMaxFft / 2];
+  const int tid = threadIdx.x;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int s0 = (int)(((int64_t)g * nseg) / G), s1 = (int)(((int64_t)(g + 1) * nseg) / G);
+  const int half = nfft / 2;
+  // twiddles W^k = exp(-2 pi i k / nfft)
+  for (int k = tid; k < half; k += kFftThreads) {
+    float sv, cv;
+    sincospif(-2.0f * (float)k / (float)nfft, &sv, &cv);
+    tw[k] = make_float2(cv, sv);
+  }
+  constexpr int kBinsPerThread = kMaxFft / kFftThreads;
+  float acc[kBinsPerThread];
+#pragma unroll
+  for (int q = 0; q < kBinsPerThread; ++q) acc[q] = 0.f;
+  for (int sg = s0; sg < s1; ++sg) {
+    __syncthreads();
+    const int64_t base = (int64_t)sg * half;
+    for (int i = tid; i < nfft; i += kFftThreads) {
+      float2 v = ld2(y, base + i);
+      float w = 0.5f - 0.5f * cospif(2.0f * (float)i / (float)nfft);
+      int r = __brev((unsigned)i) >> (32 - log2n);
+      buf[r] = make_float2(v.x * w, v.y * w);
+    }
+    __syncthreads();
+    for (int st = 1; st <= log2n; ++st) {
+      const int m = 1 << st, mh = m >> 1;
+      for (int b = tid; b < half; b += kFftThreads) {
+        int grp = b / mh, k = b % mh;
+        int i0 = grp * m + k, i1 = i0 + mh;
+        float2 wv = tw[k * (nfft / m)];
+        float2 a = buf[i0], c = buf[i1];
+        float2 t = make_float2(wv.x * c.x - wv.y * c.y, wv.x * c.y + wv.y * c.x);
+        buf[i0] = make_float2(a.x + t.x, a.y + t.y);
+        buf[i1] = make_float2(a.x - t.x, a.y - t.y);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kBinsPerThread; ++q) {
+      int k = tid + q * kFftThreads;
+      if (k < nfft) {
+        float2 X = buf[k];
+        acc[q] += X.x * X.x + X.y * X.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kBinsPerThread; ++q) {
+    int k = tid + q * kFftThreads;
+    if (k < nfft) part[(int64_t)g * nfft + k] = acc[q];
+  }
+}
+
+__global__ __launch_bounds__(kFftThreads) void k_welch_final(const float* __restrict__ part, int G,
+                                                             int nseg, int nfft, int half_bins,
+                                                             float* __restrict__ psd,
+                                                             float* __restrict__ acpr) {
+  __shared__ float sh[6 * kFftThreads];
+  const int tid = threadIdx.x;
+  const float scale = 1.0f / ((float)nseg * 0.375f * (float)nfft);   // sum of Hann^2 = 3 nfft / 8
+  Comp lo, mn, up;
+  for (int k = tid; k < nfft; k += kFftThreads) {
+    Comp s;
+    for (int g = 0; g < G; ++g) s.add(part[(int64_t)g * nfft + k]);
+    float v = s.value() * scale;
+    psd[k] = v;
+    int ks = k < nfft / 2 ? k : k - nfft;
+    int a = ks < 0 ? -ks : ks;
+    if (a <= half_bins) mn.add(v);
+    else if (ks > half_bins && ks <= 3 * half_bins) up.add(v);
+    else if (ks < -half_bins && ks >= -3 * half_bins) lo.add(v);
+  }
+  sh[tid] = lo.s; sh[kFftThreads + tid] = lo.c;
+  sh[2 * kFftThreads + tid] = mn.s; sh[3 * kFftThreads + tid] = mn.c;
+  sh[4 * kFftThreads + tid] = up.s; sh[5 * kFftThreads + tid] = up.c;
+  __syncthreads();
+  if (tid == 0) {
+    Comp L, Mn, U;
+    for (int i = 0; i < kFftThreads; ++i) {
+      L.add(sh[i]); L.add(sh[kFftThreads + i]);
+      Mn.add(sh[2 * kFftThreads + i]); Mn.add(sh[3 * kFftThreads + i]);
+      U.add(sh[4 * kFftThreads + i]); U.add(sh[5 * kFftThreads + i]);
+    }
+    float pm = Mn.value();
+    float aL = 10.f * log10f(L.value() / pm), aU = 10.f * log10f(U.value() / pm);
+    acpr[0] = aL;
+    acpr[1] = aU;
+    acpr[2] = fmaxf(aL, aU);
+  }
+}
+
+}  // namespace
+
+void launch_welch(const float* y, int64_t n, int nfft, float* seg_part, int n_groups,
+                  hipStream_t s) {
+  int log2n = 0;
+  while ((1 << log2n) < nfft) ++log2n;
+  int nseg = (int)((n - nfft) / (nfft / 2) + 1);
+  k_welch<<<n_groups, kFftThreads, 0, s>>>(y, n, nfft, log2n, nseg, seg_part);
+}
+
+void launch_welch_final(const float* seg_part, int n_groups, int nseg, int nfft, int half_bins,
+                        float* psd, float* acpr, hipStream_t s) {
+  k_welch_final<<<1, kFftThreads, 0, s>>>(seg_part, n_groups, nseg, nfft, half_bins, psd, acpr);
+}
+
+}  // namespace dpdmi

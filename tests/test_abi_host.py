@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI: the library loads, exports every function that
+include/dpdmi.h declares, and rejects invalid arguments before any HIP call
+(so these run without a GPU; no call here reaches a kernel launch)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2205_05158_amd as D
+from paper_2205_05158_amd import _lib as L
+import dpd_synth as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = C.c_void_p(0x100000)          # aligned, never dereferenced: validation fails first
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "dpdmi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(\w+)\s*\(", txt, flags=re.M))
+                  - {"if", "while", "for", "return", "sizeof"})
+
+
+def test_library_exports_every_declared_function(dpdlib):
+    names = header_functions()
+    assert "dpd_forward" in names and "pa_gmp_forward" in names
+    for n in names:
+        assert hasattr(dpdlib, n), f"missing export {n}"
+    assert set(names) == set(L.EXPORTS)
+    assert D.dpd_version().endswith("gfx950")
+
+
+def test_param_and_coeff_counts(dpdlib):
+    for T, nl, H in [(4, 2, 20), (10, 3, 64), (16, 4, 128), (1, 1, 1)]:
+        assert D.dpd_tdnn_param_count(D.tdnn_desc(T, nl, H)) == S.tdnn_param_count(T, nl, H)
+    for K, M, Lg in [(5, 3, 2), (7, 5, 3), (9, 7, 4), (1, 0, 0)]:
+        assert D.dpd_gmp_coeff_count(D.gmp_desc(K, M, Lg)) == S.gmp_coeff_count(K, M, Lg)
+    assert D.dpd_gmp_coeff_count(D.gmp_desc(0, 1, 1)) == -1
+
+
+def test_workspace_size_grows_with_problem(dpdlib):
+    t = D.tdnn_desc(10, 3, 64)
+    g = D.gmp_desc(7, 5, 3)
+    a = D.dpd_workspace_size(t, g, D.make_batch([0, 1000]))
+    b = D.dpd_workspace_size(t, g, D.make_batch([0, 100000]))
+    assert 0 < a < b
+    p = D.dpd_workspace_size(D.tdnn_desc(10, 3, 64, impl="plain"), g, D.make_batch([0, 1000]))
+    assert p > 0
+
+
+def _fwd(tdnn, batch, x=FAKE, w=FAKE, u=FAKE, ws=FAKE, nbytes=1 << 40):
+    return L.lib().dpd_forward(C.byref(tdnn), C.byref(batch), x, w, u, ws, nbytes, None)
+
+
+@pytest.mark.parametrize("desc,code", [
+    (dict(taps=0), L.DPD_ERR_SHAPE), (dict(taps=33), L.DPD_ERR_SHAPE),
+    (dict(hidden=0), L.DPD_ERR_SHAPE), (dict(n_hidden=9), L.DPD_ERR_SHAPE),
+    (dict(residual=2), L.DPD_ERR_SHAPE), (dict(precision=7), L.DPD_ERR_SHAPE),
+    (dict(impl=3), L.DPD_ERR_SHAPE),
+    (dict(precision=L.DPD_BF16, impl=L.DPD_IMPL_PLAIN), L.DPD_ERR_UNSUPPORTED),
+    (dict(taps=3, hidden=7, n_hidden=1), L.DPD_ERR_UNSUPPORTED),   # no tuned kernel for this shape
+])
+def test_tdnn_descriptor_rejected(dpdlib, desc, code):
+    base = dict(taps=10, n_hidden=3, hidden=64, residual=0, precision=0, impl=0)
+    base.update(desc)
+    t = L.TdnnDesc(**base)
+    assert _fwd(t, D.make_batch([0, 100])) == code
+
+
+@pytest.mark.parametrize("offsets,code", [
+    ([1, 100], L.DPD_ERR_SHAPE),          # must start at 0
+    ([0, 50, 50], L.DPD_ERR_SHAPE),       # empty stream
+    ([0, 50, 20], L.DPD_ERR_SHAPE),       # decreasing
+    ([0], L.DPD_ERR_SHAPE),               # no stream
+])
+def test_batch_rejected(dpdlib, offsets, code):
+    assert _fwd(D.tdnn_desc(10, 3, 64), D.make_batch(offsets)) == code
+
+
+def test_too_many_streams_rejected(dpdlib):
+    off = np.arange(0, 130 * 10, 10)
+    assert _fwd(D.tdnn_desc(10, 3, 64), D.make_batch(off)) == L.DPD_ERR_SHAPE
+
+
+def test_null_and_alignment_and_workspace(dpdlib):
+    t = D.tdnn_desc(10, 3, 64)
+    b = D.make_batch([0, 100])
+    assert _fwd(t, b, x=None) == L.DPD_ERR_NULL
+    assert _fwd(t, b, u=None) == L.DPD_ERR_NULL
+    assert _fwd(t, b, x=C.c_void_p(0x100004)) == L.DPD_ERR_ALIGN
+    assert _fwd(t, b, nbytes=16) == L.DPD_ERR_WORKSPACE
+    lib = L.lib()
+    assert lib.dpd_forward(None, C.byref(b), FAKE, FAKE, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    g = D.gmp_desc(7, 5, 3)
+    assert lib.pa_gmp_forward(C.byref(g), C.byref(b), FAKE, FAKE, FAKE, None) == L.DPD_ERR_SHAPE  # u == y
+    bad = D.gmp_desc(13, 1, 1)
+    assert lib.pa_gmp_forward(C.byref(bad), C.byref(b), FAKE, FAKE, C.c_void_p(0x200000), None) == L.DPD_ERR_SHAPE
+    # zero target gain is not a valid NMSE reference
+    assert lib.cascade_nmse(C.byref(b), FAKE, FAKE, 0.0, 0.0, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    # gradient without a loss output
+    assert lib.dpd_cascade(C.byref(t), C.byref(g), C.byref(b), FAKE, FAKE, FAKE, 1.0, 0.0, None, None,
+                           None, FAKE, None, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    # unsupported (TDNN, GMP) pair for the fused backward
+    g2 = D.gmp_desc(9, 7, 4)
+    assert lib.dpd_backward(C.byref(t), C.byref(g2), C.byref(b), FAKE, FAKE, FAKE, 1.0, 0.0, FAKE, FAKE,
+                            FAKE, 1 << 40, None) == L.DPD_ERR_UNSUPPORTED
+
+
+def test_acpr_arguments_rejected(dpdlib):
+    lib = L.lib()
+    for n, nfft, hb in [(4096, 1000, 10), (100, 4096, 10), (8192, 4096, 700), (8192, 8192, 10)]:
+        assert lib.cascade_acpr(FAKE, n, nfft, hb, FAKE, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert lib.cascade_acpr(FAKE, 8192, 4096, 512, FAKE, FAKE, FAKE, 0, None) == L.DPD_ERR_WORKSPACE
+    assert D.dpd_acpr_workspace_size(8192, 4096) > 0
+
+
+def test_status_strings(dpdlib):
+    for code in range(-6, 1):
+        assert D.status_string(code).startswith("DPD_")
