@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the direct-learning DPD step on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input, through the C ABI:
+TDNN DPD forward -> GMP PA forward -> NMSE against G x -> hand-written reverse mode
+to the TDNN weights (dpd_cascade with u, y, NMSE, dW and loss outputs), then the
+Welch PSD / ACPR of the PA output (cascade_acpr).  Inputs are resident in HBM
+before the timed region.  Prints one JSON line.
+
+Default workload: 2^24 samples of a PAPR-clipped (10 dB) OFDM-like signal, BF16-MFMA
+TDNN with 16 taps and 4 hidden tanh layers of 128, FP32 GMP PA with K = 9, M = 7, L = 4.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_gbs": 8000.0,
+    "mfma_bf16_tflops": 2500.0,
+    "mfma_fp32_tflops": 157.3,
+    "valu_fp32_tflops": 157.3,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="bf16_16m")
+    ap.add_argument("--impl", default="tuned", choices=["tuned", "plain"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp32", "bf16"])
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20,
+                    help="samples of the workload the CPU oracle is timed on")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl_name, n_sample):
+    """The FP64 oracle as it stands, on a bounded sample of the workload: the first
+    n_sample samples (single stream), the first frames (frames), or the first streams
+    whose lengths add up to at most n_sample (per-stream parameters)."""
+    import numpy as np
+    import dpd_synth as S
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    wl = S.WORKLOADS[wl_name]
+    if wl.per_stream_params:
+        lens = S.stream_lengths(wl.n_streams)
+        k = max(1, int(np.searchsorted(np.cumsum(lens), n_sample, side="right")))
+        inp = S.make_workload(wl_name, n_streams=k)
+    elif wl.frame_len is not None:
+        inp = S.make_workload(wl_name, n_streams=max(1, n_sample // wl.frame_len),
+                              max_len=min(n_sample, wl.frame_len))
+    else:
+        inp = S.make_workload(wl_name, max_len=n_sample)
+    model = O.Model(wl.taps, wl.n_hidden, wl.hidden, wl.K, wl.M, wl.L)
+    n0 = int(inp.offsets[1])
+    t0 = time.perf_counter()
+    res = O.cascade(inp.x, inp.offsets, inp.w, inp.coef, model, per_stream=wl.per_stream_params)
+    if n0 >= 4096:
+        O.welch_psd(res.y[:n0], 4096)
+    dt = time.perf_counter() - t0
+    n = int(inp.offsets[-1])
+    return {"value": n / dt / 1e6, "unit": "Msamples/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {n} samples of {wl_name} ({inp.offsets.size - 1} stream(s)); "
+                      f"FP64 NumPy forward + NMSE + gradient + Welch PSD; "
+                      f"BLAS threads {threads}, elementwise NumPy single-threaded; {dt:.1f} s",
+            "seconds": dt}, inp, res
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the hot path shards by "
+                                   "streams or time chunks across GPUs (see the design notes), "
+                                   "but no multi-GPU run is implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import dpd_synth as S
+    import paper_2205_05158_amd as D
+    from paper_2205_05158_amd import flops as F
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    if not os.path.exists(D.LIB_PATH):
+        from paper_2205_05158_amd import build as B
+        B.build()
+    torch.cuda.set_device(0)
+    wl = S.WORKLOADS[args.workload]
+    prec = args.precision or wl.precision
+    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+    inp = S.make_workload(args.workload)
+    n = inp.n_total
+    cas = D.Cascade(wl.taps, wl.n_hidden, wl.hidden, wl.K, wl.M, wl.L, inp.offsets,
+                    per_stream_params=wl.per_stream_params, precision=prec, impl=args.impl)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x, w, coef = dev(inp.x), dev(inp.w), dev(inp.coef)
+    u = torch.empty_like(x)
+    y = torch.empty_like(x)
+    nm = torch.empty(3 * (cas.S + 1), dtype=torch.float32, device="cuda")
+    dw = torch.empty(cas._w_shape(), dtype=torch.float32, device="cuda")
+    loss = torch.empty(cas.n_sets, dtype=torch.float32, device="cuda")
+    # ACPR on the first stream (all single-stream workloads: the whole signal)
+    n0 = int(inp.offsets[1])
+    do_acpr = n0 >= 4096 and 3 * (wl.n_active // 2) * (4096 // wl.n_fft) < 2048
+    half_bins = (wl.n_active // 2) * (4096 // wl.n_fft)
+    if do_acpr:
+        acpr_ws = torch.empty(D.dpd_acpr_workspace_size(n0, 4096), dtype=torch.uint8, device="cuda")
+        psd = torch.empty(4096, dtype=torch.float32, device="cuda")
+        acpr = torch.empty(3, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        D.dpd_cascade(cas.tdnn, cas.gmp, cas.batch, x, w, coef, 1.0, u, y, nm, dw, loss,
+                      cas.workspace, stream)
+        if do_acpr:
+            D.cascade_acpr(y, n0, 4096, half_bins, psd, acpr, acpr_ws, stream)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    D.dpd_profile_report()                     # drop anything recorded before
+    D.dpd_profile_enable(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    D.dpd_profile_enable(False)
+    prof = D.dpd_profile_report()
+    wall = t1 - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = n * args.steps / wall / 1e6
+    print(f"[bench] {args.steps} steps, {ms_per_step:.3f} ms/step (events), wall {wall:.3f} s",
+          file=sys.stderr, flush=True)
+
+    # ---- roofline of the dominant kernel (average duration from the live HIP events)
+    kern = {k: (c, ms) for k, (c, ms) in prof.items()}
+    dom = max(kern, key=lambda k: kern[k][1])
+    cnt, tot = kern[dom]
+    t_avg = tot / cnt / 1e3                     # seconds per launch
+    tf = F.tdnn_flops(wl.taps, wl.n_hidden, wl.hidden)
+    gf = F.gmp_train_flops(wl.K, wl.M, wl.L)
+    mma_peak = PEAK["mfma_bf16_tflops"] if prec == "bf16" else PEAK["mfma_fp32_tflops"]
+    per_kernel = {
+        "tdnn_bwd": {"mma": tf["bwd_mma"], "alu": tf["bwd_out"] + gf["total"]},
+        "tdnn_fwd": {"mma": tf["fwd_mma"], "alu": tf["out"]},
+        "plain_backward": {"mma": 0, "alu": tf["bwd_mma"] + tf["bwd_out"] + gf["bwd"]},
+        "plain_forward": {"mma": 0, "alu": tf["fwd_mma"] + tf["out"]},
+    }
+    roof = None
+    if dom in per_kernel:
+        work = per_kernel[dom]
+        t_mma = work["mma"] * n / (mma_peak * 1e12)
+        t_alu = work["alu"] * n / (PEAK["valu_fp32_tflops"] * 1e12)
+        if t_mma >= t_alu:
+            ach = work["mma"] * n / t_avg / 1e12
+            roof = {"bound": "mfma", "achieved": ach, "peak": mma_peak, "unit": "TFLOP/s",
+                    "frac": ach / mma_peak, "traffic": None}
+        else:
+            ach = work["alu"] * n / t_avg / 1e12
+            roof = {"bound": "alu", "achieved": ach, "peak": PEAK["valu_fp32_tflops"],
+                    "unit": "TFLOP/s", "frac": ach / PEAK["valu_fp32_tflops"], "traffic": None}
+        roof["kernel"] = dom
+        roof["kernel_ms"] = t_avg * 1e3
+        roof["flops_per_sample"] = work
+        roof["samples_per_launch"] = n
+        roof["composite_frac"] = max(t_mma, t_alu) / t_avg
+    step_flops = (tf["total"] + gf["total"]) * n
+
+    out = {
+        "metric": "Msamples/s DPD+PA forward+backward at <=0.1 dB NMSE gap vs FP64; % roofline",
+        "value": value, "unit": "Msamples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": args.workload, "samples": n, "streams": int(cas.S),
+                   "tdnn": f"{wl.taps} taps x5 features, {wl.n_hidden}x{wl.hidden} tanh",
+                   "gmp": f"K{wl.K} M{wl.M} L{wl.L}", "impl": args.impl,
+                   "step": "dpd_cascade(u, y, nmse, dW, loss) + cascade_acpr" if do_acpr
+                           else "dpd_cascade(u, y, nmse, dW, loss)",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "algorithmic_tflops": step_flops / (ms_per_step / 1e3) / 1e12,
+        "kernels_ms_per_step": {k: ms / args.steps for k, (c, ms) in kern.items()},
+        "loss": float(loss.sum().item()), "nmse_db": float(nm[-3:].cpu().numpy()[2]),
+    }
+    if do_acpr:
+        out["acpr_db"] = [float(v) for v in acpr.cpu().numpy()]
+
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline on {args.cpu_sample} samples", file=sys.stderr, flush=True)
+        cb, sinp, sres = cpu_baseline(args.workload, args.cpu_sample)
+        out["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
+        # NMSE parity of this GPU path on the same sample
+        scas = D.Cascade(wl.taps, wl.n_hidden, wl.hidden, wl.K, wl.M, wl.L, sinp.offsets,
+                         per_stream_params=wl.per_stream_params, precision=prec, impl=args.impl)
+        r = scas.run(dev(sinp.x), dev(sinp.w), dev(sinp.coef), want_grad=True)
+        g_db = float(r["nmse"][-1, 2].item())
+        o_db = float(10 * np.log10(sres.E.sum() / sres.R.sum()))
+        gd = r["dw"].cpu().double().numpy().reshape(sres.dw.shape)
+        out["parity"] = {"sample_samples": int(sinp.offsets[-1]), "nmse_gpu_db": g_db,
+                         "nmse_oracle_db": o_db, "nmse_gap_db": abs(g_db - o_db),
+                         "grad_rel_err": float(np.linalg.norm(gd - sres.dw) / np.linalg.norm(sres.dw))}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -266,8 +266,9 @@ def make_workload(name_or_wl, n_streams: int | None = None, max_len: int | None 
         lens = [wl.frame_len] * nf
     else:
         lens = [n]
-    if max_len is not None:
-        pieces = [sig[i * (lens[0]):(i * lens[0]) + min(l, max_len)] for i, l in enumerate(lens)]
+    if max_len is not None or n_streams is not None:
+        cap = lens[0] if max_len is None else max_len
+        pieces = [sig[i * lens[0]:i * lens[0] + min(l, cap)] for i, l in enumerate(lens)]
         if n_streams is not None:
             pieces = pieces[:n_streams]
         sig = np.concatenate(pieces)

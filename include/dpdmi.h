@@ -26,8 +26,9 @@
  *   - Arguments are validated on the host before any HIP call; on failure a
  *     negative dpd_status is returned and nothing is enqueued.  A launch failure
  *     reported by the runtime after enqueueing returns DPD_ERR_LAUNCH.
- *   - Calls are thread-safe; the library keeps no mutable global state apart
- *     from a lazily filled, mutex-guarded cache of device properties.
+ *   - Calls are thread-safe; the library's only mutable global state is a lazily
+ *     filled, mutex-guarded cache of device properties and the opt-in kernel timer
+ *     (dpd_profile_enable), also mutex-guarded.
  */
 #ifndef DPDMI_H
 #define DPDMI_H
@@ -151,6 +152,15 @@ dpd_status cascade_acpr(const float* y, int64_t n, int32_t nfft, int32_t half_bi
                         float* psd, float* acpr, void* workspace, size_t workspace_bytes,
                         hipStream_t stream);
 size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft);
+
+/* Opt-in kernel timing, for profiling tools.  While enabled (on != 0), every kernel
+ * the library launches is bracketed by two HIP events recorded on the caller's
+ * stream (the only case in which the library creates runtime objects).
+ * dpd_profile_report waits for the recorded events, writes one line
+ * "<kernel> <launches> <total ms>" per kernel into buf_host (NUL-terminated,
+ * truncated to cap bytes), releases the events and returns the number of kernels. */
+dpd_status dpd_profile_enable(int32_t on);
+int32_t dpd_profile_report(char* buf_host, size_t cap);
 
 /* Human-readable name of a status code (static storage). */
 const char* dpd_status_string(dpd_status status);

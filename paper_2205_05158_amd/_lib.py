@@ -57,6 +57,8 @@ _SIGS = {
                               C.c_float, C.c_float, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
+    "dpd_profile_enable": (C.c_int, [C.c_int32]),
+    "dpd_profile_report": (C.c_int32, [C.c_char_p, C.c_size_t]),
     "dpd_status_string": (C.c_char_p, [C.c_int]),
     "dpd_version": (C.c_char_p, []),
 }
@@ -182,6 +184,21 @@ def cascade_acpr(y, n, nfft, half_bins, psd, acpr, workspace, stream=None):
     _check(lib().cascade_acpr(_ptr(y), n, nfft, half_bins, _ptr(psd), _ptr(acpr), _ptr(workspace),
                               workspace.numel() * workspace.element_size(), _stream(stream)),
            "cascade_acpr")
+
+
+def dpd_profile_enable(on: bool = True):
+    _check(lib().dpd_profile_enable(1 if on else 0), "dpd_profile_enable")
+
+
+def dpd_profile_report() -> dict:
+    """{kernel: (launches, total_ms)} since the last report; waits for the events."""
+    buf = C.create_string_buffer(1 << 16)
+    lib().dpd_profile_report(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out
 
 
 def dpd_version() -> str:

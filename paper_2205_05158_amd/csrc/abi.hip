@@ -2,10 +2,14 @@
 // argument is checked before the first HIP call; nothing is allocated; all work
 // goes onto the caller's stream.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -165,6 +169,47 @@ dpd_status launch_status() {
   return e == hipSuccess ? DPD_OK : DPD_ERR_LAUNCH;
 }
 
+// ------------------------------------------------------------ opt-in kernel timing
+// When enabled, every kernel launch the library makes is bracketed by two HIP
+// events recorded on the caller's stream; dpd_profile_report() waits for them and
+// returns per-kernel counts and total milliseconds.  Disabled by default: then no
+// event is created and nothing is recorded.
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> recs;
+};
+Prof& prof() {
+  static Prof p;
+  return p;
+}
+
+struct ProfScope {
+  hipStream_t s;
+  hipEvent_t b = nullptr;
+  bool active = false;
+  std::string name;
+  ProfScope(const char* n, hipStream_t st) : s(st), name(n) {
+    Prof& p = prof();
+    std::lock_guard<std::mutex> lock(p.mu);
+    if (!p.on) return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    (void)hipEventRecord(a, s);
+    p.recs.push_back({name, a, b});
+    active = true;
+  }
+  ~ProfScope() {
+    if (active) (void)hipEventRecord(b, s);
+  }
+};
+#define DPD_PROF(name) ProfScope _prof_scope_##__LINE__(name, stream)
+
 // ------------------------------------------------------------ plain path pieces
 void plain_forward(const dpd_tdnn_desc& d, const Problem& p, const float* x, const float* w,
                    float* u, const Ws& L, void* ws, hipStream_t s) {
@@ -310,15 +355,16 @@ dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const 
   Ws L = ws_layout(tdnn, nullptr, p);
   if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
   if (tdnn->impl == DPD_IMPL_PLAIN) {
+    DPD_PROF("plain_forward");
     plain_forward(*tdnn, p, x, w, u, L, workspace, stream);
   } else {
     TdnnDims td;
     tdnn_dims(*tdnn, &td);
     void* pack = at<void>(workspace, L.pack);
-    launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream);
+    { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
     StreamTable tab = make_table(p, kBwdTile);
     int grid = std::min(tab.n_tiles, 4 * device_cus());
-    launch_tdnn_fwd(td, tab, x, pack, u, grid, stream);
+    { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, grid, stream); }
   }
   return launch_status();
 }
@@ -333,7 +379,7 @@ dpd_status pa_gmp_forward(const dpd_gmp_desc* gmp, const dpd_batch* batch, const
   if (!aligned(u, 8) || !aligned(y, 8) || !aligned(coef, 4)) return DPD_ERR_ALIGN;
   if (u == y) return DPD_ERR_SHAPE;
   StreamTable tab = make_table(p, kBwdTile);
-  launch_gmp_fwd(*gmp, tab, u, coef, y, stream);
+  { DPD_PROF("gmp_fwd"); launch_gmp_fwd(*gmp, tab, u, coef, y, stream); }
   return launch_status();
 }
 
@@ -351,8 +397,8 @@ dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x, 
   if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
   StreamTable tab = make_table(p, kNmseTile);
   float2* part = at<float2>(workspace, L.tile_part);
-  launch_nmse_tiles(tab, y, x, g_re, g_im, part, stream);
-  launch_nmse_final(tab, part, out, nullptr, nullptr, stream);
+  { DPD_PROF("nmse_tiles"); launch_nmse_tiles(tab, y, x, g_re, g_im, part, stream); }
+  { DPD_PROF("nmse_final"); launch_nmse_final(tab, part, out, nullptr, nullptr, stream); }
   return launch_status();
 }
 
@@ -382,36 +428,38 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   int64_t P = param_count(*tdnn);
   if (tdnn->impl == DPD_IMPL_PLAIN) {
     float* ybuf = y ? y : at<float>(workspace, L.y_buf);
-    plain_forward(*tdnn, p, x, w, ubuf, L, workspace, stream);
-    plain_gmp_forward(*gmp, p, ubuf, coef, ybuf, stream);
+    { DPD_PROF("plain_forward"); plain_forward(*tdnn, p, x, w, ubuf, L, workspace, stream); }
+    { DPD_PROF("plain_gmp_fwd"); plain_gmp_forward(*gmp, p, ubuf, coef, ybuf, stream); }
     StreamTable tab = make_table(p, kNmseTile);
-    launch_nmse_tiles(tab, ybuf, x, g_re, g_im, part, stream);
-    launch_nmse_final(tab, part, nmse, lossp, inv_r, stream);
-    if (dw)
+    { DPD_PROF("nmse_tiles"); launch_nmse_tiles(tab, ybuf, x, g_re, g_im, part, stream); }
+    { DPD_PROF("nmse_final"); launch_nmse_final(tab, part, nmse, lossp, inv_r, stream); }
+    if (dw) {
+      DPD_PROF("plain_backward");
       plain_backward(*tdnn, *gmp, p, x, w, coef, g_re, g_im, ubuf, ybuf, dw, inv_r, L, workspace,
                      stream);
+    }
     return launch_status();
   }
   TdnnDims td;
   tdnn_dims(*tdnn, &td);
   void* pack = at<void>(workspace, L.pack);
-  launch_pack(td, w, p.n_sets, P, pack, stream);
+  { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, P, pack, stream); }
   StreamTable tab = make_table(p, kBwdTile);
   int fgrid = std::min(tab.n_tiles, 4 * device_cus());
-  launch_tdnn_fwd(td, tab, x, pack, ubuf, fgrid, stream);
-  if (y) launch_gmp_fwd(*gmp, tab, ubuf, coef, y, stream);
+  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, ubuf, fgrid, stream); }
   if (dw) {
+    // the fused kernel also writes y for its tiles
     int grid = std::min(tab.n_tiles, std::min(kMaxGrid, 2 * device_cus()));
     float* slots = at<float>(workspace, L.slots);
-    launch_tdnn_bwd(td, *gmp, tab, x, ubuf, coef, g_re, g_im, pack, part, slots, grid, stream);
-    launch_nmse_final(tab, part, nmse, lossp, inv_r, stream);
-    launch_dw_finalize(td, tab, grid, slots, inv_r, dw, stream);
+    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, *gmp, tab, x, ubuf, coef, g_re, g_im, pack, part, slots, y, grid, stream); }
+    { DPD_PROF("nmse_final"); launch_nmse_final(tab, part, nmse, lossp, inv_r, stream); }
+    { DPD_PROF("dw_finalize"); launch_dw_finalize(td, tab, grid, slots, inv_r, dw, stream); }
   } else {
     float* ybuf = y ? y : at<float>(workspace, L.y_buf);
-    if (!y) launch_gmp_fwd(*gmp, tab, ubuf, coef, ybuf, stream);
+    { DPD_PROF("gmp_fwd"); launch_gmp_fwd(*gmp, tab, ubuf, coef, ybuf, stream); }
     StreamTable nt = make_table(p, kNmseTile);
-    launch_nmse_tiles(nt, ybuf, x, g_re, g_im, part, stream);
-    launch_nmse_final(nt, part, nmse, lossp, inv_r, stream);
+    { DPD_PROF("nmse_tiles"); launch_nmse_tiles(nt, ybuf, x, g_re, g_im, part, stream); }
+    { DPD_PROF("nmse_final"); launch_nmse_final(nt, part, nmse, lossp, inv_r, stream); }
   }
   return launch_status();
 }
@@ -444,9 +492,48 @@ dpd_status cascade_acpr(const float* y, int64_t n, int32_t nfft, int32_t half_bi
   int64_t nseg = (n - nfft) / (nfft / 2) + 1;
   int groups = (int)std::min<int64_t>(nseg, 1024);
   float* seg_part = static_cast<float*>(workspace);
-  launch_welch(y, n, nfft, seg_part, groups, stream);
-  launch_welch_final(seg_part, groups, (int)nseg, nfft, half_bins, psd, acpr, stream);
+  { DPD_PROF("welch"); launch_welch(y, n, nfft, seg_part, groups, stream); }
+  { DPD_PROF("welch_final"); launch_welch_final(seg_part, groups, (int)nseg, nfft, half_bins, psd, acpr, stream); }
   return launch_status();
+}
+
+dpd_status dpd_profile_enable(int32_t on) {
+  Prof& p = prof();
+  std::lock_guard<std::mutex> lock(p.mu);
+  p.on = on != 0;
+  return DPD_OK;
+}
+
+int32_t dpd_profile_report(char* buf_host, size_t cap) {
+  Prof& p = prof();
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lock(p.mu);
+    recs.swap(p.recs);
+  }
+  std::map<std::string, std::pair<int, double>> acc;
+  for (auto& r : recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& e = acc[r.name];
+      e.first += 1;
+      e.second += ms;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  std::string out;
+  for (auto& kv : acc) {
+    char line[256];
+    snprintf(line, sizeof(line), "%s %d %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    out += line;
+  }
+  if (buf_host && cap > 0) {
+    size_t n = std::min(cap - 1, out.size());
+    memcpy(buf_host, out.data(), n);
+    buf_host[n] = 0;
+  }
+  return (int32_t)acc.size();
 }
 
 const char* dpd_status_string(dpd_status status) {

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(kGmpThreads) void k_gmp_fwd(StreamTable st, const f
   }
   __syncthreads();
   for (int i = threadIdx.x; i < QW; i += S) {
+    DPD_KEEP_LOADS_LOCAL();
     float2 Q[M + 1];
     gmp_q<K, M, L>(&rw[i + L], cf, Q);     // position t0 - M + i sits at u index i + L
 #pragma unroll

@@ -45,8 +45,9 @@ __device__ __forceinline__ float2 cfma_r(float2 acc, float r, float2 c) {   // a
   return make_float2(fmaf(acc.x, r, c.x), fmaf(acc.y, r, c.y));
 }
 
-// Q_l(p) for l = 0..M; rw points at r[p] inside a window that covers p-L..p+L.
-template <int K, int M, int L>
+// Q_l(p) for l = L0..L1-1 (default: all taps); rw points at r[p] inside a window that
+// covers p-L..p+L.
+template <int K, int M, int L, int L0 = 0, int L1 = M + 1>
 __device__ __forceinline__ void gmp_q(const float* rw, const float2* cf, float2 (&Q)[M + 1]) {
   using G = Gmp<K, M, L>;
   float r0 = rw[0];
@@ -57,7 +58,8 @@ __device__ __forceinline__ void gmp_q(const float* rw, const float2* cf, float2 
     rr[g] = rw[g];
   }
 #pragma unroll
-  for (int l = 0; l <= M; ++l) {
+  for (int l = L0; l < L1; ++l) {
+    DPD_KEEP_LOADS_LOCAL();
     float2 acc = cf[G::ia(K - 1, l)];
 #pragma unroll
     for (int k = K - 2; k >= 0; --k) acc = cfma_r(acc, r0, cf[G::ia(k, l)]);
@@ -92,11 +94,12 @@ __device__ __forceinline__ float2 gmp_d2(const float2* dcf, int l, int g, float 
   return acc;
 }
 
-// Backward contribution at sample m.
+// Backward contribution at sample m of the memory taps l = L0..L1-1 (default: all;
+// the full gradient is the sum over a partition of the taps).
 //   uw, rw: u and |u| at m inside a window covering m-L..m+L
 //   gyw: g_y at m inside a window covering m-L..m+M+L
-//   Qm: Q_l(m)
-template <int K, int M, int L>
+//   Qm: Q_l(m) (entries L0..L1-1 used)
+template <int K, int M, int L, int L0 = 0, int L1 = M + 1>
 __device__ __forceinline__ float2 gmp_grad(const float2* uw, const float* rw, const float2* gyw,
                                            const float2 (&Qm)[M + 1], const float2* cf,
                                            const float2* dcf) {
@@ -108,7 +111,8 @@ __device__ __forceinline__ float2 gmp_grad(const float2* uw, const float* rw, co
   float2 gu = make_float2(0.f, 0.f);
   float s1 = 0.f, s2 = 0.f;
 #pragma unroll
-  for (int l = 0; l <= M; ++l) {
+  for (int l = L0; l < L1; ++l) {
+    DPD_KEEP_LOADS_LOCAL();
     float2 gyl = gyw[l];
     float2 t = cmulc(Qm[l], gyl);
     gu.x += t.x;

@@ -69,7 +69,8 @@ void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u
 // Fused GMP forward/backward + TDNN recompute/backward, dW partial slots and E/R tile partials.
 void launch_tdnn_bwd(const TdnnDims& td, const dpd_gmp_desc& g, const StreamTable& st,
                      const float* x, const float* u, const float* coef, float g_re, float g_im,
-                     const void* pack, float2* tile_part, float* slots, int grid, hipStream_t s);
+                     const void* pack, float2* tile_part, float* slots, float* y, int grid,
+                     hipStream_t s);
 void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
                         const float* inv_r_set, float* dw, hipStream_t s);
 

@@ -71,19 +71,28 @@ __global__ __launch_bounds__(kFftThreads) void k_welch(const float* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kFftThreads) void k_welch_final(const float* __restrict__ part, int G,
-                                                             int nseg, int nfft, int half_bins,
-                                                             float* __restrict__ psd,
+// psd[k] = sum over groups (fixed order, Neumaier) / (nseg * sum of Hann^2); one
+// thread per bin.
+__global__ __launch_bounds__(kFftThreads) void k_welch_sum(const float* __restrict__ part, int G,
+                                                           int nseg, int nfft,
+                                                           float* __restrict__ psd) {
+  const int k = blockIdx.x * kFftThreads + threadIdx.x;
+  if (k >= nfft) return;
+  const float scale = 1.0f / ((float)nseg * 0.375f * (float)nfft);   // sum of Hann^2 = 3 nfft / 8
+  Comp s;
+  for (int g = 0; g < G; ++g) s.add(part[(int64_t)g * nfft + k]);
+  psd[k] = s.value() * scale;
+}
+
+// Channel powers of the PSD and the ACPR (one workgroup, fixed order).
+__global__ __launch_bounds__(kFftThreads) void k_welch_final(const float* __restrict__ psd,
+                                                             int nfft, int half_bins,
                                                              float* __restrict__ acpr) {
   __shared__ float sh[6 * kFftThreads];
   const int tid = threadIdx.x;
-  const float scale = 1.0f / ((float)nseg * 0.375f * (float)nfft);   // sum of Hann^2 = 3 nfft / 8
   Comp lo, mn, up;
   for (int k = tid; k < nfft; k += kFftThreads) {
-    Comp s;
-    for (int g = 0; g < G; ++g) s.add(part[(int64_t)g * nfft + k]);
-    float v = s.value() * scale;
-    psd[k] = v;
+    float v = psd[k];
     int ks = k < nfft / 2 ? k : k - nfft;
     int a = ks < 0 ? -ks : ks;
     if (a <= half_bins) mn.add(v);
@@ -121,7 +130,9 @@ void launch_welch(const float* y, int64_t n, int nfft, float* seg_part, int n_gr
 
 void launch_welch_final(const float* seg_part, int n_groups, int nseg, int nfft, int half_bins,
                         float* psd, float* acpr, hipStream_t s) {
-  k_welch_final<<<1, kFftThreads, 0, s>>>(seg_part, n_groups, nseg, nfft, half_bins, psd, acpr);
+  k_welch_sum<<<(nfft + kFftThreads - 1) / kFftThreads, kFftThreads, 0, s>>>(seg_part, n_groups,
+                                                                            nseg, nfft, psd);
+  k_welch_final<<<1, kFftThreads, 0, s>>>(psd, nfft, half_bins, acpr);
 }
 
 }  // namespace dpdmi

@@ -16,6 +16,7 @@
 // samples) and each wave accumulates its share of 32x32 dW blocks over the
 // workgroup's 128 samples into a per-(workgroup, stream) slot in global memory.
 #include <algorithm>
+#include <type_traits>
 
 #include "gmp.hpp"
 #include "kernels.hpp"
@@ -193,12 +194,10 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
 }
 
 // ------------------------------------------------------------------ MLP pieces
-// Per-lane state of one wave's 32-sample block.
+// B operands of one 32-row block: 2 x 8 bf16 (bf16) or 16 floats (fp32), i.e. the 16
+// accumulator rows of the lane in K-step order.
 template <class C>
-struct Acts {
-  typename C::A feat[C::NKS1];                   // layer-1 B operands (features)
-  typename C::A hb[C::NB][C::KS == 16 ? 2 : 16]; // B operands of layer i+1 (= h_i), per layer below
-};
+using BlockOps = typename C::A[C::KS == 16 ? 2 : 16];
 
 // Features of the lane's sample: xw points at x[n] in an LDS window (xw[-t] = x[n-t]).
 template <class C>
@@ -230,37 +229,33 @@ __device__ __forceinline__ void make_features(const float2* xw, int h, typename 
   }
 }
 
-// B operand of K step ks of a hidden layer from the previous layer's per-lane values.
+// B operand of K step ks of a hidden layer from the previous layer's blocks.
 template <class C>
-__device__ __forceinline__ typename C::A b_operand(const typename C::A (&hb)[C::NB][C::KS == 16 ? 2 : 16], int ks) {
+__device__ __forceinline__ typename C::A b_operand(const BlockOps<C> (&hb)[C::NB], int ks) {
   if constexpr (C::KS == 16) return hb[ks / 2][ks % 2];
   else return hb[ks / 16][ks % 16];
 }
 
-// Store fp32 accumulator-layout values v[mb][j] as B operands.
 template <class C>
-__device__ __forceinline__ void to_operands(const float (&v)[C::NB][16], typename C::A (&hb)[C::NB][C::KS == 16 ? 2 : 16]) {
+__device__ __forceinline__ void block_to_operands(const float (&v)[16], BlockOps<C>& out) {
+  if constexpr (C::KS == 16) {
 #pragma unroll
-  for (int mb = 0; mb < C::NB; ++mb) {
-    if constexpr (C::KS == 16) {
+    for (int q = 0; q < 2; ++q) {
+      bf16x8 a;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        bf16x8 a;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) a[e] = (__bf16)v[mb][8 * q + e];
-        hb[mb][q] = a;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 16; ++j) hb[mb][j] = v[mb][j];
+      for (int e = 0; e < 8; ++e) a[e] = (__bf16)v[8 * q + e];
+      out[q] = a;
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) out[j] = v[j];
   }
 }
 
 template <class C>
-__device__ __forceinline__ float operand_value(const typename C::A (&hb)[C::NB][C::KS == 16 ? 2 : 16], int mb, int j) {
-  if constexpr (C::KS == 16) return (float)hb[mb][j / 8][j % 8];
-  else return hb[mb][j];
+__device__ __forceinline__ float operand_value(const BlockOps<C>& b, int j) {
+  if constexpr (C::KS == 16) return (float)b[j / 8][j % 8];
+  else return b[j];
 }
 
 template <class C>
@@ -269,75 +264,66 @@ __device__ __forceinline__ f32x16 mfma(typename C::A a, typename C::A b, f32x16 
   else return mfma_f32(a, b, c);
 }
 
-// One dense layer: acc[mb] = sum_ks A(mb, ks) B(ks).  Apk: packed [NB][nks][64].
+// One 32-row block mb of a dense layer: sum_ks A(mb, ks) B(ks); Apk is [NB][NKS][64].
 template <class C, int NKS, class BF>
-__device__ __forceinline__ void dense(const typename C::A* __restrict__ Apk, int lane, BF&& bop,
-                                      f32x16 (&acc)[C::NB]) {
+__device__ __forceinline__ f32x16 dense_block(const typename C::A* __restrict__ Apk, int mb,
+                                              int lane, BF&& bop) {
+  f32x16 acc;
 #pragma unroll
-  for (int mb = 0; mb < C::NB; ++mb)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) acc[mb][j] = 0.f;
+  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) {
-    typename C::A b = bop(ks);
-#pragma unroll
-    for (int mb = 0; mb < C::NB; ++mb) {
-      typename C::A a = Apk[((int64_t)mb * NKS + ks) * 64 + lane];
-      acc[mb] = mfma<C>(a, b, acc[mb]);
-    }
+    typename C::A a = Apk[((int64_t)mb * NKS + ks) * 64 + lane];
+    acc = mfma<C>(a, bop(ks), acc);
   }
+  return acc;
 }
 
-// Forward through all hidden layers; keeps every layer's operands in `st` and the
-// last layer's fp32 values in `last`.  vec: LDS copy of the float vector block.
+// Forward through all hidden layers one 32-neuron block at a time.  Keeps every
+// layer's B operands in hb (hb[i] = h_{i+1}) and returns the two linear outputs.
+// vec: LDS copy of the float vector block (biases, output layer).
 template <class C, int NL>
-__device__ __forceinline__ void mlp_forward(const char* __restrict__ pk, const float* vec, int lane,
-                                            int h, const float2* xw,
-                                            typename C::A (&feat)[C::NKS1],
-                                            typename C::A (&hb)[NL][C::NB][C::KS == 16 ? 2 : 16],
-                                            float (&last)[C::NB][16]) {
+__device__ __forceinline__ float2 mlp_forward(const char* __restrict__ pk, const float* vec,
+                                              int lane, int h, const float2* xw,
+                                              BlockOps<C> (&hb)[NL][C::NB]) {
+  using A = typename C::A;
+  A feat[C::NKS1];
   make_features<C>(xw, h, feat);
-  f32x16 acc[C::NB];
-  const typename C::A* A1 = reinterpret_cast<const typename C::A*>(pk + C::OFF_FWD1);
-  dense<C, C::NKS1>(A1, lane, [&](int ks) { return feat[ks]; }, acc);
-#pragma unroll
-  for (int i = 0; i < NL; ++i) {
-    if (i > 0) {
-      const typename C::A* Ah =
-          reinterpret_cast<const typename C::A*>(pk + C::OFF_FWDH) + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
-      dense<C, C::NKSH>(Ah, lane, [&](int ks) { return b_operand<C>(hb[i - 1], ks); }, acc);
-    }
-    float v[C::NB][16];
-#pragma unroll
-    for (int mb = 0; mb < C::NB; ++mb) {
-      const float* bias = vec + (i * C::NB + mb) * 32 + h * 16;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) v[mb][j] = tanh_f32(acc[mb][j] + bias[j]);
-    }
-    to_operands<C>(v, hb[i]);
-    if (i == NL - 1) {
-#pragma unroll
-      for (int mb = 0; mb < C::NB; ++mb)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) last[mb][j] = v[mb][j];
-    }
-  }
-}
-
-template <class C>
-__device__ __forceinline__ float2 output_layer(const float* vec, int h, const float (&last)[C::NB][16], int nl) {
-  const float* wo = vec + nl * C::HP;
+  const float* wo = vec + NL * C::HP;
   float o0 = 0.f, o1 = 0.f;
 #pragma unroll
-  for (int mb = 0; mb < C::NB; ++mb)
+  for (int i = 0; i < NL; ++i) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      o0 = fmaf(wo[(0 * C::NB + mb) * 32 + h * 16 + j], last[mb][j], o0);
-      o1 = fmaf(wo[(1 * C::NB + mb) * 32 + h * 16 + j], last[mb][j], o1);
+    for (int mb = 0; mb < C::NB; ++mb) {
+      DPD_KEEP_LOADS_LOCAL();
+      f32x16 acc;
+      if (i == 0) {
+        acc = dense_block<C, C::NKS1>(reinterpret_cast<const A*>(pk + C::OFF_FWD1), mb, lane,
+                                      [&](int ks) { return feat[ks]; });
+      } else {
+        const A* Ah = reinterpret_cast<const A*>(pk + C::OFF_FWDH) + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
+        acc = dense_block<C, C::NKSH>(Ah, mb, lane, [&](int ks) { return b_operand<C>(hb[i - 1], ks); });
+      }
+      const float* bias = vec + (i * C::NB + mb) * 32 + h * 16;
+      float v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if constexpr (C::KS == 16) v[j] = tanh_bf16(acc[j] + bias[j]);
+        else v[j] = tanh_f32(acc[j] + bias[j]);
+      }
+      block_to_operands<C>(v, hb[i][mb]);
+      if (i == NL - 1) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          o0 = fmaf(wo[(0 * C::NB + mb) * 32 + h * 16 + j], v[j], o0);
+          o1 = fmaf(wo[(1 * C::NB + mb) * 32 + h * 16 + j], v[j], o1);
+        }
+      }
     }
+  }
   o0 += __shfl_xor(o0, 32);
   o1 += __shfl_xor(o1, 32);
-  const float* bo = vec + nl * C::HP + 2 * C::HP;
+  const float* bo = vec + NL * C::HP + 2 * C::HP;
   return make_float2(o0 + bo[0], o1 + bo[1]);
 }
 
@@ -369,12 +355,9 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const flo
       xw[i] = (p >= lo && p < hi) ? ld2(x, p) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    typename C::A feat[C::NKS1];
-    typename C::A hb[NL][C::NB][C::KS == 16 ? 2 : 16];
-    float last[C::NB][16];
+    BlockOps<C> hb[NL][C::NB];
     int col = 32 * wave + sl;
-    mlp_forward<C, NL>(pk, vec, lane, h, &xw[col + T - 1], feat, hb, last);
-    float2 o = output_layer<C>(vec, h, last, NL);
+    float2 o = mlp_forward<C, NL>(pk, vec, lane, h, &xw[col + T - 1], hb);
     int64_t n = t0 + col;
     if (h == 0 && n < hi) {
       if (residual) {
@@ -406,59 +389,69 @@ struct BwdLds {
   static constexpr int GMP_BYTES = (2 * G::J + QW * (M + 1) + YW) * 8;
   static constexpr int STAGE_BYTES = (C::HP + HROWS) * LD * (int)sizeof(typename C::E);
   static constexpr int UNION_BYTES = cmax(GMP_BYTES, STAGE_BYTES);
+  // dW blocks per layer and the register-resident accumulators that hold them:
+  // layer blocks bi = 4q + wave, q = 0..ceil(blocks/4)-1, in dwacc[Q0 + q].
+  static constexpr int NBL1 = C::NB * C::NN1, NBLH = C::NB * C::NB, NBLO = C::NB;
+  static constexpr int Q1 = (NBL1 + 3) / 4, QH = (NBLH + 3) / 4, QO = (NBLO + 3) / 4;
+  static constexpr int NQ = Q1 + (NL - 1) * QH + QO;
+  static constexpr int BIAS = NL * C::HP + 32;   // bias-gradient accumulators
 };
 
+// Stage the lane's 16 accumulator-order values of every block (one sample column).
 template <class C>
-__device__ __forceinline__ void stage_acc_rows(typename C::E* stage, int ld, int col, int h,
-                                               const float (&v)[C::NB][16]) {
+__device__ __forceinline__ void stage_ops(typename C::E* stage, int ld, int col, int h,
+                                          const BlockOps<C> (&b)[C::NB]) {
 #pragma unroll
   for (int mb = 0; mb < C::NB; ++mb)
 #pragma unroll
-    for (int j = 0; j < 16; ++j) stage[(32 * mb + mfma_row(j, h)) * ld + col] = (typename C::E)v[mb][j];
+    for (int j = 0; j < 16; ++j)
+      stage[(32 * mb + mfma_row(j, h)) * ld + col] = (typename C::E)operand_value<C>(b[mb], j);
 }
 
-// dW blocks of one layer: rows = NMB*32 (delta staging), cols = NNB*32 (h staging).
-// Accumulates into the slot's W block [rows][cols] and bias [rows] (bias from the
-// row sums of delta).  Blocks are dealt to the waves round-robin.
-template <class C, int NMB, int NNB>
-__device__ __forceinline__ void dw_layer(const typename C::E* dst, const typename C::E* hst, int ld,
-                                         int wave, int lane, float* __restrict__ slotW,
-                                         float* __restrict__ slotB, bool first) {
+// One 32x32 dW block over the tile's samples: rows mb of the delta staging against
+// rows nb of the activation staging (both [row][sample]).
+template <class C>
+__device__ __forceinline__ f32x16 dw_block(const typename C::E* dst, const typename C::E* hst, int ld,
+                                           int mb, int nb, int lane, f32x16 acc) {
   const int h = lane / 32, r = lane % 32;
-  constexpr int NSTEP = kTile / C::KS;
-  for (int bi = wave; bi < NMB * NNB; bi += kThreads / 64) {
-    const int mb = bi / NNB, nb = bi % NNB;
-    f32x16 acc;
-    float* out = slotW + (int64_t)(32 * mb) * (NNB * 32) + 32 * nb + r;
+  const typename C::E* arow = dst + (32 * mb + r) * ld;
+  const typename C::E* brow = hst + (32 * nb + r) * ld;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = first ? 0.f : out[(int64_t)mfma_row(j, h) * (NNB * 32)];
-    const typename C::E* arow = dst + (32 * mb + r) * ld;
-    const typename C::E* brow = hst + (32 * nb + r) * ld;
-#pragma unroll 8
-    for (int ks = 0; ks < NSTEP; ++ks) {
-      typename C::A a, b;
-      if constexpr (C::KS == 16) {
-        a = *reinterpret_cast<const bf16x8*>(arow + 16 * ks + 8 * h);
-        b = *reinterpret_cast<const bf16x8*>(brow + 16 * ks + 8 * h);
-      } else {
-        a = arow[2 * ks + h];
-        b = brow[2 * ks + h];
-      }
-      acc = mfma<C>(a, b, acc);
+  for (int ks = 0; ks < kTile / C::KS; ++ks) {
+    typename C::A a, b;
+    if constexpr (C::KS == 16) {
+      a = *reinterpret_cast<const bf16x8*>(arow + 16 * ks + 8 * h);
+      b = *reinterpret_cast<const bf16x8*>(brow + 16 * ks + 8 * h);
+    } else {
+      a = arow[2 * ks + h];
+      b = brow[2 * ks + h];
     }
+    acc = mfma<C>(a, b, acc);
+  }
+  return acc;
+}
+
+// Sum over the tile's samples of delta row 32*mb + lane%32 (the bias gradient).
+template <class C>
+__device__ __forceinline__ float delta_row_sum(const typename C::E* dst, int ld, int mb, int lane) {
+  const int h = lane / 32, r = lane % 32;
+  const typename C::E* arow = dst + (32 * mb + r) * ld + h * (kTile / 2);
+  float sum = 0.f;
+  if constexpr (C::KS == 16) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) out[(int64_t)mfma_row(j, h) * (NNB * 32)] = acc[j];
-    if (nb == 0) {
-      // bias gradient: row sums of delta over the tile's samples
-      float sum = 0.f;
-      for (int c = h * (kTile / 2); c < (h + 1) * (kTile / 2); ++c) sum += (float)arow[c];
-      sum += __shfl_xor(sum, 32);
-      if (h == 0) {
-        float* bo = slotB + 32 * mb + r;
-        *bo = first ? sum : *bo + sum;
-      }
+    for (int c = 0; c < kTile / 2; c += 8) {
+      bf16x8 v = *reinterpret_cast<const bf16x8*>(arow + c);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) sum += (float)v[e];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kTile / 2; c += 4) {
+      float4 v = *reinterpret_cast<const float4*>(arow + c);
+      sum += (v.x + v.y) + (v.z + v.w);
     }
   }
+  return sum + __shfl_xor(sum, 32);
 }
 
 template <int PREC, int T, int H, int NL, int K, int M, int L>
@@ -467,18 +460,21 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
                                                        const float* __restrict__ coef, float g_re,
                                                        float g_im, const char* __restrict__ pack,
                                                        float2* __restrict__ tile_part,
-                                                       float* __restrict__ slots) {
+                                                       float* __restrict__ slots,
+                                                       float* __restrict__ y_out) {
   using C = Cfg<PREC, T, H, NL>;
   using G = Gmp<K, M, L>;
   using B = BwdLds<PREC, T, H, NL, K, M, L>;
   using E = typename C::E;
+  using A = typename C::A;
   constexpr int S = kTile;
   __shared__ float2 xw[B::XW];
   __shared__ float2 uw[B::UW];
   __shared__ float rw[B::UW];
-  __shared__ float2 guw[S];
+  __shared__ float2 guw[2 * S];        // g_u partial sums of the two tap halves
   __shared__ float vec[C::NVEC];
   __shared__ float red[4 * kThreads];
+  __shared__ float bacc[B::BIAS];
   __shared__ __attribute__((aligned(16))) char un[B::UNION_BYTES];
   float2* cf = reinterpret_cast<float2*>(un);
   float2* dcf = cf + G::J;
@@ -491,19 +487,83 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   const int g_wg = blockIdx.x, G_wg = gridDim.x;
   const int t_begin = wg_tile_start(g_wg, G_wg, st.n_tiles);
   const int t_end = wg_tile_start(g_wg + 1, G_wg, st.n_tiles);
-  int prev_stream = -1;
+
+  // dW accumulators of this wave's blocks, kept in registers for the whole tile range
+  // of one stream and written to its slot once.
+  f32x16 dwacc[B::NQ];
+#pragma unroll
+  for (int q = 0; q < B::NQ; ++q)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dwacc[q][j] = 0.f;
+  for (int i = tid; i < B::BIAS; i += kThreads) bacc[i] = 0.f;
+
+  // Write this workgroup's partial dW of stream s (plain stores: each (workgroup,
+  // stream) slot is written exactly once) and reset the accumulators.  Caller syncs.
+  auto flush = [&](int s) {
+    float* slot = slots + (int64_t)(g_wg + s) * C::SLOT;
+#pragma unroll
+    for (int q = 0; q < B::NQ; ++q) {
+      // decode (layer, block) of dwacc[q] for this wave
+      int li, ql, nnb, nbl;
+      if (q < B::Q1) { li = 0; ql = q; nnb = C::NN1; nbl = B::NBL1; }
+      else if (q < B::Q1 + (NL - 1) * B::QH) { li = 1 + (q - B::Q1) / B::QH; ql = (q - B::Q1) % B::QH; nnb = C::NB; nbl = B::NBLH; }
+      else { li = NL; ql = q - B::Q1 - (NL - 1) * B::QH; nnb = C::NB; nbl = B::NBLO; }
+      int bi = 4 * ql + wave;
+      if (bi < nbl) {
+        int mb = bi / nnb, nb = bi % nnb;
+        float* out = slot + C::dw_off(li) + (int64_t)(32 * mb) * (nnb * 32) + 32 * nb + sl;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) out[(int64_t)mfma_row(j, h) * (nnb * 32)] = dwacc[q][j];
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) dwacc[q][j] = 0.f;
+    }
+    for (int i = tid; i < B::BIAS; i += kThreads) {
+      int li = i / C::HP, o = i % C::HP;
+      float* dstb = li < NL ? slot + C::dw_off(li) + (int64_t)C::HP * (li == 0 ? C::C1 : C::HP) + o
+                            : slot + C::dw_off(NL) + 32 * C::HP + (i - NL * C::HP);
+      *dstb = bacc[i];
+      bacc[i] = 0.f;
+    }
+  };
+
+  // accumulate the owned blocks of one layer (li: 0 = input layer, NL = output layer)
+  auto accumulate = [&](auto li_c) {
+    constexpr int li = decltype(li_c)::value;
+    constexpr int nnb = li == 0 ? C::NN1 : C::NB;
+    constexpr int nbl = li == 0 ? B::NBL1 : (li == NL ? B::NBLO : B::NBLH);
+    constexpr int q0 = li == 0 ? 0 : (li == NL ? B::Q1 + (NL - 1) * B::QH : B::Q1 + (li - 1) * B::QH);
+    constexpr int nql = li == 0 ? B::Q1 : (li == NL ? B::QO : B::QH);
+    float* bl = bacc + (li == NL ? NL * C::HP : li * C::HP);
+#pragma unroll
+    for (int q = 0; q < nql; ++q) {
+      DPD_KEEP_LOADS_LOCAL();
+      int bi = 4 * q + wave;
+      if (bi < nbl) {
+        int mb = bi / nnb, nb = bi % nnb;
+        dwacc[q0 + q] = dw_block<C>(dst, hst, B::LD, mb, nb, lane, dwacc[q0 + q]);
+        if (nb == 0) {
+          float sum = delta_row_sum<C>(dst, B::LD, mb, lane);
+          if (h == 0) bl[32 * mb + sl] += sum;
+        }
+      }
+    }
+  };
+
+  int cur_stream = -1;
   for (int t = t_begin; t < t_end; ++t) {
     const int s = stream_of_tile(st, t);
     const int set = st.per_stream ? s : 0;
-    const bool first = s != prev_stream;
-    prev_stream = s;
     const int64_t lo = st.off[s], hi = st.off[s + 1];
     const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
     const char* pk = pack + set * C::PACK;
     const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
-    float* slot = slots + (int64_t)(g_wg + s) * C::SLOT;
 
-    __syncthreads();   // previous tile finished with every LDS buffer
+    __syncthreads();   // previous tile finished with every LDS buffer and accumulator
+    if (s != cur_stream) {
+      if (cur_stream >= 0) flush(cur_stream);
+      cur_stream = s;
+    }
     for (int j = tid; j < G::J; j += kThreads) {
       float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
       cf[j] = c;
@@ -525,12 +585,21 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       rw[i] = sqrtf(v.x * v.x + v.y * v.y);
     }
     __syncthreads();
-    // ---- GMP: Q_l(p) on the Q window
-    for (int i = tid; i < B::QW; i += kThreads) {
+    // ---- GMP: Q_l(p) on the Q window; waves 0-1 take taps [0, LH), waves 2-3 [LH, M]
+    constexpr int LH = (M + 1) / 2;
+    const bool upper = tid >= kThreads / 2;
+    for (int i = tid % (kThreads / 2); i < B::QW; i += kThreads / 2) {
+      DPD_KEEP_LOADS_LOCAL();
       float2 Q[M + 1];
-      gmp_q<K, M, L>(&rw[i + L], cf, Q);
+      if (upper) {
+        gmp_q<K, M, L, LH, M + 1>(&rw[i + L], cf, Q);
 #pragma unroll
-      for (int l = 0; l <= M; ++l) qw[i][l] = Q[l];
+        for (int l = LH; l <= M; ++l) qw[i][l] = Q[l];
+      } else {
+        gmp_q<K, M, L, 0, LH>(&rw[i + L], cf, Q);
+#pragma unroll
+        for (int l = 0; l < LH; ++l) qw[i][l] = Q[l];
+      }
     }
     __syncthreads();
     // ---- y, g_y = 2(y - Gx) (zero outside the stream), E and R on the tile
@@ -553,6 +622,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
         if (i >= L && i < L + S) {
           Ec.add(er * er + ei * ei);
           Rc.add(tr * tr + ti * ti);
+          if (y_out) st2(y_out, n, y);
         }
       }
       gyw[i] = g;
@@ -570,15 +640,20 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       __syncthreads();
     }
     if (tid == 0) tile_part[t] = make_float2(red[0] + red[kThreads], red[2 * kThreads] + red[3 * kThreads]);
-    // ---- g_u on the tile
-    if (tid < S) {
-      int64_t m = t0 + tid;
+    // ---- g_u on the tile: the two halves of the taps in two partial sums
+    {
+      static_assert(S == kThreads / 2, "one sample per thread and tap half");
+      const int i = tid % S;
+      int64_t m = t0 + i;
       float2 gu = make_float2(0.f, 0.f);
       if (m < hi) {
         float2 Qm[M + 1];
 #pragma unroll
-        for (int l = 0; l <= M; ++l) Qm[l] = qw[tid + B::QB][l];
-        gu = gmp_grad<K, M, L>(&uw[tid + B::UB], &rw[tid + B::UB], &gyw[tid + L], Qm, cf, dcf);
+        for (int l = 0; l <= M; ++l) Qm[l] = qw[i + B::QB][l];
+        if (upper)
+          gu = gmp_grad<K, M, L, LH, M + 1>(&uw[i + B::UB], &rw[i + B::UB], &gyw[i + L], Qm, cf, dcf);
+        else
+          gu = gmp_grad<K, M, L, 0, LH>(&uw[i + B::UB], &rw[i + B::UB], &gyw[i + L], Qm, cf, dcf);
       }
       guw[tid] = gu;
     }
@@ -586,50 +661,43 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
 
     // ---- TDNN: recompute this wave's 32 samples, then the reverse mode
     const int col = 32 * wave + sl;
-    typename C::A feat[C::NKS1];
-    typename C::A hb[NL][C::NB][C::KS == 16 ? 2 : 16];
-    float last[C::NB][16];
-    mlp_forward<C, NL>(pk, vec, lane, h, &xw[col + B::XB], feat, hb, last);
-    const float2 g = guw[col];
+    BlockOps<C> hb[NL][C::NB];
+    (void)mlp_forward<C, NL>(pk, vec, lane, h, &xw[col + B::XB], hb);
+    const float2 g = make_float2(guw[col].x + guw[S + col].x, guw[col].y + guw[S + col].y);
     // output layer: delta_o = (Re g_u, Im g_u) in rows 0, 1 of a 32-row block
-    {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        int row = mfma_row(j, h);
-        float v = row == 0 ? g.x : (row == 1 ? g.y : 0.f);
-        dst[row * B::LD + col] = (E)v;
-      }
-      stage_acc_rows<C>(hst, B::LD, col, h, last);
+    for (int j = 0; j < 16; ++j) {
+      int row = mfma_row(j, h);
+      dst[row * B::LD + col] = (E)(row == 0 ? g.x : (row == 1 ? g.y : 0.f));
     }
+    stage_ops<C>(hst, B::LD, col, h, hb[NL - 1]);
     __syncthreads();
-    dw_layer<C, 1, C::NB>(dst, hst, B::LD, wave, lane, slot + C::dw_off(NL),
-                          slot + C::dw_off(NL) + 32 * C::HP, first);
+    accumulate(std::integral_constant<int, NL>{});
     // delta_nl = (Wo^T delta_o) * (1 - h_nl^2)
-    float dl[C::NB][16];
+    BlockOps<C> db[C::NB];
     {
       const float* wo = vec + NL * C::HP;
 #pragma unroll
-      for (int mb = 0; mb < C::NB; ++mb)
+      for (int mb = 0; mb < C::NB; ++mb) {
+        float v[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          float hv = operand_value<C>(hb[NL - 1], mb, j);
+          float hv = operand_value<C>(hb[NL - 1][mb], j);
           float w0 = wo[(0 * C::NB + mb) * 32 + h * 16 + j], w1 = wo[(1 * C::NB + mb) * 32 + h * 16 + j];
-          dl[mb][j] = (w0 * g.x + w1 * g.y) * (1.f - hv * hv);
+          v[j] = (w0 * g.x + w1 * g.y) * (1.f - hv * hv);
         }
+        block_to_operands<C>(v, db[mb]);
+      }
     }
-#pragma unroll
-    for (int i = NL; i >= 1; --i) {   // hidden layer i: delta_i in dl, input h_{i-1}
-      __syncthreads();                // staging free
-      stage_acc_rows<C>(dst, B::LD, col, h, dl);
-      if (i >= 2) {
-        float hv[C::NB][16];
-#pragma unroll
-        for (int mb = 0; mb < C::NB; ++mb)
-#pragma unroll
-          for (int j = 0; j < 16; ++j) hv[mb][j] = operand_value<C>(hb[i - 2], mb, j);
-        stage_acc_rows<C>(hst, B::LD, col, h, hv);
+    auto layer = [&](auto i_c) {       // hidden layer i: delta_i in db, input h_{i-1}
+      constexpr int i = decltype(i_c)::value;
+      __syncthreads();                 // staging free
+      stage_ops<C>(dst, B::LD, col, h, db);
+      if constexpr (i >= 2) {
+        stage_ops<C>(hst, B::LD, col, h, hb[i - 2]);
       } else {
-        // features in natural order: row k = KS*ks + (KS/2)*h + e
+        A feat[C::NKS1];
+        make_features<C>(&xw[col + B::XB], h, feat);
 #pragma unroll
         for (int ks = 0; ks < C::NKS1; ++ks) {
           if constexpr (C::KS == 16) {
@@ -644,37 +712,45 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
           if ((k & 1) == h) hst[k * B::LD + col] = (E)0.f;
       }
       // delta_{i-1} = (W_i^T delta_i) * (1 - h_{i-1}^2) while the staging settles
-      float dn[C::NB][16];
-      if (i >= 2) {
-        typename C::A db[C::NB][C::KS == 16 ? 2 : 16];
-        to_operands<C>(dl, db);
-        f32x16 acc[C::NB];
-        const typename C::A* Ab =
-            reinterpret_cast<const typename C::A*>(pk + C::OFF_BWDH) + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
-        dense<C, C::NKSH>(Ab, lane, [&](int ks) { return b_operand<C>(db, ks); }, acc);
+      BlockOps<C> dn[C::NB];
+      if constexpr (i >= 2) {
+        const A* Ab = reinterpret_cast<const A*>(pk + C::OFF_BWDH) + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
 #pragma unroll
-        for (int mb = 0; mb < C::NB; ++mb)
+        for (int mb = 0; mb < C::NB; ++mb) {
+          DPD_KEEP_LOADS_LOCAL();
+          f32x16 acc = dense_block<C, C::NKSH>(Ab, mb, lane, [&](int ks) { return b_operand<C>(db, ks); });
+          float v[16];
 #pragma unroll
           for (int j = 0; j < 16; ++j) {
-            float hv = operand_value<C>(hb[i - 2], mb, j);
-            dn[mb][j] = acc[mb][j] * (1.f - hv * hv);
+            float hv = operand_value<C>(hb[i - 2][mb], j);
+            v[j] = acc[j] * (1.f - hv * hv);
           }
+          block_to_operands<C>(v, dn[mb]);
+        }
       }
       __syncthreads();
-      if (i >= 2)
-        dw_layer<C, C::NB, C::NB>(dst, hst, B::LD, wave, lane, slot + C::dw_off(i - 1),
-                                  slot + C::dw_off(i - 1) + (int64_t)C::HP * C::HP, first);
-      else
-        dw_layer<C, C::NB, C::NN1>(dst, hst, B::LD, wave, lane, slot + C::dw_off(0),
-                                   slot + C::dw_off(0) + (int64_t)C::HP * C::C1, first);
-      if (i >= 2) {
+      accumulate(std::integral_constant<int, i - 1>{});
+      if constexpr (i >= 2) {
 #pragma unroll
-        for (int mb = 0; mb < C::NB; ++mb)
+        for (int mb = 0; mb < C::NB; ++mb) {
+          if constexpr (C::KS == 16) {
+            db[mb][0] = dn[mb][0];
+            db[mb][1] = dn[mb][1];
+          } else {
 #pragma unroll
-          for (int j = 0; j < 16; ++j) dl[mb][j] = dn[mb][j];
+            for (int j = 0; j < 16; ++j) db[mb][j] = dn[mb][j];
+          }
+        }
       }
-    }
+    };
+    static_assert(NL >= 1 && NL <= 4, "hidden layer count of the tuned kernel");
+    if constexpr (NL >= 4) layer(std::integral_constant<int, 4>{});
+    if constexpr (NL >= 3) layer(std::integral_constant<int, 3>{});
+    if constexpr (NL >= 2) layer(std::integral_constant<int, 2>{});
+    layer(std::integral_constant<int, 1>{});
   }
+  __syncthreads();
+  if (cur_stream >= 0) flush(cur_stream);
 }
 
 // ------------------------------------------------------------------ dW finalize
@@ -785,11 +861,12 @@ void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, 
 
 void launch_tdnn_bwd(const TdnnDims& td, const dpd_gmp_desc& g, const StreamTable& st,
                      const float* x, const float* u, const float* coef, float g_re, float g_im,
-                     const void* pack, float2* tile_part, float* slots, int grid, hipStream_t s) {
+                     const void* pack, float2* tile_part, float* slots, float* y, int grid,
+                     hipStream_t s) {
   bwd_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, g.K, g.M, g.L,
                [&]<int P_, int T_, int H_, int NL_, int K_, int M_, int L_>() {
                  k_tdnn_bwd<P_, T_, H_, NL_, K_, M_, L_><<<grid, kThreads, 0, s>>>(
-                     st, x, u, coef, g_re, g_im, static_cast<const char*>(pack), tile_part, slots);
+                     st, x, u, coef, g_re, g_im, static_cast<const char*>(pack), tile_part, slots, y);
                });
 }
 

@@ -76,3 +76,10 @@ def test_workload_shapes():
     inp = D.make_workload("batched_64s", n_streams=3, max_len=5000)
     assert inp.w.shape == (3, 11714) and inp.coef.shape == (3, 258, 2)
     assert inp.offsets[-1] == inp.x.shape[0]
+
+
+def test_workload_stream_selection_without_truncation():
+    inp = D.make_workload("train_1m_8f", n_streams=1)
+    assert list(inp.offsets) == [0, 131072]
+    full = D.make_workload("train_1m_8f")
+    np.testing.assert_array_equal(full.x[:131072], inp.x)
