@@ -122,6 +122,13 @@ int device_cus() {
   return cache[dev];
 }
 
+// Persistent forward grid: as many workgroups as fit at once (the weights of one
+// parameter set occupy most of a CU's LDS for the largest models).
+int fwd_grid(const TdnnDims& td) {
+  int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (td.fwd_lds + 1024)));
+  return per_cu * device_cus();
+}
+
 // ------------------------------------------------------------ workspace layout
 struct Ws {
   size_t tile_part = 0, inv_r = 0, loss_tmp = 0, u_buf = 0, y_buf = 0, gu_buf = 0;
@@ -363,7 +370,7 @@ dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const 
     void* pack = at<void>(workspace, L.pack);
     { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
     StreamTable tab = make_table(p, kBwdTile);
-    int grid = std::min(tab.n_tiles, 4 * device_cus());
+    int grid = std::min(tab.n_tiles, fwd_grid(td));
     { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, grid, stream); }
   }
   return launch_status();
@@ -445,7 +452,7 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   void* pack = at<void>(workspace, L.pack);
   { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, P, pack, stream); }
   StreamTable tab = make_table(p, kBwdTile);
-  int fgrid = std::min(tab.n_tiles, 4 * device_cus());
+  int fgrid = std::min(tab.n_tiles, fwd_grid(td));
   { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, ubuf, fgrid, stream); }
   if (dw) {
     // the fused kernel also writes y for its tiles

@@ -48,6 +48,7 @@ struct TdnnDims {
   int nks1;         // MFMA K steps of layer 1
   int nksh;         // MFMA K steps of a hidden layer
   int64_t pack_bytes;  // bytes of one packed parameter set
+  int64_t fwd_lds;     // LDS bytes of the forward kernel
   // packed offsets (bytes) inside one set
   int64_t off_fwd1, off_fwdh, off_bwdh, off_bias, off_wo, off_bo;
   // natural-layout dW (floats) per slot: layer rows x cols, bias in the last used column

@@ -281,9 +281,10 @@ __device__ __forceinline__ f32x16 dense_block(const typename C::A* __restrict__ 
 
 // Forward through all hidden layers one 32-neuron block at a time.  Keeps every
 // layer's B operands in hb (hb[i] = h_{i+1}) and returns the two linear outputs.
-// vec: LDS copy of the float vector block (biases, output layer).
+// wf: the forward weight operands (layer 1 then hidden layers, packed order; global
+// or LDS); vec: LDS copy of the float vector block (biases, output layer).
 template <class C, int NL>
-__device__ __forceinline__ float2 mlp_forward(const char* __restrict__ pk, const float* vec,
+__device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const float* vec,
                                               int lane, int h, const float2* xw,
                                               BlockOps<C> (&hb)[NL][C::NB]) {
   using A = typename C::A;
@@ -298,10 +299,9 @@ __device__ __forceinline__ float2 mlp_forward(const char* __restrict__ pk, const
       DPD_KEEP_LOADS_LOCAL();
       f32x16 acc;
       if (i == 0) {
-        acc = dense_block<C, C::NKS1>(reinterpret_cast<const A*>(pk + C::OFF_FWD1), mb, lane,
-                                      [&](int ks) { return feat[ks]; });
+        acc = dense_block<C, C::NKS1>(wf, mb, lane, [&](int ks) { return feat[ks]; });
       } else {
-        const A* Ah = reinterpret_cast<const A*>(pk + C::OFF_FWDH) + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
+        const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
         acc = dense_block<C, C::NKSH>(Ah, mb, lane, [&](int ks) { return b_operand<C>(hb[i - 1], ks); });
       }
       const float* bias = vec + (i * C::NB + mb) * 32 + h * 16;
@@ -328,17 +328,28 @@ __device__ __forceinline__ float2 mlp_forward(const char* __restrict__ pk, const
 }
 
 // ------------------------------------------------------------------ forward kernel
+// Each workgroup owns a contiguous range of tiles; the forward weight operands of the
+// current parameter set live in LDS (reloaded only when the set changes), so every
+// MFMA A operand is one conflict-free 16-byte (bf16) or 4-byte (fp32) LDS read.
 template <int PREC, int T, int H, int NL>
 __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
                                                        const char* __restrict__ pack, int residual,
                                                        float* __restrict__ u) {
   using C = Cfg<PREC, T, H, NL>;
+  using A = typename C::A;
   constexpr int XW = kTile + T - 1;
+  // forward operands in 16-byte units; models whose forward weights exceed the LDS
+  // budget read them from global memory (L2) instead
+  constexpr bool kLdsWeights = C::OFF_BWDH <= 144 * 1024;
+  constexpr int NWF = kLdsWeights ? (int)(C::OFF_BWDH / 16) : 1;
   __shared__ float2 xw[XW];
   __shared__ float vec[C::NVEC];
+  __shared__ __attribute__((aligned(16))) uint4 wf[NWF];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, h = lane / 32, sl = lane % 32;
+  const int t_begin = wg_tile_start(blockIdx.x, gridDim.x, st.n_tiles);
+  const int t_end = wg_tile_start(blockIdx.x + 1, gridDim.x, st.n_tiles);
   int cur_set = -1;
-  for (int t = blockIdx.x; t < st.n_tiles; t += gridDim.x) {
+  for (int t = t_begin; t < t_end; ++t) {
     int s = stream_of_tile(st, t);
     int set = st.per_stream ? s : 0;
     int64_t lo = st.off[s], hi = st.off[s + 1];
@@ -348,6 +359,10 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const flo
     if (set != cur_set) {
       const float* src = reinterpret_cast<const float*>(pk + C::OFF_VEC);
       for (int i = threadIdx.x; i < C::NVEC; i += kThreads) vec[i] = src[i];
+      if constexpr (kLdsWeights) {
+        const uint4* wsrc = reinterpret_cast<const uint4*>(pk);
+        for (int i = threadIdx.x; i < NWF; i += kThreads) wf[i] = wsrc[i];
+      }
       cur_set = set;
     }
     for (int i = threadIdx.x; i < XW; i += kThreads) {
@@ -357,7 +372,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const flo
     __syncthreads();
     BlockOps<C> hb[NL][C::NB];
     int col = 32 * wave + sl;
-    float2 o = mlp_forward<C, NL>(pk, vec, lane, h, &xw[col + T - 1], hb);
+    const A* wops = kLdsWeights ? reinterpret_cast<const A*>(wf) : reinterpret_cast<const A*>(pk);
+    float2 o = mlp_forward<C, NL>(wops, vec, lane, h, &xw[col + T - 1], hb);
     int64_t n = t0 + col;
     if (h == 0 && n < hi) {
       if (residual) {
@@ -662,7 +678,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     // ---- TDNN: recompute this wave's 32 samples, then the reverse mode
     const int col = 32 * wave + sl;
     BlockOps<C> hb[NL][C::NB];
-    (void)mlp_forward<C, NL>(pk, vec, lane, h, &xw[col + B::XB], hb);
+    (void)mlp_forward<C, NL>(reinterpret_cast<const A*>(pk + C::OFF_FWD1), vec, lane, h,
+                             &xw[col + B::XB], hb);
     const float2 g = make_float2(guw[col].x + guw[S + col].x, guw[col].y + guw[S + col].y);
     // output layer: delta_o = (Re g_u, Im g_u) in rows 0, 1 of a 32-row block
 #pragma unroll
@@ -829,6 +846,7 @@ bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out) {
     td.nks1 = C::NKS1;
     td.nksh = C::NKSH;
     td.pack_bytes = C::PACK;
+    td.fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (kTile + T_) + 4 * C::NVEC;
     td.dw_slot = C::SLOT;
   });
   *out = td;
