@@ -41,7 +41,21 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="samples of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 device-to-device copies of 256 MiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_copy": a.numel() * 4, "copies": 5}))
 
 
 def cpu_baseline(wl_name, n_sample):
@@ -83,6 +97,9 @@ def cpu_baseline(wl_name, n_sample):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the hot path shards by "
