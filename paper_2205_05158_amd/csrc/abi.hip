@@ -27,7 +27,7 @@ constexpr int kNmseTile = 256;        // tile of the stand-alone NMSE pass
 constexpr int kPlainChunk = 1 << 17;  // samples per chunk of the plain path
 constexpr int kPlainDwBlock = 2048;   // samples per split-K block of the plain dW
 constexpr int kMaxGrid = 512;         // persistent workgroups (sizes the dW slots)
-constexpr int kBwdTile = 128;         // samples per workgroup tile of the tuned kernels
+constexpr int kGmpTile = 128;         // table tile handed to the stand-alone GMP pass
 
 struct Problem {
   int S = 0, n_sets = 0, per_stream = 0;
@@ -369,7 +369,7 @@ dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const 
     tdnn_dims(*tdnn, &td);
     void* pack = at<void>(workspace, L.pack);
     { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
-    StreamTable tab = make_table(p, kBwdTile);
+    StreamTable tab = make_table(p, td.tile);
     int grid = std::min(tab.n_tiles, fwd_grid(td));
     { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, grid, stream); }
   }
@@ -385,7 +385,7 @@ dpd_status pa_gmp_forward(const dpd_gmp_desc* gmp, const dpd_batch* batch, const
   if (!u || !coef || !y) return DPD_ERR_NULL;
   if (!aligned(u, 8) || !aligned(y, 8) || !aligned(coef, 4)) return DPD_ERR_ALIGN;
   if (u == y) return DPD_ERR_SHAPE;
-  StreamTable tab = make_table(p, kBwdTile);
+  StreamTable tab = make_table(p, kGmpTile);
   { DPD_PROF("gmp_fwd"); launch_gmp_fwd(*gmp, tab, u, coef, y, stream); }
   return launch_status();
 }
@@ -451,7 +451,7 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   tdnn_dims(*tdnn, &td);
   void* pack = at<void>(workspace, L.pack);
   { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, P, pack, stream); }
-  StreamTable tab = make_table(p, kBwdTile);
+  StreamTable tab = make_table(p, td.tile);
   int fgrid = std::min(tab.n_tiles, fwd_grid(td));
   { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, ubuf, fgrid, stream); }
   if (dw) {

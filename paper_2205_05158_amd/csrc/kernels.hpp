@@ -47,6 +47,7 @@ struct TdnnDims {
   int kin_p;        // kin padded to the MFMA K step
   int nks1;         // MFMA K steps of layer 1
   int nksh;         // MFMA K steps of a hidden layer
+  int tile;         // samples per workgroup tile of the tuned kernels
   int64_t pack_bytes;  // bytes of one packed parameter set
   int64_t fwd_lds;     // LDS bytes of the forward kernel
   // packed offsets (bytes) inside one set

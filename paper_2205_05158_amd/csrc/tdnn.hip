@@ -2,19 +2,24 @@
 // network (Sec. III-C core, eq. (8) slot) on MFMA, plus the fused
 // direct-learning backward (Sec. V-A-2) through the GMP PA (eq. (9)).
 //
-// Formulation.  A layer h_i = tanh(W_i h_{i-1} + b_i) over 32 samples is computed
-// transposed, h_i^T = W_i h_{i-1}^T, with the weights as the MFMA A operand
-// (rows = output neurons) and the activations as the B operand (columns = samples).
-// In the 32x32 accumulator layout a lane owns one sample column and 16 neuron rows
-// rho(j, h); those rows are exactly a B-operand K-slice of the next layer once the
-// next layer's weights are permuted the same way.  So activations never leave the
-// registers between layers; the pack kernel writes every weight matrix in that
-// per-lane operand order (one 16-byte bf16 or 4-byte fp32 load per lane per MFMA).
-// The backward chain delta_{i-1}^T = W_i^T delta_i^T uses the same trick with a
-// second, transposed pack.  dW_i = sum_s delta_i[s] h_{i-1}[s]^T contracts over
-// samples, so delta and h are staged through LDS (rows = neurons, columns =
-// samples) and each wave accumulates its share of 32x32 dW blocks over the
-// workgroup's 128 samples into a per-(workgroup, stream) slot in global memory.
+// Formulation.  A layer h_i = tanh(W_i h_{i-1} + b_i) over a wave's block of samples
+// is computed transposed, h_i^T = W_i h_{i-1}^T: weights are the MFMA A operand
+// (rows = output neurons), activations the B operand (columns = samples).  In the
+// accumulator layout a lane owns one sample column and a few neuron rows; those rows
+// are exactly a K-slice of the next layer's B operand once the next layer's weights
+// are permuted the same way, so activations never leave the registers between
+// layers.  The pack kernel writes every weight matrix in that per-lane operand order
+// (one 16-byte bf16 or 4-byte fp32 read per lane per MFMA).  The backward chain
+// delta_{i-1}^T = W_i^T delta_i^T uses the same trick with a transposed pack.
+// dW_i = sum_s delta_i[s] h_{i-1}[s]^T contracts over samples: delta and h are staged
+// through LDS (rows = neurons, columns = samples) and the waves accumulate 32x32 dW
+// blocks over the tile's samples in MFMA accumulators that stay in registers for the
+// workgroup's whole tile range; each (workgroup, stream) slot is written once.
+//
+// MFMA geometry: BF16 layers use 16x16x32 tiles (16 samples per wave, 64-sample
+// workgroup tiles), which halves the per-wave activation state of the deepest model
+// relative to 32x32 tiles; FP32 layers use 32x32x2 tiles (32 samples per wave,
+// 128-sample workgroup tiles).  The dW contraction always uses 32x32 tiles.
 #include <algorithm>
 #include <type_traits>
 
@@ -25,44 +30,83 @@ namespace dpdmi {
 
 namespace {
 
-constexpr int kThreads = 256;        // 4 waves
-constexpr int kTile = 128;           // samples per workgroup tile (32 per wave)
-
-template <int PREC> struct Prec;
-template <> struct Prec<DPD_BF16> {
-  static constexpr int KS = 16;      // MFMA K per instruction
-  using A = bf16x8;                  // one lane's A/B operand
-  using E = __bf16;                  // LDS staging element
-};
-template <> struct Prec<DPD_FP32> {
-  static constexpr int KS = 2;
-  using A = float;
-  using E = float;
-};
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// ------------------------------------------------------------------ MFMA geometry
+// MT: rows (neurons) and columns (samples) of a tile; KS: K per instruction; NR:
+// accumulator values per lane; LG = 64 / MT lane groups, each holding one K-slice of
+// an operand; EPL: operand elements per lane.  row(j, g): neuron row of accumulator
+// value j in lane group g.  A layer's value (row block mb, value j) is element
+// e_of(mb, j) of the next layer's B operand for K step ks_of(mb, j); mb_of and j_of
+// invert that map.
+template <int PREC, int MT> struct Mma;
+
+template <> struct Mma<DPD_BF16, 32> {
+  static constexpr int MT = 32, KS = 16, NR = 16, LG = 2, EPL = 8;
+  using A = bf16x8;
+  using Acc = f32x16;
+  using E = __bf16;
+  __device__ static Acc mma(A a, A b, Acc c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+  __host__ __device__ static constexpr int row(int j, int g) { return 8 * (j >> 2) + 4 * g + (j & 3); }
+  __host__ __device__ static constexpr int ks_of(int mb, int j) { return 2 * mb + j / 8; }
+  __host__ __device__ static constexpr int e_of(int, int j) { return j % 8; }
+  __host__ __device__ static constexpr int mb_of(int ks, int) { return ks / 2; }
+  __host__ __device__ static constexpr int j_of(int ks, int e) { return 8 * (ks % 2) + e; }
+};
+
+template <> struct Mma<DPD_BF16, 16> {
+  static constexpr int MT = 16, KS = 32, NR = 4, LG = 4, EPL = 8;
+  using A = bf16x8;
+  using Acc = f32x4;
+  using E = __bf16;
+  __device__ static Acc mma(A a, A b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+  __host__ __device__ static constexpr int row(int j, int g) { return 4 * g + j; }
+  __host__ __device__ static constexpr int ks_of(int mb, int) { return mb / 2; }
+  __host__ __device__ static constexpr int e_of(int mb, int j) { return 4 * (mb % 2) + j; }
+  __host__ __device__ static constexpr int mb_of(int ks, int e) { return 2 * ks + e / 4; }
+  __host__ __device__ static constexpr int j_of(int, int e) { return e % 4; }
+};
+
+template <> struct Mma<DPD_FP32, 32> {
+  static constexpr int MT = 32, KS = 2, NR = 16, LG = 2, EPL = 1;
+  using A = float;
+  using Acc = f32x16;
+  using E = float;
+  __device__ static Acc mma(A a, A b, Acc c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+  __host__ __device__ static constexpr int row(int j, int g) { return 8 * (j >> 2) + 4 * g + (j & 3); }
+  __host__ __device__ static constexpr int ks_of(int mb, int j) { return 16 * mb + j; }
+  __host__ __device__ static constexpr int e_of(int, int) { return 0; }
+  __host__ __device__ static constexpr int mb_of(int ks, int) { return ks / 16; }
+  __host__ __device__ static constexpr int j_of(int ks, int) { return ks % 16; }
+};
+
 template <int PREC, int T, int H, int NL>
 struct Cfg {
-  using P = Prec<PREC>;
-  using A = typename P::A;
-  using E = typename P::E;
-  static constexpr int KS = P::KS;
+  using X = Mma<PREC, PREC == DPD_BF16 ? 16 : 32>;    // layer tiles
+  using D = Mma<PREC, 32>;                              // dW tiles
+  using A = typename X::A;
+  using E = typename X::E;
+  static constexpr int MT = X::MT, KS = X::KS, NR = X::NR, LG = X::LG;
+  static constexpr int S = MT * kWaves;                // samples per workgroup tile
   static constexpr int KIN = 5 * T;
   static constexpr int KIN_P = round_up(KIN, KS);
   static constexpr int NKS1 = KIN_P / KS;
   static constexpr int HP = round_up(H, 32);
-  static constexpr int NB = HP / 32;
-  static constexpr int NKSH = HP / KS;
-  static constexpr int C1 = round_up(KIN_P, 32);     // dW columns of layer 1
+  static constexpr int NB = HP / MT;                    // row blocks of a layer
+  static constexpr int NKSH = HP / KS;                  // K steps of a hidden layer
+  static constexpr int C1 = round_up(KIN_P, 32);        // dW columns of layer 1
   static constexpr int NN1 = C1 / 32;
+  static constexpr int NBD = HP / 32;                   // dW row blocks
   // packed parameter set (bytes)
   static constexpr int64_t ES = sizeof(A);
   static constexpr int64_t OFF_FWD1 = 0;
   static constexpr int64_t OFF_FWDH = OFF_FWD1 + (int64_t)NB * NKS1 * 64 * ES;
   static constexpr int64_t OFF_BWDH = OFF_FWDH + (int64_t)(NL - 1) * NB * NKSH * 64 * ES;
   static constexpr int64_t OFF_VEC = OFF_BWDH + (int64_t)(NL - 1) * NB * NKSH * 64 * ES;
-  // float vector block: bias [NL][NB][2][16], wo [2][NB][2][16], bo[2] (+2 pad)
+  // float vector block: bias [NL][NB][LG][NR], wo [2][NB][LG][NR], bo[2] (+2 pad)
   static constexpr int NVEC = NL * HP + 2 * HP + 4;
   static constexpr int64_t PACK = OFF_VEC + (int64_t)NVEC * 4;
   // natural dW slot (floats): per layer W block [rows][cols] then bias [rows]
@@ -72,6 +116,12 @@ struct Cfg {
   static constexpr int64_t SLOT = DW_L1 + (NL - 1) * DW_H + DW_O;
   __host__ __device__ static constexpr int64_t dw_off(int li) {   // li = 0..NL (NL = output)
     return li == 0 ? 0 : DW_L1 + (int64_t)(li - 1) * DW_H;
+  }
+  // feature index held by element e of K step ks in lane group g (layer 1)
+  __host__ __device__ static constexpr int nat_k(int ks, int g, int e) { return KS * ks + (KS / LG) * g + e; }
+  // previous-layer neuron held by element e of K step ks in lane group g (hidden layers)
+  __host__ __device__ static constexpr int hid_k(int ks, int g, int e) {
+    return MT * X::mb_of(ks, e) + X::row(X::j_of(ks, e), g);
   }
 };
 
@@ -118,74 +168,71 @@ template <int PREC, int T, int H, int NL>
 __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
                        char* __restrict__ pack) {
   using C = Cfg<PREC, T, H, NL>;
+  using X = typename C::X;
+  constexpr int EPL = X::EPL;
   const int set = blockIdx.y;
   const float* ws = w + set * w_stride;
   char* ps = pack + set * C::PACK;
   const int64_t n1 = (int64_t)C::NB * C::NKS1 * 64;
   const int64_t nh = (int64_t)(NL - 1) * C::NB * C::NKSH * 64;
   const int64_t total = n1 + 2 * nh + C::NVEC;
-  constexpr int EPL = PREC == DPD_BF16 ? 8 : 1;   // values per lane entry
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    float v[EPL];
-    int64_t e = idx;
-    if (e < n1 + 2 * nh) {
-      int lane = (int)(e % 64);
-      int rowl = lane % 32, h = lane / 32;
-      int64_t q = e / 64;
+    if (idx < n1 + 2 * nh) {
+      const int lane = (int)(idx % 64);
+      const int rowl = lane % C::MT, g = lane / C::MT;
+      const int64_t q = idx / 64;
       int sec, layer = 0, mb, ks;
-      if (e < n1) {
+      if (idx < n1) {
         sec = 0; mb = (int)(q / C::NKS1); ks = (int)(q % C::NKS1);
       } else {
-        int64_t r = e < n1 + nh ? (e - n1) / 64 : (e - n1 - nh) / 64;
-        sec = e < n1 + nh ? 1 : 2;
+        const int64_t r = idx < n1 + nh ? (idx - n1) / 64 : (idx - n1 - nh) / 64;
+        sec = idx < n1 + nh ? 1 : 2;
         layer = (int)(r / ((int64_t)C::NB * C::NKSH)) + 2;   // layer index i = 2..NL
-        int64_t rr = r % ((int64_t)C::NB * C::NKSH);
+        const int64_t rr = r % ((int64_t)C::NB * C::NKSH);
         mb = (int)(rr / C::NKSH); ks = (int)(rr % C::NKSH);
       }
+      const int m = C::MT * mb + rowl;                        // A-operand row
+      float v[EPL];
       for (int ee = 0; ee < EPL; ++ee) {
         float val = 0.f;
         if (sec == 0) {
-          int o = 32 * mb + rowl;
-          int k = PREC == DPD_BF16 ? 16 * ks + 8 * h + ee : 2 * ks + h;
-          if (o < H && k < C::KIN) val = ws[so.w[0] + (int64_t)o * C::KIN + k];
+          const int k = C::nat_k(ks, g, ee);
+          if (m < H && k < C::KIN) val = ws[so.w[0] + (int64_t)m * C::KIN + k];
         } else {
-          // K index of a hidden-layer input in accumulator-row order
-          int kk = PREC == DPD_BF16 ? 32 * (ks / 2) + mfma_row(8 * (ks % 2) + ee, h)
-                                    : 32 * (ks / 16) + mfma_row(ks % 16, h);
-          int m = 32 * mb + rowl;
-          const float* Wi = ws + so.w[layer - 1];          // W_i is [H][H]
-          if (sec == 1) {        // forward: A[o = m][k = kk]
-            if (m < H && kk < H) val = Wi[(int64_t)m * H + kk];
-          } else {               // backward: A[i = m][o = kk] = W_i[o][i]
-            if (m < H && kk < H) val = Wi[(int64_t)kk * H + m];
-          }
+          const int kk = C::hid_k(ks, g, ee);
+          const float* Wi = ws + so.w[layer - 1];             // W_i is [H][H]
+          if (m < H && kk < H)
+            val = sec == 1 ? Wi[(int64_t)m * H + kk]           // forward: A[o][k] = W_i[o][k]
+                           : Wi[(int64_t)kk * H + m];          // backward: A[k][o] = W_i[o][k]
         }
         v[ee] = val;
       }
-      if constexpr (PREC == DPD_BF16) {
+      if constexpr (EPL == 8) {
         bf16x8 a;
         for (int ee = 0; ee < 8; ++ee) a[ee] = (__bf16)v[ee];
-        reinterpret_cast<bf16x8*>(ps)[e] = a;
+        reinterpret_cast<bf16x8*>(ps)[idx] = a;
       } else {
-        reinterpret_cast<float*>(ps)[e] = v[0];
+        reinterpret_cast<float*>(ps)[idx] = v[0];
       }
     } else {
-      int f = (int)(e - n1 - 2 * nh);
+      // float vector block, rows in accumulator order: r = MT*mb + NR*g + j holds
+      // neuron MT*mb + row(j, g)
+      const int f = (int)(idx - n1 - 2 * nh);
+      auto neuron = [&](int r) {
+        const int mb = r / C::MT, g = (r % C::MT) / C::NR, j = r % C::NR;
+        return C::MT * mb + X::row(j, g);
+      };
       float val = 0.f;
-      if (f < NL * C::HP) {                  // bias [i][mb][h][j]
-        int i = f / C::HP, r = f % C::HP;
-        int mb = r / 32, h = (r % 32) / 16, j = r % 16;
-        int o = 32 * mb + mfma_row(j, h);
+      if (f < NL * C::HP) {
+        const int i = f / C::HP, o = neuron(f % C::HP);
         if (o < H) val = ws[so.b[i] + o];
-      } else if (f < NL * C::HP + 2 * C::HP) {   // wo [c][mb][h][j]
-        int r0 = f - NL * C::HP;
-        int c = r0 / C::HP, r = r0 % C::HP;
-        int mb = r / 32, h = (r % 32) / 16, j = r % 16;
-        int o = 32 * mb + mfma_row(j, h);
+      } else if (f < NL * C::HP + 2 * C::HP) {
+        const int r0 = f - NL * C::HP;
+        const int c = r0 / C::HP, o = neuron(r0 % C::HP);
         if (o < H) val = ws[so.w[NL] + (int64_t)c * H + o];
       } else {
-        int c = f - NL * C::HP - 2 * C::HP;
+        const int c = f - NL * C::HP - 2 * C::HP;
         if (c < 2) val = ws[so.b[NL] + c];
       }
       reinterpret_cast<float*>(ps + C::OFF_VEC)[f] = val;
@@ -193,21 +240,38 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
   }
 }
 
-// ------------------------------------------------------------------ MLP pieces
-// B operands of one 32-row block: 2 x 8 bf16 (bf16) or 16 floats (fp32), i.e. the 16
-// accumulator rows of the lane in K-step order.
-template <class C>
-using BlockOps = typename C::A[C::KS == 16 ? 2 : 16];
+// ------------------------------------------------------------------ layer pieces
+// A layer's values in B-operand form: NKS operands per lane.
+template <class C, int NKS>
+using Ops = typename C::A[NKS];
 
-// Features of the lane's sample: xw points at x[n] in an LDS window (xw[-t] = x[n-t]).
 template <class C>
-__device__ __forceinline__ void make_features(const float2* xw, int h, typename C::A (&feat)[C::NKS1]) {
+__device__ __forceinline__ void set_elem(typename C::A& a, int e, float v) {
+  if constexpr (C::X::EPL == 8) a[e] = (__bf16)v;
+  else { (void)e; a = v; }
+}
+template <class C>
+__device__ __forceinline__ float get_elem(const typename C::A& a, int e) {
+  if constexpr (C::X::EPL == 8) return (float)a[e];
+  else { (void)e; return a; }
+}
+// value j of row block mb of a layer held in operand form
+template <class C, int NKS>
+__device__ __forceinline__ float value_at(const Ops<C, NKS>& ops, int mb, int j) {
+  return get_elem<C>(ops[C::X::ks_of(mb, j)], C::X::e_of(mb, j));
+}
+
+// Features of the lane's sample (I, Q, |x|, |x|^2, |x|^3 per tap): xw points at x[n] in
+// an LDS window (xw[-t] = x[n-t]); element e of operand ks in lane group g holds feature
+// nat_k(ks, g, e), zero beyond 5T.
+template <class C>
+__device__ __forceinline__ void make_features(const float2* xw, int g, Ops<C, C::NKS1>& feat) {
   float f[C::KIN_P];
 #pragma unroll
   for (int t = 0; t < C::KIN / 5; ++t) {
-    float2 z = xw[-t];
-    float m2 = z.x * z.x + z.y * z.y;
-    float m = sqrtf(m2);
+    const float2 z = xw[-t];
+    const float m2 = z.x * z.x + z.y * z.y;
+    const float m = sqrtf(m2);
     f[5 * t + 0] = z.x;
     f[5 * t + 1] = z.y;
     f[5 * t + 2] = m;
@@ -217,79 +281,49 @@ __device__ __forceinline__ void make_features(const float2* xw, int h, typename 
 #pragma unroll
   for (int k = C::KIN; k < C::KIN_P; ++k) f[k] = 0.f;
 #pragma unroll
-  for (int ks = 0; ks < C::NKS1; ++ks) {
-    if constexpr (C::KS == 16) {
-      bf16x8 a;
+  for (int ks = 0; ks < C::NKS1; ++ks)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = (__bf16)(h ? f[16 * ks + 8 + e] : f[16 * ks + e]);
-      feat[ks] = a;
-    } else {
-      feat[ks] = h ? f[2 * ks + 1] : f[2 * ks];
+    for (int e = 0; e < C::X::EPL; ++e) {
+      float v = f[C::nat_k(ks, 0, e)];
+#pragma unroll
+      for (int gg = 1; gg < C::LG; ++gg) v = g == gg ? f[C::nat_k(ks, gg, e)] : v;
+      set_elem<C>(feat[ks], e, v);
     }
-  }
 }
 
-// B operand of K step ks of a hidden layer from the previous layer's blocks.
-template <class C>
-__device__ __forceinline__ typename C::A b_operand(const BlockOps<C> (&hb)[C::NB], int ks) {
-  if constexpr (C::KS == 16) return hb[ks / 2][ks % 2];
-  else return hb[ks / 16][ks % 16];
-}
-
-template <class C>
-__device__ __forceinline__ void block_to_operands(const float (&v)[16], BlockOps<C>& out) {
-  if constexpr (C::KS == 16) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      bf16x8 a;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = (__bf16)v[8 * q + e];
-      out[q] = a;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) out[j] = v[j];
-  }
-}
-
-template <class C>
-__device__ __forceinline__ float operand_value(const BlockOps<C>& b, int j) {
-  if constexpr (C::KS == 16) return (float)b[j / 8][j % 8];
-  else return b[j];
-}
-
-template <class C>
-__device__ __forceinline__ f32x16 mfma(typename C::A a, typename C::A b, f32x16 c) {
-  if constexpr (C::KS == 16) return mfma_bf16(a, b, c);
-  else return mfma_f32(a, b, c);
-}
-
-// One 32-row block mb of a dense layer: sum_ks A(mb, ks) B(ks); Apk is [NB][NKS][64].
+// One row block mb of a dense layer: sum_ks A(mb, ks) B(ks); Apk is [NB][NKS][64].
 template <class C, int NKS, class BF>
-__device__ __forceinline__ f32x16 dense_block(const typename C::A* __restrict__ Apk, int mb,
-                                              int lane, BF&& bop) {
-  f32x16 acc;
+__device__ __forceinline__ typename C::X::Acc dense_block(const typename C::A* __restrict__ Apk, int mb,
+                                                          int lane, BF&& bop) {
+  typename C::X::Acc acc;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  for (int j = 0; j < C::NR; ++j) acc[j] = 0.f;
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) {
-    typename C::A a = Apk[((int64_t)mb * NKS + ks) * 64 + lane];
-    acc = mfma<C>(a, bop(ks), acc);
+    const typename C::A a = Apk[((int64_t)mb * NKS + ks) * 64 + lane];
+    acc = C::X::mma(a, bop(ks), acc);
   }
   return acc;
 }
 
-// Forward through all hidden layers one 32-neuron block at a time.  Keeps every
-// layer's B operands in hb (hb[i] = h_{i+1}) and returns the two linear outputs.
-// wf: the forward weight operands (layer 1 then hidden layers, packed order; global
-// or LDS); vec: LDS copy of the float vector block (biases, output layer).
+// Sum over the LG lane groups that share a sample column.
+template <class C>
+__device__ __forceinline__ float lane_group_sum(float v) {
+  if constexpr (C::LG == 4) v += __shfl_xor(v, 16);
+  return v + __shfl_xor(v, 32);
+}
+
+// Forward through all hidden layers one row block at a time.  hb[i] holds h_{i+1} in
+// operand form; returns the two linear outputs (valid in every lane group).
+// wf: forward weight operands (layer 1, then the hidden layers; global or LDS);
+// vec: LDS copy of the float vector block (biases, output layer).
 template <class C, int NL>
 __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const float* vec,
-                                              int lane, int h, const float2* xw,
-                                              BlockOps<C> (&hb)[NL][C::NB]) {
+                                              int lane, int g, const float2* xw,
+                                              Ops<C, C::NKSH> (&hb)[NL]) {
   using A = typename C::A;
-  A feat[C::NKS1];
-  make_features<C>(xw, h, feat);
+  Ops<C, C::NKS1> feat;
+  make_features<C>(xw, g, feat);
   const float* wo = vec + NL * C::HP;
   float o0 = 0.f, o1 = 0.f;
 #pragma unroll
@@ -297,63 +331,61 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
 #pragma unroll
     for (int mb = 0; mb < C::NB; ++mb) {
       DPD_KEEP_LOADS_LOCAL();
-      f32x16 acc;
+      typename C::X::Acc acc;
       if (i == 0) {
         acc = dense_block<C, C::NKS1>(wf, mb, lane, [&](int ks) { return feat[ks]; });
       } else {
         const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
-        acc = dense_block<C, C::NKSH>(Ah, mb, lane, [&](int ks) { return b_operand<C>(hb[i - 1], ks); });
+        acc = dense_block<C, C::NKSH>(Ah, mb, lane, [&](int ks) { return hb[i - 1][ks]; });
       }
-      const float* bias = vec + (i * C::NB + mb) * 32 + h * 16;
-      float v[16];
+      const int vb = (mb * C::LG + g) * C::NR;
+      const float* bias = vec + i * C::HP + vb;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if constexpr (C::KS == 16) v[j] = tanh_bf16(acc[j] + bias[j]);
-        else v[j] = tanh_f32(acc[j] + bias[j]);
-      }
-      block_to_operands<C>(v, hb[i][mb]);
-      if (i == NL - 1) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          o0 = fmaf(wo[(0 * C::NB + mb) * 32 + h * 16 + j], v[j], o0);
-          o1 = fmaf(wo[(1 * C::NB + mb) * 32 + h * 16 + j], v[j], o1);
+      for (int j = 0; j < C::NR; ++j) {
+        float v;
+        if constexpr (C::X::EPL == 8) v = tanh_bf16(acc[j] + bias[j]);
+        else v = tanh_f32(acc[j] + bias[j]);
+        set_elem<C>(hb[i][C::X::ks_of(mb, j)], C::X::e_of(mb, j), v);
+        if (i == NL - 1) {
+          o0 = fmaf(wo[vb + j], v, o0);
+          o1 = fmaf(wo[C::HP + vb + j], v, o1);
         }
       }
     }
   }
-  o0 += __shfl_xor(o0, 32);
-  o1 += __shfl_xor(o1, 32);
+  o0 = lane_group_sum<C>(o0);
+  o1 = lane_group_sum<C>(o1);
   const float* bo = vec + NL * C::HP + 2 * C::HP;
   return make_float2(o0 + bo[0], o1 + bo[1]);
 }
 
 // ------------------------------------------------------------------ forward kernel
 // Each workgroup owns a contiguous range of tiles; the forward weight operands of the
-// current parameter set live in LDS (reloaded only when the set changes), so every
-// MFMA A operand is one conflict-free 16-byte (bf16) or 4-byte (fp32) LDS read.
+// current parameter set live in LDS (reloaded only when the set changes) unless they
+// exceed the LDS budget, in which case they are read from global memory (L2).
 template <int PREC, int T, int H, int NL>
 __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
                                                        const char* __restrict__ pack, int residual,
                                                        float* __restrict__ u) {
   using C = Cfg<PREC, T, H, NL>;
   using A = typename C::A;
-  constexpr int XW = kTile + T - 1;
-  // forward operands in 16-byte units; models whose forward weights exceed the LDS
-  // budget read them from global memory (L2) instead
+  constexpr int S = C::S;
+  constexpr int XW = S + T - 1;
   constexpr bool kLdsWeights = C::OFF_BWDH <= 144 * 1024;
   constexpr int NWF = kLdsWeights ? (int)(C::OFF_BWDH / 16) : 1;
   __shared__ float2 xw[XW];
   __shared__ float vec[C::NVEC];
   __shared__ __attribute__((aligned(16))) uint4 wf[NWF];
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, h = lane / 32, sl = lane % 32;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int g = lane / C::MT, sl = lane % C::MT;
   const int t_begin = wg_tile_start(blockIdx.x, gridDim.x, st.n_tiles);
   const int t_end = wg_tile_start(blockIdx.x + 1, gridDim.x, st.n_tiles);
   int cur_set = -1;
   for (int t = t_begin; t < t_end; ++t) {
-    int s = stream_of_tile(st, t);
-    int set = st.per_stream ? s : 0;
-    int64_t lo = st.off[s], hi = st.off[s + 1];
-    int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * kTile;
+    const int s = stream_of_tile(st, t);
+    const int set = st.per_stream ? s : 0;
+    const int64_t lo = st.off[s], hi = st.off[s + 1];
+    const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
     const char* pk = pack + set * C::PACK;
     __syncthreads();   // previous tile done with the LDS windows
     if (set != cur_set) {
@@ -366,18 +398,18 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const flo
       cur_set = set;
     }
     for (int i = threadIdx.x; i < XW; i += kThreads) {
-      int64_t p = t0 - (T - 1) + i;
+      const int64_t p = t0 - (T - 1) + i;
       xw[i] = (p >= lo && p < hi) ? ld2(x, p) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    BlockOps<C> hb[NL][C::NB];
-    int col = 32 * wave + sl;
+    Ops<C, C::NKSH> hb[NL];
+    const int col = C::MT * wave + sl;
     const A* wops = kLdsWeights ? reinterpret_cast<const A*>(wf) : reinterpret_cast<const A*>(pk);
-    float2 o = mlp_forward<C, NL>(wops, vec, lane, h, &xw[col + T - 1], hb);
-    int64_t n = t0 + col;
-    if (h == 0 && n < hi) {
+    float2 o = mlp_forward<C, NL>(wops, vec, lane, g, &xw[col + T - 1], hb);
+    const int64_t n = t0 + col;
+    if (g == 0 && n < hi) {
       if (residual) {
-        float2 xv = xw[col + T - 1];
+        const float2 xv = xw[col + T - 1];
         o.x += xv.x;
         o.y += xv.y;
       }
@@ -391,7 +423,8 @@ template <int PREC, int T, int H, int NL, int K, int M, int L>
 struct BwdLds {
   using C = Cfg<PREC, T, H, NL>;
   using G = Gmp<K, M, L>;
-  static constexpr int S = kTile;
+  static constexpr int S = C::S;
+  static constexpr int TP = kThreads / S;         // tap partitions of the GMP work
   static constexpr int XB = cmax(T - 1, L);
   static constexpr int XW = S + XB + M + L;       // x  [t0 - XB, t0 + S + M + L)
   static constexpr int UB = M + 2 * L;
@@ -401,48 +434,43 @@ struct BwdLds {
   static constexpr int YW = S + M + 2 * L;        // gy [t0 - L, t0 + S + M + L)
   static constexpr int LD = S + (PREC == DPD_BF16 ? 8 : 4);   // staging row stride (elements)
   static constexpr int HROWS = cmax(C::C1, C::HP);
-  // union: GMP phase vs. dW staging
-  static constexpr int GMP_BYTES = (2 * G::J + QW * (M + 1) + YW) * 8;
+  // union: GMP phase (coefficients, Q, g_y, reduction scratch) vs. dW staging
+  static constexpr int GMP_BYTES = (2 * G::J + QW * (M + 1) + YW) * 8 + 4 * kThreads * 4;
   static constexpr int STAGE_BYTES = (C::HP + HROWS) * LD * (int)sizeof(typename C::E);
   static constexpr int UNION_BYTES = cmax(GMP_BYTES, STAGE_BYTES);
-  // dW blocks per layer and the register-resident accumulators that hold them:
-  // layer blocks bi = 4q + wave, q = 0..ceil(blocks/4)-1, in dwacc[Q0 + q].
-  static constexpr int NBL1 = C::NB * C::NN1, NBLH = C::NB * C::NB, NBLO = C::NB;
-  static constexpr int Q1 = (NBL1 + 3) / 4, QH = (NBLH + 3) / 4, QO = (NBLO + 3) / 4;
-  static constexpr int NQ = Q1 + (NL - 1) * QH + QO;
+  // 32x32 dW blocks of all layers (layer 1, hidden, output), dealt round-robin over
+  // the waves: block bi is held by wave bi % kWaves in dwacc[bi / kWaves].
+  static constexpr int NBL1 = C::NBD * C::NN1, NBLH = C::NBD * C::NBD, NBLO = C::NBD;
+  static constexpr int NBT = NBL1 + (NL - 1) * NBLH + NBLO;
+  static constexpr int NQ = (NBT + kWaves - 1) / kWaves;
+  __host__ __device__ static constexpr int blk_off(int li) {   // li = 0..NL (NL = output)
+    return li == 0 ? 0 : NBL1 + (li - 1) * NBLH;
+  }
+  __host__ __device__ static constexpr int blk_cnt(int li) { return li == 0 ? NBL1 : (li == NL ? NBLO : NBLH); }
+  __host__ __device__ static constexpr int blk_cols(int li) { return li == 0 ? C::NN1 : C::NBD; }
   static constexpr int BIAS = NL * C::HP + 32;   // bias-gradient accumulators
 };
-
-// Stage the lane's 16 accumulator-order values of every block (one sample column).
-template <class C>
-__device__ __forceinline__ void stage_ops(typename C::E* stage, int ld, int col, int h,
-                                          const BlockOps<C> (&b)[C::NB]) {
-#pragma unroll
-  for (int mb = 0; mb < C::NB; ++mb)
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      stage[(32 * mb + mfma_row(j, h)) * ld + col] = (typename C::E)operand_value<C>(b[mb], j);
-}
 
 // One 32x32 dW block over the tile's samples: rows mb of the delta staging against
 // rows nb of the activation staging (both [row][sample]).
 template <class C>
 __device__ __forceinline__ f32x16 dw_block(const typename C::E* dst, const typename C::E* hst, int ld,
                                            int mb, int nb, int lane, f32x16 acc) {
+  using D = typename C::D;
   const int h = lane / 32, r = lane % 32;
   const typename C::E* arow = dst + (32 * mb + r) * ld;
   const typename C::E* brow = hst + (32 * nb + r) * ld;
 #pragma unroll
-  for (int ks = 0; ks < kTile / C::KS; ++ks) {
-    typename C::A a, b;
-    if constexpr (C::KS == 16) {
+  for (int ks = 0; ks < C::S / D::KS; ++ks) {
+    typename D::A a, b;
+    if constexpr (D::EPL == 8) {
       a = *reinterpret_cast<const bf16x8*>(arow + 16 * ks + 8 * h);
       b = *reinterpret_cast<const bf16x8*>(brow + 16 * ks + 8 * h);
     } else {
       a = arow[2 * ks + h];
       b = brow[2 * ks + h];
     }
-    acc = mfma<C>(a, b, acc);
+    acc = D::mma(a, b, acc);
   }
   return acc;
 }
@@ -451,23 +479,58 @@ __device__ __forceinline__ f32x16 dw_block(const typename C::E* dst, const typen
 template <class C>
 __device__ __forceinline__ float delta_row_sum(const typename C::E* dst, int ld, int mb, int lane) {
   const int h = lane / 32, r = lane % 32;
-  const typename C::E* arow = dst + (32 * mb + r) * ld + h * (kTile / 2);
+  const typename C::E* arow = dst + (32 * mb + r) * ld + h * (C::S / 2);
   float sum = 0.f;
-  if constexpr (C::KS == 16) {
+  if constexpr (C::D::EPL == 8) {
 #pragma unroll
-    for (int c = 0; c < kTile / 2; c += 8) {
-      bf16x8 v = *reinterpret_cast<const bf16x8*>(arow + c);
+    for (int c = 0; c < C::S / 2; c += 8) {
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(arow + c);
 #pragma unroll
       for (int e = 0; e < 8; ++e) sum += (float)v[e];
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < kTile / 2; c += 4) {
-      float4 v = *reinterpret_cast<const float4*>(arow + c);
+    for (int c = 0; c < C::S / 2; c += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(arow + c);
       sum += (v.x + v.y) + (v.z + v.w);
     }
   }
   return sum + __shfl_xor(sum, 32);
+}
+
+// Stage a layer held in operand form: value (mb, j) of lane group g goes to row
+// MT*mb + row(j, g), column col.
+template <class C, int NKS>
+__device__ __forceinline__ void stage_layer(typename C::E* stage, int ld, int col, int g,
+                                            const Ops<C, NKS>& ops) {
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+    for (int e = 0; e < C::X::EPL; ++e) {
+      const int mb = C::X::mb_of(ks, e), j = C::X::j_of(ks, e);
+      stage[(C::MT * mb + C::X::row(j, g)) * ld + col] = (typename C::E)get_elem<C>(ops[ks], e);
+    }
+}
+
+// Runs fq(L0, L1) with the compile-time tap range [L0, L1) of partition p out of TP.
+template <int M, int TP, class FQ>
+__device__ __forceinline__ void for_partition(int p, FQ&& fq) {
+  static_assert(TP == 1 || TP == 2 || TP == 4, "tap partitions");
+  auto run = [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    fq(std::integral_constant<int, (M + 1) * P / TP>{}, std::integral_constant<int, (M + 1) * (P + 1) / TP>{});
+  };
+  if constexpr (TP == 1) {
+    run(std::integral_constant<int, 0>{});
+  } else if constexpr (TP == 2) {
+    if (p == 0) run(std::integral_constant<int, 0>{});
+    else run(std::integral_constant<int, 1>{});
+  } else {
+    if (p == 0) run(std::integral_constant<int, 0>{});
+    else if (p == 1) run(std::integral_constant<int, 1>{});
+    else if (p == 2) run(std::integral_constant<int, 2>{});
+    else run(std::integral_constant<int, 3>{});
+  }
 }
 
 template <int PREC, int T, int H, int NL, int K, int M, int L>
@@ -479,27 +542,31 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
                                                        float* __restrict__ slots,
                                                        float* __restrict__ y_out) {
   using C = Cfg<PREC, T, H, NL>;
+  using X = typename C::X;
   using G = Gmp<K, M, L>;
   using B = BwdLds<PREC, T, H, NL, K, M, L>;
   using E = typename C::E;
   using A = typename C::A;
-  constexpr int S = kTile;
+  constexpr int S = C::S;
+  constexpr int TP = B::TP;
   __shared__ float2 xw[B::XW];
   __shared__ float2 uw[B::UW];
   __shared__ float rw[B::UW];
-  __shared__ float2 guw[2 * S];        // g_u partial sums of the two tap halves
+  __shared__ float2 guw[TP * S];       // g_u partial sums of the tap partitions
   __shared__ float vec[C::NVEC];
-  __shared__ float red[4 * kThreads];
   __shared__ float bacc[B::BIAS];
   __shared__ __attribute__((aligned(16))) char un[B::UNION_BYTES];
   float2* cf = reinterpret_cast<float2*>(un);
   float2* dcf = cf + G::J;
   float2(*qw)[M + 1] = reinterpret_cast<float2(*)[M + 1]>(dcf + G::J);
   float2* gyw = reinterpret_cast<float2*>(qw + B::QW);
+  float* red = reinterpret_cast<float*>(gyw + B::YW);
   E* dst = reinterpret_cast<E*>(un);
   E* hst = dst + C::HP * B::LD;
 
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64, h = lane / 32, sl = lane % 32;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int g = lane / C::MT, sl = lane % C::MT;
   const int g_wg = blockIdx.x, G_wg = gridDim.x;
   const int t_begin = wg_tile_start(g_wg, G_wg, st.n_tiles);
   const int t_end = wg_tile_start(g_wg + 1, G_wg, st.n_tiles);
@@ -517,25 +584,31 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   // stream) slot is written exactly once) and reset the accumulators.  Caller syncs.
   auto flush = [&](int s) {
     float* slot = slots + (int64_t)(g_wg + s) * C::SLOT;
+    // fresh copies of the lane and wave indices: keeps the store addresses from being
+    // precomputed outside the tile loop (they would not fit in registers)
+    int ln = lane, wv = wave_u;
+    asm volatile("" : "+v"(ln), "+s"(wv));
+    const int h = ln / 32, r = ln % 32;
 #pragma unroll
     for (int q = 0; q < B::NQ; ++q) {
-      // decode (layer, block) of dwacc[q] for this wave
-      int li, ql, nnb, nbl;
-      if (q < B::Q1) { li = 0; ql = q; nnb = C::NN1; nbl = B::NBL1; }
-      else if (q < B::Q1 + (NL - 1) * B::QH) { li = 1 + (q - B::Q1) / B::QH; ql = (q - B::Q1) % B::QH; nnb = C::NB; nbl = B::NBLH; }
-      else { li = NL; ql = q - B::Q1 - (NL - 1) * B::QH; nnb = C::NB; nbl = B::NBLO; }
-      int bi = 4 * ql + wave;
-      if (bi < nbl) {
-        int mb = bi / nnb, nb = bi % nnb;
-        float* out = slot + C::dw_off(li) + (int64_t)(32 * mb) * (nnb * 32) + 32 * nb + sl;
+      const int bi = kWaves * q + wv;
+      int li = -1;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) out[(int64_t)mfma_row(j, h) * (nnb * 32)] = dwacc[q][j];
+      for (int l2 = 0; l2 <= NL; ++l2)
+        if (bi >= B::blk_off(l2) && bi < B::blk_off(l2) + B::blk_cnt(l2)) li = l2;
+      if (li >= 0) {
+        const int nnb = li == 0 ? C::NN1 : C::NBD;
+        const int blk = bi - B::blk_off(li);
+        const int mb = blk / nnb, nb = blk % nnb;
+        float* out = slot + C::dw_off(li) + (int64_t)(32 * mb) * (nnb * 32) + 32 * nb + r;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) out[(int64_t)C::D::row(j, h) * (nnb * 32)] = dwacc[q][j];
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j) dwacc[q][j] = 0.f;
     }
     for (int i = tid; i < B::BIAS; i += kThreads) {
-      int li = i / C::HP, o = i % C::HP;
+      const int li = i / C::HP, o = i % C::HP;
       float* dstb = li < NL ? slot + C::dw_off(li) + (int64_t)C::HP * (li == 0 ? C::C1 : C::HP) + o
                             : slot + C::dw_off(NL) + 32 * C::HP + (i - NL * C::HP);
       *dstb = bacc[i];
@@ -543,24 +616,27 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     }
   };
 
-  // accumulate the owned blocks of one layer (li: 0 = input layer, NL = output layer)
+  // Accumulate this wave's dW blocks of layer li (0 = input layer, NL = output layer)
+  // from the staged delta and activation rows.
   auto accumulate = [&](auto li_c) {
     constexpr int li = decltype(li_c)::value;
-    constexpr int nnb = li == 0 ? C::NN1 : C::NB;
-    constexpr int nbl = li == 0 ? B::NBL1 : (li == NL ? B::NBLO : B::NBLH);
-    constexpr int q0 = li == 0 ? 0 : (li == NL ? B::Q1 + (NL - 1) * B::QH : B::Q1 + (li - 1) * B::QH);
-    constexpr int nql = li == 0 ? B::Q1 : (li == NL ? B::QO : B::QH);
-    float* bl = bacc + (li == NL ? NL * C::HP : li * C::HP);
+    constexpr int off = B::blk_off(li), cnt = B::blk_cnt(li), nnb = B::blk_cols(li);
+    constexpr int q0 = off / kWaves, q1 = (off + cnt - 1) / kWaves;
+    float* bl = bacc + li * C::HP;
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int h = ln / 32, r = ln % 32;
 #pragma unroll
-    for (int q = 0; q < nql; ++q) {
+    for (int q = q0; q <= q1; ++q) {
       DPD_KEEP_LOADS_LOCAL();
-      int bi = 4 * q + wave;
-      if (bi < nbl) {
-        int mb = bi / nnb, nb = bi % nnb;
-        dwacc[q0 + q] = dw_block<C>(dst, hst, B::LD, mb, nb, lane, dwacc[q0 + q]);
+      const int bi = kWaves * q + wave_u;
+      if (bi >= off && bi < off + cnt) {
+        const int blk = bi - off;
+        const int mb = blk / nnb, nb = blk % nnb;
+        dwacc[q] = dw_block<C>(dst, hst, B::LD, mb, nb, ln, dwacc[q]);
         if (nb == 0) {
-          float sum = delta_row_sum<C>(dst, B::LD, mb, lane);
-          if (h == 0) bl[32 * mb + sl] += sum;
+          const float sum = delta_row_sum<C>(dst, B::LD, mb, ln);
+          if (h == 0) bl[32 * mb + r] += sum;
         }
       }
     }
@@ -581,9 +657,9 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       cur_stream = s;
     }
     for (int j = tid; j < G::J; j += kThreads) {
-      float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
+      const float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
       cf[j] = c;
-      float k = (float)G::order(j);
+      const float k = (float)G::order(j);
       dcf[j] = make_float2(k * c.x, k * c.y);
     }
     {
@@ -591,57 +667,53 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       for (int i = tid; i < C::NVEC; i += kThreads) vec[i] = src[i];
     }
     for (int i = tid; i < B::XW; i += kThreads) {
-      int64_t p = t0 - B::XB + i;
+      const int64_t p = t0 - B::XB + i;
       xw[i] = (p >= lo && p < hi) ? ld2(x, p) : make_float2(0.f, 0.f);
     }
     for (int i = tid; i < B::UW; i += kThreads) {
-      int64_t p = t0 - B::UB + i;
-      float2 v = (p >= lo && p < hi) ? ld2(u, p) : make_float2(0.f, 0.f);
+      const int64_t p = t0 - B::UB + i;
+      const float2 v = (p >= lo && p < hi) ? ld2(u, p) : make_float2(0.f, 0.f);
       uw[i] = v;
       rw[i] = sqrtf(v.x * v.x + v.y * v.y);
     }
     __syncthreads();
-    // ---- GMP: Q_l(p) on the Q window; waves 0-1 take taps [0, LH), waves 2-3 [LH, M]
-    constexpr int LH = (M + 1) / 2;
-    const bool upper = tid >= kThreads / 2;
-    for (int i = tid % (kThreads / 2); i < B::QW; i += kThreads / 2) {
+    // ---- GMP: Q_l(p) on the Q window; thread group `part` takes one partition of the taps
+    const int part = tid / S, pi = tid % S;
+    for (int i = pi; i < B::QW; i += S) {
       DPD_KEEP_LOADS_LOCAL();
-      float2 Q[M + 1];
-      if (upper) {
-        gmp_q<K, M, L, LH, M + 1>(&rw[i + L], cf, Q);
+      for_partition<M, TP>(part, [&](auto l0c, auto l1c) {
+        constexpr int L0 = decltype(l0c)::value, L1 = decltype(l1c)::value;
+        float2 Q[M + 1];
+        gmp_q<K, M, L, L0, L1>(&rw[i + L], cf, Q);
 #pragma unroll
-        for (int l = LH; l <= M; ++l) qw[i][l] = Q[l];
-      } else {
-        gmp_q<K, M, L, 0, LH>(&rw[i + L], cf, Q);
-#pragma unroll
-        for (int l = 0; l < LH; ++l) qw[i][l] = Q[l];
-      }
+        for (int l = L0; l < L1; ++l) qw[i][l] = Q[l];
+      });
     }
     __syncthreads();
     // ---- y, g_y = 2(y - Gx) (zero outside the stream), E and R on the tile
     Comp Ec, Rc;
     for (int i = tid; i < B::YW; i += kThreads) {
-      int64_t n = t0 - L + i;
-      float2 g = make_float2(0.f, 0.f);
+      const int64_t n = t0 - L + i;
+      float2 gyv = make_float2(0.f, 0.f);
       if (n >= lo && n < hi) {
         float2 y = make_float2(0.f, 0.f);
 #pragma unroll
         for (int l = 0; l <= M; ++l) {
-          float2 v = cmul(uw[i + M + L - l], qw[i + M - l][l]);
+          const float2 v = cmul(uw[i + M + L - l], qw[i + M - l][l]);
           y.x += v.x;
           y.y += v.y;
         }
-        float2 xv = xw[i - L + B::XB];
-        float tr = g_re * xv.x - g_im * xv.y, ti = g_re * xv.y + g_im * xv.x;
-        float er = y.x - tr, ei = y.y - ti;
-        g = make_float2(2.f * er, 2.f * ei);
+        const float2 xv = xw[i - L + B::XB];
+        const float tr = g_re * xv.x - g_im * xv.y, ti = g_re * xv.y + g_im * xv.x;
+        const float er = y.x - tr, ei = y.y - ti;
+        gyv = make_float2(2.f * er, 2.f * ei);
         if (i >= L && i < L + S) {
           Ec.add(er * er + ei * ei);
           Rc.add(tr * tr + ti * ti);
           if (y_out) st2(y_out, n, y);
         }
       }
-      gyw[i] = g;
+      gyw[i] = gyv;
     }
     // E/R tile partial (fixed tree)
     red[tid] = Ec.s; red[kThreads + tid] = Ec.c; red[2 * kThreads + tid] = Rc.s; red[3 * kThreads + tid] = Rc.c;
@@ -656,108 +728,97 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       __syncthreads();
     }
     if (tid == 0) tile_part[t] = make_float2(red[0] + red[kThreads], red[2 * kThreads] + red[3 * kThreads]);
-    // ---- g_u on the tile: the two halves of the taps in two partial sums
+    // ---- g_u on the tile: one partial sum per tap partition
     {
-      static_assert(S == kThreads / 2, "one sample per thread and tap half");
-      const int i = tid % S;
-      int64_t m = t0 + i;
+      const int64_t m = t0 + pi;
       float2 gu = make_float2(0.f, 0.f);
       if (m < hi) {
-        float2 Qm[M + 1];
+        for_partition<M, TP>(part, [&](auto l0c, auto l1c) {
+          constexpr int L0 = decltype(l0c)::value, L1 = decltype(l1c)::value;
+          float2 Qm[M + 1];
 #pragma unroll
-        for (int l = 0; l <= M; ++l) Qm[l] = qw[i + B::QB][l];
-        if (upper)
-          gu = gmp_grad<K, M, L, LH, M + 1>(&uw[i + B::UB], &rw[i + B::UB], &gyw[i + L], Qm, cf, dcf);
-        else
-          gu = gmp_grad<K, M, L, 0, LH>(&uw[i + B::UB], &rw[i + B::UB], &gyw[i + L], Qm, cf, dcf);
+          for (int l = L0; l < L1; ++l) Qm[l] = qw[pi + B::QB][l];
+          gu = gmp_grad<K, M, L, L0, L1>(&uw[pi + B::UB], &rw[pi + B::UB], &gyw[pi + L], Qm, cf, dcf);
+        });
       }
       guw[tid] = gu;
     }
     __syncthreads();   // g_u ready; the GMP part of the union is free from here on
 
-    // ---- TDNN: recompute this wave's 32 samples, then the reverse mode
-    const int col = 32 * wave + sl;
-    BlockOps<C> hb[NL][C::NB];
-    (void)mlp_forward<C, NL>(reinterpret_cast<const A*>(pk + C::OFF_FWD1), vec, lane, h,
+    // ---- TDNN: recompute this wave's samples, then the reverse mode
+    const int col = C::MT * wave + sl;
+    Ops<C, C::NKSH> hb[NL];
+    (void)mlp_forward<C, NL>(reinterpret_cast<const A*>(pk + C::OFF_FWD1), vec, lane, g,
                              &xw[col + B::XB], hb);
-    const float2 g = make_float2(guw[col].x + guw[S + col].x, guw[col].y + guw[S + col].y);
+    float2 gsum = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int p = 0; p < TP; ++p) {
+      gsum.x += guw[p * S + col].x;
+      gsum.y += guw[p * S + col].y;
+    }
     // output layer: delta_o = (Re g_u, Im g_u) in rows 0, 1 of a 32-row block
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      int row = mfma_row(j, h);
-      dst[row * B::LD + col] = (E)(row == 0 ? g.x : (row == 1 ? g.y : 0.f));
-    }
-    stage_ops<C>(hst, B::LD, col, h, hb[NL - 1]);
+    for (int sb = 0; sb < 32 / C::MT; ++sb)
+#pragma unroll
+      for (int j = 0; j < C::NR; ++j) {
+        const int row = C::MT * sb + X::row(j, g);
+        dst[row * B::LD + col] = (E)(row == 0 ? gsum.x : (row == 1 ? gsum.y : 0.f));
+      }
+    stage_layer<C, C::NKSH>(hst, B::LD, col, g, hb[NL - 1]);
     __syncthreads();
     accumulate(std::integral_constant<int, NL>{});
-    // delta_nl = (Wo^T delta_o) * (1 - h_nl^2)
-    BlockOps<C> db[C::NB];
+    // delta_NL = (Wo^T delta_o) * (1 - h_NL^2)
+    Ops<C, C::NKSH> db;
     {
       const float* wo = vec + NL * C::HP;
 #pragma unroll
-      for (int mb = 0; mb < C::NB; ++mb) {
-        float v[16];
+      for (int mb = 0; mb < C::NB; ++mb)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          float hv = operand_value<C>(hb[NL - 1][mb], j);
-          float w0 = wo[(0 * C::NB + mb) * 32 + h * 16 + j], w1 = wo[(1 * C::NB + mb) * 32 + h * 16 + j];
-          v[j] = (w0 * g.x + w1 * g.y) * (1.f - hv * hv);
+        for (int j = 0; j < C::NR; ++j) {
+          const float hv = value_at<C, C::NKSH>(hb[NL - 1], mb, j);
+          const int vi = (mb * C::LG + g) * C::NR + j;
+          const float v = (wo[vi] * gsum.x + wo[C::HP + vi] * gsum.y) * (1.f - hv * hv);
+          set_elem<C>(db[X::ks_of(mb, j)], X::e_of(mb, j), v);
         }
-        block_to_operands<C>(v, db[mb]);
-      }
     }
     auto layer = [&](auto i_c) {       // hidden layer i: delta_i in db, input h_{i-1}
       constexpr int i = decltype(i_c)::value;
       __syncthreads();                 // staging free
-      stage_ops<C>(dst, B::LD, col, h, db);
+      stage_layer<C, C::NKSH>(dst, B::LD, col, g, db);
       if constexpr (i >= 2) {
-        stage_ops<C>(hst, B::LD, col, h, hb[i - 2]);
+        stage_layer<C, C::NKSH>(hst, B::LD, col, g, hb[i - 2]);
       } else {
-        A feat[C::NKS1];
-        make_features<C>(&xw[col + B::XB], h, feat);
+        Ops<C, C::NKS1> feat;
+        make_features<C>(&xw[col + B::XB], g, feat);
 #pragma unroll
-        for (int ks = 0; ks < C::NKS1; ++ks) {
-          if constexpr (C::KS == 16) {
+        for (int ks = 0; ks < C::NKS1; ++ks)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) hst[(16 * ks + 8 * h + e) * B::LD + col] = feat[ks][e];
-          } else {
-            hst[(2 * ks + h) * B::LD + col] = feat[ks];
-          }
-        }
+          for (int e = 0; e < X::EPL; ++e)
+            hst[C::nat_k(ks, g, e) * B::LD + col] = (E)get_elem<C>(feat[ks], e);
 #pragma unroll
         for (int k = C::KIN_P; k < C::C1; ++k)
-          if ((k & 1) == h) hst[k * B::LD + col] = (E)0.f;
+          if (k % C::LG == g) hst[k * B::LD + col] = (E)0.f;
       }
       // delta_{i-1} = (W_i^T delta_i) * (1 - h_{i-1}^2) while the staging settles
-      BlockOps<C> dn[C::NB];
+      Ops<C, C::NKSH> dn;
       if constexpr (i >= 2) {
         const A* Ab = reinterpret_cast<const A*>(pk + C::OFF_BWDH) + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
 #pragma unroll
         for (int mb = 0; mb < C::NB; ++mb) {
           DPD_KEEP_LOADS_LOCAL();
-          f32x16 acc = dense_block<C, C::NKSH>(Ab, mb, lane, [&](int ks) { return b_operand<C>(db, ks); });
-          float v[16];
+          const typename X::Acc acc = dense_block<C, C::NKSH>(Ab, mb, lane, [&](int ks) { return db[ks]; });
 #pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            float hv = operand_value<C>(hb[i - 2][mb], j);
-            v[j] = acc[j] * (1.f - hv * hv);
+          for (int j = 0; j < C::NR; ++j) {
+            const float hv = value_at<C, C::NKSH>(hb[i - 2], mb, j);
+            set_elem<C>(dn[X::ks_of(mb, j)], X::e_of(mb, j), acc[j] * (1.f - hv * hv));
           }
-          block_to_operands<C>(v, dn[mb]);
         }
       }
       __syncthreads();
       accumulate(std::integral_constant<int, i - 1>{});
       if constexpr (i >= 2) {
 #pragma unroll
-        for (int mb = 0; mb < C::NB; ++mb) {
-          if constexpr (C::KS == 16) {
-            db[mb][0] = dn[mb][0];
-            db[mb][1] = dn[mb][1];
-          } else {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) db[mb][j] = dn[mb][j];
-          }
-        }
+        for (int ks = 0; ks < C::NKSH; ++ks) db[ks] = dn[ks];
       }
     };
     static_assert(NL >= 1 && NL <= 4, "hidden layer count of the tuned kernel");
@@ -778,25 +839,23 @@ __global__ void k_dw_finalize(StreamTable st, int G_wg, const float* __restrict_
                               const float* __restrict__ inv_r, int64_t P, float* __restrict__ dw) {
   using C = Cfg<PREC, T, H, NL>;
   const int set = blockIdx.y;
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= P) return;
-  // natural offset of packed index j
-  int64_t nat;
+  int64_t nat = -1;
   {
     int64_t pos = 0;
     int din = C::KIN;
-    nat = -1;
     for (int li = 0; li <= NL && nat < 0; ++li) {
-      int dout = li == NL ? 2 : H;
-      int cols = li == 0 ? C::C1 : C::HP;
-      int rows = li == NL ? 32 : C::HP;
-      int64_t nw = (int64_t)dout * din;
+      const int dout = li == NL ? 2 : H;
+      const int cols = li == 0 ? C::C1 : C::HP;
+      const int rows = li == NL ? 32 : C::HP;
+      const int64_t nw = (int64_t)dout * din;
       if (j < pos + nw) {
-        int64_t r = j - pos;
-        int o = (int)(r / din), k = (int)(r % din);
+        const int64_t r = j - pos;
+        const int o = (int)(r / din), k = (int)(r % din);
         nat = C::dw_off(li) + (int64_t)o * cols + k;
       } else if (j < pos + nw + dout) {
-        int o = (int)(j - pos - nw);
+        const int o = (int)(j - pos - nw);
         nat = C::dw_off(li) + (int64_t)rows * cols + o;
       }
       pos += nw + dout;
@@ -806,8 +865,8 @@ __global__ void k_dw_finalize(StreamTable st, int G_wg, const float* __restrict_
   float acc = 0.f;
   for (int s = 0; s < st.n; ++s) {
     if ((st.per_stream ? s : 0) != set) continue;
-    int g0 = wg_of_tile(st.tile0[s], G_wg, st.n_tiles);
-    int g1 = wg_of_tile(st.tile0[s + 1] - 1, G_wg, st.n_tiles);
+    const int g0 = wg_of_tile(st.tile0[s], G_wg, st.n_tiles);
+    const int g1 = wg_of_tile(st.tile0[s + 1] - 1, G_wg, st.n_tiles);
     for (int g = g0; g <= g1; ++g) acc += slots[(int64_t)(g + s) * C::SLOT + nat];
   }
   dw[set * P + j] = acc * inv_r[set];
@@ -818,7 +877,7 @@ SrcOff src_offsets(int T, int H, int NL) {
   int64_t pos = 0;
   int din = 5 * T;
   for (int i = 0; i <= NL; ++i) {
-    int dout = i == NL ? 2 : H;
+    const int dout = i == NL ? 2 : H;
     so.w[i] = pos;
     pos += (int64_t)dout * din;
     so.b[i] = pos;
@@ -838,15 +897,16 @@ bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out) {
   td.hidden = d.hidden;
   td.residual = d.residual;
   td.prec = d.precision;
-  bool ok = tdnn_dispatch(d.precision, d.taps, d.hidden, d.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
+  const bool ok = tdnn_dispatch(d.precision, d.taps, d.hidden, d.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
     using C = Cfg<P_, T_, H_, NL_>;
     td.kin = C::KIN;
     td.hp = C::HP;
     td.kin_p = C::KIN_P;
     td.nks1 = C::NKS1;
     td.nksh = C::NKSH;
+    td.tile = C::S;
     td.pack_bytes = C::PACK;
-    td.fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (kTile + T_) + 4 * C::NVEC;
+    td.fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (C::S + T_) + 4 * C::NVEC;
     td.dw_slot = C::SLOT;
   });
   *out = td;
@@ -861,10 +921,9 @@ bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g) {
 
 void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack,
                  hipStream_t s) {
-  SrcOff so = src_offsets(td.taps, td.hidden, td.n_hidden);
+  const SrcOff so = src_offsets(td.taps, td.hidden, td.n_hidden);
   tdnn_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
     dim3 grid(64, n_sets);
-    (void)sizeof(Cfg<P_, T_, H_, NL_>);
     k_pack<P_, T_, H_, NL_><<<grid, 256, 0, s>>>(w, w_stride, so, static_cast<char*>(pack));
   });
 }
@@ -890,10 +949,10 @@ void launch_tdnn_bwd(const TdnnDims& td, const dpd_gmp_desc& g, const StreamTabl
 
 void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
                         const float* inv_r_set, float* dw, hipStream_t s) {
-  int64_t P = (int64_t)td.hidden * (5 * td.taps) + td.hidden +
-              (int64_t)(td.n_hidden - 1) * ((int64_t)td.hidden * td.hidden + td.hidden) +
-              2 * (int64_t)td.hidden + 2;
-  int n_sets = st.per_stream ? st.n : 1;
+  const int64_t P = (int64_t)td.hidden * (5 * td.taps) + td.hidden +
+                    (int64_t)(td.n_hidden - 1) * ((int64_t)td.hidden * td.hidden + td.hidden) +
+                    2 * (int64_t)td.hidden + 2;
+  const int n_sets = st.per_stream ? st.n : 1;
   tdnn_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
     dim3 g2((unsigned)((P + 255) / 256), n_sets);
     k_dw_finalize<P_, T_, H_, NL_><<<g2, 256, 0, s>>>(st, grid, slots, inv_r_set, P, dw);
