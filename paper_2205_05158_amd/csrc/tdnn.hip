@@ -92,12 +92,17 @@ struct Cfg {
   static constexpr int MT = X::MT, KS = X::KS, NR = X::NR, LG = X::LG;
   static constexpr int S = MT * kWaves;                // samples per workgroup tile
   static constexpr int KIN = 5 * T;
-  static constexpr int KIN_P = round_up(KIN, KS);
-  static constexpr int NKS1 = KIN_P / KS;
+  // Layer-1 K order: lane group g holds the features of its own taps [g*TPG, (g+1)*TPG):
+  // element f = EPL*ks + e of its K-slices is feature f%5 of tap g*TPG + f/5 (zero when
+  // f >= 5*TPG or the tap is >= T), so each lane computes only its own taps' features.
+  static constexpr int TPG = (T + LG - 1) / LG;
+  static constexpr int FPG = 5 * TPG;
+  static constexpr int NKS1 = (FPG + X::EPL - 1) / X::EPL;
+  static constexpr int KIN_P = NKS1 * KS;
   static constexpr int HP = round_up(H, 32);
   static constexpr int NB = HP / MT;                    // row blocks of a layer
   static constexpr int NKSH = HP / KS;                  // K steps of a hidden layer
-  static constexpr int C1 = round_up(KIN_P, 32);        // dW columns of layer 1
+  static constexpr int C1 = round_up(KIN, 32);          // dW columns of layer 1
   static constexpr int NN1 = C1 / 32;
   static constexpr int NBD = HP / 32;                   // dW row blocks
   // packed parameter set (bytes)
@@ -117,8 +122,10 @@ struct Cfg {
   __host__ __device__ static constexpr int64_t dw_off(int li) {   // li = 0..NL (NL = output)
     return li == 0 ? 0 : DW_L1 + (int64_t)(li - 1) * DW_H;
   }
-  // feature index held by element e of K step ks in lane group g (layer 1)
-  __host__ __device__ static constexpr int nat_k(int ks, int g, int e) { return KS * ks + (KS / LG) * g + e; }
+  // feature index held by element e of K step ks in lane group g (layer 1), -1 for padding
+  __host__ __device__ static constexpr int feat_k(int ks, int g, int e) {
+    return (X::EPL * ks + e < FPG && g * TPG + (X::EPL * ks + e) / 5 < T) ? FPG * g + X::EPL * ks + e : -1;
+  }
   // previous-layer neuron held by element e of K step ks in lane group g (hidden layers)
   __host__ __device__ static constexpr int hid_k(int ks, int g, int e) {
     return MT * X::mb_of(ks, e) + X::row(X::j_of(ks, e), g);
@@ -197,8 +204,8 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
       for (int ee = 0; ee < EPL; ++ee) {
         float val = 0.f;
         if (sec == 0) {
-          const int k = C::nat_k(ks, g, ee);
-          if (m < H && k < C::KIN) val = ws[so.w[0] + (int64_t)m * C::KIN + k];
+          const int k = C::feat_k(ks, g, ee);
+          if (m < H && k >= 0) val = ws[so.w[0] + (int64_t)m * C::KIN + k];
         } else {
           const int kk = C::hid_k(ks, g, ee);
           const float* Wi = ws + so.w[layer - 1];             // W_i is [H][H]
@@ -261,15 +268,23 @@ __device__ __forceinline__ float value_at(const Ops<C, NKS>& ops, int mb, int j)
   return get_elem<C>(ops[C::X::ks_of(mb, j)], C::X::e_of(mb, j));
 }
 
-// Features of the lane's sample (I, Q, |x|, |x|^2, |x|^3 per tap): xw points at x[n] in
-// an LDS window (xw[-t] = x[n-t]); element e of operand ks in lane group g holds feature
-// nat_k(ks, g, e), zero beyond 5T.
+// Features (I, Q, |x|, |x|^2, |x|^3 per tap) of the lane's sample for the taps of its
+// lane group g (see Cfg::feat_k): xw points at x[n] in an LDS window (xw[-t] = x[n-t]).
 template <class C>
 __device__ __forceinline__ void make_features(const float2* xw, int g, Ops<C, C::NKS1>& feat) {
-  float f[C::KIN_P];
+  constexpr int T = C::KIN / 5, EPL = C::X::EPL;
+  float f[C::NKS1 * EPL];
+  const int tb = g * C::TPG;
 #pragma unroll
-  for (int t = 0; t < C::KIN / 5; ++t) {
-    const float2 z = xw[-t];
+  for (int t = 0; t < C::TPG; ++t) {
+    float2 z;
+    if constexpr (T % C::LG == 0) {
+      z = xw[-(tb + t)];
+    } else {
+      const bool ok = tb + t < T;
+      z = xw[-(ok ? tb + t : T - 1)];
+      z = ok ? z : make_float2(0.f, 0.f);
+    }
     const float m2 = z.x * z.x + z.y * z.y;
     const float m = sqrtf(m2);
     f[5 * t + 0] = z.x;
@@ -279,16 +294,11 @@ __device__ __forceinline__ void make_features(const float2* xw, int g, Ops<C, C:
     f[5 * t + 4] = m2 * m;
   }
 #pragma unroll
-  for (int k = C::KIN; k < C::KIN_P; ++k) f[k] = 0.f;
+  for (int k = C::FPG; k < C::NKS1 * EPL; ++k) f[k] = 0.f;
 #pragma unroll
   for (int ks = 0; ks < C::NKS1; ++ks)
 #pragma unroll
-    for (int e = 0; e < C::X::EPL; ++e) {
-      float v = f[C::nat_k(ks, 0, e)];
-#pragma unroll
-      for (int gg = 1; gg < C::LG; ++gg) v = g == gg ? f[C::nat_k(ks, gg, e)] : v;
-      set_elem<C>(feat[ks], e, v);
-    }
+    for (int e = 0; e < EPL; ++e) set_elem<C>(feat[ks], e, f[EPL * ks + e]);
 }
 
 // One row block mb of a dense layer: sum_ks A(mb, ks) B(ks); Apk is [NB][NKS][64].
@@ -432,63 +442,127 @@ struct BwdLds {
   static constexpr int QB = M + L;
   static constexpr int QW = S + 2 * QB;           // Q  [t0 - QB, t0 + S + QB)
   static constexpr int YW = S + M + 2 * L;        // gy [t0 - L, t0 + S + M + L)
-  static constexpr int LD = S + (PREC == DPD_BF16 ? 8 : 4);   // staging row stride (elements)
+  // dW staging [row][sample].  bf16 rows are 128 bytes with the 16-byte chunks of row r
+  // XOR-swizzled by (r/2) mod 8, so the 16-byte MFMA operand reads of 16 consecutive
+  // rows hit all 64 banks once; fp32 rows are padded by 4 floats instead.
+  static constexpr bool SWZ = PREC == DPD_BF16;
+  static_assert(!SWZ || S == 64, "swizzled staging assumes 8 chunks per row");
+  static constexpr int LD = SWZ ? S : S + 4;      // staging row stride (elements)
+  __device__ static int off(int row, int col) {
+    if constexpr (SWZ) return row * LD + ((((col >> 3) ^ (row >> 1)) & 7) << 3) + (col & 7);
+    else return row * LD + col;
+  }
+  // Rows of lane group g in a layer block are row(j, 0) + 4g (both geometries), so the
+  // staging element of (row MT*mb + row(j, g), column col) is
+  // (MT*mb + row(j, 0))*LD + lb[par(j)] with two lane bases; par(j) is the bit of
+  // row(j, 0) that reaches the swizzle (row(j, 0) < 4 for 16-row blocks).
+  static_assert(!SWZ || C::MT == 16, "swizzled staging pairs with 16-row layer blocks");
+  __host__ __device__ static constexpr int par(int j) { return SWZ ? (C::X::row(j, 0) >> 1) & 1 : 0; }
+  __device__ static void lane_bases(int g, int col, int (&lb)[2]) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+      lb[p] = 4 * g * LD + (SWZ ? ((((col >> 3) ^ (2 * g + p)) & 7) << 3) + (col & 7) : col);
+  }
   static constexpr int HROWS = cmax(C::C1, C::HP);
-  // union: GMP phase (coefficients, Q, g_y, reduction scratch) vs. dW staging
-  static constexpr int GMP_BYTES = (2 * G::J + QW * (M + 1) + YW) * 8 + 4 * kThreads * 4;
+  // union: GMP phase (coefficients, Q, g_y, E/R reduction scratch, g_u partial sums)
+  // vs. dW staging
+  static constexpr int GMP_BYTES = (2 * G::J + QW * (M + 1) + YW + TP * S) * 8 + 4 * kThreads * 4;
   static constexpr int STAGE_BYTES = (C::HP + HROWS) * LD * (int)sizeof(typename C::E);
   static constexpr int UNION_BYTES = cmax(GMP_BYTES, STAGE_BYTES);
-  // 32x32 dW blocks of all layers (layer 1, hidden, output), dealt round-robin over
-  // the waves: block bi is held by wave bi % kWaves in dwacc[bi / kWaves].
-  static constexpr int NBL1 = C::NBD * C::NN1, NBLH = C::NBD * C::NBD, NBLO = C::NBD;
-  static constexpr int NBT = NBL1 + (NL - 1) * NBLH + NBLO;
+  // bytes of static LDS besides the weight operands
+  static constexpr int BIAS_N = NL * C::HP + 32;  // bias-gradient accumulators
+  static constexpr int BASE_BYTES = (XW + UW) * 8 + UW * 4 + C::NVEC * 4 + BIAS_N * 4 + UNION_BYTES;
+  // forward (and, if they fit too, backward) weight operands in LDS
+  static constexpr int kLdsBudget = 160 * 1024;
+  static constexpr bool W_FWD = BASE_BYTES + C::OFF_BWDH <= kLdsBudget;
+  static constexpr bool W_BWD = BASE_BYTES + C::OFF_VEC <= kLdsBudget;
+  static constexpr int64_t W_BYTES = W_BWD ? C::OFF_VEC : (W_FWD ? C::OFF_BWDH : 16);
+  // 32x32 dW blocks of the tanh layers (layer 1, then the hidden layers), dealt
+  // round-robin over the waves: block bi is held by wave bi % kWaves in dwacc[bi / kWaves].
+  // The output layer's 2 x HP dW is one register per thread instead (2*HP <= threads).
+  static constexpr int NBL1 = C::NBD * C::NN1, NBLH = C::NBD * C::NBD;
+  static constexpr int NBT = NBL1 + (NL - 1) * NBLH;
   static constexpr int NQ = (NBT + kWaves - 1) / kWaves;
-  __host__ __device__ static constexpr int blk_off(int li) {   // li = 0..NL (NL = output)
+  static_assert(2 * C::HP <= kThreads, "one output-layer dW element per thread");
+  __host__ __device__ static constexpr int blk_off(int li) {   // li = 0..NL-1
     return li == 0 ? 0 : NBL1 + (li - 1) * NBLH;
   }
-  __host__ __device__ static constexpr int blk_cnt(int li) { return li == 0 ? NBL1 : (li == NL ? NBLO : NBLH); }
+  __host__ __device__ static constexpr int blk_cnt(int li) { return li == 0 ? NBL1 : NBLH; }
   __host__ __device__ static constexpr int blk_cols(int li) { return li == 0 ? C::NN1 : C::NBD; }
-  static constexpr int BIAS = NL * C::HP + 32;   // bias-gradient accumulators
 };
 
 // One 32x32 dW block over the tile's samples: rows mb of the delta staging against
-// rows nb of the activation staging (both [row][sample]).
-template <class C>
-__device__ __forceinline__ f32x16 dw_block(const typename C::E* dst, const typename C::E* hst, int ld,
+// rows nb of the activation staging (both [row][sample]).  All operand reads are
+// issued before the MFMAs.
+//
+// bf16 (swizzled staging): lo[ks] is the lane's element offset of its 16-byte operand
+// chunk in K step ks within a 32-row block; rowsum (when not null) receives the sum of
+// delta row 32*mb + lane%32 over the tile's samples, from the same operand registers.
+template <class C, class B>
+__device__ __forceinline__ void dw_block_bf16(const __bf16* dst, const __bf16* hst, int mb, int nb,
+                                              const int (&lo)[4], f32x16& acc, float* rowsum) {
+  static_assert(C::S == 64, "four K steps of 16 samples");
+  bf16x8 a[4], b[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    a[ks] = *reinterpret_cast<const bf16x8*>(dst + 32 * B::LD * mb + lo[ks]);
+    b[ks] = *reinterpret_cast<const bf16x8*>(hst + 32 * B::LD * nb + lo[ks]);
+  }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) acc = C::D::mma(a[ks], b[ks], acc);
+  if (rowsum) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+    float sum = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const bf16x2 pr = {a[ks][e], a[ks][e + 1]};
+        sum = __builtin_amdgcn_fdot2_f32_bf16(pr, one, sum, false);
+      }
+    *rowsum = sum + __shfl_xor(sum, 32);
+  }
+}
+
+template <class C, class B>
+__device__ __forceinline__ f32x16 dw_block(const typename C::E* dst, const typename C::E* hst,
                                            int mb, int nb, int lane, f32x16 acc) {
   using D = typename C::D;
+  constexpr int NK = C::S / D::KS;
   const int h = lane / 32, r = lane % 32;
-  const typename C::E* arow = dst + (32 * mb + r) * ld;
-  const typename C::E* brow = hst + (32 * nb + r) * ld;
+  const int ra = 32 * mb + r, rb = 32 * nb + r;
+  typename D::A a[NK], b[NK];
 #pragma unroll
-  for (int ks = 0; ks < C::S / D::KS; ++ks) {
-    typename D::A a, b;
+  for (int ks = 0; ks < NK; ++ks) {
     if constexpr (D::EPL == 8) {
-      a = *reinterpret_cast<const bf16x8*>(arow + 16 * ks + 8 * h);
-      b = *reinterpret_cast<const bf16x8*>(brow + 16 * ks + 8 * h);
+      a[ks] = *reinterpret_cast<const bf16x8*>(dst + B::off(ra, 16 * ks + 8 * h));
+      b[ks] = *reinterpret_cast<const bf16x8*>(hst + B::off(rb, 16 * ks + 8 * h));
     } else {
-      a = arow[2 * ks + h];
-      b = brow[2 * ks + h];
+      a[ks] = dst[B::off(ra, 2 * ks + h)];
+      b[ks] = hst[B::off(rb, 2 * ks + h)];
     }
-    acc = D::mma(a, b, acc);
   }
+#pragma unroll
+  for (int ks = 0; ks < NK; ++ks) acc = D::mma(a[ks], b[ks], acc);
   return acc;
 }
 
 // Sum over the tile's samples of delta row 32*mb + lane%32 (the bias gradient).
-template <class C>
-__device__ __forceinline__ float delta_row_sum(const typename C::E* dst, int ld, int mb, int lane) {
+template <class C, class B>
+__device__ __forceinline__ float delta_row_sum(const typename C::E* dst, int mb, int lane) {
   const int h = lane / 32, r = lane % 32;
-  const typename C::E* arow = dst + (32 * mb + r) * ld + h * (C::S / 2);
+  const int row = 32 * mb + r;
   float sum = 0.f;
   if constexpr (C::D::EPL == 8) {
 #pragma unroll
     for (int c = 0; c < C::S / 2; c += 8) {
-      const bf16x8 v = *reinterpret_cast<const bf16x8*>(arow + c);
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(dst + B::off(row, h * (C::S / 2) + c));
 #pragma unroll
       for (int e = 0; e < 8; ++e) sum += (float)v[e];
     }
   } else {
+    const typename C::E* arow = dst + B::off(row, h * (C::S / 2));
 #pragma unroll
     for (int c = 0; c < C::S / 2; c += 4) {
       const float4 v = *reinterpret_cast<const float4*>(arow + c);
@@ -499,16 +573,17 @@ __device__ __forceinline__ float delta_row_sum(const typename C::E* dst, int ld,
 }
 
 // Stage a layer held in operand form: value (mb, j) of lane group g goes to row
-// MT*mb + row(j, g), column col.
-template <class C, int NKS>
-__device__ __forceinline__ void stage_layer(typename C::E* stage, int ld, int col, int g,
+// MT*mb + row(j, g), column col, i.e. element (MT*mb + row(j, 0))*LD + lb[par(j)] with
+// the lane bases of BwdLds::lane_bases.
+template <class C, class B, int NKS>
+__device__ __forceinline__ void stage_layer(typename C::E* stage, const int (&lb)[2],
                                             const Ops<C, NKS>& ops) {
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
     for (int e = 0; e < C::X::EPL; ++e) {
       const int mb = C::X::mb_of(ks, e), j = C::X::j_of(ks, e);
-      stage[(C::MT * mb + C::X::row(j, g)) * ld + col] = (typename C::E)get_elem<C>(ops[ks], e);
+      stage[(C::MT * mb + C::X::row(j, 0)) * B::LD + lb[B::par(j)]] = (typename C::E)get_elem<C>(ops[ks], e);
     }
 }
 
@@ -552,24 +627,32 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   __shared__ float2 xw[B::XW];
   __shared__ float2 uw[B::UW];
   __shared__ float rw[B::UW];
-  __shared__ float2 guw[TP * S];       // g_u partial sums of the tap partitions
   __shared__ float vec[C::NVEC];
-  __shared__ float bacc[B::BIAS];
+  __shared__ float bacc[B::BIAS_N];
   __shared__ __attribute__((aligned(16))) char un[B::UNION_BYTES];
+  __shared__ __attribute__((aligned(16))) uint4 wlds[B::W_BYTES / 16];
   float2* cf = reinterpret_cast<float2*>(un);
   float2* dcf = cf + G::J;
   float2(*qw)[M + 1] = reinterpret_cast<float2(*)[M + 1]>(dcf + G::J);
   float2* gyw = reinterpret_cast<float2*>(qw + B::QW);
-  float* red = reinterpret_cast<float*>(gyw + B::YW);
+  float2* guw = gyw + B::YW;            // g_u partial sums of the tap partitions
+  float* red = reinterpret_cast<float*>(guw + TP * S);
   E* dst = reinterpret_cast<E*>(un);
   E* hst = dst + C::HP * B::LD;
 
-  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
-  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-  const int g = lane / C::MT, sl = lane % C::MT;
+  const int tid = threadIdx.x;
+  const int wave_u = __builtin_amdgcn_readfirstlane(tid / 64);
   const int g_wg = blockIdx.x, G_wg = gridDim.x;
   const int t_begin = wg_tile_start(g_wg, G_wg, st.n_tiles);
   const int t_end = wg_tile_start(g_wg + 1, G_wg, st.n_tiles);
+
+  // Lane-dependent values are re-derived at the top of every tile from an opaque copy of
+  // the thread index, so the compiler cannot precompute the hundreds of per-block LDS and
+  // global addresses outside the tile loop (they would not fit in registers).
+  int lane = tid % 64;
+  // lane offsets of the dW operand chunks (bf16 swizzled staging): row lane%32, chunk
+  // 2*ks + lane/32
+  int dlo[4] = {0, 0, 0, 0};
 
   // dW accumulators of this wave's blocks, kept in registers for the whole tile range
   // of one stream and written to its slot once.
@@ -578,14 +661,13 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   for (int q = 0; q < B::NQ; ++q)
 #pragma unroll
     for (int j = 0; j < 16; ++j) dwacc[q][j] = 0.f;
-  for (int i = tid; i < B::BIAS; i += kThreads) bacc[i] = 0.f;
+  float dwo = 0.f;   // output-layer dW element (tid / HP, tid % HP)
+  for (int i = tid; i < B::BIAS_N; i += kThreads) bacc[i] = 0.f;
 
   // Write this workgroup's partial dW of stream s (plain stores: each (workgroup,
   // stream) slot is written exactly once) and reset the accumulators.  Caller syncs.
   auto flush = [&](int s) {
     float* slot = slots + (int64_t)(g_wg + s) * C::SLOT;
-    // fresh copies of the lane and wave indices: keeps the store addresses from being
-    // precomputed outside the tile loop (they would not fit in registers)
     int ln = lane, wv = wave_u;
     asm volatile("" : "+v"(ln), "+s"(wv));
     const int h = ln / 32, r = ln % 32;
@@ -594,20 +676,22 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       const int bi = kWaves * q + wv;
       int li = -1;
 #pragma unroll
-      for (int l2 = 0; l2 <= NL; ++l2)
+      for (int l2 = 0; l2 < NL; ++l2)
         if (bi >= B::blk_off(l2) && bi < B::blk_off(l2) + B::blk_cnt(l2)) li = l2;
       if (li >= 0) {
         const int nnb = li == 0 ? C::NN1 : C::NBD;
         const int blk = bi - B::blk_off(li);
         const int mb = blk / nnb, nb = blk % nnb;
-        float* out = slot + C::dw_off(li) + (int64_t)(32 * mb) * (nnb * 32) + 32 * nb + r;
+        float* out = slot + C::dw_off(li) + (32 * mb) * (nnb * 32) + 32 * nb + r;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) out[(int64_t)C::D::row(j, h) * (nnb * 32)] = dwacc[q][j];
+        for (int j = 0; j < 16; ++j) out[C::D::row(j, h) * (nnb * 32)] = dwacc[q][j];
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j) dwacc[q][j] = 0.f;
     }
-    for (int i = tid; i < B::BIAS; i += kThreads) {
+    if (tid < 2 * C::HP) slot[C::dw_off(NL) + tid] = dwo;   // row tid / HP, column tid % HP
+    dwo = 0.f;
+    for (int i = tid; i < B::BIAS_N; i += kThreads) {
       const int li = i / C::HP, o = i % C::HP;
       float* dstb = li < NL ? slot + C::dw_off(li) + (int64_t)C::HP * (li == 0 ? C::C1 : C::HP) + o
                             : slot + C::dw_off(NL) + 32 * C::HP + (i - NL * C::HP);
@@ -623,9 +707,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     constexpr int off = B::blk_off(li), cnt = B::blk_cnt(li), nnb = B::blk_cols(li);
     constexpr int q0 = off / kWaves, q1 = (off + cnt - 1) / kWaves;
     float* bl = bacc + li * C::HP;
-    int ln = lane;
-    asm volatile("" : "+v"(ln));
-    const int h = ln / 32, r = ln % 32;
+    const int h = lane / 32, r = lane % 32;
 #pragma unroll
     for (int q = q0; q <= q1; ++q) {
       DPD_KEEP_LOADS_LOCAL();
@@ -633,10 +715,16 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       if (bi >= off && bi < off + cnt) {
         const int blk = bi - off;
         const int mb = blk / nnb, nb = blk % nnb;
-        dwacc[q] = dw_block<C>(dst, hst, B::LD, mb, nb, ln, dwacc[q]);
-        if (nb == 0) {
-          const float sum = delta_row_sum<C>(dst, B::LD, mb, ln);
-          if (h == 0) bl[32 * mb + r] += sum;
+        if constexpr (B::SWZ) {
+          float sum;
+          dw_block_bf16<C, B>(dst, hst, mb, nb, dlo, dwacc[q], nb == 0 ? &sum : nullptr);
+          if (nb == 0 && h == 0) bl[32 * mb + r] += sum;
+        } else {
+          dwacc[q] = dw_block<C, B>(dst, hst, mb, nb, lane, dwacc[q]);
+          if (nb == 0) {
+            const float sum = delta_row_sum<C, B>(dst, mb, lane);
+            if (h == 0) bl[32 * mb + r] += sum;
+          }
         }
       }
     }
@@ -650,10 +738,25 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
     const char* pk = pack + set * C::PACK;
     const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+    lane = tq % 64;
+    const int g = lane / C::MT, sl = lane % C::MT;
+    const int col = C::MT * wave_u + sl;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int r = lane % 32, c = 2 * ks + lane / 32;
+      dlo[ks] = B::SWZ ? r * B::LD + (((c ^ (r >> 1)) & 7) << 3) : 0;
+    }
 
     __syncthreads();   // previous tile finished with every LDS buffer and accumulator
     if (s != cur_stream) {
       if (cur_stream >= 0) flush(cur_stream);
+      // a new stream may bring a new parameter set: stage its weight operands
+      if constexpr (B::W_FWD) {
+        const uint4* wsrc = reinterpret_cast<const uint4*>(pk);
+        for (int i = tid; i < (int)(B::W_BYTES / 16); i += kThreads) wlds[i] = wsrc[i];
+      }
       cur_stream = s;
     }
     for (int j = tid; j < G::J; j += kThreads) {
@@ -678,7 +781,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     }
     __syncthreads();
     // ---- GMP: Q_l(p) on the Q window; thread group `part` takes one partition of the taps
-    const int part = tid / S, pi = tid % S;
+    const int part = tq / S, pi = tq % S;
     for (int i = pi; i < B::QW; i += S) {
       DPD_KEEP_LOADS_LOCAL();
       for_partition<M, TP>(part, [&](auto l0c, auto l1c) {
@@ -741,32 +844,62 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
           gu = gmp_grad<K, M, L, L0, L1>(&uw[pi + B::UB], &rw[pi + B::UB], &gyw[pi + L], Qm, cf, dcf);
         });
       }
-      guw[tid] = gu;
+      guw[tq] = gu;
     }
-    __syncthreads();   // g_u ready; the GMP part of the union is free from here on
-
-    // ---- TDNN: recompute this wave's samples, then the reverse mode
-    const int col = C::MT * wave + sl;
-    Ops<C, C::NKSH> hb[NL];
-    (void)mlp_forward<C, NL>(reinterpret_cast<const A*>(pk + C::OFF_FWD1), vec, lane, g,
-                             &xw[col + B::XB], hb);
+    __syncthreads();   // g_u partial sums ready
     float2 gsum = make_float2(0.f, 0.f);
 #pragma unroll
     for (int p = 0; p < TP; ++p) {
       gsum.x += guw[p * S + col].x;
       gsum.y += guw[p * S + col].y;
     }
-    // output layer: delta_o = (Re g_u, Im g_u) in rows 0, 1 of a 32-row block
-#pragma unroll
-    for (int sb = 0; sb < 32 / C::MT; ++sb)
-#pragma unroll
-      for (int j = 0; j < C::NR; ++j) {
-        const int row = C::MT * sb + X::row(j, g);
-        dst[row * B::LD + col] = (E)(row == 0 ? gsum.x : (row == 1 ? gsum.y : 0.f));
-      }
-    stage_layer<C, C::NKSH>(hst, B::LD, col, g, hb[NL - 1]);
+    __syncthreads();   // the GMP part of the union is free from here on
+
+    // ---- TDNN: recompute this wave's samples, then the reverse mode
+    const A* wfwd = B::W_FWD ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
+    const A* wbwd = B::W_BWD ? reinterpret_cast<const A*>(wlds) + C::OFF_BWDH / sizeof(A)
+                             : reinterpret_cast<const A*>(pk + C::OFF_BWDH);
+    Ops<C, C::NKSH> hb[NL];
+    (void)mlp_forward<C, NL>(wfwd, vec, lane, g, &xw[col + B::XB], hb);
+    int lb[2];
+    B::lane_bases(g, col, lb);
+    // output layer: delta_o = (Re g_u, Im g_u) in staging rows 0 and 1
+    if (g == 0) {
+      dst[B::off(0, col)] = (E)gsum.x;
+      dst[B::off(1, col)] = (E)gsum.y;
+    }
+    stage_layer<C, B, C::NKSH>(hst, lb, hb[NL - 1]);
     __syncthreads();
-    accumulate(std::integral_constant<int, NL>{});
+    // output-layer dW element (c, n) += sum_s delta_o[c][s] h_NL[n][s]; bias by n == 0
+    if (tid < 2 * C::HP) {
+      const int c = tid / C::HP, n = tid % C::HP;
+      float acc = 0.f, bsum = 0.f;
+      if constexpr (B::SWZ) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+#pragma unroll
+        for (int k = 0; k < S / 8; ++k) {
+          const bf16x8 da = *reinterpret_cast<const bf16x8*>(dst + B::off(c, 8 * k));
+          const bf16x8 hv = *reinterpret_cast<const bf16x8*>(hst + B::off(n, 8 * k));
+#pragma unroll
+          for (int e = 0; e < 8; e += 2) {
+            const bf16x2 p = {da[e], da[e + 1]}, q2 = {hv[e], hv[e + 1]};
+            acc = __builtin_amdgcn_fdot2_f32_bf16(p, q2, acc, false);
+            bsum = __builtin_amdgcn_fdot2_f32_bf16(p, one, bsum, false);
+          }
+        }
+      } else {
+#pragma unroll 2
+        for (int k = 0; k < S; k += 4) {
+          const float4 da = *reinterpret_cast<const float4*>(dst + B::off(c, k));
+          const float4 hv = *reinterpret_cast<const float4*>(hst + B::off(n, k));
+          acc = fmaf(da.x, hv.x, fmaf(da.y, hv.y, fmaf(da.z, hv.z, fmaf(da.w, hv.w, acc))));
+          bsum += (da.x + da.y) + (da.z + da.w);
+        }
+      }
+      dwo += acc;
+      if (n == 0) bacc[NL * C::HP + c] += bsum;
+    }
     // delta_NL = (Wo^T delta_o) * (1 - h_NL^2)
     Ops<C, C::NKSH> db;
     {
@@ -784,25 +917,29 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     auto layer = [&](auto i_c) {       // hidden layer i: delta_i in db, input h_{i-1}
       constexpr int i = decltype(i_c)::value;
       __syncthreads();                 // staging free
-      stage_layer<C, C::NKSH>(dst, B::LD, col, g, db);
+      stage_layer<C, B, C::NKSH>(dst, lb, db);
       if constexpr (i >= 2) {
-        stage_layer<C, C::NKSH>(hst, B::LD, col, g, hb[i - 2]);
+        stage_layer<C, B, C::NKSH>(hst, lb, hb[i - 2]);
       } else {
+        // features at their natural rows: lane group g holds rows [g*FPG, g*FPG + FPG)
         Ops<C, C::NKS1> feat;
         make_features<C>(&xw[col + B::XB], g, feat);
 #pragma unroll
         for (int ks = 0; ks < C::NKS1; ++ks)
 #pragma unroll
-          for (int e = 0; e < X::EPL; ++e)
-            hst[C::nat_k(ks, g, e) * B::LD + col] = (E)get_elem<C>(feat[ks], e);
+          for (int e = 0; e < X::EPL; ++e) {
+            const int f = X::EPL * ks + e;
+            const int k = C::FPG * g + f;
+            if (f < C::FPG && k < C::KIN) hst[B::off(k, col)] = (E)get_elem<C>(feat[ks], e);
+          }
 #pragma unroll
-        for (int k = C::KIN_P; k < C::C1; ++k)
-          if (k % C::LG == g) hst[k * B::LD + col] = (E)0.f;
+        for (int k = C::KIN; k < C::C1; ++k)
+          if (k % C::LG == g) hst[B::off(k, col)] = (E)0.f;
       }
       // delta_{i-1} = (W_i^T delta_i) * (1 - h_{i-1}^2) while the staging settles
       Ops<C, C::NKSH> dn;
       if constexpr (i >= 2) {
-        const A* Ab = reinterpret_cast<const A*>(pk + C::OFF_BWDH) + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
+        const A* Ab = wbwd + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
 #pragma unroll
         for (int mb = 0; mb < C::NB; ++mb) {
           DPD_KEEP_LOADS_LOCAL();
