@@ -182,7 +182,8 @@ def main():
     gf = F.gmp_train_flops(wl.K, wl.M, wl.L)
     mma_peak = PEAK["mfma_bf16_tflops"] if prec == "bf16" else PEAK["mfma_fp32_tflops"]
     per_kernel = {
-        "tdnn_bwd": {"mma": tf["bwd_mma"], "alu": tf["bwd_out"] + gf["total"]},
+        "tdnn_bwd": {"mma": tf["bwd_mma"], "alu": tf["bwd_out"]},
+        "gmp_bwd": {"mma": 0, "alu": gf["total"]},
         "tdnn_fwd": {"mma": tf["fwd_mma"], "alu": tf["out"]},
         "plain_backward": {"mma": 0, "alu": tf["bwd_mma"] + tf["bwd_out"] + gf["bwd"]},
         "plain_forward": {"mma": 0, "alu": tf["fwd_mma"] + tf["out"]},

@@ -163,6 +163,7 @@ Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
     tdnn_dims(*d, &td);
     w.pack = take((size_t)td.pack_bytes * p.n_sets);
     w.slots = take(sizeof(float) * (size_t)td.dw_slot * (kMaxGrid + p.S));
+    w.gu_buf = take(sizeof(float2) * p.n_total);
   }
   w.total = pos;
   return w;
@@ -455,11 +456,14 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   int fgrid = std::min(tab.n_tiles, fwd_grid(td));
   { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, ubuf, fgrid, stream); }
   if (dw) {
-    // the fused kernel also writes y for its tiles
+    // GMP forward + reverse mode (y, E/R tile partials, g_u), then the TDNN reverse mode
+    StreamTable gt = make_table(p, gmp_bwd_tile());
+    float* gub = at<float>(workspace, L.gu_buf);
+    { DPD_PROF("gmp_bwd"); launch_gmp_bwd(*gmp, gt, x, ubuf, coef, g_re, g_im, part, gub, y, stream); }
     int grid = std::min(tab.n_tiles, std::min(kMaxGrid, 2 * device_cus()));
     float* slots = at<float>(workspace, L.slots);
-    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, *gmp, tab, x, ubuf, coef, g_re, g_im, pack, part, slots, y, grid, stream); }
-    { DPD_PROF("nmse_final"); launch_nmse_final(tab, part, nmse, lossp, inv_r, stream); }
+    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, stream); }
+    { DPD_PROF("nmse_final"); launch_nmse_final(gt, part, nmse, lossp, inv_r, stream); }
     { DPD_PROF("dw_finalize"); launch_dw_finalize(td, tab, grid, slots, inv_r, dw, stream); }
   } else {
     float* ybuf = y ? y : at<float>(workspace, L.y_buf);

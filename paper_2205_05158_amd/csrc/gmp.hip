@@ -62,7 +62,127 @@ __global__ __launch_bounds__(kGmpThreads) void k_gmp_fwd(StreamTable st, const f
   }
 }
 
+// GMP forward and reverse mode over tiles of kGmpBwdTile samples, one workgroup per tile
+// (no persistent state, so it runs at the occupancy its registers allow):
+//   y = GMP(u) (stored when y_out is not null), g_y = 2 (y - G x) inside the stream,
+//   the tile's E = sum |y - G x|^2 and R = sum |G x|^2 (fixed reduction tree), and
+//   g_u[m] = dL/du[m] of L = sum |y - G x|^2 (the gather form in gmp.hpp).
+constexpr int kGmpBwdThreads = 256;
+
+template <int K, int M, int L>
+__global__ __launch_bounds__(kGmpBwdThreads) void k_gmp_bwd(StreamTable st, const float* __restrict__ x,
+                                                            const float* __restrict__ u,
+                                                            const float* __restrict__ coef, float g_re,
+                                                            float g_im, float2* __restrict__ tile_part,
+                                                            float* __restrict__ gu_out,
+                                                            float* __restrict__ y_out) {
+  using G = Gmp<K, M, L>;
+  constexpr int S = kGmpBwdThreads;     // samples per tile (st.tile == S)
+  constexpr int UB = M + 2 * L;
+  constexpr int UW = S + 2 * UB;        // u  [t0 - UB, t0 + S + UB)
+  constexpr int QB = M + L;
+  constexpr int QW = S + 2 * QB;        // Q  [t0 - QB, t0 + S + QB)
+  constexpr int YW = S + M + 2 * L;     // gy [t0 - L, t0 + S + M + L), also the x window
+  __shared__ float2 cf[G::J];
+  __shared__ float2 dcf[G::J];
+  __shared__ float2 uw[UW];
+  __shared__ float rw[UW];
+  __shared__ float2 xw[YW];
+  __shared__ float2 qw[QW][M + 1];
+  __shared__ float2 gyw[YW];
+  __shared__ float red[4 * S];
+
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x;
+  const int s = stream_of_tile(st, t);
+  const int64_t lo = st.off[s], hi = st.off[s + 1];
+  const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
+  const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
+  for (int j = tid; j < G::J; j += S) {
+    const float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
+    cf[j] = c;
+    const float k = (float)G::order(j);
+    dcf[j] = make_float2(k * c.x, k * c.y);
+  }
+  for (int i = tid; i < UW; i += S) {
+    const int64_t p = t0 - UB + i;
+    const float2 v = (p >= lo && p < hi) ? ld2(u, p) : make_float2(0.f, 0.f);
+    uw[i] = v;
+    rw[i] = sqrtf(v.x * v.x + v.y * v.y);
+  }
+  for (int i = tid; i < YW; i += S) {
+    const int64_t p = t0 - L + i;
+    xw[i] = (p >= lo && p < hi) ? ld2(x, p) : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  // Q_l(p) for every position of the Q window (qw[i] is position t0 - QB + i)
+  for (int i = tid; i < QW; i += S) {
+    DPD_KEEP_LOADS_LOCAL();
+    float2 Q[M + 1];
+    gmp_q<K, M, L>(&rw[i + L], cf, Q);
+#pragma unroll
+    for (int l = 0; l <= M; ++l) qw[i][l] = Q[l];
+  }
+  __syncthreads();
+  // y and g_y on [t0 - L, t0 + S + M + L); E and R on the tile's own samples
+  Comp Ec, Rc;
+  for (int i = tid; i < YW; i += S) {
+    const int64_t n = t0 - L + i;
+    float2 gyv = make_float2(0.f, 0.f);
+    if (n >= lo && n < hi) {
+      float2 y = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int l = 0; l <= M; ++l) {
+        const float2 v = cmul(uw[i + M + L - l], qw[i + M - l][l]);
+        y.x += v.x;
+        y.y += v.y;
+      }
+      const float2 xv = xw[i];
+      const float tr = g_re * xv.x - g_im * xv.y, ti = g_re * xv.y + g_im * xv.x;
+      const float er = y.x - tr, ei = y.y - ti;
+      gyv = make_float2(2.f * er, 2.f * ei);
+      if (i >= L && i < L + S) {
+        Ec.add(er * er + ei * ei);
+        Rc.add(tr * tr + ti * ti);
+        if (y_out) st2(y_out, n, y);
+      }
+    }
+    gyw[i] = gyv;
+  }
+  red[tid] = Ec.s; red[S + tid] = Ec.c; red[2 * S + tid] = Rc.s; red[3 * S + tid] = Rc.c;
+  __syncthreads();
+  for (int w2 = S / 2; w2 > 0; w2 >>= 1) {
+    if (tid < w2) {
+      Comp a{red[tid], red[S + tid]}, b{red[2 * S + tid], red[3 * S + tid]};
+      a.add(red[tid + w2]); a.add(red[S + tid + w2]);
+      b.add(red[2 * S + tid + w2]); b.add(red[3 * S + tid + w2]);
+      red[tid] = a.s; red[S + tid] = a.c; red[2 * S + tid] = b.s; red[3 * S + tid] = b.c;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) tile_part[t] = make_float2(red[0] + red[S], red[2 * S] + red[3 * S]);
+  // g_u at the tile's own samples
+  const int64_t m = t0 + tid;
+  if (m < hi) {
+    float2 Qm[M + 1];
+#pragma unroll
+    for (int l = 0; l <= M; ++l) Qm[l] = qw[tid + QB][l];
+    const float2 gu = gmp_grad<K, M, L>(&uw[tid + UB], &rw[tid + UB], &gyw[tid + L], Qm, cf, dcf);
+    st2(gu_out, m, gu);
+  }
+}
+
 }  // namespace
+
+void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
+                    const float* coef, float g_re, float g_im, float2* tile_part, float* gu,
+                    float* y, hipStream_t s) {
+  gmp_dispatch(g.K, g.M, g.L, [&]<int K, int M, int L>() {
+    k_gmp_bwd<K, M, L><<<st.n_tiles, kGmpBwdThreads, 0, s>>>(st, x, u, coef, g_re, g_im, tile_part, gu, y);
+  });
+}
+
+int gmp_bwd_tile() { return kGmpBwdThreads; }
 
 void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,
                     float* y, hipStream_t s) {

@@ -68,11 +68,15 @@ void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, 
 // GMP forward over the table's tiles.
 void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,
                     float* y, hipStream_t s);
-// Fused GMP forward/backward + TDNN recompute/backward, dW partial slots and E/R tile partials.
-void launch_tdnn_bwd(const TdnnDims& td, const dpd_gmp_desc& g, const StreamTable& st,
-                     const float* x, const float* u, const float* coef, float g_re, float g_im,
-                     const void* pack, float2* tile_part, float* slots, float* y, int grid,
-                     hipStream_t s);
+// GMP forward + reverse mode over tiles of gmp_bwd_tile() samples: y (optional), E/R
+// tile partials and g_u = dL/du.  Supported (K, M, L) are those of gmp_dispatch.
+int gmp_bwd_tile();
+void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
+                    const float* coef, float g_re, float g_im, float2* tile_part, float* gu,
+                    float* y, hipStream_t s);
+// TDNN recompute + reverse mode from g_u: dW partial slots per (workgroup, stream).
+void launch_tdnn_bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu,
+                     const void* pack, float* slots, int grid, hipStream_t s);
 void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
                         const float* inv_r_set, float* dw, hipStream_t s);
 

@@ -1,6 +1,7 @@
 // Tuned TDNN DPD kernels for gfx950: the dense layers of the tapped-delay-line
-// network (Sec. III-C core, eq. (8) slot) on MFMA, plus the fused
-// direct-learning backward (Sec. V-A-2) through the GMP PA (eq. (9)).
+// network (Sec. III-C core, eq. (8) slot) on MFMA, and its reverse mode for direct
+// learning (Sec. V-A-2) from the PA-input gradient g_u that the GMP backward kernel
+// (eq. (9), gmp.hip) produces.
 //
 // Formulation.  A layer h_i = tanh(W_i h_{i-1} + b_i) over a wave's block of samples
 // is computed transposed, h_i^T = W_i h_{i-1}^T: weights are the MFMA A operand
@@ -143,24 +144,6 @@ bool tdnn_dispatch(int prec, int T, int H, int NL, F&& f) {
   DPD_CASE(DPD_BF16, 4, 20, 2)
   DPD_CASE(DPD_BF16, 10, 64, 3)
   DPD_CASE(DPD_BF16, 16, 128, 4)
-#undef DPD_CASE
-  return false;
-}
-
-// (TDNN, GMP) pairs the fused backward kernel is built for.
-template <class F>
-bool bwd_dispatch(int prec, int T, int H, int NL, int K, int M, int L, F&& f) {
-#define DPD_CASE(P_, T_, H_, NL_, K_, M_, L_)                                                  \
-  if (prec == P_ && T == T_ && H == H_ && NL == NL_ && K == K_ && M == M_ && L == L_) {         \
-    f.template operator()<P_, T_, H_, NL_, K_, M_, L_>();                                      \
-    return true;                                                                               \
-  }
-  DPD_CASE(DPD_FP32, 4, 20, 2, 5, 3, 2)
-  DPD_CASE(DPD_FP32, 10, 64, 3, 7, 5, 3)
-  DPD_CASE(DPD_FP32, 16, 128, 4, 9, 7, 4)
-  DPD_CASE(DPD_BF16, 4, 20, 2, 5, 3, 2)
-  DPD_CASE(DPD_BF16, 10, 64, 3, 7, 5, 3)
-  DPD_CASE(DPD_BF16, 16, 128, 4, 9, 7, 4)
 #undef DPD_CASE
   return false;
 }
@@ -429,19 +412,12 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const flo
 }
 
 // ------------------------------------------------------------------ backward kernel
-template <int PREC, int T, int H, int NL, int K, int M, int L>
+template <int PREC, int T, int H, int NL>
 struct BwdLds {
   using C = Cfg<PREC, T, H, NL>;
-  using G = Gmp<K, M, L>;
   static constexpr int S = C::S;
-  static constexpr int TP = kThreads / S;         // tap partitions of the GMP work
-  static constexpr int XB = cmax(T - 1, L);
-  static constexpr int XW = S + XB + M + L;       // x  [t0 - XB, t0 + S + M + L)
-  static constexpr int UB = M + 2 * L;
-  static constexpr int UW = S + 2 * UB;           // u  [t0 - UB, t0 + S + UB)
-  static constexpr int QB = M + L;
-  static constexpr int QW = S + 2 * QB;           // Q  [t0 - QB, t0 + S + QB)
-  static constexpr int YW = S + M + 2 * L;        // gy [t0 - L, t0 + S + M + L)
+  static constexpr int XB = T - 1;
+  static constexpr int XW = S + XB;               // x  [t0 - XB, t0 + S)
   // dW staging [row][sample].  bf16 rows are 128 bytes with the 16-byte chunks of row r
   // XOR-swizzled by (r/2) mod 8, so the 16-byte MFMA operand reads of 16 consecutive
   // rows hit all 64 banks once; fp32 rows are padded by 4 floats instead.
@@ -464,14 +440,10 @@ struct BwdLds {
       lb[p] = 4 * g * LD + (SWZ ? ((((col >> 3) ^ (2 * g + p)) & 7) << 3) + (col & 7) : col);
   }
   static constexpr int HROWS = cmax(C::C1, C::HP);
-  // union: GMP phase (coefficients, Q, g_y, E/R reduction scratch, g_u partial sums)
-  // vs. dW staging
-  static constexpr int GMP_BYTES = (2 * G::J + QW * (M + 1) + YW + TP * S) * 8 + 4 * kThreads * 4;
   static constexpr int STAGE_BYTES = (C::HP + HROWS) * LD * (int)sizeof(typename C::E);
-  static constexpr int UNION_BYTES = cmax(GMP_BYTES, STAGE_BYTES);
   // bytes of static LDS besides the weight operands
   static constexpr int BIAS_N = NL * C::HP + 32;  // bias-gradient accumulators
-  static constexpr int BASE_BYTES = (XW + UW) * 8 + UW * 4 + C::NVEC * 4 + BIAS_N * 4 + UNION_BYTES;
+  static constexpr int BASE_BYTES = XW * 8 + C::NVEC * 4 + BIAS_N * 4 + STAGE_BYTES;
   // forward (and, if they fit too, backward) weight operands in LDS
   static constexpr int kLdsBudget = 160 * 1024;
   static constexpr bool W_FWD = BASE_BYTES + C::OFF_BWDH <= kLdsBudget;
@@ -587,56 +559,26 @@ __device__ __forceinline__ void stage_layer(typename C::E* stage, const int (&lb
     }
 }
 
-// Runs fq(L0, L1) with the compile-time tap range [L0, L1) of partition p out of TP.
-template <int M, int TP, class FQ>
-__device__ __forceinline__ void for_partition(int p, FQ&& fq) {
-  static_assert(TP == 1 || TP == 2 || TP == 4, "tap partitions");
-  auto run = [&](auto pc) {
-    constexpr int P = decltype(pc)::value;
-    fq(std::integral_constant<int, (M + 1) * P / TP>{}, std::integral_constant<int, (M + 1) * (P + 1) / TP>{});
-  };
-  if constexpr (TP == 1) {
-    run(std::integral_constant<int, 0>{});
-  } else if constexpr (TP == 2) {
-    if (p == 0) run(std::integral_constant<int, 0>{});
-    else run(std::integral_constant<int, 1>{});
-  } else {
-    if (p == 0) run(std::integral_constant<int, 0>{});
-    else if (p == 1) run(std::integral_constant<int, 1>{});
-    else if (p == 2) run(std::integral_constant<int, 2>{});
-    else run(std::integral_constant<int, 3>{});
-  }
-}
-
-template <int PREC, int T, int H, int NL, int K, int M, int L>
+// Reverse mode of the TDNN over the stream table's tiles, from g_u (= dL/du per sample,
+// zero-extended outside the streams): each workgroup owns a contiguous tile range,
+// recomputes the forward pass of its samples, runs the delta chain and accumulates
+// dW over its tiles in registers; one slot per (workgroup, stream) is written.
+template <int PREC, int T, int H, int NL>
 __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const float* __restrict__ x,
-                                                       const float* __restrict__ u,
-                                                       const float* __restrict__ coef, float g_re,
-                                                       float g_im, const char* __restrict__ pack,
-                                                       float2* __restrict__ tile_part,
-                                                       float* __restrict__ slots,
-                                                       float* __restrict__ y_out) {
+                                                       const float* __restrict__ gu,
+                                                       const char* __restrict__ pack,
+                                                       float* __restrict__ slots) {
   using C = Cfg<PREC, T, H, NL>;
   using X = typename C::X;
-  using G = Gmp<K, M, L>;
-  using B = BwdLds<PREC, T, H, NL, K, M, L>;
+  using B = BwdLds<PREC, T, H, NL>;
   using E = typename C::E;
   using A = typename C::A;
   constexpr int S = C::S;
-  constexpr int TP = B::TP;
   __shared__ float2 xw[B::XW];
-  __shared__ float2 uw[B::UW];
-  __shared__ float rw[B::UW];
   __shared__ float vec[C::NVEC];
   __shared__ float bacc[B::BIAS_N];
-  __shared__ __attribute__((aligned(16))) char un[B::UNION_BYTES];
+  __shared__ __attribute__((aligned(16))) char un[B::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint4 wlds[B::W_BYTES / 16];
-  float2* cf = reinterpret_cast<float2*>(un);
-  float2* dcf = cf + G::J;
-  float2(*qw)[M + 1] = reinterpret_cast<float2(*)[M + 1]>(dcf + G::J);
-  float2* gyw = reinterpret_cast<float2*>(qw + B::QW);
-  float2* guw = gyw + B::YW;            // g_u partial sums of the tap partitions
-  float* red = reinterpret_cast<float*>(guw + TP * S);
   E* dst = reinterpret_cast<E*>(un);
   E* hst = dst + C::HP * B::LD;
 
@@ -737,7 +679,6 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const int64_t lo = st.off[s], hi = st.off[s + 1];
     const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
     const char* pk = pack + set * C::PACK;
-    const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
     int tq = tid;
     asm volatile("" : "+v"(tq));
     lane = tq % 64;
@@ -752,108 +693,22 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     __syncthreads();   // previous tile finished with every LDS buffer and accumulator
     if (s != cur_stream) {
       if (cur_stream >= 0) flush(cur_stream);
-      // a new stream may bring a new parameter set: stage its weight operands
+      // a new stream may bring a new parameter set: stage its vector block and weights
+      const float* src = reinterpret_cast<const float*>(pk + C::OFF_VEC);
+      for (int i = tid; i < C::NVEC; i += kThreads) vec[i] = src[i];
       if constexpr (B::W_FWD) {
         const uint4* wsrc = reinterpret_cast<const uint4*>(pk);
         for (int i = tid; i < (int)(B::W_BYTES / 16); i += kThreads) wlds[i] = wsrc[i];
       }
       cur_stream = s;
     }
-    for (int j = tid; j < G::J; j += kThreads) {
-      const float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
-      cf[j] = c;
-      const float k = (float)G::order(j);
-      dcf[j] = make_float2(k * c.x, k * c.y);
-    }
-    {
-      const float* src = reinterpret_cast<const float*>(pk + C::OFF_VEC);
-      for (int i = tid; i < C::NVEC; i += kThreads) vec[i] = src[i];
-    }
     for (int i = tid; i < B::XW; i += kThreads) {
       const int64_t p = t0 - B::XB + i;
       xw[i] = (p >= lo && p < hi) ? ld2(x, p) : make_float2(0.f, 0.f);
     }
-    for (int i = tid; i < B::UW; i += kThreads) {
-      const int64_t p = t0 - B::UB + i;
-      const float2 v = (p >= lo && p < hi) ? ld2(u, p) : make_float2(0.f, 0.f);
-      uw[i] = v;
-      rw[i] = sqrtf(v.x * v.x + v.y * v.y);
-    }
+    const int64_t n = t0 + col;
+    const float2 gsum = n < hi ? ld2(gu, n) : make_float2(0.f, 0.f);
     __syncthreads();
-    // ---- GMP: Q_l(p) on the Q window; thread group `part` takes one partition of the taps
-    const int part = tq / S, pi = tq % S;
-    for (int i = pi; i < B::QW; i += S) {
-      DPD_KEEP_LOADS_LOCAL();
-      for_partition<M, TP>(part, [&](auto l0c, auto l1c) {
-        constexpr int L0 = decltype(l0c)::value, L1 = decltype(l1c)::value;
-        float2 Q[M + 1];
-        gmp_q<K, M, L, L0, L1>(&rw[i + L], cf, Q);
-#pragma unroll
-        for (int l = L0; l < L1; ++l) qw[i][l] = Q[l];
-      });
-    }
-    __syncthreads();
-    // ---- y, g_y = 2(y - Gx) (zero outside the stream), E and R on the tile
-    Comp Ec, Rc;
-    for (int i = tid; i < B::YW; i += kThreads) {
-      const int64_t n = t0 - L + i;
-      float2 gyv = make_float2(0.f, 0.f);
-      if (n >= lo && n < hi) {
-        float2 y = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int l = 0; l <= M; ++l) {
-          const float2 v = cmul(uw[i + M + L - l], qw[i + M - l][l]);
-          y.x += v.x;
-          y.y += v.y;
-        }
-        const float2 xv = xw[i - L + B::XB];
-        const float tr = g_re * xv.x - g_im * xv.y, ti = g_re * xv.y + g_im * xv.x;
-        const float er = y.x - tr, ei = y.y - ti;
-        gyv = make_float2(2.f * er, 2.f * ei);
-        if (i >= L && i < L + S) {
-          Ec.add(er * er + ei * ei);
-          Rc.add(tr * tr + ti * ti);
-          if (y_out) st2(y_out, n, y);
-        }
-      }
-      gyw[i] = gyv;
-    }
-    // E/R tile partial (fixed tree)
-    red[tid] = Ec.s; red[kThreads + tid] = Ec.c; red[2 * kThreads + tid] = Rc.s; red[3 * kThreads + tid] = Rc.c;
-    __syncthreads();
-    for (int w2 = kThreads / 2; w2 > 0; w2 >>= 1) {
-      if (tid < w2) {
-        Comp a{red[tid], red[kThreads + tid]}, b{red[2 * kThreads + tid], red[3 * kThreads + tid]};
-        a.add(red[tid + w2]); a.add(red[kThreads + tid + w2]);
-        b.add(red[2 * kThreads + tid + w2]); b.add(red[3 * kThreads + tid + w2]);
-        red[tid] = a.s; red[kThreads + tid] = a.c; red[2 * kThreads + tid] = b.s; red[3 * kThreads + tid] = b.c;
-      }
-      __syncthreads();
-    }
-    if (tid == 0) tile_part[t] = make_float2(red[0] + red[kThreads], red[2 * kThreads] + red[3 * kThreads]);
-    // ---- g_u on the tile: one partial sum per tap partition
-    {
-      const int64_t m = t0 + pi;
-      float2 gu = make_float2(0.f, 0.f);
-      if (m < hi) {
-        for_partition<M, TP>(part, [&](auto l0c, auto l1c) {
-          constexpr int L0 = decltype(l0c)::value, L1 = decltype(l1c)::value;
-          float2 Qm[M + 1];
-#pragma unroll
-          for (int l = L0; l < L1; ++l) Qm[l] = qw[pi + B::QB][l];
-          gu = gmp_grad<K, M, L, L0, L1>(&uw[pi + B::UB], &rw[pi + B::UB], &gyw[pi + L], Qm, cf, dcf);
-        });
-      }
-      guw[tq] = gu;
-    }
-    __syncthreads();   // g_u partial sums ready
-    float2 gsum = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int p = 0; p < TP; ++p) {
-      gsum.x += guw[p * S + col].x;
-      gsum.y += guw[p * S + col].y;
-    }
-    __syncthreads();   // the GMP part of the union is free from here on
 
     // ---- TDNN: recompute this wave's samples, then the reverse mode
     const A* wfwd = B::W_FWD ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
@@ -1051,9 +906,9 @@ bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out) {
 }
 
 bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g) {
-  if (!g) return tdnn_dispatch(d.precision, d.taps, d.hidden, d.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {});
-  return bwd_dispatch(d.precision, d.taps, d.hidden, d.n_hidden, g->K, g->M, g->L,
-                      [&]<int P_, int T_, int H_, int NL_, int K_, int M_, int L_>() {});
+  if (!tdnn_dispatch(d.precision, d.taps, d.hidden, d.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {}))
+    return false;
+  return !g || gmp_dispatch(g->K, g->M, g->L, [&]<int K_, int M_, int L_>() {});
 }
 
 void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack,
@@ -1073,15 +928,11 @@ void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, 
   });
 }
 
-void launch_tdnn_bwd(const TdnnDims& td, const dpd_gmp_desc& g, const StreamTable& st,
-                     const float* x, const float* u, const float* coef, float g_re, float g_im,
-                     const void* pack, float2* tile_part, float* slots, float* y, int grid,
-                     hipStream_t s) {
-  bwd_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, g.K, g.M, g.L,
-               [&]<int P_, int T_, int H_, int NL_, int K_, int M_, int L_>() {
-                 k_tdnn_bwd<P_, T_, H_, NL_, K_, M_, L_><<<grid, kThreads, 0, s>>>(
-                     st, x, u, coef, g_re, g_im, static_cast<const char*>(pack), tile_part, slots, y);
-               });
+void launch_tdnn_bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu,
+                     const void* pack, float* slots, int grid, hipStream_t s) {
+  tdnn_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
+    k_tdnn_bwd<P_, T_, H_, NL_><<<grid, kThreads, 0, s>>>(st, x, gu, static_cast<const char*>(pack), slots);
+  });
 }
 
 void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
