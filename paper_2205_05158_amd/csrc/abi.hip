@@ -125,7 +125,7 @@ int device_cus() {
 // Persistent forward grid: as many workgroups as fit at once (the weights of one
 // parameter set occupy most of a CU's LDS for the largest models).
 int fwd_grid(const TdnnDims& td) {
-  int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / (td.fwd_lds + 1024)));
+  int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024) / (td.fwd_lds + 1024)));
   return per_cu * device_cus();
 }
 
@@ -370,7 +370,7 @@ dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const 
     tdnn_dims(*tdnn, &td);
     void* pack = at<void>(workspace, L.pack);
     { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
-    StreamTable tab = make_table(p, td.tile);
+    StreamTable tab = make_table(p, td.fwd_tile);
     int grid = std::min(tab.n_tiles, fwd_grid(td));
     { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, grid, stream); }
   }
@@ -452,9 +452,10 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   tdnn_dims(*tdnn, &td);
   void* pack = at<void>(workspace, L.pack);
   { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, P, pack, stream); }
+  StreamTable ftab = make_table(p, td.fwd_tile);
+  int fgrid = std::min(ftab.n_tiles, fwd_grid(td));
+  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fgrid, stream); }
   StreamTable tab = make_table(p, td.tile);
-  int fgrid = std::min(tab.n_tiles, fwd_grid(td));
-  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, ubuf, fgrid, stream); }
   if (dw) {
     // GMP forward + reverse mode (y, E/R tile partials, g_u), then the TDNN reverse mode
     StreamTable gt = make_table(p, gmp_bwd_tile());

@@ -47,7 +47,8 @@ struct TdnnDims {
   int kin_p;        // kin padded to the MFMA K step
   int nks1;         // MFMA K steps of layer 1
   int nksh;         // MFMA K steps of a hidden layer
-  int tile;         // samples per workgroup tile of the tuned kernels
+  int tile;         // samples per workgroup tile of the tuned backward kernel
+  int fwd_tile;     // samples per workgroup tile of the tuned forward kernel
   int64_t pack_bytes;  // bytes of one packed parameter set
   int64_t fwd_lds;     // LDS bytes of the forward kernel
   // packed offsets (bytes) inside one set

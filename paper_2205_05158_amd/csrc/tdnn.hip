@@ -31,8 +31,10 @@ namespace dpdmi {
 
 namespace {
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 4;               // backward kernel: one wave per SIMD
 constexpr int kThreads = 64 * kWaves;
+constexpr int kFwdWaves = 8;            // forward kernel: two waves per SIMD share the LDS weights
+constexpr int kFwdThreads = 64 * kFwdWaves;
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -299,6 +301,48 @@ __device__ __forceinline__ typename C::X::Acc dense_block(const typename C::A* _
   return acc;
 }
 
+// A whole layer, block by block: epi(mb, acc) receives sum_ks A(mb, ks) B(ks) for
+// mb = 0..NB-1.  For short K (bf16 operands) the A operands of block mb+1 are read
+// while block mb's MFMAs run, and block mb's epilogue runs after block mb+1's MFMAs
+// are issued, so the loads, the matrix cores and the vector ALU overlap within the
+// wave.  Long K (fp32 operands) runs one block at a time.
+template <class C, int NKS, class BF, class EPI>
+__device__ __forceinline__ void dense_layer(const typename C::A* __restrict__ Apk, int lane, BF&& bop,
+                                            EPI&& epi) {
+  using A = typename C::A;
+  using Acc = typename C::X::Acc;
+  if constexpr (NKS <= 8) {
+    A cur[NKS], nxt[NKS];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) cur[ks] = Apk[ks * 64 + lane];
+    Acc prev;
+#pragma unroll
+    for (int mb = 0; mb < C::NB; ++mb) {
+      if (mb + 1 < C::NB) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) nxt[ks] = Apk[((int64_t)(mb + 1) * NKS + ks) * 64 + lane];
+      }
+      DPD_KEEP_LOADS_LOCAL();
+      Acc acc;
+#pragma unroll
+      for (int j = 0; j < C::NR; ++j) acc[j] = 0.f;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) acc = C::X::mma(cur[ks], bop(ks), acc);
+      if (mb > 0) epi(mb - 1, prev);
+      prev = acc;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) cur[ks] = nxt[ks];
+    }
+    epi(C::NB - 1, prev);
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < C::NB; ++mb) {
+      DPD_KEEP_LOADS_LOCAL();
+      epi(mb, dense_block<C, NKS>(Apk, mb, lane, bop));
+    }
+  }
+}
+
 // Sum over the LG lane groups that share a sample column.
 template <class C>
 __device__ __forceinline__ float lane_group_sum(float v) {
@@ -321,16 +365,7 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
   float o0 = 0.f, o1 = 0.f;
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
-#pragma unroll
-    for (int mb = 0; mb < C::NB; ++mb) {
-      DPD_KEEP_LOADS_LOCAL();
-      typename C::X::Acc acc;
-      if (i == 0) {
-        acc = dense_block<C, C::NKS1>(wf, mb, lane, [&](int ks) { return feat[ks]; });
-      } else {
-        const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
-        acc = dense_block<C, C::NKSH>(Ah, mb, lane, [&](int ks) { return hb[i - 1][ks]; });
-      }
+    auto epi = [&](int mb, const typename C::X::Acc& acc) {
       const int vb = (mb * C::LG + g) * C::NR;
       const float* bias = vec + i * C::HP + vb;
 #pragma unroll
@@ -344,6 +379,12 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
           o1 = fmaf(wo[C::HP + vb + j], v, o1);
         }
       }
+    };
+    if (i == 0) {
+      dense_layer<C, C::NKS1>(wf, lane, [&](int ks) { return feat[ks]; }, epi);
+    } else {
+      const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
+      dense_layer<C, C::NKSH>(Ah, lane, [&](int ks) { return hb[i - 1][ks]; }, epi);
     }
   }
   o0 = lane_group_sum<C>(o0);
@@ -353,16 +394,17 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
 }
 
 // ------------------------------------------------------------------ forward kernel
-// Each workgroup owns a contiguous range of tiles; the forward weight operands of the
-// current parameter set live in LDS (reloaded only when the set changes) unless they
-// exceed the LDS budget, in which case they are read from global memory (L2).
+// Each workgroup (kFwdWaves waves, MT samples each) owns a contiguous range of tiles; the
+// forward weight operands of the current parameter set live in LDS (reloaded only when
+// the set changes) unless they exceed the LDS budget, in which case they are read from
+// global memory (L2).
 template <int PREC, int T, int H, int NL>
-__global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
-                                                       const char* __restrict__ pack, int residual,
-                                                       float* __restrict__ u) {
+__global__ __launch_bounds__(kFwdThreads) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
+                                                          const char* __restrict__ pack, int residual,
+                                                          float* __restrict__ u) {
   using C = Cfg<PREC, T, H, NL>;
   using A = typename C::A;
-  constexpr int S = C::S;
+  constexpr int S = C::MT * kFwdWaves;
   constexpr int XW = S + T - 1;
   constexpr bool kLdsWeights = C::OFF_BWDH <= 144 * 1024;
   constexpr int NWF = kLdsWeights ? (int)(C::OFF_BWDH / 16) : 1;
@@ -383,14 +425,14 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_fwd(StreamTable st, const flo
     __syncthreads();   // previous tile done with the LDS windows
     if (set != cur_set) {
       const float* src = reinterpret_cast<const float*>(pk + C::OFF_VEC);
-      for (int i = threadIdx.x; i < C::NVEC; i += kThreads) vec[i] = src[i];
+      for (int i = threadIdx.x; i < C::NVEC; i += kFwdThreads) vec[i] = src[i];
       if constexpr (kLdsWeights) {
         const uint4* wsrc = reinterpret_cast<const uint4*>(pk);
-        for (int i = threadIdx.x; i < NWF; i += kThreads) wf[i] = wsrc[i];
+        for (int i = threadIdx.x; i < NWF; i += kFwdThreads) wf[i] = wsrc[i];
       }
       cur_set = set;
     }
-    for (int i = threadIdx.x; i < XW; i += kThreads) {
+    for (int i = threadIdx.x; i < XW; i += kFwdThreads) {
       const int64_t p = t0 - (T - 1) + i;
       xw[i] = (p >= lo && p < hi) ? ld2(x, p) : make_float2(0.f, 0.f);
     }
@@ -795,16 +837,14 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       Ops<C, C::NKSH> dn;
       if constexpr (i >= 2) {
         const A* Ab = wbwd + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
-#pragma unroll
-        for (int mb = 0; mb < C::NB; ++mb) {
-          DPD_KEEP_LOADS_LOCAL();
-          const typename X::Acc acc = dense_block<C, C::NKSH>(Ab, mb, lane, [&](int ks) { return db[ks]; });
+        dense_layer<C, C::NKSH>(Ab, lane, [&](int ks) { return db[ks]; },
+                                [&](int mb, const typename X::Acc& acc) {
 #pragma unroll
           for (int j = 0; j < C::NR; ++j) {
             const float hv = value_at<C, C::NKSH>(hb[i - 2], mb, j);
             set_elem<C>(dn[X::ks_of(mb, j)], X::e_of(mb, j), acc[j] * (1.f - hv * hv));
           }
-        }
+        });
       }
       __syncthreads();
       accumulate(std::integral_constant<int, i - 1>{});
@@ -897,8 +937,9 @@ bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out) {
     td.nks1 = C::NKS1;
     td.nksh = C::NKSH;
     td.tile = C::S;
+    td.fwd_tile = C::MT * kFwdWaves;
     td.pack_bytes = C::PACK;
-    td.fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (C::S + T_) + 4 * C::NVEC;
+    td.fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (td.fwd_tile + T_) + 4 * C::NVEC;
     td.dw_slot = C::SLOT;
   });
   *out = td;
@@ -923,7 +964,7 @@ void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_strid
 void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
                      float* u, int grid, hipStream_t s) {
   tdnn_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
-    k_tdnn_fwd<P_, T_, H_, NL_><<<grid, kThreads, 0, s>>>(st, x, static_cast<const char*>(pack),
+    k_tdnn_fwd<P_, T_, H_, NL_><<<grid, kFwdThreads, 0, s>>>(st, x, static_cast<const char*>(pack),
                                                          td.residual, u);
   });
 }
