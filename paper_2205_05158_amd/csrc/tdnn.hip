@@ -503,6 +503,13 @@ struct BwdLds {
   }
   __host__ __device__ static constexpr int blk_cnt(int li) { return li == 0 ? NBL1 : NBLH; }
   __host__ __device__ static constexpr int blk_cols(int li) { return li == 0 ? C::NN1 : C::NBD; }
+  // (row block, column block) of block blk of a layer with nnb column blocks; the column
+  // index is rotated by the row index so the bias rows (column block 0) spread over the
+  // waves
+  __device__ static void blk_rc(int blk, int nnb, int& mb, int& nb) {
+    mb = blk / nnb;
+    nb = (blk % nnb + mb) % nnb;
+  }
 };
 
 // One 32x32 dW block over the tile's samples: rows mb of the delta staging against
@@ -510,33 +517,39 @@ struct BwdLds {
 // issued before the MFMAs.
 //
 // bf16 (swizzled staging): lo[ks] is the lane's element offset of its 16-byte operand
-// chunk in K step ks within a 32-row block; rowsum (when not null) receives the sum of
-// delta row 32*mb + lane%32 over the tile's samples, from the same operand registers.
-template <class C, class B>
-__device__ __forceinline__ void dw_block_bf16(const __bf16* dst, const __bf16* hst, int mb, int nb,
-                                              const int (&lo)[4], f32x16& acc, float* rowsum) {
-  static_assert(C::S == 64, "four K steps of 16 samples");
+// chunk in K step ks within a 32-row block; the bias row sums come from the same
+// operand registers.
+struct DwOps {
   bf16x8 a[4], b[4];
+};
+template <class C, class B>
+__device__ __forceinline__ void dw_load_bf16(const __bf16* dst, const __bf16* hst, int mb, int nb,
+                                             const int (&lo)[4], DwOps& o) {
+  static_assert(C::S == 64, "four K steps of 16 samples");
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
-    a[ks] = *reinterpret_cast<const bf16x8*>(dst + 32 * B::LD * mb + lo[ks]);
-    b[ks] = *reinterpret_cast<const bf16x8*>(hst + 32 * B::LD * nb + lo[ks]);
+    o.a[ks] = *reinterpret_cast<const bf16x8*>(dst + 32 * B::LD * mb + lo[ks]);
+    o.b[ks] = *reinterpret_cast<const bf16x8*>(hst + 32 * B::LD * nb + lo[ks]);
   }
+}
+template <class C>
+__device__ __forceinline__ void dw_mma_bf16(const DwOps& o, f32x16& acc) {
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) acc = C::D::mma(a[ks], b[ks], acc);
-  if (rowsum) {
-    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-    const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
-    float sum = 0.f;
+  for (int ks = 0; ks < 4; ++ks) acc = C::D::mma(o.a[ks], o.b[ks], acc);
+}
+// sum over the tile's samples of the delta row held in o.a (both lane halves)
+__device__ __forceinline__ float dw_rowsum_bf16(const DwOps& o) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
+  float sum = 0.f;
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
+  for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        const bf16x2 pr = {a[ks][e], a[ks][e + 1]};
-        sum = __builtin_amdgcn_fdot2_f32_bf16(pr, one, sum, false);
-      }
-    *rowsum = sum + __shfl_xor(sum, 32);
-  }
+    for (int e = 0; e < 8; e += 2) {
+      const bf16x2 pr = {o.a[ks][e], o.a[ks][e + 1]};
+      sum = __builtin_amdgcn_fdot2_f32_bf16(pr, one, sum, false);
+    }
+  return sum + __shfl_xor(sum, 32);
 }
 
 template <class C, class B>
@@ -626,6 +639,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
 
   const int tid = threadIdx.x;
   const int wave_u = __builtin_amdgcn_readfirstlane(tid / 64);
+  __builtin_assume(wave_u >= 0 && wave_u < kWaves);
   const int g_wg = blockIdx.x, G_wg = gridDim.x;
   const int t_begin = wg_tile_start(g_wg, G_wg, st.n_tiles);
   const int t_end = wg_tile_start(g_wg + 1, G_wg, st.n_tiles);
@@ -664,8 +678,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
         if (bi >= B::blk_off(l2) && bi < B::blk_off(l2) + B::blk_cnt(l2)) li = l2;
       if (li >= 0) {
         const int nnb = li == 0 ? C::NN1 : C::NBD;
-        const int blk = bi - B::blk_off(li);
-        const int mb = blk / nnb, nb = blk % nnb;
+        int mb, nb;
+        B::blk_rc(bi - B::blk_off(li), nnb, mb, nb);
         float* out = slot + C::dw_off(li) + (32 * mb) * (nnb * 32) + 32 * nb + r;
 #pragma unroll
         for (int j = 0; j < 16; ++j) out[C::D::row(j, h) * (nnb * 32)] = dwacc[q][j];
@@ -692,18 +706,41 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     constexpr int q0 = off / kWaves, q1 = (off + cnt - 1) / kWaves;
     float* bl = bacc + li * C::HP;
     const int h = lane / 32, r = lane % 32;
+    if constexpr (B::SWZ) {
+      // the operands of the wave's next block are read while this block's MFMAs run
+      DwOps ops[2];
+      auto valid = [&](int q) { const int bi = kWaves * q + wave_u; return bi >= off && bi < off + cnt; };
+      auto load = [&](int q, DwOps& o) {
+        int mb, nb;
+        B::blk_rc(kWaves * q + wave_u - off, nnb, mb, nb);
+        dw_load_bf16<C, B>(dst, hst, mb, nb, dlo, o);
+      };
+      if (valid(q0)) load(q0, ops[0]);
+#pragma unroll
+      for (int q = q0; q <= q1; ++q) {
+        if (q + 1 <= q1 && valid(q + 1)) load(q + 1, ops[(q + 1 - q0) & 1]);
+        DPD_KEEP_LOADS_LOCAL();
+        if (valid(q)) {
+          const DwOps& o = ops[(q - q0) & 1];
+          dw_mma_bf16<C>(o, dwacc[q]);
+          int mb, nb;
+          B::blk_rc(kWaves * q + wave_u - off, nnb, mb, nb);
+          if (nb == 0) {
+            const float sum = dw_rowsum_bf16(o);
+            if (h == 0) bl[32 * mb + r] += sum;
+          }
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int q = q0; q <= q1; ++q) {
       DPD_KEEP_LOADS_LOCAL();
       const int bi = kWaves * q + wave_u;
       if (bi >= off && bi < off + cnt) {
-        const int blk = bi - off;
-        const int mb = blk / nnb, nb = blk % nnb;
-        if constexpr (B::SWZ) {
-          float sum;
-          dw_block_bf16<C, B>(dst, hst, mb, nb, dlo, dwacc[q], nb == 0 ? &sum : nullptr);
-          if (nb == 0 && h == 0) bl[32 * mb + r] += sum;
-        } else {
+        int mb, nb;
+        B::blk_rc(bi - off, nnb, mb, nb);
+        {
           dwacc[q] = dw_block<C, B>(dst, hst, mb, nb, lane, dwacc[q]);
           if (nb == 0) {
             const float sum = delta_row_sum<C, B>(dst, mb, lane);
@@ -714,12 +751,24 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     }
   };
 
+  // the x window and g_u of the next tile are read one tile ahead, into registers
+  static_assert(B::XW <= kThreads, "one x-window element per thread");
+  float2 xpre = make_float2(0.f, 0.f), gpre = make_float2(0.f, 0.f);
+  auto prefetch = [&](int tt) {
+    const int s2 = stream_of_tile(st, tt);
+    const int64_t lo2 = st.off[s2], hi2 = st.off[s2 + 1];
+    const int64_t t02 = lo2 + (int64_t)(tt - st.tile0[s2]) * S;
+    const int64_t p = t02 - B::XB + tid;
+    xpre = (tid < B::XW && p >= lo2 && p < hi2) ? ld2(x, p) : make_float2(0.f, 0.f);
+    const int64_t n2 = t02 + C::MT * wave_u + (tid % 64) % C::MT;
+    gpre = n2 < hi2 ? ld2(gu, n2) : make_float2(0.f, 0.f);
+  };
+  if (t_begin < t_end) prefetch(t_begin);
+
   int cur_stream = -1;
   for (int t = t_begin; t < t_end; ++t) {
     const int s = stream_of_tile(st, t);
     const int set = st.per_stream ? s : 0;
-    const int64_t lo = st.off[s], hi = st.off[s + 1];
-    const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
     const char* pk = pack + set * C::PACK;
     int tq = tid;
     asm volatile("" : "+v"(tq));
@@ -744,12 +793,9 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       }
       cur_stream = s;
     }
-    for (int i = tid; i < B::XW; i += kThreads) {
-      const int64_t p = t0 - B::XB + i;
-      xw[i] = (p >= lo && p < hi) ? ld2(x, p) : make_float2(0.f, 0.f);
-    }
-    const int64_t n = t0 + col;
-    const float2 gsum = n < hi ? ld2(gu, n) : make_float2(0.f, 0.f);
+    if (tid < B::XW) xw[tid] = xpre;
+    const float2 gsum = gpre;          // g_u of this lane's sample (zero past the stream)
+    if (t + 1 < t_end) prefetch(t + 1);
     __syncthreads();
 
     // ---- TDNN: recompute this wave's samples, then the reverse mode
