@@ -486,11 +486,19 @@ struct BwdLds {
   // bytes of static LDS besides the weight operands
   static constexpr int BIAS_N = NL * C::HP + 32;  // bias-gradient accumulators
   static constexpr int BASE_BYTES = XW * 8 + C::NVEC * 4 + BIAS_N * 4 + STAGE_BYTES;
-  // forward (and, if they fit too, backward) weight operands in LDS
+  // Weight operands staged in LDS, the byte range [W_LO, W_HI) of the packed set: both
+  // packs when they fit, else the backward (transposed) pack, whose short delta-chain
+  // blocks hide global-memory latency worse than the tanh-heavy recompute blocks, else
+  // the forward pack, else none.
   static constexpr int kLdsBudget = 160 * 1024;
-  static constexpr bool W_FWD = BASE_BYTES + C::OFF_BWDH <= kLdsBudget;
-  static constexpr bool W_BWD = BASE_BYTES + C::OFF_VEC <= kLdsBudget;
-  static constexpr int64_t W_BYTES = W_BWD ? C::OFF_VEC : (W_FWD ? C::OFF_BWDH : 16);
+  static constexpr bool FIT_ALL = BASE_BYTES + C::OFF_VEC <= kLdsBudget;
+  static constexpr bool FIT_BWD = BASE_BYTES + (C::OFF_VEC - C::OFF_BWDH) <= kLdsBudget;
+  static constexpr bool FIT_FWD = BASE_BYTES + C::OFF_BWDH <= kLdsBudget;
+  static constexpr int64_t W_LO = FIT_ALL ? 0 : (FIT_BWD ? C::OFF_BWDH : 0);
+  static constexpr int64_t W_HI = FIT_ALL ? C::OFF_VEC : (FIT_BWD ? C::OFF_VEC : (FIT_FWD ? C::OFF_BWDH : 0));
+  static constexpr bool W_FWD = W_LO == 0 && W_HI >= C::OFF_BWDH;
+  static constexpr bool W_BWD = W_LO <= C::OFF_BWDH && W_HI == C::OFF_VEC;
+  static constexpr int64_t W_BYTES = W_HI > W_LO ? W_HI - W_LO : 16;
   // 32x32 dW blocks of the tanh layers (layer 1, then the hidden layers), dealt
   // round-robin over the waves: block bi is held by wave bi % kWaves in dwacc[bi / kWaves].
   // The output layer's 2 x HP dW is one register per thread instead (2*HP <= threads).
@@ -787,8 +795,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       // a new stream may bring a new parameter set: stage its vector block and weights
       const float* src = reinterpret_cast<const float*>(pk + C::OFF_VEC);
       for (int i = tid; i < C::NVEC; i += kThreads) vec[i] = src[i];
-      if constexpr (B::W_FWD) {
-        const uint4* wsrc = reinterpret_cast<const uint4*>(pk);
+      if constexpr (B::W_HI > B::W_LO) {
+        const uint4* wsrc = reinterpret_cast<const uint4*>(pk + B::W_LO);
         for (int i = tid; i < (int)(B::W_BYTES / 16); i += kThreads) wlds[i] = wsrc[i];
       }
       cur_stream = s;
@@ -800,7 +808,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
 
     // ---- TDNN: recompute this wave's samples, then the reverse mode
     const A* wfwd = B::W_FWD ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
-    const A* wbwd = B::W_BWD ? reinterpret_cast<const A*>(wlds) + C::OFF_BWDH / sizeof(A)
+    const A* wbwd = B::W_BWD ? reinterpret_cast<const A*>(reinterpret_cast<const char*>(wlds) + (C::OFF_BWDH - B::W_LO))
                              : reinterpret_cast<const A*>(pk + C::OFF_BWDH);
     Ops<C, C::NKSH> hb[NL];
     (void)mlp_forward<C, NL>(wfwd, vec, lane, g, &xw[col + B::XB], hb);
