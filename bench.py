@@ -30,6 +30,41 @@ PEAK = {  # MI355X published peaks
 }
 
 
+def source_digest() -> str:
+    """Digest of everything the kernels are built from (sources, header, build flags)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2205_05158_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    files += [os.path.join(ROOT, "include", "dpdmi.h"),
+              os.path.join(ROOT, "paper_2205_05158_amd", "build.py")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3
+    summaries (FETCH_SIZE + WRITE_SIZE, copy-calibrated), only when they were taken on
+    the current sources; None otherwise."""
+    pdir = os.path.join(ROOT, "profiles")
+    want = {"workload": workload, "kernel": kernel, "source": source_digest()}
+    if not os.path.isdir(pdir):
+        return None
+    for f in sorted(os.listdir(pdir)):
+        if not f.endswith((".md", ".txt")):
+            continue
+        for line in open(os.path.join(pdir, f)):
+            if not line.startswith("traffic-record:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+            if all(kv.get(k) == v for k, v in want.items()):
+                return float(kv["read_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -41,6 +76,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1 << 20,
                     help="samples of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the unit-throughput probes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device-to-device copies of 256 MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -56,6 +92,59 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_per_copy": a.numel() * 4, "copies": 5}))
+
+
+def measure_peaks(torch):
+    """Unit throughputs measured on this GPU by libdpdpeaks.so (timed with HIP events on
+    torch's current stream, where the probes are launched): bf16 MFMA 16x16x32, non-packed
+    fp32 FMA, exp2+reciprocal pairs (the transcendental part of a tanh) and an HBM copy."""
+    import ctypes as C
+    from paper_2205_05158_amd import build as B
+    lib = C.CDLL(B.PEAKS_LIB)
+    for name in ("peak_mfma_bf16", "peak_fma_f32", "peak_trans"):
+        getattr(lib, name).argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
+        getattr(lib, name).restype = C.c_int
+    lib.peak_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]
+    lib.peak_copy.restype = C.c_int
+    props = torch.cuda.get_device_properties(0)
+    cus = props.multi_processor_count
+    blocks = 8 * cus                          # 256-thread workgroups, 8 per CU
+    sink = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    sh = C.c_void_p(st.cuda_stream)
+
+    def timed(fn, reps=3):
+        fn()
+        best = 1e30
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+        return best
+
+    def check(rc):
+        if rc != 0:
+            raise RuntimeError(f"peak probe launch failed: {rc}")
+
+    it = 4096
+    t = timed(lambda: check(lib.peak_mfma_bf16(C.c_void_p(sink.data_ptr()), blocks, it, sh)))
+    mfma = blocks * 4 * it * 4 * (16 * 16 * 32 * 2) / t / 1e12      # 4 waves x 4 chains
+    t = timed(lambda: check(lib.peak_fma_f32(C.c_void_p(sink.data_ptr()), blocks, it, sh)))
+    fma = blocks * 256 * it * 8 * 2 / t / 1e12
+    t = timed(lambda: check(lib.peak_trans(C.c_void_p(sink.data_ptr()), blocks, it, sh)))
+    trans = blocks * 256 * it * 4 / t / 1e9                          # exp2+rcp pairs
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    t = timed(lambda: check(lib.peak_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                          nbytes, 16 * cus, sh)))
+    hbm = 2 * nbytes / t / 1e9
+    del a, b
+    return {"mfma_bf16_tflops": mfma, "valu_fp32_fma_tflops": fma,
+            "exp2_rcp_pairs_gps": trans, "hbm_copy_gbs": hbm}
 
 
 def cpu_baseline(wl_name, n_sample):
@@ -196,17 +285,35 @@ def main():
         if t_mma >= t_alu:
             ach = work["mma"] * n / t_avg / 1e12
             roof = {"bound": "mfma", "achieved": ach, "peak": mma_peak, "unit": "TFLOP/s",
-                    "frac": ach / mma_peak, "traffic": None}
+                    "frac": ach / mma_peak, "traffic": profiled_traffic(args.workload, dom)}
         else:
             ach = work["alu"] * n / t_avg / 1e12
             roof = {"bound": "alu", "achieved": ach, "peak": PEAK["valu_fp32_tflops"],
-                    "unit": "TFLOP/s", "frac": ach / PEAK["valu_fp32_tflops"], "traffic": None}
+                    "unit": "TFLOP/s", "frac": ach / PEAK["valu_fp32_tflops"],
+                    "traffic": profiled_traffic(args.workload, dom)}
         roof["kernel"] = dom
         roof["kernel_ms"] = t_avg * 1e3
         roof["flops_per_sample"] = work
         roof["samples_per_launch"] = n
         roof["composite_frac"] = max(t_mma, t_alu) / t_avg
     step_flops = (tf["total"] + gf["total"]) * n
+    peaks = None if args.no_peaks else measure_peaks(torch)
+    if roof is not None and peaks is not None:
+        mp = (peaks["mfma_bf16_tflops"] if roof["bound"] == "mfma" and prec == "bf16" else
+              peaks["valu_fp32_fma_tflops"] if roof["bound"] == "alu" else None)
+        roof["measured_peak"] = mp
+        roof["frac_of_measured_peak"] = roof["achieved"] / mp if mp else None
+    # whole-step composite bound: each unit's algorithmic work at its published peak
+    # (tanh: 2 transcendentals, at the measured exp2+reciprocal rate when available)
+    n_tanh = wl.n_hidden * wl.hidden * n
+    t_mfma = (tf["fwd_mma"] + tf["bwd_mma"]) * n / (mma_peak * 1e12)
+    t_valu = (tf["out"] + tf["bwd_out"] + gf["total"]) * n / (PEAK["valu_fp32_tflops"] * 1e12)
+    t_tanh = n_tanh / (peaks["exp2_rcp_pairs_gps"] * 1e9) if peaks else None
+    t_hbm = 32 * n / (PEAK["hbm_gbs"] * 1e9)
+    bound = max(t_mfma, t_valu + (t_tanh or 0.0), t_hbm)
+    step_roof = {"t_mfma_ms": t_mfma * 1e3, "t_valu_ms": t_valu * 1e3,
+                 "t_tanh_ms": None if t_tanh is None else t_tanh * 1e3, "t_hbm_ms": t_hbm * 1e3,
+                 "bound_ms": bound * 1e3, "frac": bound * 1e3 / ms_per_step}
 
     out = {
         "metric": "Msamples/s DPD+PA forward+backward at <=0.1 dB NMSE gap vs FP64; % roofline",
@@ -220,6 +327,8 @@ def main():
                            else "dpd_cascade(u, y, nmse, dW, loss)",
                    "parallelism": "single GPU"},
         "roofline": roof,
+        "step_roofline": step_roof,
+        "peaks_measured": peaks,
         "algorithmic_tflops": step_flops / (ms_per_step / 1e3) / 1e12,
         "kernels_ms_per_step": {k: ms / args.steps for k, (c, ms) in kern.items()},
         "loss": float(loss.sum().item()), "nmse_db": float(nm[-3:].cpu().numpy()[2]),
