@@ -131,7 +131,7 @@ int fwd_grid(const TdnnDims& td) {
 
 // ------------------------------------------------------------ workspace layout
 struct Ws {
-  size_t tile_part = 0, inv_r = 0, loss_tmp = 0, u_buf = 0, y_buf = 0, gu_buf = 0;
+  size_t tile_part = 0, inv_r = 0, loss_tmp = 0, u_buf = 0, y_buf = 0, gu_buf = 0, gmp_tab = 0;
   size_t act = 0, part = 0, acc = 0, pack = 0, slots = 0, total = 0;
   int64_t act_floats_per_sample = 0;
 };
@@ -139,7 +139,7 @@ struct Ws {
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
-  (void)g;
+
   Ws w;
   size_t pos = 0;
   auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
@@ -164,6 +164,7 @@ Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
     w.pack = take((size_t)td.pack_bytes * p.n_sets);
     w.slots = take(sizeof(float) * (size_t)td.dw_slot * (kMaxGrid + p.S));
     w.gu_buf = take(sizeof(float2) * p.n_total);
+    if (g) w.gmp_tab = take(sizeof(float2) * 2 * (size_t)coeff_count(*g) * p.n_sets);
   }
   w.total = pos;
   return w;
@@ -460,7 +461,8 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
     // GMP forward + reverse mode (y, E/R tile partials, g_u), then the TDNN reverse mode
     StreamTable gt = make_table(p, gmp_bwd_tile());
     float* gub = at<float>(workspace, L.gu_buf);
-    { DPD_PROF("gmp_bwd"); launch_gmp_bwd(*gmp, gt, x, ubuf, coef, g_re, g_im, part, gub, y, stream); }
+    float2* gtab = at<float2>(workspace, L.gmp_tab);
+    { DPD_PROF("gmp_bwd"); launch_gmp_bwd(*gmp, gt, x, ubuf, coef, gtab, g_re, g_im, part, gub, y, stream); }
     int grid = std::min(tab.n_tiles, std::min(kMaxGrid, 2 * device_cus()));
     float* slots = at<float>(workspace, L.slots);
     { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, stream); }

@@ -62,8 +62,25 @@ __global__ __launch_bounds__(kGmpThreads) void k_gmp_fwd(StreamTable st, const f
   }
 }
 
+// Per parameter set, the coefficient table read by k_gmp_bwd: tab[set][j] = C_j and
+// tab[set][J + j] = order(j) * C_j (the coefficients of the envelope derivative).
+template <int K, int M, int L>
+__global__ void k_gmp_table(const float* __restrict__ coef, float2* __restrict__ tab) {
+  using G = Gmp<K, M, L>;
+  const int set = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= G::J) return;
+  const float* cs = coef + (int64_t)set * 2 * G::J;
+  const float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
+  const float k = (float)G::order(j);
+  tab[(int64_t)set * 2 * G::J + j] = c;
+  tab[(int64_t)set * 2 * G::J + G::J + j] = make_float2(k * c.x, k * c.y);
+}
+
 // GMP forward and reverse mode over tiles of kGmpBwdTile samples, one workgroup per tile
-// (no persistent state, so it runs at the occupancy its registers allow):
+// (no persistent state, so it runs at the occupancy its registers allow).  The
+// coefficients are read from the table (wave-uniform addresses: scalar loads into
+// SGPRs, used directly as FMA operands):
 //   y = GMP(u) (stored when y_out is not null), g_y = 2 (y - G x) inside the stream,
 //   the tile's E = sum |y - G x|^2 and R = sum |G x|^2 (fixed reduction tree), and
 //   g_u[m] = dL/du[m] of L = sum |y - G x|^2 (the gather form in gmp.hpp).
@@ -72,7 +89,7 @@ constexpr int kGmpBwdThreads = 256;
 template <int K, int M, int L>
 __global__ __launch_bounds__(kGmpBwdThreads) void k_gmp_bwd(StreamTable st, const float* __restrict__ x,
                                                             const float* __restrict__ u,
-                                                            const float* __restrict__ coef, float g_re,
+                                                            const float2* __restrict__ tab, float g_re,
                                                             float g_im, float2* __restrict__ tile_part,
                                                             float* __restrict__ gu_out,
                                                             float* __restrict__ y_out) {
@@ -83,8 +100,6 @@ __global__ __launch_bounds__(kGmpBwdThreads) void k_gmp_bwd(StreamTable st, cons
   constexpr int QB = M + L;
   constexpr int QW = S + 2 * QB;        // Q  [t0 - QB, t0 + S + QB)
   constexpr int YW = S + M + 2 * L;     // gy [t0 - L, t0 + S + M + L), also the x window
-  __shared__ float2 cf[G::J];
-  __shared__ float2 dcf[G::J];
   __shared__ float2 uw[UW];
   __shared__ float rw[UW];
   __shared__ float2 xw[YW];
@@ -97,13 +112,8 @@ __global__ __launch_bounds__(kGmpBwdThreads) void k_gmp_bwd(StreamTable st, cons
   const int s = stream_of_tile(st, t);
   const int64_t lo = st.off[s], hi = st.off[s + 1];
   const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
-  const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
-  for (int j = tid; j < G::J; j += S) {
-    const float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
-    cf[j] = c;
-    const float k = (float)G::order(j);
-    dcf[j] = make_float2(k * c.x, k * c.y);
-  }
+  const float2* cf = tab + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
+  const float2* dcf = cf + G::J;
   for (int i = tid; i < UW; i += S) {
     const int64_t p = t0 - UB + i;
     const float2 v = (p >= lo && p < hi) ? ld2(u, p) : make_float2(0.f, 0.f);
@@ -175,10 +185,13 @@ __global__ __launch_bounds__(kGmpBwdThreads) void k_gmp_bwd(StreamTable st, cons
 }  // namespace
 
 void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
-                    const float* coef, float g_re, float g_im, float2* tile_part, float* gu,
-                    float* y, hipStream_t s) {
+                    const float* coef, float2* tab, float g_re, float g_im, float2* tile_part,
+                    float* gu, float* y, hipStream_t s) {
   gmp_dispatch(g.K, g.M, g.L, [&]<int K, int M, int L>() {
-    k_gmp_bwd<K, M, L><<<st.n_tiles, kGmpBwdThreads, 0, s>>>(st, x, u, coef, g_re, g_im, tile_part, gu, y);
+    const int n_sets = st.per_stream ? st.n : 1;
+    dim3 tg((Gmp<K, M, L>::J + 255) / 256, n_sets);
+    k_gmp_table<K, M, L><<<tg, 256, 0, s>>>(coef, tab);
+    k_gmp_bwd<K, M, L><<<st.n_tiles, kGmpBwdThreads, 0, s>>>(st, x, u, tab, g_re, g_im, tile_part, gu, y);
   });
 }
 

@@ -66,6 +66,7 @@ __device__ __forceinline__ void gmp_q(const float* rw, const float2* cf, float2 
     if (K > 1) {
 #pragma unroll
       for (int g = 1; g <= L; ++g) {
+        DPD_KEEP_LOADS_LOCAL();
         float2 hb = cf[G::ib(K - 1, l, g)];
 #pragma unroll
         for (int k = K - 2; k >= 1; --k) hb = cfma_r(hb, rl[g], cf[G::ib(k, l, g)]);
@@ -125,6 +126,7 @@ __device__ __forceinline__ float2 gmp_grad(const float2* uw, const float* rw, co
       s2 += w.x * d.x - w.y * d.y;
 #pragma unroll
       for (int g = 1; g <= L; ++g) {
+        DPD_KEEP_LOADS_LOCAL();
         float2 wb = cmulc(gyw[l + g], uw[g]);            // conj(g_y[m+l+g]) u[m+g]
         float2 cb = cf[G::ib(1, l, g)];
         s1 += wb.x * cb.x - wb.y * cb.y;

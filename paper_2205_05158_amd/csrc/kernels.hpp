@@ -70,11 +70,13 @@ void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, 
 void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,
                     float* y, hipStream_t s);
 // GMP forward + reverse mode over tiles of gmp_bwd_tile() samples: y (optional), E/R
-// tile partials and g_u = dL/du.  Supported (K, M, L) are those of gmp_dispatch.
+// tile partials and g_u = dL/du.  Supported (K, M, L) are those of gmp_dispatch.  tab:
+// workspace of 2 * J float2 per parameter set (the coefficients and their
+// derivative-weighted copy, written first on the same stream).
 int gmp_bwd_tile();
 void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
-                    const float* coef, float g_re, float g_im, float2* tile_part, float* gu,
-                    float* y, hipStream_t s);
+                    const float* coef, float2* tab, float g_re, float g_im, float2* tile_part,
+                    float* gu, float* y, hipStream_t s);
 // TDNN recompute + reverse mode from g_u: dW partial slots per (workgroup, stream).
 void launch_tdnn_bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu,
                      const void* pack, float* slots, int grid, hipStream_t s);
