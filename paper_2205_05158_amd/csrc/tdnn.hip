@@ -116,7 +116,17 @@ struct Cfg {
   static constexpr int64_t OFF_VEC = OFF_BWDH + (int64_t)(NL - 1) * NB * NKSH * 64 * ES;
   // float vector block: bias [NL][NB][LG][NR], wo [2][NB][LG][NR], bo[2] (+2 pad)
   static constexpr int NVEC = NL * HP + 2 * HP + 4;
-  static constexpr int64_t PACK = OFF_VEC + (int64_t)NVEC * 4;
+  // bf16 models also carry a row-major copy of the hidden weights W_i (i = 2..NL), shared
+  // in LDS by the backward kernel's forward recompute (two 8-byte reads per operand) and
+  // its delta chain (two transposing 8-byte reads per operand): element (o, k) of a layer
+  // at o*HP + 4*((k/4) ^ swz(o)) + k%4.  The chunk swizzle swaps the two 2-bit fields of
+  // o mod 16, which keeps both read patterns free of bank conflicts.
+  static constexpr bool SHARED_W = X::EPL == 8;
+  static constexpr int NCH = HP / 4;                    // 8-byte chunks per row
+  __host__ __device__ static constexpr int swz(int o) { return (((o & 3) << 2) | ((o >> 2) & 3)) & (NCH - 1); }
+  static constexpr int64_t OFF_WH = OFF_VEC + (int64_t)NVEC * 4;
+  static constexpr int64_t WH_LAYER = (int64_t)HP * HP * 2;
+  static constexpr int64_t PACK = OFF_WH + (SHARED_W ? (NL - 1) * WH_LAYER : 0);
   // natural dW slot (floats): per layer W block [rows][cols] then bias [rows]
   static constexpr int64_t DW_L1 = (int64_t)HP * C1 + HP;
   static constexpr int64_t DW_H = (int64_t)HP * HP + HP;
@@ -167,10 +177,23 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
   char* ps = pack + set * C::PACK;
   const int64_t n1 = (int64_t)C::NB * C::NKS1 * 64;
   const int64_t nh = (int64_t)(NL - 1) * C::NB * C::NKSH * 64;
-  const int64_t total = n1 + 2 * nh + C::NVEC;
+  const int64_t nw = C::SHARED_W ? (int64_t)(NL - 1) * C::HP * C::HP : 0;
+  const int64_t total = n1 + 2 * nh + C::NVEC + nw;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    if (idx < n1 + 2 * nh) {
+    if (idx >= n1 + 2 * nh + C::NVEC) {
+      // row-major swizzled hidden weights (bf16)
+      if constexpr (C::SHARED_W) {
+        const int64_t f = idx - (n1 + 2 * nh + C::NVEC);
+        const int i = (int)(f / ((int64_t)C::HP * C::HP)) + 2;     // layer index 2..NL
+        const int r = (int)(f % ((int64_t)C::HP * C::HP));
+        const int o = r / C::HP, kk = r % C::HP;
+        const float* Wi = ws + so.w[i - 1];
+        const float val = (o < H && kk < H) ? Wi[(int64_t)o * H + kk] : 0.f;
+        __bf16* dstw = reinterpret_cast<__bf16*>(ps + C::OFF_WH + (int64_t)(i - 2) * C::WH_LAYER);
+        dstw[o * C::HP + 4 * ((kk / 4) ^ C::swz(o)) + kk % 4] = (__bf16)val;
+      }
+    } else if (idx < n1 + 2 * nh) {
       const int lane = (int)(idx % 64);
       const int rowl = lane % C::MT, g = lane / C::MT;
       const int64_t q = idx / 64;
@@ -306,21 +329,65 @@ __device__ __forceinline__ typename C::X::Acc dense_block(const typename C::A* _
 // while block mb's MFMAs run, and block mb's epilogue runs after block mb+1's MFMAs
 // are issued, so the loads, the matrix cores and the vector ALU overlap within the
 // wave.  Long K (fp32 operands) runs one block at a time.
-template <class C, int NKS, class BF, class EPI>
-__device__ __forceinline__ void dense_layer(const typename C::A* __restrict__ Apk, int lane, BF&& bop,
-                                            EPI&& epi) {
+// A-operand loaders: la(mb, ks) returns the lane's operand of row block mb, K step ks.
+// Packed operand order ([row block][K step][64 lanes]):
+template <class C, int NKS>
+struct PackedA {
+  const typename C::A* __restrict__ p;
+  int lane;
+  __device__ typename C::A operator()(int mb, int ks) const { return p[((int64_t)mb * NKS + ks) * 64 + lane]; }
+};
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+// Row-major swizzled hidden weights (Cfg::OFF_WH) in LDS, forward operand: row o = 16 mb +
+// lane%16 of W_i, K elements 32 ks + 4 g + (0..3) and 32 ks + 16 + 4 g + (0..3).
+template <class C>
+struct SharedFwdA {
+  const __bf16* w;     // LDS copy of one layer
+  int lane;
+  __device__ bf16x8 operator()(int mb, int ks) const {
+    const int o = 16 * mb + lane % 16, g = lane / 16;
+    const __bf16* row = w + o * C::HP;
+    const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row + 4 * ((8 * ks + g) ^ C::swz(o)));
+    const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 4 * ((8 * ks + 4 + g) ^ C::swz(o)));
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  }
+};
+// The same copy read as the transposed (delta-chain) operand: row = input neuron
+// 16 mb + lane%16, K elements = output neurons 32 ks + 4 g + (0..3) and 32 ks + 16 + 4 g +
+// (0..3).  Each transposing read: lane l of a 16-lane group supplies the 8-byte chunk of
+// output neuron o0 + l/4 holding input neurons 16 mb + 4 (l%4) .. +3, and receives input
+// neuron 16 mb + l for output neurons o0 .. o0+3.
+template <class C>
+struct SharedBwdA {
+  const __bf16* w;
+  int lane;
+  __device__ bf16x8 operator()(int mb, int ks) const {
+    const int l = lane % 16, g = lane / 16;
+    const int c = 4 * mb + l % 4;
+    const int o1 = 32 * ks + 4 * g + l / 4, o2 = o1 + 16;
+    typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+    const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+        (lds_bf16x4*)(w + o1 * C::HP + 4 * (c ^ C::swz(o1))));
+    const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
+        (lds_bf16x4*)(w + o2 * C::HP + 4 * (c ^ C::swz(o2))));
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  }
+};
+
+template <class C, int NKS, class LA, class BF, class EPI>
+__device__ __forceinline__ void dense_layer(LA&& la, BF&& bop, EPI&& epi) {
   using A = typename C::A;
   using Acc = typename C::X::Acc;
   if constexpr (NKS <= 8) {
     A cur[NKS], nxt[NKS];
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) cur[ks] = Apk[ks * 64 + lane];
+    for (int ks = 0; ks < NKS; ++ks) cur[ks] = la(0, ks);
     Acc prev;
 #pragma unroll
     for (int mb = 0; mb < C::NB; ++mb) {
       if (mb + 1 < C::NB) {
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) nxt[ks] = Apk[((int64_t)(mb + 1) * NKS + ks) * 64 + lane];
+        for (int ks = 0; ks < NKS; ++ks) nxt[ks] = la(mb + 1, ks);
       }
       DPD_KEEP_LOADS_LOCAL();
       Acc acc;
@@ -338,7 +405,12 @@ __device__ __forceinline__ void dense_layer(const typename C::A* __restrict__ Ap
 #pragma unroll
     for (int mb = 0; mb < C::NB; ++mb) {
       DPD_KEEP_LOADS_LOCAL();
-      epi(mb, dense_block<C, NKS>(Apk, mb, lane, bop));
+      Acc acc;
+#pragma unroll
+      for (int j = 0; j < C::NR; ++j) acc[j] = 0.f;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) acc = C::X::mma(la(mb, ks), bop(ks), acc);
+      epi(mb, acc);
     }
   }
 }
@@ -352,11 +424,12 @@ __device__ __forceinline__ float lane_group_sum(float v) {
 
 // Forward through all hidden layers one row block at a time.  hb[i] holds h_{i+1} in
 // operand form; returns the two linear outputs (valid in every lane group).
-// wf: forward weight operands (layer 1, then the hidden layers; global or LDS);
-// vec: LDS copy of the float vector block (biases, output layer).
+// wf: forward weight operands (layer 1, then the hidden layers; global or LDS); when wh
+// is not null the hidden layers are read from the shared row-major copy there instead
+// (LDS, Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
 template <class C, int NL>
-__device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const float* vec,
-                                              int lane, int g, const float2* xw,
+__device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const __bf16* wh,
+                                              const float* vec, int lane, int g, const float2* xw,
                                               Ops<C, C::NKSH> (&hb)[NL]) {
   using A = typename C::A;
   Ops<C, C::NKS1> feat;
@@ -381,10 +454,17 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
       }
     };
     if (i == 0) {
-      dense_layer<C, C::NKS1>(wf, lane, [&](int ks) { return feat[ks]; }, epi);
-    } else {
+      dense_layer<C, C::NKS1>(PackedA<C, C::NKS1>{wf, lane}, [&](int ks) { return feat[ks]; }, epi);
+    } else if constexpr (C::SHARED_W) {
+      if (wh) {
+        dense_layer<C, C::NKSH>(SharedFwdA<C>{wh + (int64_t)(i - 1) * (C::WH_LAYER / 2), lane},
+                                [&](int ks) { return hb[i - 1][ks]; }, epi);
+        continue;
+      }
+    }
+    if (i > 0) {
       const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
-      dense_layer<C, C::NKSH>(Ah, lane, [&](int ks) { return hb[i - 1][ks]; }, epi);
+      dense_layer<C, C::NKSH>(PackedA<C, C::NKSH>{Ah, lane}, [&](int ks) { return hb[i - 1][ks]; }, epi);
     }
   }
   o0 = lane_group_sum<C>(o0);
@@ -440,7 +520,7 @@ __global__ __launch_bounds__(kFwdThreads) void k_tdnn_fwd(StreamTable st, const 
     Ops<C, C::NKSH> hb[NL];
     const int col = C::MT * wave + sl;
     const A* wops = kLdsWeights ? reinterpret_cast<const A*>(wf) : reinterpret_cast<const A*>(pk);
-    float2 o = mlp_forward<C, NL>(wops, vec, lane, g, &xw[col + T - 1], hb);
+    float2 o = mlp_forward<C, NL>(wops, nullptr, vec, lane, g, &xw[col + T - 1], hb);
     const int64_t n = t0 + col;
     if (g == 0 && n < hi) {
       if (residual) {
@@ -491,6 +571,9 @@ struct BwdLds {
   // blocks hide global-memory latency worse than the tanh-heavy recompute blocks, else
   // the forward pack, else none.
   static constexpr int kLdsBudget = 160 * 1024;
+  // bf16: layer-1 operands + the shared row-major hidden weights, when they fit
+  static constexpr int64_t SH_BYTES = C::OFF_FWDH + (C::SHARED_W ? (NL - 1) * C::WH_LAYER : 0);
+  static constexpr bool SHW = C::SHARED_W && BASE_BYTES + SH_BYTES <= kLdsBudget;
   static constexpr bool FIT_ALL = BASE_BYTES + C::OFF_VEC <= kLdsBudget;
   static constexpr bool FIT_BWD = BASE_BYTES + (C::OFF_VEC - C::OFF_BWDH) <= kLdsBudget;
   static constexpr bool FIT_FWD = BASE_BYTES + C::OFF_BWDH <= kLdsBudget;
@@ -498,7 +581,7 @@ struct BwdLds {
   static constexpr int64_t W_HI = FIT_ALL ? C::OFF_VEC : (FIT_BWD ? C::OFF_VEC : (FIT_FWD ? C::OFF_BWDH : 0));
   static constexpr bool W_FWD = W_LO == 0 && W_HI >= C::OFF_BWDH;
   static constexpr bool W_BWD = W_LO <= C::OFF_BWDH && W_HI == C::OFF_VEC;
-  static constexpr int64_t W_BYTES = W_HI > W_LO ? W_HI - W_LO : 16;
+  static constexpr int64_t W_BYTES = SHW ? SH_BYTES : (W_HI > W_LO ? W_HI - W_LO : 16);
   // 32x32 dW blocks of the tanh layers (layer 1, then the hidden layers), dealt
   // round-robin over the waves: block bi is held by wave bi % kWaves in dwacc[bi / kWaves].
   // The output layer's 2 x HP dW is one register per thread instead (2*HP <= threads).
@@ -795,7 +878,13 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       // a new stream may bring a new parameter set: stage its vector block and weights
       const float* src = reinterpret_cast<const float*>(pk + C::OFF_VEC);
       for (int i = tid; i < C::NVEC; i += kThreads) vec[i] = src[i];
-      if constexpr (B::W_HI > B::W_LO) {
+      if constexpr (B::SHW) {
+        const uint4* w1 = reinterpret_cast<const uint4*>(pk);
+        for (int i = tid; i < (int)(C::OFF_FWDH / 16); i += kThreads) wlds[i] = w1[i];
+        const uint4* wh = reinterpret_cast<const uint4*>(pk + C::OFF_WH);
+        for (int i = tid; i < (int)((B::SH_BYTES - C::OFF_FWDH) / 16); i += kThreads)
+          wlds[C::OFF_FWDH / 16 + i] = wh[i];
+      } else if constexpr (B::W_HI > B::W_LO) {
         const uint4* wsrc = reinterpret_cast<const uint4*>(pk + B::W_LO);
         for (int i = tid; i < (int)(B::W_BYTES / 16); i += kThreads) wlds[i] = wsrc[i];
       }
@@ -807,11 +896,13 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     __syncthreads();
 
     // ---- TDNN: recompute this wave's samples, then the reverse mode
-    const A* wfwd = B::W_FWD ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
+    const A* wfwd = (B::SHW || B::W_FWD) ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
     const A* wbwd = B::W_BWD ? reinterpret_cast<const A*>(reinterpret_cast<const char*>(wlds) + (C::OFF_BWDH - B::W_LO))
                              : reinterpret_cast<const A*>(pk + C::OFF_BWDH);
+    const __bf16* wsh = B::SHW ? reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(wlds) + C::OFF_FWDH)
+                               : nullptr;
     Ops<C, C::NKSH> hb[NL];
-    (void)mlp_forward<C, NL>(wfwd, vec, lane, g, &xw[col + B::XB], hb);
+    (void)mlp_forward<C, NL>(wfwd, wsh, vec, lane, g, &xw[col + B::XB], hb);
     int lb[2];
     B::lane_bases(g, col, lb);
     // output layer: delta_o = (Re g_u, Im g_u) in staging rows 0 and 1
@@ -890,15 +981,20 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       // delta_{i-1} = (W_i^T delta_i) * (1 - h_{i-1}^2) while the staging settles
       Ops<C, C::NKSH> dn;
       if constexpr (i >= 2) {
-        const A* Ab = wbwd + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
-        dense_layer<C, C::NKSH>(Ab, lane, [&](int ks) { return db[ks]; },
-                                [&](int mb, const typename X::Acc& acc) {
+        auto epi = [&](int mb, const typename X::Acc& acc) {
 #pragma unroll
           for (int j = 0; j < C::NR; ++j) {
             const float hv = value_at<C, C::NKSH>(hb[i - 2], mb, j);
             set_elem<C>(dn[X::ks_of(mb, j)], X::e_of(mb, j), acc[j] * (1.f - hv * hv));
           }
-        });
+        };
+        if constexpr (B::SHW) {
+          dense_layer<C, C::NKSH>(SharedBwdA<C>{wsh + (int64_t)(i - 2) * (C::WH_LAYER / 2), lane},
+                                  [&](int ks) { return db[ks]; }, epi);
+        } else {
+          const A* Ab = wbwd + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
+          dense_layer<C, C::NKSH>(PackedA<C, C::NKSH>{Ab, lane}, [&](int ks) { return db[ks]; }, epi);
+        }
       }
       __syncthreads();
       accumulate(std::integral_constant<int, i - 1>{});
