@@ -84,13 +84,11 @@ __device__ __forceinline__ float tanh_f32(float x) {
   return copysignf(t, x);
 }
 
-// tanh for values that are rounded to bf16 right after: 1 - 2/(e^{2x} + 1) with the
-// hardware base-2 exponential and reciprocal.  Exact limits (e = inf gives 1, e = 0
-// gives -1, no clamp needed); absolute error a few float32 ulps of 1, far below the
-// bf16 rounding of the result.
-__device__ __forceinline__ float tanh_bf16(float x) {
-  float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);   // e^{2x}
-  return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+// tanh(y / (2 log2 e)) for a pre-activation already scaled by 2 log2 e (bf16 layers fold
+// that factor into the bias and apply it with the bias add): 1 - 2/(2^y + 1).
+constexpr float kTanhScale = 2.8853900817779268f;   // 2 log2(e)
+__device__ __forceinline__ float tanh_bf16_scaled(float y) {
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(__builtin_amdgcn_exp2f(y) + 1.0f), 1.0f);
 }
 
 // Compiler-level memory fence: keeps loads from being hoisted across it (e.g. the

@@ -126,7 +126,10 @@ struct Cfg {
   __host__ __device__ static constexpr int swz(int o) { return (((o & 3) << 2) | ((o >> 2) & 3)) & (NCH - 1); }
   static constexpr int64_t OFF_WH = OFF_VEC + (int64_t)NVEC * 4;
   static constexpr int64_t WH_LAYER = (int64_t)HP * HP * 2;
-  static constexpr int64_t PACK = OFF_WH + (SHARED_W ? (NL - 1) * WH_LAYER : 0);
+  // bf16 models: the output layer as one 16-row MFMA A block (rows 0, 1 = the two outputs,
+  // K in the accumulator order of the last hidden layer), [K step][64 lanes]
+  static constexpr int64_t OFF_WO = OFF_WH + (SHARED_W ? (NL - 1) * WH_LAYER : 0);
+  static constexpr int64_t PACK = OFF_WO + (SHARED_W ? (int64_t)NKSH * 64 * 16 : 0);
   // natural dW slot (floats): per layer W block [rows][cols] then bias [rows]
   static constexpr int64_t DW_L1 = (int64_t)HP * C1 + HP;
   static constexpr int64_t DW_H = (int64_t)HP * HP + HP;
@@ -178,10 +181,24 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
   const int64_t n1 = (int64_t)C::NB * C::NKS1 * 64;
   const int64_t nh = (int64_t)(NL - 1) * C::NB * C::NKSH * 64;
   const int64_t nw = C::SHARED_W ? (int64_t)(NL - 1) * C::HP * C::HP : 0;
-  const int64_t total = n1 + 2 * nh + C::NVEC + nw;
+  const int64_t no = C::SHARED_W ? (int64_t)C::NKSH * 64 : 0;
+  const int64_t total = n1 + 2 * nh + C::NVEC + nw + no;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    if (idx >= n1 + 2 * nh + C::NVEC) {
+    if (idx >= n1 + 2 * nh + C::NVEC + nw) {
+      // output-layer A block (bf16)
+      if constexpr (C::SHARED_W) {
+        const int64_t f = idx - (n1 + 2 * nh + C::NVEC + nw);
+        const int lane = (int)(f % 64), ks = (int)(f / 64);
+        const int m = lane % C::MT, g = lane / C::MT;
+        bf16x8 a;
+        for (int ee = 0; ee < 8; ++ee) {
+          const int kk = C::hid_k(ks, g, ee);
+          a[ee] = (__bf16)((m < 2 && kk < H) ? ws[so.w[NL] + (int64_t)m * H + kk] : 0.f);
+        }
+        reinterpret_cast<bf16x8*>(ps + C::OFF_WO)[f] = a;
+      }
+    } else if (idx >= n1 + 2 * nh + C::NVEC) {
       // row-major swizzled hidden weights (bf16)
       if constexpr (C::SHARED_W) {
         const int64_t f = idx - (n1 + 2 * nh + C::NVEC);
@@ -240,8 +257,9 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
       };
       float val = 0.f;
       if (f < NL * C::HP) {
+        // bf16 layers take their bias pre-scaled by 2 log2 e (see tanh_bf16_scaled)
         const int i = f / C::HP, o = neuron(f % C::HP);
-        if (o < H) val = ws[so.b[i] + o];
+        if (o < H) val = ws[so.b[i] + o] * (EPL == 8 ? kTanhScale : 1.0f);
       } else if (f < NL * C::HP + 2 * C::HP) {
         const int r0 = f - NL * C::HP;
         const int c = r0 / C::HP, o = neuron(r0 % C::HP);
@@ -429,6 +447,7 @@ __device__ __forceinline__ float lane_group_sum(float v) {
 // (LDS, Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
 template <class C, int NL>
 __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const __bf16* wh,
+                                              const typename C::A* __restrict__ wout,
                                               const float* vec, int lane, int g, const float2* xw,
                                               Ops<C, C::NKSH> (&hb)[NL]) {
   using A = typename C::A;
@@ -444,13 +463,16 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
 #pragma unroll
       for (int j = 0; j < C::NR; ++j) {
         float v;
-        if constexpr (C::X::EPL == 8) v = tanh_bf16(acc[j] + bias[j]);
-        else v = tanh_f32(acc[j] + bias[j]);
-        set_elem<C>(hb[i][C::X::ks_of(mb, j)], C::X::e_of(mb, j), v);
-        if (i == NL - 1) {
-          o0 = fmaf(wo[vb + j], v, o0);
-          o1 = fmaf(wo[C::HP + vb + j], v, o1);
+        if constexpr (C::X::EPL == 8) {
+          v = tanh_bf16_scaled(fmaf(acc[j], kTanhScale, bias[j]));
+        } else {
+          v = tanh_f32(acc[j] + bias[j]);
+          if (i == NL - 1) {
+            o0 = fmaf(wo[vb + j], v, o0);
+            o1 = fmaf(wo[C::HP + vb + j], v, o1);
+          }
         }
+        set_elem<C>(hb[i][C::X::ks_of(mb, j)], C::X::e_of(mb, j), v);
       }
     };
     if (i == 0) {
@@ -467,10 +489,21 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
       dense_layer<C, C::NKSH>(PackedA<C, C::NKSH>{Ah, lane}, [&](int ks) { return hb[i - 1][ks]; }, epi);
     }
   }
-  o0 = lane_group_sum<C>(o0);
-  o1 = lane_group_sum<C>(o1);
   const float* bo = vec + NL * C::HP + 2 * C::HP;
-  return make_float2(o0 + bo[0], o1 + bo[1]);
+  if constexpr (C::X::EPL == 8) {
+    // output layer on the matrix cores: rows 0 and 1 of a 16-row block land in lane
+    // group 0 (accumulator values 0 and 1); other lane groups return garbage
+    typename C::X::Acc acc;
+#pragma unroll
+    for (int j = 0; j < C::NR; ++j) acc[j] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < C::NKSH; ++ks) acc = C::X::mma(wout[ks * 64 + lane], hb[NL - 1][ks], acc);
+    return make_float2(acc[0] + bo[0], acc[1] + bo[1]);
+  } else {
+    o0 = lane_group_sum<C>(o0);
+    o1 = lane_group_sum<C>(o1);
+    return make_float2(o0 + bo[0], o1 + bo[1]);
+  }
 }
 
 // ------------------------------------------------------------------ forward kernel
@@ -520,7 +553,8 @@ __global__ __launch_bounds__(kFwdThreads) void k_tdnn_fwd(StreamTable st, const 
     Ops<C, C::NKSH> hb[NL];
     const int col = C::MT * wave + sl;
     const A* wops = kLdsWeights ? reinterpret_cast<const A*>(wf) : reinterpret_cast<const A*>(pk);
-    float2 o = mlp_forward<C, NL>(wops, nullptr, vec, lane, g, &xw[col + T - 1], hb);
+    float2 o = mlp_forward<C, NL>(wops, nullptr, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
+                                  &xw[col + T - 1], hb);
     const int64_t n = t0 + col;
     if (g == 0 && n < hi) {
       if (residual) {
@@ -902,7 +936,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const __bf16* wsh = B::SHW ? reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(wlds) + C::OFF_FWDH)
                                : nullptr;
     Ops<C, C::NKSH> hb[NL];
-    (void)mlp_forward<C, NL>(wfwd, wsh, vec, lane, g, &xw[col + B::XB], hb);
+    (void)mlp_forward<C, NL>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
+                             &xw[col + B::XB], hb);
     int lb[2];
     B::lane_bases(g, col, lb);
     // output layer: delta_o = (Re g_u, Im g_u) in staging rows 0 and 1
