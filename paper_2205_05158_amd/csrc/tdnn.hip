@@ -574,32 +574,38 @@ struct BwdLds {
   static constexpr int S = C::S;
   static constexpr int XB = T - 1;
   static constexpr int XW = S + XB;               // x  [t0 - XB, t0 + S)
-  // dW staging [row][sample].  bf16 rows are 128 bytes with the 16-byte chunks of row r
-  // XOR-swizzled by (r/2) mod 8, so the 16-byte MFMA operand reads of 16 consecutive
-  // rows hit all 64 banks once; fp32 rows are padded by 4 floats instead.
-  static constexpr bool SWZ = PREC == DPD_BF16;
-  static_assert(!SWZ || S == 64, "swizzled staging assumes 8 chunks per row");
-  static constexpr int LD = SWZ ? S : S + 4;      // staging row stride (elements)
+  static constexpr int HROWS = cmax(C::C1, C::HP);
+  // dW staging.  bf16 (SM): sample-major [sample][RW neurons]; the 8-byte chunk c (4
+  // neurons) of sample s sits at chunk position c ^ tsw(s), tsw(s) = 4 (s % 4) + (s / 4) % 4
+  // (within groups of MCH chunks), so a lane's 8-byte write of its 4 consecutive neurons
+  // over 16 consecutive samples, and the transposing reads of 4 samples x 4 chunks that
+  // build the dW MFMA operands, hit distinct banks.  fp32: [row][sample], rows padded by
+  // 4 floats.
+  static constexpr bool SM = PREC == DPD_BF16;
+  static_assert(!SM || (S == 64 && C::MT == 16), "sample-major staging of 64-sample bf16 tiles");
+  static constexpr int RW = HROWS;                // SM: neurons per staged sample
+  static constexpr int MCH = RW / 4 < 16 ? RW / 4 : 16;
+  static constexpr int MBP = MCH / 4;             // 16-neuron row blocks per swizzle group
+  static constexpr int LD = S + 4;                // fp32: staging row stride (elements)
+  __host__ __device__ static int tsw(int s) { return ((4 * (s & 3)) | ((s >> 2) & 3)) & (MCH - 1); }
   __device__ static int off(int row, int col) {
-    if constexpr (SWZ) return row * LD + ((((col >> 3) ^ (row >> 1)) & 7) << 3) + (col & 7);
+    if constexpr (SM) return col * RW + 4 * ((row >> 2) ^ tsw(col)) + (row & 3);
     else return row * LD + col;
   }
-  // Rows of lane group g in a layer block are row(j, 0) + 4g (both geometries), so the
-  // staging element of (row MT*mb + row(j, g), column col) is
-  // (MT*mb + row(j, 0))*LD + lb[par(j)] with two lane bases; par(j) is the bit of
-  // row(j, 0) that reaches the swizzle (row(j, 0) < 4 for 16-row blocks).
-  static_assert(!SWZ || C::MT == 16, "swizzled staging pairs with 16-row layer blocks");
-  __host__ __device__ static constexpr int par(int j) { return SWZ ? (C::X::row(j, 0) >> 1) & 1 : 0; }
-  __device__ static void lane_bases(int g, int col, int (&lb)[2]) {
+  // fp32: rows of lane group g in a layer block are row(j, 0) + 4g, so the staging element
+  // of (row MT*mb + row(j, g), column col) is (MT*mb + row(j, 0))*LD + lb[0] with
+  // lb[0] = 4g*LD + col.  bf16: sb[m] = element of neuron chunk 4m + g of sample col, for
+  // m < MBP; chunk 4mb + g of a 16-row block mb is at sb[mb % MBP] + 4*MCH*(mb / MBP).
+  __device__ static void lane_bases(int g, int col, int (&lb)[4]) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
-      lb[p] = 4 * g * LD + (SWZ ? ((((col >> 3) ^ (2 * g + p)) & 7) << 3) + (col & 7) : col);
+    for (int m = 0; m < 4; ++m)
+      lb[m] = SM ? col * RW + 4 * ((4 * (m % MBP) + g) ^ tsw(col)) : 4 * g * LD + col;
   }
-  static constexpr int HROWS = cmax(C::C1, C::HP);
-  static constexpr int STAGE_BYTES = (C::HP + HROWS) * LD * (int)sizeof(typename C::E);
+  static constexpr int STAGE_BYTES = SM ? 2 * S * RW * 2 : (C::HP + HROWS) * LD * 4;
   // bytes of static LDS besides the weight operands
   static constexpr int BIAS_N = NL * C::HP + 32;  // bias-gradient accumulators
-  static constexpr int BASE_BYTES = XW * 8 + C::NVEC * 4 + BIAS_N * 4 + STAGE_BYTES;
+  static constexpr int DSTO_BYTES = SM ? 2 * S * 2 : 0;   // bf16: output-layer delta, [2][S]
+  static constexpr int BASE_BYTES = XW * 8 + C::NVEC * 4 + BIAS_N * 4 + STAGE_BYTES + DSTO_BYTES;
   // Weight operands staged in LDS, the byte range [W_LO, W_HI) of the packed set: both
   // packs when they fit, else the backward (transposed) pack, whose short delta-chain
   // blocks hide global-memory latency worse than the tanh-heavy recompute blocks, else
@@ -641,21 +647,39 @@ struct BwdLds {
 // rows nb of the activation staging (both [row][sample]).  All operand reads are
 // issued before the MFMAs.
 //
-// bf16 (swizzled staging): lo[ks] is the lane's element offset of its 16-byte operand
-// chunk in K step ks within a 32-row block; the bias row sums come from the same
-// operand registers.
+// bf16 (sample-major staging): the 32x32x16 operand of lane (row r = lane%32, K half
+// h = lane/32) holds neuron 32 blk + r over samples 16 ks + 8 h + (0..7).  It is built by
+// two transposing 8-byte reads per K step: in 16-lane group G = lane/16, lane l supplies
+// the chunk of neurons 32 blk + 16 (G%2) + 4 (l%4) .. +3 of sample 16 ks + 8 (G/2) + 4 t +
+// l/4 (t = 0, 1) and receives neuron 32 blk + 16 (G%2) + l over those 4 samples.  The
+// bias row sums come from the same operand registers.
 struct DwOps {
   bf16x8 a[4], b[4];
 };
-template <class C, class B>
-__device__ __forceinline__ void dw_load_bf16(const __bf16* dst, const __bf16* hst, int mb, int nb,
-                                             const int (&lo)[4], DwOps& o) {
-  static_assert(C::S == 64, "four K steps of 16 samples");
+template <class B>
+__device__ __forceinline__ void dw_tr_operand(const __bf16* arr, int blk, int lane, bf16x8 (&op)[4]) {
+  const int G = lane / 16, l = lane % 16;
+  const int c = 8 * blk + 4 * (G % 2) + l % 4;
+  int base[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int tw = (4 * (l / 4) | ((2 * (G / 2) + t) & 3)) & (B::MCH - 1);   // tsw of the sample
+    base[t] = (8 * (G / 2) + 4 * t + l / 4) * B::RW + 4 * (c ^ tw);
+  }
+  typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) {
-    o.a[ks] = *reinterpret_cast<const bf16x8*>(dst + 32 * B::LD * mb + lo[ks]);
-    o.b[ks] = *reinterpret_cast<const bf16x8*>(hst + 32 * B::LD * nb + lo[ks]);
+    const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(arr + base[0] + 16 * ks * B::RW));
+    const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(arr + base[1] + 16 * ks * B::RW));
+    op[ks] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
   }
+}
+template <class C, class B>
+__device__ __forceinline__ void dw_load_bf16(const __bf16* dst, const __bf16* hst, int mb, int nb,
+                                             int lane, DwOps& o) {
+  static_assert(C::S == 64, "four K steps of 16 samples");
+  dw_tr_operand<B>(dst, mb, lane, o.a);
+  dw_tr_operand<B>(hst, nb, lane, o.b);
 }
 template <class C>
 __device__ __forceinline__ void dw_mma_bf16(const DwOps& o, f32x16& acc) {
@@ -724,19 +748,33 @@ __device__ __forceinline__ float delta_row_sum(const typename C::E* dst, int mb,
   return sum + __shfl_xor(sum, 32);
 }
 
-// Stage a layer held in operand form: value (mb, j) of lane group g goes to row
-// MT*mb + row(j, g), column col, i.e. element (MT*mb + row(j, 0))*LD + lb[par(j)] with
-// the lane bases of BwdLds::lane_bases.
+// Stage a layer held in operand form (lane bases of BwdLds::lane_bases).  bf16: the
+// lane's 4 consecutive neurons 16 mb + 4 g + (0..3) of row block mb are 4 consecutive
+// elements of its operand register (one 8-byte write); fp32: value (mb, j) goes to row
+// MT*mb + row(j, g), column col.
 template <class C, class B, int NKS>
-__device__ __forceinline__ void stage_layer(typename C::E* stage, const int (&lb)[2],
+__device__ __forceinline__ void stage_layer(typename C::E* stage, const int (&lb)[4],
                                             const Ops<C, NKS>& ops) {
+  if constexpr (B::SM) {
 #pragma unroll
-  for (int ks = 0; ks < NKS; ++ks)
+    for (int ks = 0; ks < NKS; ++ks) {
+      const uint4 w = __builtin_bit_cast(uint4, ops[ks]);
 #pragma unroll
-    for (int e = 0; e < C::X::EPL; ++e) {
-      const int mb = C::X::mb_of(ks, e), j = C::X::j_of(ks, e);
-      stage[(C::MT * mb + C::X::row(j, 0)) * B::LD + lb[B::par(j)]] = (typename C::E)get_elem<C>(ops[ks], e);
+      for (int h2 = 0; h2 < 2; ++h2) {
+        const int mb = C::X::mb_of(ks, 4 * h2);          // elements 4 h2 .. 4 h2 + 3
+        const uint2 v = h2 ? make_uint2(w.z, w.w) : make_uint2(w.x, w.y);
+        *reinterpret_cast<uint2*>(stage + lb[mb % B::MBP] + 4 * B::MCH * (mb / B::MBP)) = v;
+      }
     }
+  } else {
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+      for (int e = 0; e < C::X::EPL; ++e) {
+        const int mb = C::X::mb_of(ks, e), j = C::X::j_of(ks, e);
+        stage[(C::MT * mb + C::X::row(j, 0)) * B::LD + lb[0]] = (typename C::E)get_elem<C>(ops[ks], e);
+      }
+  }
 }
 
 // Reverse mode of the TDNN over the stream table's tiles, from g_u (= dL/du per sample,
@@ -759,8 +797,9 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   __shared__ float bacc[B::BIAS_N];
   __shared__ __attribute__((aligned(16))) char un[B::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint4 wlds[B::W_BYTES / 16];
+  __shared__ __attribute__((aligned(16))) __bf16 dsto[B::SM ? 2 * S : 8];
   E* dst = reinterpret_cast<E*>(un);
-  E* hst = dst + C::HP * B::LD;
+  E* hst = dst + (B::SM ? S * B::RW : C::HP * B::LD);
 
   const int tid = threadIdx.x;
   const int wave_u = __builtin_amdgcn_readfirstlane(tid / 64);
@@ -773,9 +812,6 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   // the thread index, so the compiler cannot precompute the hundreds of per-block LDS and
   // global addresses outside the tile loop (they would not fit in registers).
   int lane = tid % 64;
-  // lane offsets of the dW operand chunks (bf16 swizzled staging): row lane%32, chunk
-  // 2*ks + lane/32
-  int dlo[4] = {0, 0, 0, 0};
 
   // dW accumulators of this wave's blocks, kept in registers for the whole tile range
   // of one stream and written to its slot once.
@@ -784,7 +820,9 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   for (int q = 0; q < B::NQ; ++q)
 #pragma unroll
     for (int j = 0; j < 16; ++j) dwacc[q][j] = 0.f;
-  float dwo = 0.f;   // output-layer dW element (tid / HP, tid % HP)
+  // output-layer dW: fp32, element (tid / HP, tid % HP); bf16, rows 0 and 1 at column
+  // 32 wave + lane of the lanes lane < 32 of waves wave < HP / 32
+  float dwo = 0.f, dwo1 = 0.f;
   for (int i = tid; i < B::BIAS_N; i += kThreads) bacc[i] = 0.f;
 
   // Write this workgroup's partial dW of stream s (plain stores: each (workgroup,
@@ -812,8 +850,15 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
 #pragma unroll
       for (int j = 0; j < 16; ++j) dwacc[q][j] = 0.f;
     }
-    if (tid < 2 * C::HP) slot[C::dw_off(NL) + tid] = dwo;   // row tid / HP, column tid % HP
-    dwo = 0.f;
+    if constexpr (B::SM) {
+      if (wv < C::NBD && ln < 32) {
+        slot[C::dw_off(NL) + 32 * wv + ln] = dwo;
+        slot[C::dw_off(NL) + C::HP + 32 * wv + ln] = dwo1;
+      }
+    } else {
+      if (tid < 2 * C::HP) slot[C::dw_off(NL) + tid] = dwo;   // row tid / HP, column tid % HP
+    }
+    dwo = dwo1 = 0.f;
     for (int i = tid; i < B::BIAS_N; i += kThreads) {
       const int li = i / C::HP, o = i % C::HP;
       float* dstb = li < NL ? slot + C::dw_off(li) + (int64_t)C::HP * (li == 0 ? C::C1 : C::HP) + o
@@ -831,14 +876,14 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     constexpr int q0 = off / kWaves, q1 = (off + cnt - 1) / kWaves;
     float* bl = bacc + li * C::HP;
     const int h = lane / 32, r = lane % 32;
-    if constexpr (B::SWZ) {
+    if constexpr (B::SM) {
       // the operands of the wave's next block are read while this block's MFMAs run
       DwOps ops[2];
       auto valid = [&](int q) { const int bi = kWaves * q + wave_u; return bi >= off && bi < off + cnt; };
       auto load = [&](int q, DwOps& o) {
         int mb, nb;
         B::blk_rc(kWaves * q + wave_u - off, nnb, mb, nb);
-        dw_load_bf16<C, B>(dst, hst, mb, nb, dlo, o);
+        dw_load_bf16<C, B>(dst, hst, mb, nb, lane, o);
       };
       if (valid(q0)) load(q0, ops[0]);
 #pragma unroll
@@ -900,11 +945,6 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     lane = tq % 64;
     const int g = lane / C::MT, sl = lane % C::MT;
     const int col = C::MT * wave_u + sl;
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int r = lane % 32, c = 2 * ks + lane / 32;
-      dlo[ks] = B::SWZ ? r * B::LD + (((c ^ (r >> 1)) & 7) << 3) : 0;
-    }
 
     __syncthreads();   // previous tile finished with every LDS buffer and accumulator
     if (s != cur_stream) {
@@ -938,41 +978,63 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     Ops<C, C::NKSH> hb[NL];
     (void)mlp_forward<C, NL>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
                              &xw[col + B::XB], hb);
-    int lb[2];
+    int lb[4];
     B::lane_bases(g, col, lb);
-    // output layer: delta_o = (Re g_u, Im g_u) in staging rows 0 and 1
+    // output layer: delta_o = (Re g_u, Im g_u) (bf16: its own [2][S] array; fp32: staging
+    // rows 0 and 1)
     if (g == 0) {
-      dst[B::off(0, col)] = (E)gsum.x;
-      dst[B::off(1, col)] = (E)gsum.y;
+      if constexpr (B::SM) {
+        dsto[col] = (__bf16)gsum.x;
+        dsto[S + col] = (__bf16)gsum.y;
+      } else {
+        dst[B::off(0, col)] = (E)gsum.x;
+        dst[B::off(1, col)] = (E)gsum.y;
+      }
     }
     stage_layer<C, B, C::NKSH>(hst, lb, hb[NL - 1]);
     __syncthreads();
-    // output-layer dW element (c, n) += sum_s delta_o[c][s] h_NL[n][s]; bias by n == 0
-    if (tid < 2 * C::HP) {
+    if constexpr (B::SM) {
+      // output-layer dW on the matrix cores: wave w takes neurons 32 w .. 32 w + 31 of
+      // h_NL; A rows 0, 1 = delta_o (other rows zero), so rows 0 and 1 of the product are
+      // dW_o for those columns (accumulator values 0 and 1 of lanes 0..31)
+      if (wave_u < C::NBD) {
+        bf16x8 bop[4], aop[4];
+        dw_tr_operand<B>(hst, wave_u, lane, bop);
+        const int r = lane % 32, h = lane / 32;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          bf16x8 z;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) z[e] = (__bf16)0.f;
+          aop[ks] = r < 2 ? *reinterpret_cast<const bf16x8*>(dsto + r * S + 16 * ks + 8 * h) : z;
+        }
+        f32x16 tmp;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) tmp[j] = 0.f;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) tmp = C::D::mma(aop[ks], bop[ks], tmp);
+        if (h == 0) {
+          dwo += tmp[0];
+          dwo1 += tmp[1];
+        }
+        if (wave_u == 0) {        // output-layer bias: rows 0 and 1 summed over the samples
+          DwOps o;
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks) o.a[ks] = aop[ks];
+          const float sum = dw_rowsum_bf16(o);
+          if (h == 0 && r < 2) bacc[NL * C::HP + r] += sum;
+        }
+      }
+    } else if (tid < 2 * C::HP) {
+      // fp32: output-layer dW element (c, n) += sum_s delta_o[c][s] h_NL[n][s]; bias by n == 0
       const int c = tid / C::HP, n = tid % C::HP;
       float acc = 0.f, bsum = 0.f;
-      if constexpr (B::SWZ) {
-        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-        const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
-#pragma unroll
-        for (int k = 0; k < S / 8; ++k) {
-          const bf16x8 da = *reinterpret_cast<const bf16x8*>(dst + B::off(c, 8 * k));
-          const bf16x8 hv = *reinterpret_cast<const bf16x8*>(hst + B::off(n, 8 * k));
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            const bf16x2 p = {da[e], da[e + 1]}, q2 = {hv[e], hv[e + 1]};
-            acc = __builtin_amdgcn_fdot2_f32_bf16(p, q2, acc, false);
-            bsum = __builtin_amdgcn_fdot2_f32_bf16(p, one, bsum, false);
-          }
-        }
-      } else {
 #pragma unroll 2
-        for (int k = 0; k < S; k += 4) {
-          const float4 da = *reinterpret_cast<const float4*>(dst + B::off(c, k));
-          const float4 hv = *reinterpret_cast<const float4*>(hst + B::off(n, k));
-          acc = fmaf(da.x, hv.x, fmaf(da.y, hv.y, fmaf(da.z, hv.z, fmaf(da.w, hv.w, acc))));
-          bsum += (da.x + da.y) + (da.z + da.w);
-        }
+      for (int k = 0; k < S; k += 4) {
+        const float4 da = *reinterpret_cast<const float4*>(dst + B::off(c, k));
+        const float4 hv = *reinterpret_cast<const float4*>(hst + B::off(n, k));
+        acc = fmaf(da.x, hv.x, fmaf(da.y, hv.y, fmaf(da.z, hv.z, fmaf(da.w, hv.w, acc))));
+        bsum += (da.x + da.y) + (da.z + da.w);
       }
       dwo += acc;
       if (n == 0) bacc[NL * C::HP + c] += bsum;
@@ -1001,17 +1063,33 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
         // features at their natural rows: lane group g holds rows [g*FPG, g*FPG + FPG)
         Ops<C, C::NKS1> feat;
         make_features<C>(&xw[col + B::XB], g, feat);
+        if constexpr (B::SM && C::FPG % 4 == 0) {
+          // 4 consecutive features per 8-byte write; chunks of the padding rows zeroed by
+          // lane group 0
 #pragma unroll
-        for (int ks = 0; ks < C::NKS1; ++ks)
-#pragma unroll
-          for (int e = 0; e < X::EPL; ++e) {
-            const int f = X::EPL * ks + e;
+          for (int f = 0; f < C::FPG; f += 4) {
             const int k = C::FPG * g + f;
-            if (f < C::FPG && k < C::KIN) hst[B::off(k, col)] = (E)get_elem<C>(feat[ks], e);
+            const uint4 w = __builtin_bit_cast(uint4, feat[f / 8]);
+            const uint2 v = (f / 4) % 2 ? make_uint2(w.z, w.w) : make_uint2(w.x, w.y);
+            if (k < C::KIN) *reinterpret_cast<uint2*>(hst + B::off(k, col)) = v;
           }
+          if (g == 0) {
 #pragma unroll
-        for (int k = C::KIN; k < C::C1; ++k)
-          if (k % C::LG == g) hst[B::off(k, col)] = (E)0.f;
+            for (int k = C::KIN; k < C::C1; k += 4) *reinterpret_cast<uint2*>(hst + B::off(k, col)) = make_uint2(0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int ks = 0; ks < C::NKS1; ++ks)
+#pragma unroll
+            for (int e = 0; e < X::EPL; ++e) {
+              const int f = X::EPL * ks + e;
+              const int k = C::FPG * g + f;
+              if (f < C::FPG && k < C::KIN) hst[B::off(k, col)] = (E)get_elem<C>(feat[ks], e);
+            }
+#pragma unroll
+          for (int k = C::KIN; k < C::C1; ++k)
+            if (k % C::LG == g) hst[B::off(k, col)] = (E)0.f;
+        }
       }
       // delta_{i-1} = (W_i^T delta_i) * (1 - h_{i-1}^2) while the staging settles
       Ops<C, C::NKSH> dn;
