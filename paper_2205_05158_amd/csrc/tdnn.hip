@@ -33,8 +33,12 @@ namespace {
 
 constexpr int kWaves = 4;               // backward kernel: one wave per SIMD
 constexpr int kThreads = 64 * kWaves;
-constexpr int kFwdWaves = 8;            // forward kernel: two waves per SIMD share the LDS weights
-constexpr int kFwdThreads = 64 * kFwdWaves;
+// Forward kernel waves per workgroup: the workgroup shares one LDS copy of the weights, so
+// its wave count sets the waves per SIMD; the bf16 kernel of width 128 fits three per SIMD
+// in registers, the others two.
+__host__ __device__ constexpr int fwd_waves(int prec, int hidden) {
+  return prec == DPD_BF16 && hidden >= 128 ? 12 : 8;
+}
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
@@ -507,17 +511,18 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
 }
 
 // ------------------------------------------------------------------ forward kernel
-// Each workgroup (kFwdWaves waves, MT samples each) owns a contiguous range of tiles; the
+// Each workgroup (fwd_waves waves, MT samples each) owns a contiguous range of tiles; the
 // forward weight operands of the current parameter set live in LDS (reloaded only when
 // the set changes) unless they exceed the LDS budget, in which case they are read from
 // global memory (L2).
 template <int PREC, int T, int H, int NL>
-__global__ __launch_bounds__(kFwdThreads) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
+__global__ __launch_bounds__(64 * fwd_waves(PREC, H)) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
                                                           const char* __restrict__ pack, int residual,
                                                           float* __restrict__ u) {
   using C = Cfg<PREC, T, H, NL>;
   using A = typename C::A;
-  constexpr int S = C::MT * kFwdWaves;
+  constexpr int kFwdThreads = 64 * fwd_waves(PREC, H);
+  constexpr int S = C::MT * fwd_waves(PREC, H);
   constexpr int XW = S + T - 1;
   constexpr bool kLdsWeights = C::OFF_BWDH <= 144 * 1024;
   constexpr int NWF = kLdsWeights ? (int)(C::OFF_BWDH / 16) : 1;
@@ -1200,7 +1205,7 @@ bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out) {
     td.nks1 = C::NKS1;
     td.nksh = C::NKSH;
     td.tile = C::S;
-    td.fwd_tile = C::MT * kFwdWaves;
+    td.fwd_tile = C::MT * fwd_waves(P_, H_);
     td.pack_bytes = C::PACK;
     td.fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (td.fwd_tile + T_) + 4 * C::NVEC;
     td.dw_slot = C::SLOT;
@@ -1227,7 +1232,7 @@ void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_strid
 void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
                      float* u, int grid, hipStream_t s) {
   tdnn_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
-    k_tdnn_fwd<P_, T_, H_, NL_><<<grid, kFwdThreads, 0, s>>>(st, x, static_cast<const char*>(pack),
+    k_tdnn_fwd<P_, T_, H_, NL_><<<grid, 64 * fwd_waves(P_, H_), 0, s>>>(st, x, static_cast<const char*>(pack),
                                                          td.residual, u);
   });
 }
