@@ -124,7 +124,9 @@ struct Cfg {
   // in LDS by the backward kernel's forward recompute (two 8-byte reads per operand) and
   // its delta chain (two transposing 8-byte reads per operand): element (o, k) of a layer
   // at o*HP + 4*((k/4) ^ swz(o)) + k%4.  The chunk swizzle swaps the two 2-bit fields of
-  // o mod 16, which keeps both read patterns free of bank conflicts.
+  // o mod 16, so the 16-lane halves of both read patterns hit distinct banks.  (A swizzle
+  // that also separates the 32-lane halves over the 64 banks costs the backward kernel
+  // registers and measured slower.)
   static constexpr bool SHARED_W = X::EPL == 8;
   static constexpr int NCH = HP / 4;                    // 8-byte chunks per row
   __host__ __device__ static constexpr int swz(int o) { return (((o & 3) << 2) | ((o >> 2) & 3)) & (NCH - 1); }
@@ -581,30 +583,43 @@ struct BwdLds {
   static constexpr int XW = S + XB;               // x  [t0 - XB, t0 + S)
   static constexpr int HROWS = cmax(C::C1, C::HP);
   // dW staging.  bf16 (SM): sample-major [sample][RW neurons]; the 8-byte chunk c (4
-  // neurons) of sample s sits at chunk position c ^ tsw(s), tsw(s) = 4 (s % 4) + (s / 4) % 4
-  // (within groups of MCH chunks), so a lane's 8-byte write of its 4 consecutive neurons
-  // over 16 consecutive samples, and the transposing reads of 4 samples x 4 chunks that
-  // build the dW MFMA operands, hit distinct banks.  fp32: [row][sample], rows padded by
-  // 4 floats.
+  // neurons) of sample s sits at chunk position c ^ tsw(s), so the 8-byte writes of a
+  // lane group's 4 consecutive neurons over 16 consecutive samples, and the transposing
+  // reads of 4 samples x 4 chunks per 16 lanes that build the dW MFMA operands, hit
+  // distinct banks.  With 256-byte sample rows (one sweep of the 64 banks), s mod 16 =
+  // 4q + i (i = i1 i0, q = q1 q0 in bits) and tsw = 16 i1 + 8 i0 + 4 (i1 ^ q1) + 2 q0 + q1:
+  // its bits 4..1 and 3..0 each take 16 values over 16 samples (writes, 32- and 16-lane
+  // halves) and bits 4..3 and 3..2 each 4 values over 4 samples (reads).  Narrower rows
+  // use 4 i + q within the row's chunks.  fp32: [row][sample], rows padded by 4 floats.
   static constexpr bool SM = PREC == DPD_BF16;
   static_assert(!SM || (S == 64 && C::MT == 16), "sample-major staging of 64-sample bf16 tiles");
   static constexpr int RW = HROWS;                // SM: neurons per staged sample
-  static constexpr int MCH = RW / 4 < 16 ? RW / 4 : 16;
-  static constexpr int MBP = MCH / 4;             // 16-neuron row blocks per swizzle group
+  static constexpr int NPR = RW / 4;              // SM: 8-byte chunks per sample row
   static constexpr int LD = S + 4;                // fp32: staging row stride (elements)
-  __host__ __device__ static int tsw(int s) { return ((4 * (s & 3)) | ((s >> 2) & 3)) & (MCH - 1); }
+  __host__ __device__ static int tsw(int s) {
+    if (NPR == 32) {
+      const int i0 = s & 1, i1 = (s >> 1) & 1, q0 = (s >> 2) & 1, q1 = (s >> 3) & 1;
+      return 16 * i1 + 8 * i0 + 4 * (i1 ^ q1) + 2 * q0 + q1;
+    }
+    return ((4 * (s & 3)) | ((s >> 2) & 3)) & (NPR - 1);
+  }
   __device__ static int off(int row, int col) {
     if constexpr (SM) return col * RW + 4 * ((row >> 2) ^ tsw(col)) + (row & 3);
     else return row * LD + col;
   }
   // fp32: rows of lane group g in a layer block are row(j, 0) + 4g, so the staging element
   // of (row MT*mb + row(j, g), column col) is (MT*mb + row(j, 0))*LD + lb[0] with
-  // lb[0] = 4g*LD + col.  bf16: sb[m] = element of neuron chunk 4m + g of sample col, for
-  // m < MBP; chunk 4mb + g of a 16-row block mb is at sb[mb % MBP] + 4*MCH*(mb / MBP).
-  __device__ static void lane_bases(int g, int col, int (&lb)[4]) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      lb[m] = SM ? col * RW + 4 * ((4 * (m % MBP) + g) ^ tsw(col)) : 4 * g * LD + col;
+  // lb[0] = 4g*LD + col.  bf16: neuron chunk 4 mb + g of sample col is at position
+  // 4 (mb ^ (tsw >> 2)) + (g ^ (tsw & 3)), i.e. element lb[0] + 16 (mb ^ lb[1]).
+  __device__ static void lane_bases(int g, int col, int (&lb)[2]) {
+    if constexpr (SM) {
+      const int t = tsw(col);
+      lb[0] = col * RW + 4 * (g ^ (t & 3));
+      lb[1] = t >> 2;
+    } else {
+      lb[0] = 4 * g * LD + col;
+      lb[1] = 0;
+    }
   }
   static constexpr int STAGE_BYTES = SM ? 2 * S * RW * 2 : (C::HP + HROWS) * LD * 4;
   // bytes of static LDS besides the weight operands
@@ -639,12 +654,27 @@ struct BwdLds {
   }
   __host__ __device__ static constexpr int blk_cnt(int li) { return li == 0 ? NBL1 : NBLH; }
   __host__ __device__ static constexpr int blk_cols(int li) { return li == 0 ? C::NN1 : C::NBD; }
-  // (row block, column block) of block blk of a layer with nnb column blocks; the column
-  // index is rotated by the row index so the bias rows (column block 0) spread over the
-  // waves
+  // bf16 layers with one delta row block per wave: each wave's blocks share operands, a
+  // 2x2 quadrant of a 4x4 layer (QUAD) or one row block of the others (STRIP), so every
+  // staged operand a wave needs is read from LDS once per tile.
+  __host__ __device__ static constexpr bool QUAD(int nnb) { return SM && C::NBD == kWaves && nnb == 4; }
+  __host__ __device__ static constexpr bool STRIP(int nnb) { return SM && C::NBD == kWaves && nnb != 4; }
+  // (row block, column block) of block blk of a layer with nnb column blocks (block blk is
+  // held by wave blk % kWaves; the layer offsets are multiples of kWaves when QUAD or
+  // STRIP applies).  Otherwise the column index is rotated by the row index so the bias
+  // rows (column block 0) spread over the waves.
   __device__ static void blk_rc(int blk, int nnb, int& mb, int& nb) {
-    mb = blk / nnb;
-    nb = (blk % nnb + mb) % nnb;
+    if (QUAD(nnb)) {
+      const int w = blk % kWaves, k = blk / kWaves;
+      mb = 2 * (w / 2) + k / 2;
+      nb = 2 * (w % 2) + k % 2;
+    } else if (STRIP(nnb)) {
+      mb = blk % kWaves;
+      nb = blk / kWaves;
+    } else {
+      mb = blk / nnb;
+      nb = (blk % nnb + mb) % nnb;
+    }
   }
 };
 
@@ -661,15 +691,17 @@ struct BwdLds {
 struct DwOps {
   bf16x8 a[4], b[4];
 };
-template <class B>
-__device__ __forceinline__ void dw_tr_operand(const __bf16* arr, int blk, int lane, bf16x8 (&op)[4]) {
+template <class B, class P>
+__device__ __forceinline__ void dw_tr_operand(const P* stage, int blk, int lane, bf16x8 (&op)[4]) {
+  static_assert(sizeof(P) == 2, "bf16 staging");
+  const __bf16* arr = reinterpret_cast<const __bf16*>(stage);
   const int G = lane / 16, l = lane % 16;
   const int c = 8 * blk + 4 * (G % 2) + l % 4;
   int base[2];
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const int tw = (4 * (l / 4) | ((2 * (G / 2) + t) & 3)) & (B::MCH - 1);   // tsw of the sample
-    base[t] = (8 * (G / 2) + 4 * t + l / 4) * B::RW + 4 * (c ^ tw);
+    const int sm = 8 * (G / 2) + 4 * t + l / 4;   // sample mod 16
+    base[t] = sm * B::RW + 4 * (c ^ B::tsw(sm));
   }
   typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
 #pragma unroll
@@ -687,12 +719,16 @@ __device__ __forceinline__ void dw_load_bf16(const __bf16* dst, const __bf16* hs
   dw_tr_operand<B>(hst, nb, lane, o.b);
 }
 template <class C>
-__device__ __forceinline__ void dw_mma_bf16(const DwOps& o, f32x16& acc) {
+__device__ __forceinline__ void dw_mma_bf16(const bf16x8 (&a)[4], const bf16x8 (&b)[4], f32x16& acc) {
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) acc = C::D::mma(o.a[ks], o.b[ks], acc);
+  for (int ks = 0; ks < 4; ++ks) acc = C::D::mma(a[ks], b[ks], acc);
 }
-// sum over the tile's samples of the delta row held in o.a (both lane halves)
-__device__ __forceinline__ float dw_rowsum_bf16(const DwOps& o) {
+template <class C>
+__device__ __forceinline__ void dw_mma_bf16(const DwOps& o, f32x16& acc) {
+  dw_mma_bf16<C>(o.a, o.b, acc);
+}
+// sum over the tile's samples of the delta row held in a (both lane halves)
+__device__ __forceinline__ float dw_rowsum_bf16(const bf16x8 (&a)[4]) {
   typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
   const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
   float sum = 0.f;
@@ -700,7 +736,7 @@ __device__ __forceinline__ float dw_rowsum_bf16(const DwOps& o) {
   for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
     for (int e = 0; e < 8; e += 2) {
-      const bf16x2 pr = {o.a[ks][e], o.a[ks][e + 1]};
+      const bf16x2 pr = {a[ks][e], a[ks][e + 1]};
       sum = __builtin_amdgcn_fdot2_f32_bf16(pr, one, sum, false);
     }
   return sum + __shfl_xor(sum, 32);
@@ -758,9 +794,12 @@ __device__ __forceinline__ float delta_row_sum(const typename C::E* dst, int mb,
 // elements of its operand register (one 8-byte write); fp32: value (mb, j) goes to row
 // MT*mb + row(j, g), column col.
 template <class C, class B, int NKS>
-__device__ __forceinline__ void stage_layer(typename C::E* stage, const int (&lb)[4],
+__device__ __forceinline__ void stage_layer(typename C::E* stage, const int (&lb)[2],
                                             const Ops<C, NKS>& ops) {
   if constexpr (B::SM) {
+    // opaque copies: the per-block addresses are formed here, not kept live across layers
+    int b0 = lb[0], th = lb[1];
+    asm volatile("" : "+v"(b0), "+v"(th));
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const uint4 w = __builtin_bit_cast(uint4, ops[ks]);
@@ -768,7 +807,7 @@ __device__ __forceinline__ void stage_layer(typename C::E* stage, const int (&lb
       for (int h2 = 0; h2 < 2; ++h2) {
         const int mb = C::X::mb_of(ks, 4 * h2);          // elements 4 h2 .. 4 h2 + 3
         const uint2 v = h2 ? make_uint2(w.z, w.w) : make_uint2(w.x, w.y);
-        *reinterpret_cast<uint2*>(stage + lb[mb % B::MBP] + 4 * B::MCH * (mb / B::MBP)) = v;
+        *reinterpret_cast<uint2*>(stage + b0 + 16 * (mb ^ th)) = v;
       }
     }
   } else {
@@ -881,7 +920,45 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     constexpr int q0 = off / kWaves, q1 = (off + cnt - 1) / kWaves;
     float* bl = bacc + li * C::HP;
     const int h = lane / 32, r = lane % 32;
-    if constexpr (B::SM) {
+    if constexpr (B::QUAD(nnb)) {
+      // the wave's 2x2 quadrant: delta row blocks mb0, mb0 + 1 x activation column blocks
+      // nb0, nb0 + 1 (dwacc[q0 .. q0 + 3] in blk_rc order)
+      static_assert(off % kWaves == 0 && cnt == 4 * kWaves, "quadrant layout");
+      const int mb0 = 2 * (wave_u / 2), nb0 = 2 * (wave_u % 2);
+      bf16x8 a0[4], a1[4], b0[4], b1[4];
+      dw_tr_operand<B>(dst, mb0, lane, a0);
+      dw_tr_operand<B>(hst, nb0, lane, b0);
+      dw_tr_operand<B>(hst, nb0 + 1, lane, b1);
+      dw_tr_operand<B>(dst, mb0 + 1, lane, a1);
+      dw_mma_bf16<C>(a0, b0, dwacc[q0]);
+      dw_mma_bf16<C>(a0, b1, dwacc[q0 + 1]);
+      dw_mma_bf16<C>(a1, b0, dwacc[q0 + 2]);
+      dw_mma_bf16<C>(a1, b1, dwacc[q0 + 3]);
+      if (nb0 == 0) {
+        const float s0 = dw_rowsum_bf16(a0), s1 = dw_rowsum_bf16(a1);
+        if (h == 0) {
+          bl[32 * mb0 + r] += s0;
+          bl[32 * mb0 + 32 + r] += s1;
+        }
+      }
+      return;
+    } else if constexpr (B::STRIP(nnb)) {
+      // the wave's row block mb = wave against every activation column block; the next
+      // column operand is read while the current block's MFMAs run
+      static_assert(off % kWaves == 0 && cnt == nnb * kWaves, "strip layout");
+      bf16x8 a[4], b[2][4];
+      dw_tr_operand<B>(dst, wave_u, lane, a);
+      dw_tr_operand<B>(hst, 0, lane, b[0]);
+#pragma unroll
+      for (int k = 0; k < nnb; ++k) {
+        if (k + 1 < nnb) dw_tr_operand<B>(hst, k + 1, lane, b[(k + 1) & 1]);
+        DPD_KEEP_LOADS_LOCAL();
+        dw_mma_bf16<C>(a, b[k & 1], dwacc[q0 + k]);
+      }
+      const float sum = dw_rowsum_bf16(a);
+      if (h == 0) bl[32 * wave_u + r] += sum;
+      return;
+    } else if constexpr (B::SM) {
       // the operands of the wave's next block are read while this block's MFMAs run
       DwOps ops[2];
       auto valid = [&](int q) { const int bi = kWaves * q + wave_u; return bi >= off && bi < off + cnt; };
@@ -901,7 +978,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
           int mb, nb;
           B::blk_rc(kWaves * q + wave_u - off, nnb, mb, nb);
           if (nb == 0) {
-            const float sum = dw_rowsum_bf16(o);
+            const float sum = dw_rowsum_bf16(o.a);
             if (h == 0) bl[32 * mb + r] += sum;
           }
         }
@@ -983,7 +1060,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     Ops<C, C::NKSH> hb[NL];
     (void)mlp_forward<C, NL>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
                              &xw[col + B::XB], hb);
-    int lb[4];
+    int lb[2];
     B::lane_bases(g, col, lb);
     // output layer: delta_o = (Re g_u, Im g_u) (bf16: its own [2][S] array; fp32: staging
     // rows 0 and 1)
@@ -1023,10 +1100,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
           dwo1 += tmp[1];
         }
         if (wave_u == 0) {        // output-layer bias: rows 0 and 1 summed over the samples
-          DwOps o;
-#pragma unroll
-          for (int ks = 0; ks < 4; ++ks) o.a[ks] = aop[ks];
-          const float sum = dw_rowsum_bf16(o);
+          const float sum = dw_rowsum_bf16(aop);
           if (h == 0 && r < 2) bacc[NL * C::HP + r] += sum;
         }
       }
