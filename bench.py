@@ -77,6 +77,11 @@ def parse():
                     help="samples of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the unit-throughput probes")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="tuned path: keep the default launch shapes instead of autotuning them")
+    ap.add_argument("--shape", default=None,
+                    help="tuned path: launch shapes as JSON (the dpd_tune fields), installed "
+                         "instead of autotuning (e.g. to profile the shapes a bench line used)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device-to-device copies of 256 MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -231,6 +236,19 @@ def main():
         psd = torch.empty(4096, dtype=torch.float32, device="cuda")
         acpr = torch.empty(3, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
+    shape, shape_src = None, None
+    if args.impl == "tuned":
+        if args.shape:
+            cas.set_tune(json.loads(args.shape))
+            shape_src = "given"
+        elif not args.no_autotune:
+            print("[bench] autotuning launch shapes", file=sys.stderr, flush=True)
+            cas.autotune(x, w, coef, reps=3)
+            shape_src = "autotuned"
+        else:
+            shape_src = "default"
+        shape = cas.tune()
+        print(f"[bench] launch shapes ({shape_src}): {json.dumps(shape)}", file=sys.stderr, flush=True)
 
     def step():
         D.dpd_cascade(cas.tdnn, cas.gmp, cas.batch, x, w, coef, 1.0, u, y, nm, dw, loss,
@@ -325,7 +343,8 @@ def main():
                    "gmp": f"K{wl.K} M{wl.M} L{wl.L}", "impl": args.impl,
                    "step": "dpd_cascade(u, y, nmse, dW, loss) + cascade_acpr" if do_acpr
                            else "dpd_cascade(u, y, nmse, dW, loss)",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "launch_shape": shape, "launch_shape_source": shape_src},
         "roofline": roof,
         "step_roofline": step_roof,
         "peaks_measured": peaks,

@@ -17,8 +17,9 @@
  * Conventions for every entry point
  *   - Pointers named *_host are host memory; every other array pointer is DEVICE
  *     memory.  The caller allocates and owns every buffer, including the
- *     workspace.  The library never allocates, never synchronises the device,
- *     and enqueues all work on the caller's `stream` (in order).
+ *     workspace.  The library never allocates device memory, never synchronises
+ *     the device, and enqueues all work on the caller's `stream` (in order); the
+ *     one exception is dpd_autotune, which waits for its own timing events.
  *   - Complex sample streams are interleaved float32 (re, im), 8 bytes per sample,
  *     8-byte aligned.  Streams are concatenated; stream s occupies samples
  *     [offsets_host[s], offsets_host[s+1]).  Each stream is independent and
@@ -27,8 +28,9 @@
  *     negative dpd_status is returned and nothing is enqueued.  A launch failure
  *     reported by the runtime after enqueueing returns DPD_ERR_LAUNCH.
  *   - Calls are thread-safe; the library's only mutable global state is a lazily
- *     filled, mutex-guarded cache of device properties and the opt-in kernel timer
- *     (dpd_profile_enable), also mutex-guarded.
+ *     filled, mutex-guarded cache of device properties, the launch-shape table
+ *     (dpd_tune_set / dpd_autotune) and the opt-in kernel timer
+ *     (dpd_profile_enable), each mutex-guarded.
  */
 #ifndef DPDMI_H
 #define DPDMI_H
@@ -141,6 +143,51 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                        const float* coef, float g_re, float g_im,
                        float* u, float* y, float* nmse, float* dw, float* loss,
                        void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Launch shapes of the tuned path.  The many-stream persistent launches (the
+ * per-antenna DPDs of the paper's massive-MIMO setting, Sec. II and V) run with
+ * tile shapes and grid sizes picked at run time among compiled variants:
+ *   fwd_waves      waves per forward workgroup: 8 or 12 (tile = waves x 16 samples
+ *                  in bf16, waves x 32 in fp32);
+ *   fwd_wg_per_cu  forward workgroups per compute unit, 1..4 (capped by the tiles);
+ *   bwd_wg_per_cu  backward (reverse-mode) workgroups per compute unit, 1..2
+ *                  (capped at 512 workgroups and by the tiles);
+ *   gmp_tile       samples per GMP reverse-mode workgroup: 256 or 512.
+ * The shape never changes u or y (bitwise); the NMSE, the loss and dW may change by
+ * float32 rounding (their partial sums are grouped by tile and workgroup).
+ * A problem is keyed by the TDNN descriptor, the GMP descriptor (none for
+ * dpd_forward) and the batch signature (n_streams, per_stream_params, total and
+ * longest stream length).  Problems without an entry use the defaults. */
+typedef struct {
+    int32_t fwd_waves;
+    int32_t fwd_wg_per_cu;
+    int32_t bwd_wg_per_cu;
+    int32_t gmp_tile;
+} dpd_tune;
+
+/* Shape the tuned-path calls use for this problem (its table entry, else the
+ * defaults).  gmp may be NULL (the dpd_forward key).  Host only; no HIP call.
+ * DPD_ERR_UNSUPPORTED for the plain implementation. */
+dpd_status dpd_tune_get(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
+                        const dpd_batch* batch, dpd_tune* out_host);
+
+/* Install (tune_host != NULL, validated against the ranges above: DPD_ERR_SHAPE
+ * otherwise) or remove (tune_host == NULL) this problem's table entry.  Host only. */
+dpd_status dpd_tune_set(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
+                        const dpd_batch* batch, const dpd_tune* tune_host);
+
+/* Autotuner: on the given inputs, times reps (1..1000) back-to-back launches of every
+ * candidate shape of each kernel (8 forward shapes, 2 GMP tiles, 2 backward grids;
+ * the kernels run one after another, so each is tuned on its own), installs the
+ * fastest combination as this problem's entry (gmp key = gmp) and returns it.  It
+ * enqueues that work on `stream`, records HIP events on it and waits for them (it
+ * blocks; not for the hot loop), and writes only workspace memory.  Tuned
+ * implementation with supported GMP orders only (else DPD_ERR_UNSUPPORTED). */
+dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
+                        const dpd_batch* batch, const float* x, const float* w,
+                        const float* coef, float g_re, float g_im, int32_t reps,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream,
+                        dpd_tune* out_host);
 
 /* Welch PSD of one stream y [n][2] (nfft-point segments, periodic Hann window,
  * 50 % overlap, no detrending, scaled by 1/sum(w^2)), bins in natural FFT order,

@@ -39,6 +39,14 @@ class Batch(C.Structure):
                 ("offsets_host", C.POINTER(C.c_int64))]
 
 
+class Tune(C.Structure):
+    _fields_ = [("fwd_waves", C.c_int32), ("fwd_wg_per_cu", C.c_int32),
+                ("bwd_wg_per_cu", C.c_int32), ("gmp_tile", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -55,6 +63,10 @@ _SIGS = {
                                C.c_float, C.c_float, _P, _P, _P, C.c_size_t, _P]),
     "dpd_cascade": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
                               C.c_float, C.c_float, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "dpd_tune_get": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(Tune)]),
+    "dpd_tune_set": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(Tune)]),
+    "dpd_autotune": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
+                               C.c_float, C.c_float, C.c_int32, _P, C.c_size_t, _P, C.POINTER(Tune)]),
     "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dpd_profile_enable": (C.c_int, [C.c_int32]),
@@ -174,6 +186,32 @@ def dpd_cascade(tdnn, gmp, batch, x, w, coef, g, u, y, nmse, dw, loss, workspace
                              _ptr(loss), _ptr(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream)),
            "dpd_cascade")
+
+
+def _gref(gmp):
+    return None if gmp is None else C.byref(gmp)
+
+
+def dpd_tune_get(tdnn, gmp, batch) -> dict:
+    t = Tune()
+    _check(lib().dpd_tune_get(C.byref(tdnn), _gref(gmp), C.byref(batch), C.byref(t)), "dpd_tune_get")
+    return t.as_dict()
+
+
+def dpd_tune_set(tdnn, gmp, batch, tune) -> None:
+    """tune: dict with the four dpd_tune fields, or None to remove the entry."""
+    t = None if tune is None else C.byref(Tune(**{k: int(v) for k, v in tune.items()}))
+    _check(lib().dpd_tune_set(C.byref(tdnn), _gref(gmp), C.byref(batch), t), "dpd_tune_set")
+
+
+def dpd_autotune(tdnn, gmp, batch, x, w, coef, g, reps, workspace, stream=None) -> dict:
+    g = complex(g)
+    t = Tune()
+    _check(lib().dpd_autotune(C.byref(tdnn), C.byref(gmp), C.byref(batch), _ptr(x), _ptr(w), _ptr(coef),
+                              g.real, g.imag, int(reps), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream), C.byref(t)),
+           "dpd_autotune")
+    return t.as_dict()
 
 
 def dpd_acpr_workspace_size(n: int, nfft: int) -> int:

@@ -77,6 +77,21 @@ class Cascade:
         return {"u": u, "y": y, "nmse": None if nm is None else nm.view(self.S + 1, 3),
                 "dw": dw, "loss": loss}
 
+    def autotune(self, x, w, coef, reps=3):
+        """Pick this problem's launch shapes by timing on these inputs (blocks until
+        done); every later call of this process on the same problem uses them."""
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape()); self._chk(coef, self._c_shape())
+        return L.dpd_autotune(self.tdnn, self.gmp, self.batch, x, w, coef, self.gain, reps,
+                              self.workspace)
+
+    def tune(self):
+        """Launch shapes the cascade calls of this problem use."""
+        return L.dpd_tune_get(self.tdnn, self.gmp, self.batch)
+
+    def set_tune(self, tune):
+        """Install launch shapes for this problem (dict of dpd_tune fields; None resets)."""
+        L.dpd_tune_set(self.tdnn, self.gmp, self.batch, tune)
+
     def backward(self, x, w, coef):
         self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape()); self._chk(coef, self._c_shape())
         dw = torch.empty(self._w_shape(), dtype=torch.float32, device=self.device)

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <string>
@@ -122,11 +123,68 @@ int device_cus() {
   return cache[dev];
 }
 
-// Persistent forward grid: as many workgroups as fit at once (the weights of one
-// parameter set occupy most of a CU's LDS for the largest models).
-int fwd_grid(const TdnnDims& td) {
-  int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024) / (td.fwd_lds + 1024)));
-  return per_cu * device_cus();
+// ------------------------------------------------------------ launch shapes
+// The tuned path's run-time shape choices (dpd_tune): forward waves per workgroup (tile
+// = fwd_mt x waves samples) and workgroups per CU, backward workgroups per CU, GMP
+// reverse-mode tile.  Defaults: the compiled default forward tile with as many
+// workgroups per CU as fit in LDS (at most 2), 2 backward workgroups per CU, 256-sample
+// GMP tiles.
+constexpr int kTuneFwdWaves[] = {8, 12};
+constexpr int kTuneGmpTiles[] = {256, 512};
+constexpr int kTuneMaxFwdPerCu = 4, kTuneMaxBwdPerCu = 2;
+
+dpd_tune default_tune(const TdnnDims& td) {
+  dpd_tune t;
+  t.fwd_waves = td.fwd_waves;
+  t.fwd_wg_per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024) / (td.fwd_lds + 1024)));
+  t.bwd_wg_per_cu = 2;
+  t.gmp_tile = 256;
+  return t;
+}
+
+bool tune_valid(const dpd_tune& t) {
+  bool w = false, g = false;
+  for (int v : kTuneFwdWaves) w = w || t.fwd_waves == v;
+  for (int v : kTuneGmpTiles) g = g || t.gmp_tile == v;
+  return w && g && t.fwd_wg_per_cu >= 1 && t.fwd_wg_per_cu <= kTuneMaxFwdPerCu &&
+         t.bwd_wg_per_cu >= 1 && t.bwd_wg_per_cu <= kTuneMaxBwdPerCu;
+}
+
+// Process-wide table problem -> shape.  A problem is the TDNN descriptor, the GMP
+// descriptor (zeros when none) and the batch signature (streams, parameter mode, total
+// and longest length).
+typedef std::array<int64_t, 13> TuneKey;
+TuneKey tune_key(const dpd_tdnn_desc& d, const dpd_gmp_desc* g, const Problem& p) {
+  return TuneKey{d.precision, d.taps, d.hidden, d.n_hidden, d.residual, d.impl,
+                 g ? g->K : 0, g ? g->M : 0, g ? g->L : 0, p.S, p.per_stream, p.n_total, p.max_len};
+}
+struct TuneTable {
+  std::mutex mu;
+  std::map<TuneKey, dpd_tune> map;
+};
+TuneTable& tune_table() {
+  static TuneTable t;
+  return t;
+}
+dpd_tune lookup_tune(const dpd_tdnn_desc& d, const dpd_gmp_desc* g, const Problem& p,
+                     const TdnnDims& td) {
+  TuneTable& t = tune_table();
+  std::lock_guard<std::mutex> lock(t.mu);
+  auto it = t.map.find(tune_key(d, g, p));
+  return it == t.map.end() ? default_tune(td) : it->second;
+}
+void store_tune(const dpd_tdnn_desc& d, const dpd_gmp_desc* g, const Problem& p, const dpd_tune* v) {
+  TuneTable& t = tune_table();
+  std::lock_guard<std::mutex> lock(t.mu);
+  if (v) t.map[tune_key(d, g, p)] = *v;
+  else t.map.erase(tune_key(d, g, p));
+}
+
+int fwd_grid(const dpd_tune& t, const StreamTable& tab) {
+  return std::min(tab.n_tiles, t.fwd_wg_per_cu * device_cus());
+}
+int bwd_grid(const dpd_tune& t, const StreamTable& tab) {
+  return std::min(tab.n_tiles, std::min(kMaxGrid, t.bwd_wg_per_cu * device_cus()));
 }
 
 // ------------------------------------------------------------ workspace layout
@@ -371,9 +429,9 @@ dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const 
     tdnn_dims(*tdnn, &td);
     void* pack = at<void>(workspace, L.pack);
     { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
-    StreamTable tab = make_table(p, td.fwd_tile);
-    int grid = std::min(tab.n_tiles, fwd_grid(td));
-    { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, grid, stream); }
+    const dpd_tune tn = lookup_tune(*tdnn, nullptr, p, td);
+    StreamTable tab = make_table(p, td.fwd_mt * tn.fwd_waves);
+    { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, fwd_grid(tn, tab), tn.fwd_waves, stream); }
   }
   return launch_status();
 }
@@ -453,17 +511,17 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   tdnn_dims(*tdnn, &td);
   void* pack = at<void>(workspace, L.pack);
   { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, P, pack, stream); }
-  StreamTable ftab = make_table(p, td.fwd_tile);
-  int fgrid = std::min(ftab.n_tiles, fwd_grid(td));
-  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fgrid, stream); }
+  const dpd_tune tn = lookup_tune(*tdnn, gmp, p, td);
+  StreamTable ftab = make_table(p, td.fwd_mt * tn.fwd_waves);
+  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fwd_grid(tn, ftab), tn.fwd_waves, stream); }
   StreamTable tab = make_table(p, td.tile);
   if (dw) {
     // GMP forward + reverse mode (y, E/R tile partials, g_u), then the TDNN reverse mode
-    StreamTable gt = make_table(p, gmp_bwd_tile());
+    StreamTable gt = make_table(p, tn.gmp_tile);
     float* gub = at<float>(workspace, L.gu_buf);
     float2* gtab = at<float2>(workspace, L.gmp_tab);
     { DPD_PROF("gmp_bwd"); launch_gmp_bwd(*gmp, gt, x, ubuf, coef, gtab, g_re, g_im, part, gub, y, stream); }
-    int grid = std::min(tab.n_tiles, std::min(kMaxGrid, 2 * device_cus()));
+    const int grid = bwd_grid(tn, tab);
     float* slots = at<float>(workspace, L.slots);
     { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, stream); }
     { DPD_PROF("nmse_final"); launch_nmse_final(gt, part, nmse, lossp, inv_r, stream); }
@@ -485,6 +543,127 @@ dpd_status dpd_backward(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
   if (!dw || !loss) return DPD_ERR_NULL;
   return dpd_cascade(tdnn, gmp, batch, x, w, coef, g_re, g_im, nullptr, nullptr, nullptr, dw, loss,
                      workspace, workspace_bytes, stream);
+}
+
+dpd_status dpd_tune_get(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const dpd_batch* batch,
+                        dpd_tune* out_host) {
+  Problem p;
+  dpd_status st;
+  if (!out_host) return DPD_ERR_NULL;
+  if ((st = check_tdnn(tdnn)) != DPD_OK) return st;
+  if (gmp && (st = check_gmp(gmp)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (tdnn->impl != DPD_IMPL_TUNED) return DPD_ERR_UNSUPPORTED;
+  TdnnDims td;
+  tdnn_dims(*tdnn, &td);
+  *out_host = lookup_tune(*tdnn, gmp, p, td);
+  return DPD_OK;
+}
+
+dpd_status dpd_tune_set(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const dpd_batch* batch,
+                        const dpd_tune* tune_host) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_tdnn(tdnn)) != DPD_OK) return st;
+  if (gmp && (st = check_gmp(gmp)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (tdnn->impl != DPD_IMPL_TUNED) return DPD_ERR_UNSUPPORTED;
+  if (tune_host && !tune_valid(*tune_host)) return DPD_ERR_SHAPE;
+  store_tune(*tdnn, gmp, p, tune_host);
+  return DPD_OK;
+}
+
+dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const dpd_batch* batch,
+                        const float* x, const float* w, const float* coef, float g_re, float g_im,
+                        int32_t reps, void* workspace, size_t workspace_bytes, hipStream_t stream,
+                        dpd_tune* out_host) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_tdnn(tdnn)) != DPD_OK) return st;
+  if ((st = check_gmp(gmp)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!x || !w || !coef || !workspace || !out_host) return DPD_ERR_NULL;
+  if (!aligned(x, 8) || !aligned(w, 4) || !aligned(coef, 4) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (!isfinite(g_re) || !isfinite(g_im) || (g_re == 0.f && g_im == 0.f)) return DPD_ERR_SHAPE;
+  if (reps < 1 || reps > 1000) return DPD_ERR_SHAPE;
+  if (tdnn->impl != DPD_IMPL_TUNED || !tuned_supported(*tdnn, gmp)) return DPD_ERR_UNSUPPORTED;
+  Ws L = ws_layout(tdnn, gmp, p);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  TdnnDims td;
+  tdnn_dims(*tdnn, &td);
+  void* pack = at<void>(workspace, L.pack);
+  float* ubuf = at<float>(workspace, L.u_buf);
+  float* gub = at<float>(workspace, L.gu_buf);
+  float2* gtab = at<float2>(workspace, L.gmp_tab);
+  float2* part = at<float2>(workspace, L.tile_part);
+  float* slots = at<float>(workspace, L.slots);
+  const dpd_tune def = default_tune(td);
+  const StreamTable btab = make_table(p, td.tile);
+
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return DPD_ERR_LAUNCH;
+  }
+  bool failed = false;
+  // milliseconds of reps back-to-back runs of fn on the caller's stream
+  auto time_ms = [&](auto&& fn) {
+    float ms = 1e30f;
+    if (failed) return ms;
+    fn();   // untimed first run
+    if (hipEventRecord(ev[0], stream) != hipSuccess) { failed = true; return ms; }
+    for (int r = 0; r < reps; ++r) fn();
+    if (hipEventRecord(ev[1], stream) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess || hipGetLastError() != hipSuccess) {
+      failed = true;
+      ms = 1e30f;
+    }
+    return ms;
+  };
+
+  // inputs of each timed kernel: packed weights, u, g_u (default shapes)
+  launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream);
+  {
+    StreamTable ft = make_table(p, td.fwd_mt * def.fwd_waves);
+    launch_tdnn_fwd(td, ft, x, pack, ubuf, fwd_grid(def, ft), def.fwd_waves, stream);
+    StreamTable gt = make_table(p, def.gmp_tile);
+    launch_gmp_bwd(*gmp, gt, x, ubuf, coef, gtab, g_re, g_im, part, gub, nullptr, stream);
+  }
+  dpd_tune best = def;
+  float best_ms = 1e30f;
+  for (int wv : kTuneFwdWaves)
+    for (int pc = 1; pc <= kTuneMaxFwdPerCu; ++pc) {
+      dpd_tune c = def;
+      c.fwd_waves = wv;
+      c.fwd_wg_per_cu = pc;
+      StreamTable ft = make_table(p, td.fwd_mt * wv);
+      if (pc > 1 && (pc - 1) * device_cus() >= ft.n_tiles) continue;   // same grid as pc - 1
+      const float ms = time_ms([&] { launch_tdnn_fwd(td, ft, x, pack, ubuf, fwd_grid(c, ft), wv, stream); });
+      if (ms < best_ms) { best_ms = ms; best.fwd_waves = wv; best.fwd_wg_per_cu = pc; }
+    }
+  best_ms = 1e30f;
+  for (int gtile : kTuneGmpTiles) {
+    StreamTable gt = make_table(p, gtile);
+    const float ms = time_ms([&] {
+      launch_gmp_bwd(*gmp, gt, x, ubuf, coef, gtab, g_re, g_im, part, gub, nullptr, stream);
+    });
+    if (ms < best_ms) { best_ms = ms; best.gmp_tile = gtile; }
+  }
+  best_ms = 1e30f;
+  for (int pc = 1; pc <= kTuneMaxBwdPerCu; ++pc) {
+    dpd_tune c = def;
+    c.bwd_wg_per_cu = pc;
+    if (pc > 1 && (pc - 1) * device_cus() >= btab.n_tiles) continue;
+    const float ms = time_ms([&] { launch_tdnn_bwd(td, btab, x, gub, pack, slots, bwd_grid(c, btab), stream); });
+    if (ms < best_ms) { best_ms = ms; best.bwd_wg_per_cu = pc; }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (failed) return DPD_ERR_LAUNCH;
+  store_tune(*tdnn, gmp, p, &best);
+  *out_host = best;
+  return DPD_OK;
 }
 
 size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft) {

@@ -77,24 +77,21 @@ __global__ void k_gmp_table(const float* __restrict__ coef, float2* __restrict__
   tab[(int64_t)set * 2 * G::J + G::J + j] = make_float2(k * c.x, k * c.y);
 }
 
-// GMP forward and reverse mode over tiles of kGmpBwdTile samples, one workgroup per tile
+// GMP forward and reverse mode over tiles of S samples (one per thread), one workgroup per tile
 // (no persistent state, so it runs at the occupancy its registers allow).  The
 // coefficients are read from the table (wave-uniform addresses: scalar loads into
 // SGPRs, used directly as FMA operands):
 //   y = GMP(u) (stored when y_out is not null), g_y = 2 (y - G x) inside the stream,
 //   the tile's E = sum |y - G x|^2 and R = sum |G x|^2 (fixed reduction tree), and
 //   g_u[m] = dL/du[m] of L = sum |y - G x|^2 (the gather form in gmp.hpp).
-constexpr int kGmpBwdThreads = 256;
-
-template <int K, int M, int L>
-__global__ __launch_bounds__(kGmpBwdThreads) void k_gmp_bwd(StreamTable st, const float* __restrict__ x,
+template <int K, int M, int L, int S>
+__global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __restrict__ x,
                                                             const float* __restrict__ u,
                                                             const float2* __restrict__ tab, float g_re,
                                                             float g_im, float2* __restrict__ tile_part,
                                                             float* __restrict__ gu_out,
                                                             float* __restrict__ y_out) {
   using G = Gmp<K, M, L>;
-  constexpr int S = kGmpBwdThreads;     // samples per tile (st.tile == S)
   constexpr int UB = M + 2 * L;
   constexpr int UW = S + 2 * UB;        // u  [t0 - UB, t0 + S + UB)
   constexpr int QB = M + L;
@@ -191,11 +188,12 @@ void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x
     const int n_sets = st.per_stream ? st.n : 1;
     dim3 tg((Gmp<K, M, L>::J + 255) / 256, n_sets);
     k_gmp_table<K, M, L><<<tg, 256, 0, s>>>(coef, tab);
-    k_gmp_bwd<K, M, L><<<st.n_tiles, kGmpBwdThreads, 0, s>>>(st, x, u, tab, g_re, g_im, tile_part, gu, y);
+    if (st.tile == 512)
+      k_gmp_bwd<K, M, L, 512><<<st.n_tiles, 512, 0, s>>>(st, x, u, tab, g_re, g_im, tile_part, gu, y);
+    else
+      k_gmp_bwd<K, M, L, 256><<<st.n_tiles, 256, 0, s>>>(st, x, u, tab, g_re, g_im, tile_part, gu, y);
   });
 }
-
-int gmp_bwd_tile() { return kGmpBwdThreads; }
 
 void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,
                     float* y, hipStream_t s) {

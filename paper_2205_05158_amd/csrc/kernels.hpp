@@ -48,9 +48,11 @@ struct TdnnDims {
   int nks1;         // MFMA K steps of layer 1
   int nksh;         // MFMA K steps of a hidden layer
   int tile;         // samples per workgroup tile of the tuned backward kernel
-  int fwd_tile;     // samples per workgroup tile of the tuned forward kernel
+  int fwd_mt;       // samples per wave of the tuned forward kernel
+  int fwd_waves;    // default waves per forward workgroup (8 or 12 are compiled)
+  int fwd_tile;     // default samples per forward tile (fwd_mt * fwd_waves)
   int64_t pack_bytes;  // bytes of one packed parameter set
-  int64_t fwd_lds;     // LDS bytes of the forward kernel
+  int64_t fwd_lds;     // LDS bytes of the forward kernel at the default tile
   // packed offsets (bytes) inside one set
   int64_t off_fwd1, off_fwdh, off_bwdh, off_bias, off_wo, off_bo;
   // natural-layout dW (floats) per slot: layer rows x cols, bias in the last used column
@@ -63,17 +65,16 @@ bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g);
 
 void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack,
                  hipStream_t s);
-// TDNN forward over the table's tiles.
+// TDNN forward over the table's tiles (st.tile = td.fwd_mt * waves; waves 8 or 12).
 void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
-                     float* u, int grid, hipStream_t s);
+                     float* u, int grid, int waves, hipStream_t s);
 // GMP forward over the table's tiles.
 void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,
                     float* y, hipStream_t s);
-// GMP forward + reverse mode over tiles of gmp_bwd_tile() samples: y (optional), E/R
-// tile partials and g_u = dL/du.  Supported (K, M, L) are those of gmp_dispatch.  tab:
-// workspace of 2 * J float2 per parameter set (the coefficients and their
+// GMP forward + reverse mode over tiles of st.tile samples (256 or 512): y (optional),
+// E/R tile partials and g_u = dL/du.  Supported (K, M, L) are those of gmp_dispatch.
+// tab: workspace of 2 * J float2 per parameter set (the coefficients and their
 // derivative-weighted copy, written first on the same stream).
-int gmp_bwd_tile();
 void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
                     const float* coef, float2* tab, float g_re, float g_im, float2* tile_part,
                     float* gu, float* y, hipStream_t s);

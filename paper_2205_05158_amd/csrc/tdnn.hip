@@ -33,9 +33,10 @@ namespace {
 
 constexpr int kWaves = 4;               // backward kernel: one wave per SIMD
 constexpr int kThreads = 64 * kWaves;
-// Forward kernel waves per workgroup: the workgroup shares one LDS copy of the weights, so
-// its wave count sets the waves per SIMD; the bf16 kernel of width 128 fits three per SIMD
-// in registers, the others two.
+// Forward kernel waves per workgroup (a tile shape chosen at run time among the compiled
+// variants): the workgroup shares one LDS copy of the weights, so its wave count sets the
+// waves per SIMD.  Default: three per SIMD for the bf16 kernel of width 128 (it fits in
+// registers), two for the others.
 __host__ __device__ constexpr int fwd_waves(int prec, int hidden) {
   return prec == DPD_BF16 && hidden >= 128 ? 12 : 8;
 }
@@ -513,18 +514,18 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
 }
 
 // ------------------------------------------------------------------ forward kernel
-// Each workgroup (fwd_waves waves, MT samples each) owns a contiguous range of tiles; the
+// Each workgroup (FW waves, MT samples each) owns a contiguous range of tiles; the
 // forward weight operands of the current parameter set live in LDS (reloaded only when
 // the set changes) unless they exceed the LDS budget, in which case they are read from
 // global memory (L2).
-template <int PREC, int T, int H, int NL>
-__global__ __launch_bounds__(64 * fwd_waves(PREC, H)) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
+template <int PREC, int T, int H, int NL, int FW>
+__global__ __launch_bounds__(64 * FW) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
                                                           const char* __restrict__ pack, int residual,
                                                           float* __restrict__ u) {
   using C = Cfg<PREC, T, H, NL>;
   using A = typename C::A;
-  constexpr int kFwdThreads = 64 * fwd_waves(PREC, H);
-  constexpr int S = C::MT * fwd_waves(PREC, H);
+  constexpr int kFwdThreads = 64 * FW;
+  constexpr int S = C::MT * FW;
   constexpr int XW = S + T - 1;
   constexpr bool kLdsWeights = C::OFF_BWDH <= 144 * 1024;
   constexpr int NWF = kLdsWeights ? (int)(C::OFF_BWDH / 16) : 1;
@@ -1279,7 +1280,9 @@ bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out) {
     td.nks1 = C::NKS1;
     td.nksh = C::NKSH;
     td.tile = C::S;
-    td.fwd_tile = C::MT * fwd_waves(P_, H_);
+    td.fwd_mt = C::MT;
+    td.fwd_waves = fwd_waves(P_, H_);
+    td.fwd_tile = C::MT * td.fwd_waves;
     td.pack_bytes = C::PACK;
     td.fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (td.fwd_tile + T_) + 4 * C::NVEC;
     td.dw_slot = C::SLOT;
@@ -1304,12 +1307,17 @@ void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_strid
 }
 
 void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
-                     float* u, int grid, hipStream_t s) {
+                     float* u, int grid, int waves, hipStream_t s) {
   tdnn_dispatch(td.prec, td.taps, td.hidden, td.n_hidden, [&]<int P_, int T_, int H_, int NL_>() {
-    k_tdnn_fwd<P_, T_, H_, NL_><<<grid, 64 * fwd_waves(P_, H_), 0, s>>>(st, x, static_cast<const char*>(pack),
-                                                         td.residual, u);
+    auto go = [&]<int FW>() {
+      k_tdnn_fwd<P_, T_, H_, NL_, FW><<<grid, 64 * FW, 0, s>>>(st, x, static_cast<const char*>(pack),
+                                                               td.residual, u);
+    };
+    if (waves == 12) go.template operator()<12>();
+    else go.template operator()<8>();
   });
 }
+
 
 void launch_tdnn_bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu,
                      const void* pack, float* slots, int grid, hipStream_t s) {

@@ -100,3 +100,25 @@ def grad_rel(got, ref, T, nl, H):
             continue
         worst = max(worst, float(np.linalg.norm(got[..., sl] - r) / n))
     return worst
+
+
+def check_cascade(inp, got, ref, prec, grad=True):
+    wl = inp.workload
+    samp_tol = FP32_SAMPLE if prec == "fp32" else BF16_SAMPLE
+    nmse_tol = FP32_NMSE_DB if prec == "fp32" else BF16_NMSE_DB
+    grad_tol = FP32_GRAD if prec == "fp32" else BF16_GRAD
+    eu = per_sample_rel(got["u"], ref.u)
+    ey = per_sample_rel(got["y"], ref.y)
+    # NMSE per stream and pooled, against the oracle's
+    nm = got["nmse"]
+    gaps = [abs(nm[s, 2] - db(ref.E[s] / ref.R[s])) for s in range(len(ref.E))]
+    pooled = db(ref.E.sum() / ref.R.sum())
+    gaps.append(abs(nm[-1, 2] - pooled))
+    print(f"  per-sample rel err u {eu:.2e} y {ey:.2e}; max NMSE gap {max(gaps):.2e} dB", flush=True)
+    assert eu <= samp_tol and ey <= samp_tol
+    assert max(gaps) <= nmse_tol
+    if grad:
+        np.testing.assert_allclose(got["loss"], ref.loss, rtol=1e-4 if prec == "fp32" else 2e-2)
+        ge = grad_rel(got["dw"], ref.dw.reshape(got["dw"].shape), wl.taps, wl.n_hidden, wl.hidden)
+        print(f"  gradient rel err {ge:.2e}", flush=True)
+        assert ge <= grad_tol

@@ -119,3 +119,43 @@ def test_acpr_arguments_rejected(dpdlib):
 def test_status_strings(dpdlib):
     for code in range(-6, 1):
         assert D.status_string(code).startswith("DPD_")
+
+
+def test_tune_table_host(dpdlib):
+    """Launch-shape table: defaults, install / read back / remove, range checks; the
+    autotuner's argument checks (all host-side, before any HIP call)."""
+    t = D.tdnn_desc(10, 3, 64)
+    g = D.gmp_desc(7, 5, 3)
+    b = D.make_batch([0, 1000, 5000], per_stream_params=True)
+    b2 = D.make_batch([0, 1000, 5001], per_stream_params=True)
+    d = D.dpd_tune_get(t, g, b)
+    assert d["fwd_waves"] == 8 and d["bwd_wg_per_cu"] == 2 and d["gmp_tile"] == 256
+    assert 1 <= d["fwd_wg_per_cu"] <= 2
+    assert D.dpd_tune_get(D.tdnn_desc(16, 4, 128, precision="bf16"), D.gmp_desc(9, 7, 4), b)["fwd_waves"] == 12
+    mine = dict(fwd_waves=12, fwd_wg_per_cu=3, bwd_wg_per_cu=1, gmp_tile=512)
+    try:
+        D.dpd_tune_set(t, g, b, mine)
+        assert D.dpd_tune_get(t, g, b) == mine
+        assert D.dpd_tune_get(t, g, b2) == d          # another batch signature
+        assert D.dpd_tune_get(t, None, b) == d        # the forward-only key
+    finally:
+        D.dpd_tune_set(t, g, b, None)
+    assert D.dpd_tune_get(t, g, b) == d
+    lib = L.lib()
+    for bad in [dict(mine, fwd_waves=10), dict(mine, fwd_wg_per_cu=0), dict(mine, fwd_wg_per_cu=5),
+                dict(mine, bwd_wg_per_cu=3), dict(mine, gmp_tile=384)]:
+        assert lib.dpd_tune_set(C.byref(t), C.byref(g), C.byref(b), C.byref(L.Tune(**bad))) == L.DPD_ERR_SHAPE
+    plain = D.tdnn_desc(10, 3, 64, impl="plain")
+    out = L.Tune()
+    assert lib.dpd_tune_get(C.byref(plain), C.byref(g), C.byref(b), C.byref(out)) == L.DPD_ERR_UNSUPPORTED
+    assert lib.dpd_tune_get(C.byref(t), C.byref(g), C.byref(b), None) == L.DPD_ERR_NULL
+
+    def auto(tdnn=t, gmp=g, reps=2, out_=out, nbytes=1 << 40, x=FAKE):
+        return lib.dpd_autotune(C.byref(tdnn), C.byref(gmp), C.byref(b), x, FAKE, FAKE, 1.0, 0.0, reps,
+                                FAKE, nbytes, None, None if out_ is None else C.byref(out_))
+    assert auto(reps=0) == L.DPD_ERR_SHAPE
+    assert auto(out_=None) == L.DPD_ERR_NULL
+    assert auto(x=None) == L.DPD_ERR_NULL
+    assert auto(tdnn=plain) == L.DPD_ERR_UNSUPPORTED
+    assert auto(gmp=D.gmp_desc(3, 2, 1)) == L.DPD_ERR_UNSUPPORTED
+    assert auto(nbytes=16) == L.DPD_ERR_WORKSPACE

@@ -21,26 +21,7 @@ def announce(msg):
     sys.stdout.flush()
 
 
-def check_cascade(inp, got, ref, prec, grad=True):
-    wl = inp.workload
-    samp_tol = H.FP32_SAMPLE if prec == "fp32" else H.BF16_SAMPLE
-    nmse_tol = H.FP32_NMSE_DB if prec == "fp32" else H.BF16_NMSE_DB
-    grad_tol = H.FP32_GRAD if prec == "fp32" else H.BF16_GRAD
-    eu = H.per_sample_rel(got["u"], ref.u)
-    ey = H.per_sample_rel(got["y"], ref.y)
-    # NMSE per stream and pooled, against the oracle's
-    nm = got["nmse"]
-    gaps = [abs(nm[s, 2] - H.db(ref.E[s] / ref.R[s])) for s in range(len(ref.E))]
-    pooled = H.db(ref.E.sum() / ref.R.sum())
-    gaps.append(abs(nm[-1, 2] - pooled))
-    print(f"  per-sample rel err u {eu:.2e} y {ey:.2e}; max NMSE gap {max(gaps):.2e} dB", flush=True)
-    assert eu <= samp_tol and ey <= samp_tol
-    assert max(gaps) <= nmse_tol
-    if grad:
-        np.testing.assert_allclose(got["loss"], ref.loss, rtol=1e-4 if prec == "fp32" else 2e-2)
-        ge = H.grad_rel(got["dw"], ref.dw.reshape(got["dw"].shape), wl.taps, wl.n_hidden, wl.hidden)
-        print(f"  gradient rel err {ge:.2e}", flush=True)
-        assert ge <= grad_tol
+check_cascade = H.check_cascade
 
 
 @pytest.mark.parametrize("impl,prec", [("tuned", "fp32"), ("plain", "fp32"), ("tuned", "bf16")])
