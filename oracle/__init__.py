@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg may import it; the product path never does.  It shares no code
 with the HIP library.
 
-parity pins: every function here is checked by tests/test_oracle_pins.py and
-tests/test_oracle_grad.py against values fixed independently of the oracle
-(closed forms, library routines, brute force, finite differences).  The whole
+parity pins: every function here is checked by tests/test_oracle_pins.py,
+tests/test_oracle_grad.py and tests/test_oracle_adam.py (the training loop of
+oracle/adam.py) against values fixed independently of the oracle (closed forms,
+library routines, brute force, finite differences).  The whole
 cascade at full workload sizes is trusted by composition of those pinned parts.
 """
 from .dpd_pa import (Model, CascadeResult, advance, cascade, cascade_at, complex_of, db10,
