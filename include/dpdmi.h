@@ -189,6 +189,23 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                         void* workspace, size_t workspace_bytes, hipStream_t stream,
                         dpd_tune* out_host);
 
+/* One Adam step on n float32 parameters in place: the optimiser the paper trains its
+ * DPD networks with (Sec. V-A-2, learning rate 0.001), with the update rule of
+ * Kingma & Ba (Algorithm 1):
+ *   m = beta1 m + (1 - beta1) g;   v = beta2 v + (1 - beta2) g^2;
+ *   w -= lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
+ * grad, w, m, v: device float[n], 4-byte aligned (16-byte aligned buffers take the
+ * vector path), pairwise non-overlapping (DPD_ERR_SHAPE otherwise).  m and v hold the
+ * optimiser state between calls (zero before step 1, owned by the caller).  step >= 1
+ * is the caller's step counter (the bias corrections use it); 0 <= beta1, beta2 < 1;
+ * lr finite; eps finite and >= 0.  The hyper-parameters are double so that 1 - beta
+ * is formed before rounding to the float32 the kernel computes in.  With grad = the
+ * dw of dpd_backward (all parameter sets concatenated) this is one direct-learning
+ * update. */
+dpd_status dpd_adam_step(const float* grad, float* w, float* m, float* v, int64_t n,
+                         int32_t step, double lr, double beta1, double beta2, double eps,
+                         hipStream_t stream);
+
 /* Welch PSD of one stream y [n][2] (nfft-point segments, periodic Hann window,
  * 50 % overlap, no detrending, scaled by 1/sum(w^2)), bins in natural FFT order,
  * and the ACPR with main channel |k| <= half_bins, adjacent channels

@@ -67,6 +67,8 @@ _SIGS = {
     "dpd_tune_set": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(Tune)]),
     "dpd_autotune": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
                                C.c_float, C.c_float, C.c_int32, _P, C.c_size_t, _P, C.POINTER(Tune)]),
+    "dpd_adam_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int32, C.c_double, C.c_double,
+                                C.c_double, C.c_double, _P]),
     "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dpd_profile_enable": (C.c_int, [C.c_int32]),
@@ -212,6 +214,15 @@ def dpd_autotune(tdnn, gmp, batch, x, w, coef, g, reps, workspace, stream=None) 
                               workspace.numel() * workspace.element_size(), _stream(stream), C.byref(t)),
            "dpd_autotune")
     return t.as_dict()
+
+
+def dpd_adam_step(grad, w, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    n = w.numel()
+    for t in (grad, m, v):
+        if t.numel() != n:
+            raise ValueError("grad, w, m and v must have the same number of elements")
+    _check(lib().dpd_adam_step(_ptr(grad), _ptr(w), _ptr(m), _ptr(v), n, int(step), lr, beta1, beta2,
+                               eps, _stream(stream)), "dpd_adam_step")
 
 
 def dpd_acpr_workspace_size(n: int, nfft: int) -> int:

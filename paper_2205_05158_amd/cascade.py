@@ -92,6 +92,27 @@ class Cascade:
         """Install launch shapes for this problem (dict of dpd_tune fields; None resets)."""
         L.dpd_tune_set(self.tdnn, self.gmp, self.batch, tune)
 
+    def train(self, x, w, coef, steps, lr=1e-3, state=None, stream=None):
+        """Direct learning on the device: `steps` times, the gradient of the pooled NMSE
+        (dpd_backward) followed by an Adam update of w in place (dpd_adam_step).  state:
+        (m, v, t) from a previous call to continue, else fresh.  Returns the loss before
+        each step (device tensor [steps][n_sets]) and the state (m, v, t)."""
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape()); self._chk(coef, self._c_shape())
+        dev = self.device
+        if state is None:
+            m, v, t = torch.zeros_like(w), torch.zeros_like(w), 0
+        else:
+            m, v, t = state
+            self._chk(m, self._w_shape()); self._chk(v, self._w_shape())
+        dw = torch.empty_like(w)
+        losses = torch.empty((steps, self.n_sets), dtype=torch.float32, device=dev)
+        for i in range(steps):
+            L.dpd_backward(self.tdnn, self.gmp, self.batch, x, w, coef, self.gain, dw, losses[i],
+                           self.workspace, stream)
+            t += 1
+            L.dpd_adam_step(dw, w, m, v, t, lr=lr, stream=stream)
+        return losses, (m, v, t)
+
     def backward(self, x, w, coef):
         self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape()); self._chk(coef, self._c_shape())
         dw = torch.empty(self._w_shape(), dtype=torch.float32, device=self.device)

@@ -666,6 +666,24 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
   return DPD_OK;
 }
 
+dpd_status dpd_adam_step(const float* grad, float* w, float* m, float* v, int64_t n, int32_t step,
+                         double lr, double beta1, double beta2, double eps, hipStream_t stream) {
+  if (!grad || !w || !m || !v) return DPD_ERR_NULL;
+  if (n < 1 || n > ((int64_t)1 << 40) || step < 1) return DPD_ERR_SHAPE;
+  if (!isfinite(lr) || !isfinite(eps) || eps < 0.0 || !(beta1 >= 0.0 && beta1 < 1.0) ||
+      !(beta2 >= 0.0 && beta2 < 1.0))
+    return DPD_ERR_SHAPE;
+  if (!aligned(grad, 4) || !aligned(w, 4) || !aligned(m, 4) || !aligned(v, 4)) return DPD_ERR_ALIGN;
+  // the four vectors must not overlap (each is n floats)
+  const uintptr_t lo[4] = {(uintptr_t)grad, (uintptr_t)w, (uintptr_t)m, (uintptr_t)v};
+  const uintptr_t len = (uintptr_t)n * sizeof(float);
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (lo[i] < lo[j] + len && lo[j] < lo[i] + len) return DPD_ERR_SHAPE;
+  { DPD_PROF("adam"); launch_adam(grad, w, m, v, n, step, lr, beta1, beta2, eps, device_cus(), stream); }
+  return launch_status();
+}
+
 size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft) {
   if (nfft < 64 || nfft > 4096 || (nfft & (nfft - 1)) || n < nfft) return 0;
   int64_t nseg = (n - nfft) / (nfft / 2) + 1;

@@ -3,6 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <math.h>
+
 #include "common.hpp"
 
 namespace dpdmi {
@@ -38,6 +41,10 @@ void launch_plain_finalize_sets(const float* acc, int taps, int n_hidden, int hi
                                 int64_t acc_stride, int64_t P, int n_sets, const float* inv_r,
                                 float* dw, hipStream_t s);
 void launch_fill(float* p, int64_t n, float v, hipStream_t s);
+
+// Adam update of n parameters in place (bias corrections of step `step` >= 1).
+void launch_adam(const float* g, float* w, float* m, float* v, int64_t n, int step, double lr,
+                 double beta1, double beta2, double eps, int cus, hipStream_t s);
 
 // ------------------------------------------------------------------ tuned path
 struct TdnnDims {

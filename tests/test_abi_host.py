@@ -159,3 +159,18 @@ def test_tune_table_host(dpdlib):
     assert auto(tdnn=plain) == L.DPD_ERR_UNSUPPORTED
     assert auto(gmp=D.gmp_desc(3, 2, 1)) == L.DPD_ERR_UNSUPPORTED
     assert auto(nbytes=16) == L.DPD_ERR_WORKSPACE
+
+
+def test_adam_arguments_rejected(dpdlib):
+    lib = L.lib()
+    a, b, c, d = (C.c_void_p(0x100000 * k) for k in (1, 2, 3, 4))
+
+    def adam(g=a, w=b, m=c, v=d, n=1000, step=1, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        return lib.dpd_adam_step(g, w, m, v, n, step, lr, b1, b2, eps, None)
+    assert adam(g=None) == L.DPD_ERR_NULL and adam(v=None) == L.DPD_ERR_NULL
+    assert adam(n=0) == L.DPD_ERR_SHAPE and adam(step=0) == L.DPD_ERR_SHAPE
+    assert adam(b1=1.0) == L.DPD_ERR_SHAPE and adam(b2=-0.1) == L.DPD_ERR_SHAPE
+    assert adam(eps=-1.0) == L.DPD_ERR_SHAPE and adam(lr=float("nan")) == L.DPD_ERR_SHAPE
+    assert adam(w=C.c_void_p(0x100002)) == L.DPD_ERR_ALIGN
+    assert adam(m=C.c_void_p(0x100000 + 400)) == L.DPD_ERR_SHAPE      # overlaps g
+    assert adam(n=0x100000 // 4 + 1) == L.DPD_ERR_SHAPE                # now all overlap
