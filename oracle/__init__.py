@@ -5,8 +5,9 @@ CPU-baseline leg may import it; the product path never does.  It shares no code
 with the HIP library.
 
 parity pins: every function here is checked by tests/test_oracle_pins.py,
-tests/test_oracle_grad.py and tests/test_oracle_adam.py (the training loop of
-oracle/adam.py) against values fixed independently of the oracle (closed forms,
+tests/test_oracle_grad.py, tests/test_oracle_adam.py (the training loop of
+oracle/adam.py) and tests/test_oracle_ila.py (the least-squares GMP DPD of
+oracle/ila.py) against values fixed independently of the oracle (closed forms,
 library routines, brute force, finite differences).  The whole
 cascade at full workload sizes is trusted by composition of those pinned parts.
 """
