@@ -206,6 +206,31 @@ dpd_status dpd_adam_step(const float* grad, float* w, float* m, float* v, int64_
                          int32_t step, double lr, double beta1, double beta2, double eps,
                          hipStream_t stream);
 
+/* Least-squares fit of a GMP DPD by indirect learning: the TD-GMP benchmark of the
+ * paper (the per-antenna DPD with the monomials of eq. (9), coefficients found by
+ * mean-square-error estimation, Sec. IV-B) identified as a post-inverse at the PA output
+ * (least squares between the post-distorter output and the PA input, Sec. V-A-2).
+ * For every parameter set p (per stream, or one pooled over all streams):
+ *   z = y / G,  Phi = the eq. (9) monomials of z (flat coefficient order a, b, c; zero
+ *   padding at both ends of every stream),
+ *   (Phi^H Phi + lambda I) c = Phi^H t,  lambda = ridge * trace(Phi^H Phi) / J,
+ * the normal equations accumulated in float64 on the matrix cores and solved by a
+ * complex Cholesky factorisation in float64.
+ * y, t: device float[n_total][2] (PA output and PA input); coef: device float[n_sets][J][2]
+ * (usable directly as pa_gmp_forward coefficients of the DPD); info: device
+ * int32[n_sets], 0 on success, k + 1 if pivot k of the factorisation is not positive
+ * (rank-deficient basis, e.g. a stream shorter than J samples with ridge = 0; coef of
+ * that set is then zero).  normal_out (may be NULL): device double[n_sets][J][J+1][2], the
+ * rows of [Phi^H Phi | Phi^H t] (16-byte aligned).  ridge finite and >= 0.  Supported
+ * for J <= 1024.  The workspace (gmp_ls_workspace_size) holds per-split partial Gram
+ * blocks and the factorisation. */
+dpd_status gmp_ls_workspace_size(const dpd_gmp_desc* gmp, const dpd_batch* batch,
+                                 size_t* bytes_host);
+dpd_status gmp_ls_fit(const dpd_gmp_desc* gmp, const dpd_batch* batch, const float* y,
+                      float g_re, float g_im, const float* t, double ridge, float* coef,
+                      int32_t* info, double* normal_out, void* workspace,
+                      size_t workspace_bytes, hipStream_t stream);
+
 /* Welch PSD of one stream y [n][2] (nfft-point segments, periodic Hann window,
  * 50 % overlap, no detrending, scaled by 1/sum(w^2)), bins in natural FFT order,
  * and the ACPR with main channel |k| <= half_bins, adjacent channels

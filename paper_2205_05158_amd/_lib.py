@@ -69,6 +69,9 @@ _SIGS = {
                                C.c_float, C.c_float, C.c_int32, _P, C.c_size_t, _P, C.POINTER(Tune)]),
     "dpd_adam_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int32, C.c_double, C.c_double,
                                 C.c_double, C.c_double, _P]),
+    "gmp_ls_workspace_size": (C.c_int, [C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(C.c_size_t)]),
+    "gmp_ls_fit": (C.c_int, [C.POINTER(GmpDesc), C.POINTER(Batch), _P, C.c_float, C.c_float, _P, C.c_double,
+                             _P, _P, _P, _P, C.c_size_t, _P]),
     "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dpd_profile_enable": (C.c_int, [C.c_int32]),
@@ -223,6 +226,19 @@ def dpd_adam_step(grad, w, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
             raise ValueError("grad, w, m and v must have the same number of elements")
     _check(lib().dpd_adam_step(_ptr(grad), _ptr(w), _ptr(m), _ptr(v), n, int(step), lr, beta1, beta2,
                                eps, _stream(stream)), "dpd_adam_step")
+
+
+def gmp_ls_workspace_size(gmp, batch) -> int:
+    n = C.c_size_t(0)
+    _check(lib().gmp_ls_workspace_size(C.byref(gmp), C.byref(batch), C.byref(n)), "gmp_ls_workspace_size")
+    return n.value
+
+
+def gmp_ls_fit(gmp, batch, y, g, t, ridge, coef, info, normal, workspace, stream=None):
+    g = complex(g)
+    _check(lib().gmp_ls_fit(C.byref(gmp), C.byref(batch), _ptr(y), g.real, g.imag, _ptr(t), float(ridge),
+                            _ptr(coef), _ptr(info), _ptr(normal), _ptr(workspace),
+                            workspace.numel() * workspace.element_size(), _stream(stream)), "gmp_ls_fit")
 
 
 def dpd_acpr_workspace_size(n: int, nfft: int) -> int:

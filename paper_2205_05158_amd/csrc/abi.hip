@@ -684,6 +684,70 @@ dpd_status dpd_adam_step(const float* grad, float* w, float* m, float* v, int64_
   return launch_status();
 }
 
+}  // extern "C"
+
+namespace {
+struct LsWs {
+  size_t slots = 0, normal = 0, work = 0, total = 0;
+};
+LsWs ls_ws_layout(const dpd_gmp_desc& g, const Problem& p) {
+  const LsDims d = ls_dims(g.K, g.M, g.L);
+  LsWs w;
+  size_t pos = 0;
+  auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
+  w.slots = take(sizeof(double) * (size_t)(kLsMaxSplits + p.S) * d.nblk * 64 * 64);
+  w.normal = take(sizeof(double2) * (size_t)p.n_sets * d.J * (d.J + 1));
+  w.work = take(sizeof(double2) * (size_t)p.n_sets * d.J * (d.J + 1));
+  w.total = pos;
+  return w;
+}
+dpd_status check_ls_gmp(const dpd_gmp_desc* gmp) {
+  dpd_status st = check_gmp(gmp);
+  if (st != DPD_OK) return st;
+  return coeff_count(*gmp) <= kLsMaxJ ? DPD_OK : DPD_ERR_UNSUPPORTED;
+}
+}  // namespace
+
+extern "C" {
+
+dpd_status gmp_ls_workspace_size(const dpd_gmp_desc* gmp, const dpd_batch* batch, size_t* bytes_host) {
+  Problem p;
+  dpd_status st;
+  if (!bytes_host) return DPD_ERR_NULL;
+  if ((st = check_ls_gmp(gmp)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  *bytes_host = ls_ws_layout(*gmp, p).total;
+  return DPD_OK;
+}
+
+dpd_status gmp_ls_fit(const dpd_gmp_desc* gmp, const dpd_batch* batch, const float* y, float g_re,
+                      float g_im, const float* t, double ridge, float* coef, int32_t* info,
+                      double* normal_out, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_ls_gmp(gmp)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!y || !t || !coef || !info || !workspace) return DPD_ERR_NULL;
+  if (!aligned(y, 8) || !aligned(t, 8) || !aligned(coef, 4) || !aligned(info, 4) ||
+      (normal_out && !aligned(normal_out, 16)) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (!isfinite(g_re) || !isfinite(g_im) || (g_re == 0.f && g_im == 0.f)) return DPD_ERR_SHAPE;
+  if (!isfinite(ridge) || ridge < 0.0) return DPD_ERR_SHAPE;
+  const LsWs L = ls_ws_layout(*gmp, p);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  const LsDims d = ls_dims(gmp->K, gmp->M, gmp->L);
+  const StreamTable tab = make_table(p, d.chunk);
+  const int splits = ls_splits(d, tab.n_tiles, device_cus());
+  const double gr = g_re, gi = g_im, m2 = gr * gr + gi * gi;   // 1 / G
+  double2* normal = normal_out ? reinterpret_cast<double2*>(normal_out) : at<double2>(workspace, L.normal);
+  {
+    DPD_PROF("ls_fit");
+    launch_ls_fit(*gmp, tab, y, gr / m2, -gi / m2, t, ridge, splits, at<double>(workspace, L.slots),
+                  normal, at<double2>(workspace, L.work), coef, info, stream);
+  }
+  return launch_status();
+}
+
 size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft) {
   if (nfft < 64 || nfft > 4096 || (nfft & (nfft - 1)) || n < nfft) return 0;
   int64_t nseg = (n - nfft) / (nfft / 2) + 1;

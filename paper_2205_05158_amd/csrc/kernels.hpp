@@ -46,6 +46,24 @@ void launch_fill(float* p, int64_t n, float v, hipStream_t s);
 void launch_adam(const float* g, float* w, float* m, float* v, int64_t n, int step, double lr,
                  double beta1, double beta2, double eps, int cus, hipStream_t s);
 
+// Least-squares GMP fit (normal equations on the FP64 matrix cores + complex Cholesky).
+struct LsDims {
+  int J;       // complex coefficients
+  int NCP;     // real-embedding columns 2J + 2, padded to a multiple of 64
+  int nb;      // 64-column blocks
+  int nblk;    // blocks of the upper block triangle
+  int chunk;   // samples per basis chunk (stream-table tile)
+};
+constexpr int kLsMaxSplits = 64;   // sample splits per Gram block (sizes the slots)
+constexpr int kLsMaxJ = 1024;
+LsDims ls_dims(int K, int M, int L);
+int ls_splits(const LsDims& d, int n_tiles, int cus);
+// st.tile = d.chunk.  slots: (kLsMaxSplits + streams) x nblk x 64 x 64 doubles; normal
+// and work: n_sets x J x (J + 1) complex doubles; coef: n_sets x J complex floats.
+void launch_ls_fit(const dpd_gmp_desc& g, const StreamTable& st, const float* y, double gi_re,
+                   double gi_im, const float* t, double ridge, int n_splits, double* slots,
+                   double2* normal, double2* work, float* coef, int* info, hipStream_t s);
+
 // ------------------------------------------------------------------ tuned path
 struct TdnnDims {
   int taps, n_hidden, hidden, residual, prec;

@@ -174,3 +174,22 @@ def test_adam_arguments_rejected(dpdlib):
     assert adam(w=C.c_void_p(0x100002)) == L.DPD_ERR_ALIGN
     assert adam(m=C.c_void_p(0x100000 + 400)) == L.DPD_ERR_SHAPE      # overlaps g
     assert adam(n=0x100000 // 4 + 1) == L.DPD_ERR_SHAPE                # now all overlap
+
+
+def test_ls_fit_arguments_rejected(dpdlib):
+    lib = L.lib()
+    g = D.gmp_desc(7, 5, 3)
+    b = D.make_batch([0, 5000])
+    info = C.c_void_p(0x300000)
+
+    def fit(gmp=g, y=FAKE, t=C.c_void_p(0x200000), ridge=0.0, coef=FAKE, inf=info, normal=None,
+            nbytes=1 << 40, gr=1.0, gi=0.0):
+        return lib.gmp_ls_fit(C.byref(gmp), C.byref(b), y, gr, gi, t, ridge, coef, inf, normal, FAKE,
+                              nbytes, None)
+    assert fit(y=None) == L.DPD_ERR_NULL and fit(inf=None) == L.DPD_ERR_NULL
+    assert fit(ridge=-1.0) == L.DPD_ERR_SHAPE and fit(ridge=float("inf")) == L.DPD_ERR_SHAPE
+    assert fit(gr=0.0) == L.DPD_ERR_SHAPE
+    assert fit(normal=C.c_void_p(0x400008)) == L.DPD_ERR_ALIGN
+    assert fit(nbytes=16) == L.DPD_ERR_WORKSPACE
+    assert fit(gmp=D.gmp_desc(12, 15, 8)) == L.DPD_ERR_UNSUPPORTED      # J > 1024
+    assert D.gmp_ls_workspace_size(g, b) > 0
