@@ -26,8 +26,10 @@ PEAK = {  # MI355X published peaks
     "hbm_gbs": 8000.0,
     "mfma_bf16_tflops": 2500.0,
     "mfma_fp32_tflops": 157.3,
+    "mfma_fp64_tflops": 78.6,
     "valu_fp32_tflops": 157.3,
 }
+ILA_WORKLOADS = {"ila_4m": dict(signal="fwd_4m", dpd=(7, 5, 3))}
 
 
 def source_digest() -> str:
@@ -189,11 +191,123 @@ def cpu_baseline(wl_name, n_sample):
             "seconds": dt}, inp, res
 
 
+def ila_cpu_baseline(inp, dpd_orders, pa_orders, n_sample):
+    """The FP64 ILA oracle as it stands (DPD -> PA -> NMSE -> least-squares refit) on the
+    first n_sample samples, starting from the identity DPD."""
+    import numpy as np
+    import oracle.ila as OI
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    x = inp.x[:n_sample]
+    off = [0, x.shape[0]]
+    t0 = time.perf_counter()
+    hist, dpd = OI.ila(x, off, inp.coef, pa_orders, dpd_orders, 1)
+    dt = time.perf_counter() - t0
+    return ({"value": x.shape[0] / dt / 1e6, "unit": "Msamples/s", "cores": int(threads), "kind": "oracle",
+             "sample": f"first {x.shape[0]} samples; one FP64 ILA iteration (GMP DPD and PA "
+                       f"forward, NMSE, basis matrix, normal equations, solve) and the final "
+                       f"DPD -> PA pass; BLAS threads {threads}; {dt:.1f} s"}, hist, dpd)
+
+
+def bench_ila(args):
+    """One step = one ILA iteration of the TD-GMP DPD on the device: u = DPD(x), y = PA(u),
+    NMSE, then the least-squares refit (normal equations on the FP64 matrix cores,
+    reduction, Cholesky solve)."""
+    import numpy as np
+    import torch
+    import dpd_synth as S
+    import paper_2205_05158_amd as D
+
+    spec = ILA_WORKLOADS[args.workload]
+    wl = S.WORKLOADS[spec["signal"]]
+    inp = S.make_workload(spec["signal"])
+    n = inp.n_total
+    dpd_orders, pa_orders = spec["dpd"], (wl.K, wl.M, wl.L)
+    ila = D.GmpIla(dpd_orders, pa_orders, inp.offsets)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    x, pa = dev(inp.x), dev(inp.coef)
+    state = {"c": ila.identity()}
+
+    ridge = 1e-9   # keeps every timed refit well posed (info is reported)
+
+    def step():
+        u, y, nm = ila.cascade(x, state["c"], pa)
+        state["c"], state["info"], _ = ila.fit(y, u, ridge)
+        state["nm"] = nm
+
+    print(f"[bench] ila warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    D.dpd_profile_report()
+    D.dpd_profile_enable(True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    D.dpd_profile_enable(False)
+    kern = D.dpd_profile_report()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    J = ila.J
+    flops = 4 * J * (J + 1) + 8 * J          # Hermitian Phi^H Phi (upper half) + Phi^H t
+    c, ms = kern["ls_gram"]
+    kms = ms / c
+    ach = flops * n / (kms / 1e3) / 1e12
+    traffic = profiled_traffic(args.workload, "ls_gram")
+    roof = {"bound": "mfma", "achieved": ach, "peak": PEAK["mfma_fp64_tflops"], "unit": "TFLOP/s",
+            "frac": ach / PEAK["mfma_fp64_tflops"], "traffic": traffic, "kernel": "ls_gram",
+            "kernel_ms": kms, "flops_per_sample": flops, "samples_per_launch": n}
+    out = {
+        "metric": "Msamples/s of one ILA least-squares iteration of the GMP DPD; % roofline",
+        "value": n / (ms_per_step / 1e3) / 1e6, "unit": "Msamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "samples": n, "streams": int(ila.S),
+                   "dpd_gmp": "K%d M%d L%d" % dpd_orders, "pa_gmp": "K%d M%d L%d" % pa_orders,
+                   "J": J, "ridge": ridge,
+                   "step": "GMP DPD fwd + GMP PA fwd (fp32) + cascade_nmse + gmp_ls_fit "
+                           "(fp64 normal equations and Cholesky)",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "kernels_ms_per_step": {k: v / args.steps for k, (cc, v) in kern.items()},
+        "nmse_db_before_last_fit": float(state["nm"].item()),
+        "info": int(state["info"].cpu()[0]),
+    }
+    if not args.no_cpu_baseline:
+        ns = min(args.cpu_sample, 1 << 18, n)
+        print(f"[bench] ila cpu baseline on {ns} samples", file=sys.stderr, flush=True)
+        cb, hist, dpd = ila_cpu_baseline(inp, dpd_orders, pa_orders, ns)
+        out["cpu_baseline"] = cb
+        sila = D.GmpIla(dpd_orders, pa_orders, [0, ns])
+        h, c1, _ = sila.run(dev(inp.x[:ns]), pa, 1)
+        g = h.cpu().numpy()
+        cg = c1.cpu().double().numpy()[0]
+        out["parity"] = {"sample_samples": ns, "nmse_gpu_db": [float(v) for v in g],
+                         "nmse_oracle_db": [float(v) for v in hist],
+                         "nmse_gap_db": float(np.max(np.abs(g - hist))),
+                         "coef_rel_err": float(np.linalg.norm(cg - dpd[0]) / np.linalg.norm(dpd[0]))}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.workload in ILA_WORKLOADS:
+        world = int(os.environ.get("WORLD_SIZE", "1"))
+        if args.gpus != 1 or world != 1:
+            print(json.dumps({"error": "this build runs on one GPU only", "n_gpus": args.gpus}))
+            sys.exit(2)
+        return bench_ila(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the hot path shards by "

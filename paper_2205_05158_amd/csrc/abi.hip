@@ -740,10 +740,12 @@ dpd_status gmp_ls_fit(const dpd_gmp_desc* gmp, const dpd_batch* batch, const flo
   const int splits = ls_splits(d, tab.n_tiles, device_cus());
   const double gr = g_re, gi = g_im, m2 = gr * gr + gi * gi;   // 1 / G
   double2* normal = normal_out ? reinterpret_cast<double2*>(normal_out) : at<double2>(workspace, L.normal);
+  double* slots = at<double>(workspace, L.slots);
+  { DPD_PROF("ls_gram"); launch_ls_gram(*gmp, tab, y, gr / m2, -gi / m2, t, splits, slots, stream); }
+  { DPD_PROF("ls_reduce"); launch_ls_reduce(*gmp, tab, splits, slots, normal, stream); }
   {
-    DPD_PROF("ls_fit");
-    launch_ls_fit(*gmp, tab, y, gr / m2, -gi / m2, t, ridge, splits, at<double>(workspace, L.slots),
-                  normal, at<double2>(workspace, L.work), coef, info, stream);
+    DPD_PROF("ls_solve");
+    launch_ls_solve(*gmp, p.n_sets, normal, ridge, at<double2>(workspace, L.work), coef, info, stream);
   }
   return launch_status();
 }

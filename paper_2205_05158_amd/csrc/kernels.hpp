@@ -60,9 +60,12 @@ LsDims ls_dims(int K, int M, int L);
 int ls_splits(const LsDims& d, int n_tiles, int cus);
 // st.tile = d.chunk.  slots: (kLsMaxSplits + streams) x nblk x 64 x 64 doubles; normal
 // and work: n_sets x J x (J + 1) complex doubles; coef: n_sets x J complex floats.
-void launch_ls_fit(const dpd_gmp_desc& g, const StreamTable& st, const float* y, double gi_re,
-                   double gi_im, const float* t, double ridge, int n_splits, double* slots,
-                   double2* normal, double2* work, float* coef, int* info, hipStream_t s);
+void launch_ls_gram(const dpd_gmp_desc& g, const StreamTable& st, const float* y, double gi_re,
+                    double gi_im, const float* t, int n_splits, double* slots, hipStream_t s);
+void launch_ls_reduce(const dpd_gmp_desc& g, const StreamTable& st, int n_splits, const double* slots,
+                      double2* normal, hipStream_t s);
+void launch_ls_solve(const dpd_gmp_desc& g, int n_sets, const double2* normal, double ridge,
+                     double2* work, float* coef, int* info, hipStream_t s);
 
 // ------------------------------------------------------------------ tuned path
 struct TdnnDims {

@@ -355,18 +355,30 @@ int ls_splits(const LsDims& d, int n_tiles, int cus) {
   return std::max(1, std::min(n_tiles, std::min(want, kLsMaxSplits)));
 }
 
-void launch_ls_fit(const dpd_gmp_desc& g, const StreamTable& st, const float* y, double gi_re,
-                   double gi_im, const float* t, double ridge, int n_splits, double* slots,
-                   double2* normal, double2* work, float* coef, int* info, hipStream_t s) {
+static LsGeom geom_of(const dpd_gmp_desc& g) {
   const LsDims d = ls_dims(g.K, g.M, g.L);
-  LsGeom gm{g.K, g.M, g.L, d.J, d.NCP, d.nb, d.nblk};
-  const int n_sets = st.per_stream ? st.n : 1;
-  dim3 grid(d.nblk, n_splits);
+  return LsGeom{g.K, g.M, g.L, d.J, d.NCP, d.nb, d.nblk};
+}
+
+void launch_ls_gram(const dpd_gmp_desc& g, const StreamTable& st, const float* y, double gi_re,
+                    double gi_im, const float* t, int n_splits, double* slots, hipStream_t s) {
+  const LsGeom gm = geom_of(g);
+  dim3 grid(gm.nblk, n_splits);
   k_ls_gram<<<grid, kLsThreads, 0, s>>>(st, gm, y, gi_re, gi_im, t, n_splits, slots);
-  const int64_t ne = (int64_t)d.J * (d.J + 1);
+}
+
+void launch_ls_reduce(const dpd_gmp_desc& g, const StreamTable& st, int n_splits, const double* slots,
+                      double2* normal, hipStream_t s) {
+  const LsGeom gm = geom_of(g);
+  const int n_sets = st.per_stream ? st.n : 1;
+  const int64_t ne = (int64_t)gm.J * (gm.J + 1);
   dim3 rg((unsigned)((ne + 255) / 256), n_sets);
   k_ls_reduce<<<rg, 256, 0, s>>>(st, gm, n_splits, slots, normal);
-  k_ls_solve<<<n_sets, 256, 0, s>>>(gm, normal, ridge, work, coef, info);
+}
+
+void launch_ls_solve(const dpd_gmp_desc& g, int n_sets, const double2* normal, double ridge,
+                     double2* work, float* coef, int* info, hipStream_t s) {
+  k_ls_solve<<<n_sets, 256, 0, s>>>(geom_of(g), normal, ridge, work, coef, info);
 }
 
 }  // namespace dpdmi
