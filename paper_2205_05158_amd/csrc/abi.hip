@@ -695,7 +695,7 @@ LsWs ls_ws_layout(const dpd_gmp_desc& g, const Problem& p) {
   LsWs w;
   size_t pos = 0;
   auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
-  w.slots = take(sizeof(double) * (size_t)(kLsMaxSplits + p.S) * d.nblk * 64 * 64);
+  w.slots = take(sizeof(double) * (size_t)(kLsMaxSplits + p.S) * d.nblk * kLsGramBlk * kLsGramBlk);
   w.normal = take(sizeof(double2) * (size_t)p.n_sets * d.J * (d.J + 1));
   w.work = take(sizeof(double2) * (size_t)p.n_sets * d.J * (d.J + 1));
   w.total = pos;

@@ -55,10 +55,11 @@ struct LsDims {
   int chunk;   // samples per basis chunk (stream-table tile)
 };
 constexpr int kLsMaxSplits = 64;   // sample splits per Gram block (sizes the slots)
+constexpr int kLsGramBlk = 128;    // Gram block edge
 constexpr int kLsMaxJ = 1024;
 LsDims ls_dims(int K, int M, int L);
 int ls_splits(const LsDims& d, int n_tiles, int cus);
-// st.tile = d.chunk.  slots: (kLsMaxSplits + streams) x nblk x 64 x 64 doubles; normal
+// st.tile = d.chunk.  slots: (kLsMaxSplits + streams) x nblk x kLsGramBlk^2 doubles; normal
 // and work: n_sets x J x (J + 1) complex doubles; coef: n_sets x J complex floats.
 void launch_ls_gram(const dpd_gmp_desc& g, const StreamTable& st, const float* y, double gi_re,
                     double gi_im, const float* t, int n_splits, double* slots, hipStream_t s);

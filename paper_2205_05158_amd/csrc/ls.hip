@@ -12,11 +12,12 @@
 // Q = P^T P, from which
 //   Phi^H Phi = (A^T A + B^T B) + i (A^T B - B^T A),
 //   Phi^H t   = (A^T t_r + B^T t_i) + i (A^T t_i - B^T t_r).
-// Q is computed in 64 x 64 blocks of its upper block triangle; each workgroup owns one
-// block and a contiguous range of 32-sample chunks, builds the basis values of its block's
-// 128 columns for each chunk in LDS (from the stream's z window and |z|^k table) and runs
-// 16x16x4 f64 MFMAs; partial blocks go to one slot per (sample split, stream), summed in a
-// fixed order by k_ls_reduce.
+// Q is computed in 128 x 128 blocks of its upper block triangle; each workgroup (8 waves,
+// each 2 x 4 tiles of 16 x 16) owns one block and a contiguous range of 32-sample chunks,
+// builds the basis values of its block's row and column sets (one set on the diagonal)
+// for each chunk in LDS (from the stream's z window and |z|^k table) and runs 16x16x4 f64
+// MFMAs (8 per basis value built off the diagonal); partial blocks go to one slot per
+// (sample split, stream), summed in a fixed order by k_ls_reduce.
 #include "kernels.hpp"
 
 namespace dpdmi {
@@ -25,10 +26,12 @@ namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLsThreads = 256;     // 4 waves
+constexpr int kLsThreads = 512;     // 8 waves
 constexpr int kLsChunk = 32;        // samples per basis chunk (8 MFMA K steps)
-constexpr int kLsBlk = 64;          // Gram block edge
-constexpr int kLsRow = 80;          // LDS row stride (doubles) of a chunk's basis rows
+constexpr int kLsBlk = kLsGramBlk;  // Gram block edge (128)
+// LDS row stride (doubles) of a chunk's basis rows: 144 doubles = 288 banks, 32 mod 64, so
+// the two sample rows a 32-lane half of an operand read touches use disjoint banks
+constexpr int kLsRow = kLsBlk + 16;
 constexpr int kLsMaxWin = kLsChunk + DPD_MAX_GMP_M + 2 * DPD_MAX_GMP_L;
 
 // Column descriptor of the real embedding: kind 0 Re phi_j, 1 Im phi_j, 2 Re t, 3 Im t,
@@ -85,6 +88,8 @@ __global__ __launch_bounds__(kLsThreads) void k_ls_gram(StreamTable st, LsGeom g
   const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
   int bi, bj;
   blk_of(blockIdx.x, gm.nb, bi, bj);
+  const bool diag = bi == bj;                  // row and column sets coincide
+  const int tr0 = 2 * (wave % 4), tc0 = 4 * (wave / 4);   // the wave's tile rows / columns
   const int split = blockIdx.y;
   const int t_begin = wg_tile_start(split, n_splits, st.n_tiles);
   const int t_end = wg_tile_start(split + 1, n_splits, st.n_tiles);
@@ -95,88 +100,104 @@ __global__ __launch_bounds__(kLsThreads) void k_ls_gram(StreamTable st, LsGeom g
     const ColDesc d = col_desc(c, gm.K, gm.M, gm.L, gm.J);
     cd[tid] = make_int4(d.kind, d.k, HB - d.l, HB - d.q);   // window offsets of z[n-l], |z[n-q]|
   }
-  f64x4 acc[4];
+  f64x4 acc[2][4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   auto flush = [&](int s) {
     double* out = slots + ((int64_t)(split + s) * gm.nblk + blockIdx.x) * (kLsBlk * kLsBlk);
     // D layout of 16x16x4 f64: lane l holds column l % 16, rows l / 16 + 4 r
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 16 * wave + lane / 16 + 4 * r, col = 16 * j + lane % 16;
-        out[row * kLsBlk + col] = acc[j][r];
-      }
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (tr0 + i) + lane / 16 + 4 * r, col = 16 * (tc0 + j) + lane % 16;
+          out[row * kLsBlk + col] = acc[i][j][r];
+        }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   };
+  // basis build: thread tid owns column tid % ncol of the row set (then the column set)
+  // for samples tid / ncol + k * (threads / ncol)
+  const int ncol = diag ? kLsBlk : 2 * kLsBlk;
+  const int my_c = tid % ncol, s_first = tid / ncol, s_step = kLsThreads / ncol;
+  __syncthreads();
+  const int4 my_d = cd[my_c];
+
+  // the next chunk's y window and targets are read one chunk ahead, into registers
+  // (thread i < WS holds window position i, thread i < chunk target i)
+  float2 ypre = make_float2(0.f, 0.f), tpre = make_float2(0.f, 0.f);
+  auto prefetch = [&](int tt) {
+    const int s2 = stream_of_tile(st, tt);
+    const int64_t lo2 = st.off[s2], hi2 = st.off[s2 + 1];
+    const int64_t n02 = lo2 + (int64_t)(tt - st.tile0[s2]) * kLsChunk;
+    const int64_t p = n02 - HB + tid;
+    ypre = (tid < WS && p >= lo2 && p < hi2) ? ld2(y, p) : make_float2(0.f, 0.f);
+    tpre = (tid < kLsChunk && n02 + tid < hi2) ? ld2(t, n02 + tid) : make_float2(0.f, 0.f);
+  };
+  static_assert(kLsMaxWin <= kLsThreads, "one window position per thread");
+  if (t_begin < t_end) prefetch(t_begin);
 
   int cur = -1;
   for (int tt = t_begin; tt < t_end; ++tt) {
     const int s = stream_of_tile(st, tt);
-    const int64_t lo = st.off[s], hi = st.off[s + 1];
-    const int64_t n0 = lo + (int64_t)(tt - st.tile0[s]) * kLsChunk;
+    const int64_t hi = st.off[s + 1];
+    const int64_t n0 = st.off[s] + (int64_t)(tt - st.tile0[s]) * kLsChunk;
     if (s != cur) {
       if (cur >= 0) flush(cur);
       cur = s;
     }
     __syncthreads();   // previous chunk's basis consumed
-    for (int i = tid; i < WS; i += kLsThreads) {
-      const int64_t p = n0 - HB + i;
-      double2 z = make_double2(0.0, 0.0);
-      if (p >= lo && p < hi) {
-        const float2 v = ld2(y, p);
-        z = make_double2(v.x * gi_re - v.y * gi_im, v.x * gi_im + v.y * gi_re);
-      }
-      zw[i] = z;
+    if (tid < WS) {
+      const double2 z = make_double2(ypre.x * gi_re - ypre.y * gi_im, ypre.x * gi_im + ypre.y * gi_re);
+      zw[tid] = z;
       const double r = sqrt(z.x * z.x + z.y * z.y);
       double pw = 1.0;
       for (int k = 0; k < gm.K; ++k) {
-        rp[k][i] = pw;
+        rp[k][tid] = pw;
         pw *= r;
       }
     }
-    if (tid < kLsChunk) {
-      const int64_t n = n0 + tid;
-      double2 tv = make_double2(0.0, 0.0);
-      if (n < hi) {
-        const float2 v = ld2(t, n);
-        tv = make_double2(v.x, v.y);
-      }
-      tw[tid] = tv;
-    }
+    if (tid < kLsChunk) tw[tid] = make_double2(tpre.x, tpre.y);
+    if (tt + 1 < t_end) prefetch(tt + 1);
     __syncthreads();
-    // basis values of the chunk: 32 samples x 128 columns; rows past the stream are zero
-    for (int e = tid; e < kLsChunk * 2 * kLsBlk; e += kLsThreads) {
-      const int smp = e / (2 * kLsBlk), c = e % (2 * kLsBlk);
-      const int4 d = cd[c];
+    // basis values of the chunk (rows past the stream are zero)
+    double* mycol = &pb[my_c / kLsBlk][0][my_c % kLsBlk];
+    for (int smp = s_first; smp < kLsChunk; smp += s_step) {
       double v = 0.0;
       if (n0 + smp < hi) {
-        if (d.x <= 1) {
-          const double2 zl = zw[smp + d.z];
-          const double rq = rp[d.y][smp + d.w];
-          v = (d.x == 0 ? zl.x : zl.y) * rq;
-        } else if (d.x == 2) {
+        if (my_d.x <= 1) {
+          const double2 zl = zw[smp + my_d.z];
+          const double rq = rp[my_d.y][smp + my_d.w];
+          v = (my_d.x == 0 ? zl.x : zl.y) * rq;
+        } else if (my_d.x == 2) {
           v = tw[smp].x;
-        } else if (d.x == 3) {
+        } else if (my_d.x == 3) {
           v = tw[smp].y;
         }
       }
-      pb[c / kLsBlk][smp][c % kLsBlk] = v;
+      mycol[smp * kLsRow] = v;
     }
     __syncthreads();
-    // Q block += P[chunk][rows]^T P[chunk][cols]: wave w owns tile row w (16 rows), all
-    // four tile columns; A[i][k] = P[4 kk + k][16 w + i] from lane i + 16 k, B likewise
+    // Q block += P[chunk][rows]^T P[chunk][cols]: A[i][k] = P[4 kk + k][row 16 tr + i] from
+    // lane i + 16 k, B[k][j] = P[4 kk + k][col 16 tc + j] from lane j + 16 k
+    const double(*pcol)[kLsRow] = pb[diag ? 0 : 1];
 #pragma unroll
     for (int kk = 0; kk < kLsChunk / 4; ++kk) {
       const int smp = 4 * kk + lane / 16;
-      const double a = pb[0][smp][16 * wave + lane % 16];
+      const double a0 = pb[0][smp][16 * tr0 + lane % 16];
+      const double a1 = pb[0][smp][16 * (tr0 + 1) + lane % 16];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const double b = pb[1][smp][16 * j + lane % 16];
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+        const double b = pcol[smp][16 * (tc0 + j) + lane % 16];
+        acc[0][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b, acc[0][j], 0, 0, 0);
+        acc[1][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b, acc[1][j], 0, 0, 0);
       }
     }
   }
