@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "qam_constellation", "ofdm_signal", "papr_db", "papr_clip", "gmp_coefficients",
     "xavier_tdnn", "stream_lengths", "Workload", "WORKLOADS", "make_workload",
-    "tdnn_param_count", "gmp_coeff_count", "to_interleaved",
+    "tdnn_param_count", "gmp_coeff_count", "to_interleaved", "fdcnn_symbols", "xavier_fdcnn",
 ]
 
 
@@ -154,6 +154,28 @@ def xavier_tdnn(taps: int, n_hidden: int, hidden: int, seed: int) -> np.ndarray:
     w = np.concatenate(parts).astype(np.float32)
     assert w.size == tdnn_param_count(taps, n_hidden, hidden)
     return w
+
+
+def fdcnn_symbols(n_items: int, n_d: int, qam: int, seed: int) -> np.ndarray:
+    """n_items UE symbol vectors of n_d i.i.d. QAM symbols at unit mean energy, float32
+    [n_items][n_d][2] (the frequency-domain input of the FD-CNN)."""
+    rng = np.random.default_rng(seed)
+    pts = qam_constellation(qam)
+    idx = rng.integers(0, qam, size=(n_items, n_d))
+    return to_interleaved(pts[idx]).astype(np.float32)
+
+
+def xavier_fdcnn(n_d: int, side: int, n_conv: int, kc: int, seed: int) -> np.ndarray:
+    """Glorot-uniform FD-CNN parameters (conv fan-in 2 kc^2, fan-out n_conv kc^2; output
+    layer fan-in n_conv side^2, fan-out 2 n_d), zero biases, packed float32 as the
+    library's layout: conv weights, conv biases, output weights, output biases."""
+    rng = np.random.default_rng(seed)
+    F = n_conv * side * side
+    lc = math.sqrt(6.0 / (2 * kc * kc + n_conv * kc * kc))
+    lf = math.sqrt(6.0 / (F + 2 * n_d))
+    w = np.concatenate([rng.uniform(-lc, lc, n_conv * 2 * kc * kc), np.zeros(n_conv),
+                        rng.uniform(-lf, lf, 2 * n_d * F), np.zeros(2 * n_d)])
+    return w.astype(np.float32)
 
 
 def stream_lengths(n_streams: int, lo_log2: float = 14.0, hi_log2: float = 20.0,

@@ -231,6 +231,37 @@ dpd_status gmp_ls_fit(const dpd_gmp_desc* gmp, const dpd_batch* batch, const flo
                       int32_t* info, double* normal_out, void* workspace,
                       size_t workspace_bytes, hipStream_t stream);
 
+/* FD-CNN DPD, the paper's proposed frequency-domain network (Sec. IV-C; Sec. V-A uses
+ * n_d = 384 data subcarriers, side = 20, n_conv = 2, kc = 3, ReLU), applied to a batch of
+ * n_items UE symbol vectors (one UE's N_d data-subcarrier symbols of one OFDM symbol):
+ * the vector fills a side x side grid row-major (zero padded); its Re and Im planes
+ * are convolved by n_conv kernels kc x kc (each spanning both planes, biased, zero
+ * padding keeping the plane size), ReLU, flattened plane-major (F = n_conv side^2) and
+ * mapped by a linear layer with bias to 2 n_d outputs: Re of the predistorted symbols,
+ * then Im.  Parameters w (float): conv weights [n_conv][2][kc][kc], conv biases
+ * [n_conv], output weights [2 n_d][F], output biases [2 n_d].
+ * Supported: side <= 32, n_d <= side^2, n_conv <= 4, kc odd <= 7. */
+typedef struct {
+    int32_t n_d;      /* data subcarriers per symbol vector */
+    int32_t side;     /* grid side, side^2 >= n_d (the paper: ceil(sqrt(n_d))) */
+    int32_t n_conv;   /* convolution kernels */
+    int32_t kc;       /* kernel size (odd) */
+} dpd_fdcnn_desc;
+
+/* Parameter count (< 0 for an invalid or unsupported descriptor). */
+int64_t fdcnn_param_count(const dpd_fdcnn_desc* desc);
+dpd_status fdcnn_workspace_size(const dpd_fdcnn_desc* desc, int64_t n_items, size_t* bytes_host);
+/* s: device float[n_items][n_d][2]; out: device float[n_items][n_d][2] (may not alias s). */
+dpd_status fdcnn_forward(const dpd_fdcnn_desc* desc, int64_t n_items, const float* s,
+                         const float* w, float* out, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream);
+/* Reverse mode for the real-convention output gradient g_out = dL/dRe + j dL/dIm
+ * (device float[n_items][n_d][2]): dw (device float[param count], packed like w) =
+ * dL/dw summed over the items (fixed summation order: deterministic). */
+dpd_status fdcnn_backward(const dpd_fdcnn_desc* desc, int64_t n_items, const float* s,
+                          const float* w, const float* g_out, float* dw, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream);
+
 /* Welch PSD of one stream y [n][2] (nfft-point segments, periodic Hann window,
  * 50 % overlap, no detrending, scaled by 1/sum(w^2)), bins in natural FFT order,
  * and the ACPR with main channel |k| <= half_bins, adjacent channels

@@ -5,16 +5,20 @@ from ._lib import (DPD_BF16, DPD_FP32, DPD_IMPL_PLAIN, DPD_IMPL_TUNED, EXPORTS, 
                    GmpDesc, TdnnDesc, cascade_acpr, cascade_nmse, dpd_acpr_workspace_size,
                    dpd_adam_step, dpd_autotune, dpd_backward, dpd_cascade, dpd_forward, dpd_gmp_coeff_count,
                    dpd_profile_enable, dpd_profile_report, dpd_tdnn_param_count, dpd_tune_get,
-                   dpd_tune_set, dpd_version, dpd_workspace_size, gmp_desc, gmp_ls_fit,
+                   dpd_tune_set, dpd_version, dpd_workspace_size, fdcnn_backward, fdcnn_forward,
+                   fdcnn_param_count, fdcnn_workspace_size, gmp_desc, gmp_ls_fit,
                    gmp_ls_workspace_size, lib, make_batch, pa_gmp_forward, status_string, tdnn_desc)
 from .cascade import Cascade, CascadeFn
 from .ila import GmpIla
+from .fdcnn import FdCnn
 
 __all__ = [
     "DPD_BF16", "DPD_FP32", "DPD_IMPL_PLAIN", "DPD_IMPL_TUNED", "EXPORTS", "LIB_PATH", "Batch",
     "GmpDesc", "TdnnDesc", "cascade_acpr", "cascade_nmse", "dpd_acpr_workspace_size",
     "dpd_adam_step", "dpd_autotune", "dpd_backward", "dpd_cascade", "dpd_forward", "dpd_gmp_coeff_count",
     "dpd_tdnn_param_count", "dpd_tune_get", "dpd_tune_set", "dpd_profile_enable", "dpd_profile_report",
-    "dpd_version", "dpd_workspace_size", "gmp_desc", "gmp_ls_fit", "gmp_ls_workspace_size", "lib",
+    "dpd_version", "dpd_workspace_size", "fdcnn_backward", "fdcnn_forward", "fdcnn_param_count",
+    "fdcnn_workspace_size", "gmp_desc", "gmp_ls_fit", "gmp_ls_workspace_size", "lib",
     "make_batch", "pa_gmp_forward", "status_string", "tdnn_desc", "Cascade", "CascadeFn", "GmpIla",
+    "FdCnn",
 ]

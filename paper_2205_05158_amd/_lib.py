@@ -39,6 +39,10 @@ class Batch(C.Structure):
                 ("offsets_host", C.POINTER(C.c_int64))]
 
 
+class FdcnnDesc(C.Structure):
+    _fields_ = [("n_d", C.c_int32), ("side", C.c_int32), ("n_conv", C.c_int32), ("kc", C.c_int32)]
+
+
 class Tune(C.Structure):
     _fields_ = [("fwd_waves", C.c_int32), ("fwd_wg_per_cu", C.c_int32),
                 ("bwd_wg_per_cu", C.c_int32), ("gmp_tile", C.c_int32)]
@@ -72,6 +76,10 @@ _SIGS = {
     "gmp_ls_workspace_size": (C.c_int, [C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(C.c_size_t)]),
     "gmp_ls_fit": (C.c_int, [C.POINTER(GmpDesc), C.POINTER(Batch), _P, C.c_float, C.c_float, _P, C.c_double,
                              _P, _P, _P, _P, C.c_size_t, _P]),
+    "fdcnn_param_count": (C.c_int64, [C.POINTER(FdcnnDesc)]),
+    "fdcnn_workspace_size": (C.c_int, [C.POINTER(FdcnnDesc), C.c_int64, C.POINTER(C.c_size_t)]),
+    "fdcnn_forward": (C.c_int, [C.POINTER(FdcnnDesc), C.c_int64, _P, _P, _P, _P, C.c_size_t, _P]),
+    "fdcnn_backward": (C.c_int, [C.POINTER(FdcnnDesc), C.c_int64, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dpd_profile_enable": (C.c_int, [C.c_int32]),
@@ -239,6 +247,27 @@ def gmp_ls_fit(gmp, batch, y, g, t, ridge, coef, info, normal, workspace, stream
     _check(lib().gmp_ls_fit(C.byref(gmp), C.byref(batch), _ptr(y), g.real, g.imag, _ptr(t), float(ridge),
                             _ptr(coef), _ptr(info), _ptr(normal), _ptr(workspace),
                             workspace.numel() * workspace.element_size(), _stream(stream)), "gmp_ls_fit")
+
+
+def fdcnn_param_count(desc) -> int:
+    return lib().fdcnn_param_count(C.byref(desc))
+
+
+def fdcnn_workspace_size(desc, n_items) -> int:
+    n = C.c_size_t(0)
+    _check(lib().fdcnn_workspace_size(C.byref(desc), int(n_items), C.byref(n)), "fdcnn_workspace_size")
+    return n.value
+
+
+def fdcnn_forward(desc, n_items, s, w, out, workspace, stream=None):
+    _check(lib().fdcnn_forward(C.byref(desc), int(n_items), _ptr(s), _ptr(w), _ptr(out), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream)), "fdcnn_forward")
+
+
+def fdcnn_backward(desc, n_items, s, w, g_out, dw, workspace, stream=None):
+    _check(lib().fdcnn_backward(C.byref(desc), int(n_items), _ptr(s), _ptr(w), _ptr(g_out), _ptr(dw),
+                                _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream(stream)), "fdcnn_backward")
 
 
 def dpd_acpr_workspace_size(n: int, nfft: int) -> int:

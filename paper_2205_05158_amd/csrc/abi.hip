@@ -750,6 +750,81 @@ dpd_status gmp_ls_fit(const dpd_gmp_desc* gmp, const dpd_batch* batch, const flo
   return launch_status();
 }
 
+}  // extern "C"
+
+namespace {
+struct CnnWs {
+  size_t h = 0, dpre = 0, wpart = 0, cpart = 0, total = 0;
+};
+bool cnn_check(const dpd_fdcnn_desc* d, CnnDims* out) {
+  if (!d) return false;
+  const CnnDims c = cnn_dims(d->n_d, d->side, d->n_conv, d->kc);
+  if (!cnn_supported(c)) return false;
+  *out = c;
+  return true;
+}
+CnnWs cnn_ws_layout(const CnnDims& d, int64_t n_items) {
+  CnnWs w;
+  size_t pos = 0;
+  auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
+  w.h = take(sizeof(float) * (size_t)n_items * d.F);
+  w.dpre = take(sizeof(float) * (size_t)n_items * d.F);
+  w.wpart = take(sizeof(float) * (size_t)kCnnSplits * 2 * d.n_d * d.F);
+  w.cpart = take(sizeof(float) * (size_t)kCnnConvWg * (d.n_conv * 2 * d.kc * d.kc + d.n_conv));
+  w.total = pos;
+  return w;
+}
+}  // namespace
+
+extern "C" {
+
+int64_t fdcnn_param_count(const dpd_fdcnn_desc* desc) {
+  CnnDims d;
+  return cnn_check(desc, &d) ? d.params : -1;
+}
+
+dpd_status fdcnn_workspace_size(const dpd_fdcnn_desc* desc, int64_t n_items, size_t* bytes_host) {
+  CnnDims d;
+  if (!desc || !bytes_host) return DPD_ERR_NULL;
+  if (!cnn_check(desc, &d)) return DPD_ERR_UNSUPPORTED;
+  if (n_items < 1 || n_items > ((int64_t)1 << 31) - 1) return DPD_ERR_SHAPE;
+  *bytes_host = cnn_ws_layout(d, n_items).total;
+  return DPD_OK;
+}
+
+dpd_status fdcnn_forward(const dpd_fdcnn_desc* desc, int64_t n_items, const float* s, const float* w,
+                         float* out, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  CnnDims d;
+  if (!desc || !s || !w || !out || !workspace) return DPD_ERR_NULL;
+  if (!cnn_check(desc, &d)) return DPD_ERR_UNSUPPORTED;
+  if (n_items < 1 || n_items > ((int64_t)1 << 31) - 1) return DPD_ERR_SHAPE;
+  if (!aligned(s, 8) || !aligned(out, 8) || !aligned(w, 4) || !aligned(workspace, 256)) return DPD_ERR_ALIGN;
+  if (s == out) return DPD_ERR_SHAPE;
+  const CnnWs L = cnn_ws_layout(d, n_items);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  { DPD_PROF("cnn_forward"); launch_cnn_forward(d, n_items, s, w, at<float>(workspace, L.h), out, device_cus(), stream); }
+  return launch_status();
+}
+
+dpd_status fdcnn_backward(const dpd_fdcnn_desc* desc, int64_t n_items, const float* s, const float* w,
+                          const float* g_out, float* dw, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream) {
+  CnnDims d;
+  if (!desc || !s || !w || !g_out || !dw || !workspace) return DPD_ERR_NULL;
+  if (!cnn_check(desc, &d)) return DPD_ERR_UNSUPPORTED;
+  if (n_items < 1 || n_items > ((int64_t)1 << 31) - 1) return DPD_ERR_SHAPE;
+  if (!aligned(s, 8) || !aligned(g_out, 8) || !aligned(w, 4) || !aligned(dw, 4) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  const CnnWs L = cnn_ws_layout(d, n_items);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  {
+    DPD_PROF("cnn_backward");
+    launch_cnn_backward(d, n_items, s, w, g_out, at<float>(workspace, L.h), at<float>(workspace, L.dpre),
+                        at<float>(workspace, L.wpart), at<float>(workspace, L.cpart), dw, device_cus(), stream);
+  }
+  return launch_status();
+}
+
 size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft) {
   if (nfft < 64 || nfft > 4096 || (nfft & (nfft - 1)) || n < nfft) return 0;
   int64_t nseg = (n - nfft) / (nfft / 2) + 1;

@@ -68,6 +68,24 @@ void launch_ls_reduce(const dpd_gmp_desc& g, const StreamTable& st, int n_splits
 void launch_ls_solve(const dpd_gmp_desc& g, int n_sets, const double2* normal, double ridge,
                      double2* work, float* coef, int* info, hipStream_t s);
 
+// FD-CNN DPD over a batch of items (UE symbol vectors).
+struct CnnDims {
+  int n_d, side, n_conv, kc;
+  int F;           // n_conv side^2 (flattened length)
+  int64_t params;  // packed parameter count
+};
+constexpr int kCnnSplits = 16;    // item splits of the output-weight gradient
+constexpr int kCnnConvWg = 1024;  // workgroups of the convolution-gradient pass
+CnnDims cnn_dims(int n_d, int side, int n_conv, int kc);
+bool cnn_supported(const CnnDims& d);
+// h: workspace [n_items][F]; out: [n_items][n_d][2]
+void launch_cnn_forward(const CnnDims& d, int64_t n_items, const float* s, const float* w, float* h,
+                        float* out, int cus, hipStream_t st);
+// h, dpre: [n_items][F]; wpart: [kCnnSplits][2 n_d][F]; cpart: [kCnnConvWg][conv params]
+void launch_cnn_backward(const CnnDims& d, int64_t n_items, const float* s, const float* w,
+                         const float* gout, float* h, float* dpre, float* wpart, float* cpart,
+                         float* dw, int cus, hipStream_t st);
+
 // ------------------------------------------------------------------ tuned path
 struct TdnnDims {
   int taps, n_hidden, hidden, residual, prec;

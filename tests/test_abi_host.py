@@ -193,3 +193,21 @@ def test_ls_fit_arguments_rejected(dpdlib):
     assert fit(nbytes=16) == L.DPD_ERR_WORKSPACE
     assert fit(gmp=D.gmp_desc(12, 15, 8)) == L.DPD_ERR_UNSUPPORTED      # J > 1024
     assert D.gmp_ls_workspace_size(g, b) > 0
+
+
+def test_fdcnn_arguments_rejected(dpdlib):
+    lib = L.lib()
+    d = L.FdcnnDesc(384, 20, 2, 3)
+    assert D.fdcnn_param_count(d) == 2 * 2 * 9 + 2 + 768 * 800 + 768
+    for bad in [L.FdcnnDesc(401, 20, 2, 3), L.FdcnnDesc(384, 40, 2, 3), L.FdcnnDesc(384, 20, 2, 4),
+                L.FdcnnDesc(384, 20, 5, 3), L.FdcnnDesc(0, 20, 2, 3)]:
+        assert D.fdcnn_param_count(bad) == -1
+        assert lib.fdcnn_forward(C.byref(bad), 4, FAKE, FAKE, C.c_void_p(0x200000), FAKE, 1 << 40,
+                                 None) == L.DPD_ERR_UNSUPPORTED
+    assert lib.fdcnn_forward(C.byref(d), 0, FAKE, FAKE, C.c_void_p(0x200000), FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert lib.fdcnn_forward(C.byref(d), 4, FAKE, FAKE, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE   # s == out
+    assert lib.fdcnn_forward(C.byref(d), 4, None, FAKE, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    assert lib.fdcnn_backward(C.byref(d), 4, FAKE, FAKE, FAKE, FAKE, FAKE, 16, None) == L.DPD_ERR_WORKSPACE
+    assert lib.fdcnn_backward(C.byref(d), 4, FAKE, FAKE, C.c_void_p(0x100004), FAKE, FAKE, 1 << 40,
+                              None) == L.DPD_ERR_ALIGN
+    assert D.fdcnn_workspace_size(d, 100) > D.fdcnn_workspace_size(d, 10)
