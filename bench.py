@@ -30,6 +30,9 @@ PEAK = {  # MI355X published peaks
     "valu_fp32_tflops": 157.3,
 }
 ILA_WORKLOADS = {"ila_4m": dict(signal="fwd_4m", dpd=(7, 5, 3))}
+# FD-CNN: U = 8 UEs x 1024 OFDM symbols of the 5G n257 numerology (384 data subcarriers,
+# 256-QAM), the network of Sec. V-A (20 x 20 grid, two 3 x 3 kernels, 800 -> 768)
+CNN_WORKLOADS = {"fdcnn_8u": dict(items=8 * 1024, n_d=384, side=20, n_conv=2, kc=3, qam=256)}
 
 
 def source_digest() -> str:
@@ -300,11 +303,106 @@ def bench_ila(args):
     print(json.dumps(out))
 
 
+def bench_fdcnn(args):
+    """One step = FD-CNN forward (fdcnn_forward) + reverse mode (fdcnn_backward) of the
+    batch for a fixed output gradient."""
+    import numpy as np
+    import torch
+    import dpd_synth as S
+    import oracle.fdcnn as OF
+    import paper_2205_05158_amd as D
+
+    spec = CNN_WORKLOADS[args.workload]
+    shape = {k: spec[k] for k in ("n_d", "side", "n_conv", "kc")}
+    n = spec["items"]
+    s_np = S.fdcnn_symbols(n, spec["n_d"], spec["qam"], seed=1)
+    w_np = S.xavier_fdcnn(**shape, seed=2)
+    g_np = (np.random.default_rng(3).standard_normal(s_np.shape) / n).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    s, w, g = dev(s_np), dev(w_np), dev(g_np)
+    net = D.FdCnn(**shape, max_items=n)
+    state = {}
+
+    def step():
+        state["out"] = net.forward(s, w)
+        state["dw"] = net.backward(s, w, g)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    D.dpd_profile_report()
+    D.dpd_profile_enable(True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    D.dpd_profile_enable(False)
+    kern = D.dpd_profile_report()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    F = spec["n_conv"] * spec["side"] ** 2
+    gemm_flops = 2 * 2 * spec["n_d"] * F                  # one (items x F) x (F x 2 n_d) product per item
+    # (the output-weight gradient also forms the bias column: + 2 * 2 n_d per item, not counted)
+    per_k = {k: v / c for k, (c, v) in kern.items()}
+    dom = max(("cnn_out", "cnn_dh", "cnn_dwout"), key=lambda k: per_k[k])
+    ach = gemm_flops * n / (per_k[dom] / 1e3) / 1e12
+    roof = {"bound": "mfma", "achieved": ach, "peak": PEAK["mfma_fp32_tflops"], "unit": "TFLOP/s",
+            "frac": ach / PEAK["mfma_fp32_tflops"], "traffic": profiled_traffic(args.workload, dom),
+            "kernel": dom, "kernel_ms": per_k[dom], "flops_per_item": gemm_flops, "items_per_launch": n}
+    step_flops = 3 * gemm_flops + 2 * 2 * spec["n_conv"] * (2 * spec["kc"] ** 2) * spec["side"] ** 2
+    out = {
+        "metric": "Msymbols/s of FD-CNN DPD forward+backward (data-subcarrier symbols); % roofline",
+        "value": n * spec["n_d"] / (ms_per_step / 1e3) / 1e6, "unit": "Msymbols/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "items": n, **shape, "qam": spec["qam"],
+                   "step": "fdcnn_forward + fdcnn_backward", "parallelism": "single GPU"},
+        "roofline": roof,
+        "algorithmic_tflops": step_flops * n / (ms_per_step / 1e3) / 1e12,
+        "kernels_ms_per_step": {k: v / args.steps for k, (c, v) in kern.items()},
+    }
+    if not args.no_cpu_baseline:
+        ns = n   # the whole batch: the oracle finishes it in about a second
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        except Exception:  # pragma: no cover
+            threads = 1
+        sc = s_np[:ns, :, 0] + 1j * s_np[:ns, :, 1]
+        gc = g_np[:ns, :, 0] + 1j * g_np[:ns, :, 1]
+        t0 = time.perf_counter()
+        ref_out, cache = OF.forward(sc, w_np, **shape)
+        ref_dw = OF.backward(gc, cache, **shape)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": ns * spec["n_d"] / dt / 1e6, "unit": "Msymbols/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"all {ns} items; FP64 NumPy forward + reverse mode; "
+                                         f"BLAS threads {threads}; {dt:.2f} s"}
+        snet = D.FdCnn(**shape, max_items=ns)
+        o2 = snet.forward(s[:ns].contiguous(), w).cpu().double().numpy()
+        d2 = snet.backward(s[:ns].contiguous(), w, g[:ns].contiguous()).cpu().double().numpy()
+        oc = o2[..., 0] + 1j * o2[..., 1]
+        out["parity"] = {"sample_items": ns,
+                         "out_rel_err": float(np.max(np.abs(oc - ref_out)) / np.sqrt(np.mean(np.abs(ref_out) ** 2))),
+                         "grad_rel_err": float(np.linalg.norm(d2 - ref_dw) / np.linalg.norm(ref_dw))}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.workload in CNN_WORKLOADS:
+        world = int(os.environ.get("WORLD_SIZE", "1"))
+        if args.gpus != 1 or world != 1:
+            print(json.dumps({"error": "this build runs on one GPU only", "n_gpus": args.gpus}))
+            sys.exit(2)
+        return bench_fdcnn(args)
     if args.workload in ILA_WORKLOADS:
         world = int(os.environ.get("WORLD_SIZE", "1"))
         if args.gpus != 1 or world != 1:

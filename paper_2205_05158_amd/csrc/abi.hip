@@ -769,7 +769,7 @@ CnnWs cnn_ws_layout(const CnnDims& d, int64_t n_items) {
   auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
   w.h = take(sizeof(float) * (size_t)n_items * d.F);
   w.dpre = take(sizeof(float) * (size_t)n_items * d.F);
-  w.wpart = take(sizeof(float) * (size_t)kCnnSplits * 2 * d.n_d * d.F);
+  w.wpart = take(sizeof(float) * (size_t)kCnnSplits * 2 * d.n_d * (d.F + 1));
   w.cpart = take(sizeof(float) * (size_t)kCnnConvWg * (d.n_conv * 2 * d.kc * d.kc + d.n_conv));
   w.total = pos;
   return w;
@@ -802,7 +802,9 @@ dpd_status fdcnn_forward(const dpd_fdcnn_desc* desc, int64_t n_items, const floa
   if (s == out) return DPD_ERR_SHAPE;
   const CnnWs L = cnn_ws_layout(d, n_items);
   if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
-  { DPD_PROF("cnn_forward"); launch_cnn_forward(d, n_items, s, w, at<float>(workspace, L.h), out, device_cus(), stream); }
+  float* h = at<float>(workspace, L.h);
+  { DPD_PROF("cnn_conv"); launch_cnn_conv(d, n_items, s, w, h, device_cus(), stream); }
+  { DPD_PROF("cnn_out"); launch_cnn_out(d, n_items, h, w, out, stream); }
   return launch_status();
 }
 
@@ -817,11 +819,14 @@ dpd_status fdcnn_backward(const dpd_fdcnn_desc* desc, int64_t n_items, const flo
     return DPD_ERR_ALIGN;
   const CnnWs L = cnn_ws_layout(d, n_items);
   if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
-  {
-    DPD_PROF("cnn_backward");
-    launch_cnn_backward(d, n_items, s, w, g_out, at<float>(workspace, L.h), at<float>(workspace, L.dpre),
-                        at<float>(workspace, L.wpart), at<float>(workspace, L.cpart), dw, device_cus(), stream);
-  }
+  float* h = at<float>(workspace, L.h);
+  float* dpre = at<float>(workspace, L.dpre);
+  { DPD_PROF("cnn_conv"); launch_cnn_conv(d, n_items, s, w, h, device_cus(), stream); }
+  { DPD_PROF("cnn_dh"); launch_cnn_dh(d, n_items, g_out, w, h, dpre, stream); }
+  float* wpart = at<float>(workspace, L.wpart);
+  { DPD_PROF("cnn_dwout"); launch_cnn_dwout(d, n_items, g_out, h, wpart, stream); }
+  { DPD_PROF("cnn_dwout_reduce"); launch_cnn_dwout_reduce(d, wpart, dw, stream); }
+  { DPD_PROF("cnn_dwconv"); launch_cnn_dwconv(d, n_items, s, dpre, at<float>(workspace, L.cpart), dw, stream); }
   return launch_status();
 }
 

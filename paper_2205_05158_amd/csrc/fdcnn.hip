@@ -131,31 +131,28 @@ struct BwdH {
     dpre[(int64_t)m * F + n] = h[(int64_t)m * F + n] > 0.f ? v : 0.f;
   }
 };
-// dWf partial of split s: part[s][o][f] = sum_{b in split} gy[b][o] h[b][f]
+// [dWf | dbf] partial of split s: part[s][o][f] = sum_{b in split} gy[b][o] h1[b][f] with
+// h1 = [h | 1] (column F of ones gives the bias gradient)
 struct BwdW {
   const float* g; const float* h; float* part; int F, n_d, NO;
   __device__ float a(int m, int k) const { return g[((int64_t)k * n_d + m % n_d) * 2 + m / n_d]; }
-  __device__ float b(int k, int n) const { return h[(int64_t)k * F + n]; }
+  __device__ float b(int k, int n) const { return n < F ? h[(int64_t)k * F + n] : 1.f; }
   __device__ void store(int s, int m, int n, float v) const {
-    part[((int64_t)s * NO + m) * F + n] = v;
+    part[((int64_t)s * NO + m) * (F + 1) + n] = v;
   }
 };
 
-// dWf = sum of the split partials (fixed order); dbf[o] = sum_b gy[b][o]
-__global__ void k_cnn_dwf_reduce(CnnGeom g, int k_splits, int64_t n_items, const float* __restrict__ part,
-                                 const float* __restrict__ gout, float* __restrict__ dw) {
-  const int64_t nW = (int64_t)g.NO * g.F;
+// [dWf | dbf] = sum of the split partials (fixed order)
+__global__ void k_cnn_dwf_reduce(CnnGeom g, int k_splits, const float* __restrict__ part,
+                                 float* __restrict__ dw) {
+  const int64_t nW = (int64_t)g.NO * (g.F + 1);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nW) {
-    float acc = 0.f;
-    for (int s = 0; s < k_splits; ++s) acc += part[s * nW + i];
-    dw[g.off_wf + i] = acc;
-  } else if (i < nW + g.NO) {
-    const int o = (int)(i - nW);
-    float acc = 0.f;
-    for (int64_t b = 0; b < n_items; ++b) acc += gout[(b * g.n_d + o % g.n_d) * 2 + o / g.n_d];
-    dw[g.off_bf + o] = acc;
-  }
+  if (i >= nW) return;
+  float acc = 0.f;
+  for (int s = 0; s < k_splits; ++s) acc += part[s * nW + i];
+  const int o = (int)(i / (g.F + 1)), f = (int)(i % (g.F + 1));
+  if (f < g.F) dw[g.off_wf + (int64_t)o * g.F + f] = acc;
+  else dw[g.off_bf + o] = acc;
 }
 
 // Convolution weight and bias gradients: thread group k of the workgroup (entries t =
@@ -238,30 +235,45 @@ bool cnn_supported(const CnnDims& d) {
          d.n_conv * 2 * d.kc * d.kc + d.n_conv <= kCnnThreads;
 }
 
-void launch_cnn_forward(const CnnDims& d, int64_t n_items, const float* s, const float* w, float* h,
-                        float* out, int cus, hipStream_t st) {
-  const CnnGeom g = geom(d);
+void launch_cnn_conv(const CnnDims& d, int64_t n_items, const float* s, const float* w, float* h,
+                     int cus, hipStream_t st) {
   const int grid = (int)std::min<int64_t>(n_items, 8 * (int64_t)cus);
-  k_cnn_conv<<<grid, kCnnThreads, 0, st>>>(g, n_items, s, w, h);
+  k_cnn_conv<<<grid, kCnnThreads, 0, st>>>(geom(d), n_items, s, w, h);
+}
+
+void launch_cnn_out(const CnnDims& d, int64_t n_items, const float* h, const float* w, float* out,
+                    hipStream_t st) {
+  const CnnGeom g = geom(d);
   FwdOut pr{h, w + g.off_wf, w + g.off_bf, out, g.F, g.n_d};
   dim3 gg((unsigned)((n_items + kGT - 1) / kGT), (unsigned)((g.NO + kGT - 1) / kGT), 1);
   k_cnn_gemm<FwdOut><<<gg, 256, 0, st>>>(pr, (int)n_items, g.NO, g.F, 1);
 }
 
-void launch_cnn_backward(const CnnDims& d, int64_t n_items, const float* s, const float* w,
-                         const float* gout, float* h, float* dpre, float* wpart, float* cpart,
-                         float* dw, int cus, hipStream_t st) {
+void launch_cnn_dh(const CnnDims& d, int64_t n_items, const float* gout, const float* w, const float* h,
+                   float* dpre, hipStream_t st) {
   const CnnGeom g = geom(d);
-  const int grid = (int)std::min<int64_t>(n_items, 8 * (int64_t)cus);
-  k_cnn_conv<<<grid, kCnnThreads, 0, st>>>(g, n_items, s, w, h);
   BwdH ph{gout, w + g.off_wf, h, dpre, g.F, g.n_d};
   dim3 gh((unsigned)((n_items + kGT - 1) / kGT), (unsigned)((g.F + kGT - 1) / kGT), 1);
   k_cnn_gemm<BwdH><<<gh, 256, 0, st>>>(ph, (int)n_items, g.F, g.NO, 1);
+}
+
+void launch_cnn_dwout(const CnnDims& d, int64_t n_items, const float* gout, const float* h, float* wpart,
+                      hipStream_t st) {
+  const CnnGeom g = geom(d);
   BwdW pw{gout, h, wpart, g.F, g.n_d, g.NO};
-  dim3 gw((unsigned)((g.NO + kGT - 1) / kGT), (unsigned)((g.F + kGT - 1) / kGT), kCnnSplits);
-  k_cnn_gemm<BwdW><<<gw, 256, 0, st>>>(pw, g.NO, g.F, (int)n_items, kCnnSplits);
-  const int64_t nr = (int64_t)g.NO * g.F + g.NO;
-  k_cnn_dwf_reduce<<<(unsigned)((nr + 255) / 256), 256, 0, st>>>(g, kCnnSplits, n_items, wpart, gout, dw);
+  dim3 gw((unsigned)((g.NO + kGT - 1) / kGT), (unsigned)((g.F + 1 + kGT - 1) / kGT), kCnnSplits);
+  k_cnn_gemm<BwdW><<<gw, 256, 0, st>>>(pw, g.NO, g.F + 1, (int)n_items, kCnnSplits);
+}
+
+void launch_cnn_dwout_reduce(const CnnDims& d, const float* wpart, float* dw, hipStream_t st) {
+  const CnnGeom g = geom(d);
+  const int64_t nr = (int64_t)g.NO * (g.F + 1);
+  k_cnn_dwf_reduce<<<(unsigned)((nr + 255) / 256), 256, 0, st>>>(g, kCnnSplits, wpart, dw);
+}
+
+void launch_cnn_dwconv(const CnnDims& d, int64_t n_items, const float* s, const float* dpre, float* cpart,
+                       float* dw, hipStream_t st) {
+  const CnnGeom g = geom(d);
   const int cg = (int)std::min<int64_t>(n_items, kCnnConvWg);
   k_cnn_dwc<<<cg, kCnnThreads, 0, st>>>(g, n_items, s, dpre, cpart);
   k_cnn_dwc_reduce<<<1, 256, 0, st>>>(g, cg, cpart, dw);

@@ -78,13 +78,20 @@ constexpr int kCnnSplits = 16;    // item splits of the output-weight gradient
 constexpr int kCnnConvWg = 1024;  // workgroups of the convolution-gradient pass
 CnnDims cnn_dims(int n_d, int side, int n_conv, int kc);
 bool cnn_supported(const CnnDims& d);
-// h: workspace [n_items][F]; out: [n_items][n_d][2]
-void launch_cnn_forward(const CnnDims& d, int64_t n_items, const float* s, const float* w, float* h,
-                        float* out, int cus, hipStream_t st);
-// h, dpre: [n_items][F]; wpart: [kCnnSplits][2 n_d][F]; cpart: [kCnnConvWg][conv params]
-void launch_cnn_backward(const CnnDims& d, int64_t n_items, const float* s, const float* w,
-                         const float* gout, float* h, float* dpre, float* wpart, float* cpart,
-                         float* dw, int cus, hipStream_t st);
+// h, dpre: workspace [n_items][F]; out, gout: [n_items][n_d][2]; wpart: [kCnnSplits][2 n_d][F + 1];
+// cpart: [kCnnConvWg][conv params].  Forward: conv, out.  Reverse: conv, dh, dwout (+ its
+// reduction), dwconv.
+void launch_cnn_conv(const CnnDims& d, int64_t n_items, const float* s, const float* w, float* h,
+                     int cus, hipStream_t st);
+void launch_cnn_out(const CnnDims& d, int64_t n_items, const float* h, const float* w, float* out,
+                    hipStream_t st);
+void launch_cnn_dh(const CnnDims& d, int64_t n_items, const float* gout, const float* w, const float* h,
+                   float* dpre, hipStream_t st);
+void launch_cnn_dwout(const CnnDims& d, int64_t n_items, const float* gout, const float* h, float* wpart,
+                      hipStream_t st);
+void launch_cnn_dwout_reduce(const CnnDims& d, const float* wpart, float* dw, hipStream_t st);
+void launch_cnn_dwconv(const CnnDims& d, int64_t n_items, const float* s, const float* dpre, float* cpart,
+                       float* dw, hipStream_t st);
 
 // ------------------------------------------------------------------ tuned path
 struct TdnnDims {
