@@ -23,7 +23,6 @@ constexpr int kCnnMaxSide = 32;
 constexpr int kCnnMaxKc = 7;
 constexpr int kCnnMaxConv = 4;
 constexpr int kCnnPad = kCnnMaxSide + kCnnMaxKc - 1;
-constexpr int kCnnMaxF = kCnnMaxConv * kCnnMaxSide * kCnnMaxSide;
 
 struct CnnGeom {
   int n_d, side, n_conv, kc, F, NO;   // F = n_conv side^2, NO = 2 n_d
@@ -85,35 +84,58 @@ __global__ __launch_bounds__(256) void k_cnn_gemm(P pr, int M, int N, int K, int
   const int split = blockIdx.z;
   const int kb = (int)((int64_t)split * K / k_splits), ke = (int)((int64_t)(split + 1) * K / k_splits);
   const int wm = 32 * (wave % 2), wn = 32 * (wave / 2);
-  f32x16 acc;
+  constexpr int kPer = kGK * kGT / 256;   // operand elements per thread and K step
+  // the next K step's operands are read into registers while this step's MFMAs run
+  // element e of a tile: K index fastest when the operand is contiguous along K
+  // (P::A_KFAST / P::B_KFAST), else the M / N index, so consecutive lanes read
+  // consecutive addresses
+  auto kk_of = [](int e, bool kfast) { return kfast ? e % kGK : e / kGT; };
+  auto mm_of = [](int e, bool kfast) { return kfast ? e / kGK : e % kGT; };
+  float ra[kPer], rb[kPer];
+  auto fetch = [&](int k0) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+    for (int r = 0; r < kPer; ++r) {
+      const int e = tid + 256 * r;
+      const int ka = k0 + kk_of(e, P::A_KFAST), ma = mm_of(e, P::A_KFAST);
+      const int kb2 = k0 + kk_of(e, P::B_KFAST), nb = mm_of(e, P::B_KFAST);
+      ra[r] = (ka < ke && m0 + ma < M) ? pr.a(m0 + ma, ka) : 0.f;
+      rb[r] = (kb2 < ke && n0 + nb < N) ? pr.b(kb2, n0 + nb) : 0.f;
+    }
+  };
+  // two accumulation chains (even / odd K pairs) so consecutive MFMAs are independent
+  f32x16 acc0, acc1;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc0[j] = acc1[j] = 0.f;
+  if (kb < ke) fetch(kb);
   for (int k0 = kb; k0 < ke; k0 += kGK) {
     __syncthreads();
-    for (int e = tid; e < kGK * kGT; e += 256) {
-      const int kk = e / kGT, mm = e % kGT;
-      const int k = k0 + kk;
-      As[kk][mm] = (k < ke && m0 + mm < M) ? pr.a(m0 + mm, k) : 0.f;
-      Bs[kk][mm] = (k < ke && n0 + mm < N) ? pr.b(k, n0 + mm) : 0.f;
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int e = tid + 256 * r;
+      As[kk_of(e, P::A_KFAST)][mm_of(e, P::A_KFAST)] = ra[r];
+      Bs[kk_of(e, P::B_KFAST)][mm_of(e, P::B_KFAST)] = rb[r];
     }
     __syncthreads();
+    if (k0 + kGK < ke) fetch(k0 + kGK);
 #pragma unroll
-    for (int kk = 0; kk < kGK; kk += 2) {
-      const float a = As[kk + lane / 32][wm + lane % 32];
-      const float bv = Bs[kk + lane / 32][wn + lane % 32];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv, acc, 0, 0, 0);
+    for (int kk = 0; kk < kGK; kk += 4) {
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(As[kk + lane / 32][wm + lane % 32],
+                                                   Bs[kk + lane / 32][wn + lane % 32], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(As[kk + 2 + lane / 32][wm + lane % 32],
+                                                   Bs[kk + 2 + lane / 32][wn + lane % 32], acc1, 0, 0, 0);
     }
   }
   // D: register j of lane l = row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int m = m0 + wm + mfma_row(j, lane / 32), n = n0 + wn + lane % 32;
-    if (m < M && n < N) pr.store(split, m, n, acc[j]);
+    if (m < M && n < N) pr.store(split, m, n, acc0[j] + acc1[j]);
   }
 }
 
 // forward output layer: y[b][o] = sum_f h[b][f] Wf[o][f] + bf[o] -> out[b][o % n_d].(re|im)
 struct FwdOut {
+  static constexpr bool A_KFAST = true, B_KFAST = true;
   const float* h; const float* wf; const float* bf; float* out; int F, n_d;
   __device__ float a(int m, int k) const { return h[(int64_t)m * F + k]; }
   __device__ float b(int k, int n) const { return wf[(int64_t)n * F + k]; }
@@ -124,6 +146,7 @@ struct FwdOut {
 };
 // dpre[b][f] = (sum_o gy[b][o] Wf[o][f]) * (h[b][f] > 0); gy[b][o] = g_out[b][o % n_d].(re|im)
 struct BwdH {
+  static constexpr bool A_KFAST = true, B_KFAST = false;
   const float* g; const float* wf; const float* h; float* dpre; int F, n_d;
   __device__ float a(int m, int k) const { return g[((int64_t)m * n_d + k % n_d) * 2 + k / n_d]; }
   __device__ float b(int k, int n) const { return wf[(int64_t)k * F + n]; }
@@ -134,6 +157,7 @@ struct BwdH {
 // [dWf | dbf] partial of split s: part[s][o][f] = sum_{b in split} gy[b][o] h1[b][f] with
 // h1 = [h | 1] (column F of ones gives the bias gradient)
 struct BwdW {
+  static constexpr bool A_KFAST = false, B_KFAST = false;
   const float* g; const float* h; float* part; int F, n_d, NO;
   __device__ float a(int m, int k) const { return g[((int64_t)k * n_d + m % n_d) * 2 + m / n_d]; }
   __device__ float b(int k, int n) const { return n < F ? h[(int64_t)k * F + n] : 1.f; }
@@ -155,39 +179,60 @@ __global__ void k_cnn_dwf_reduce(CnnGeom g, int k_splits, const float* __restric
   else dw[g.off_bf + o] = acc;
 }
 
-// Convolution weight and bias gradients: thread group k of the workgroup (entries t =
-// 0..nt-1 per group, G = threads / nt groups) owns gradient entry t over the positions
-// f = k, k + G, ... of every item of the workgroup, in one register; the groups are then
+// Convolution weight and bias gradients.  Per iteration a workgroup stages IPW items
+// (their output-gradient planes dpre and zero-padded input planes) in LDS; thread
+// (slot, t), slot < IPW, t < nt, accumulates gradient entry t over all positions of the
+// item in its slot, in one register, across the workgroup's items.  The slots are then
 // added in LDS and the workgroup's partials written to cpart[wg][nt]; k_cnn_dwc_reduce
 // adds the workgroups in order.
+constexpr int kCnnDwcLds = 12288;   // floats of item staging (48 KB)
+
 __global__ __launch_bounds__(kCnnThreads) void k_cnn_dwc(CnnGeom g, int64_t n_items,
                                                          const float* __restrict__ s,
                                                          const float* __restrict__ dpre,
                                                          float* __restrict__ cpart) {
-  __shared__ float xp[2 * kCnnPad * kCnnPad];
-  __shared__ float dl[kCnnMaxF];
+  __shared__ float buf[kCnnDwcLds];
   __shared__ float red[kCnnThreads];
   const int nw = g.n_conv * 2 * g.kc * g.kc, nt = nw + g.n_conv;
   const int hp = g.kc / 2, W = g.side + 2 * hp, S2 = g.side * g.side;
-  const int G = kCnnThreads / nt;
-  const int t = threadIdx.x % nt, grp = threadIdx.x / nt;
-  const bool active = grp < G;
+  const int per_item = g.F + 2 * W * W;                     // dpre plane, then x planes
+  const int ipw = min(kCnnThreads / nt, kCnnDwcLds / per_item);
+  const int t = threadIdx.x % nt, slot = threadIdx.x / nt;
+  const bool active = slot < ipw;
   // entry t: (o, c, p, q) of a weight, or the bias of kernel t - nw
   const bool is_bias = t >= nw;
   const int o = is_bias ? t - nw : t / (2 * g.kc * g.kc);
   const int c = is_bias ? 0 : (t / (g.kc * g.kc)) % 2;
   const int p = is_bias ? 0 : (t / g.kc) % g.kc, q = is_bias ? 0 : t % g.kc;
   float acc = 0.f;
-  for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * ipw;
+  for (int64_t b0 = (int64_t)blockIdx.x * ipw; b0 < n_items; b0 += stride) {
     __syncthreads();
-    for (int f = threadIdx.x; f < g.F; f += kCnnThreads) dl[f] = dpre[b * g.F + f];
-    load_planes(g, s, b, xp);    // (synchronises)
-    if (active) {
-      for (int pos = grp; pos < S2; pos += G) {
-        const int i = pos / g.side, j = pos % g.side;
-        const float d = dl[o * S2 + pos];
-        acc += is_bias ? d : d * xp[c * W * W + (i + p) * W + (j + q)];
+    for (int e = threadIdx.x; e < ipw * per_item; e += kCnnThreads) buf[e] = 0.f;
+    __syncthreads();
+    for (int e = threadIdx.x; e < ipw * g.F; e += kCnnThreads) {
+      const int k = e / g.F;
+      if (b0 + k < n_items) buf[k * per_item + e % g.F] = dpre[(b0 + k) * g.F + e % g.F];
+    }
+    for (int e = threadIdx.x; e < ipw * g.n_d; e += kCnnThreads) {
+      const int k = e / g.n_d, n = e % g.n_d;
+      if (b0 + k < n_items) {
+        const float2 v = ld2(s, (b0 + k) * g.n_d + n);
+        float* xp = buf + k * per_item + g.F;
+        const int r = n / g.side + hp, cc = n % g.side + hp;
+        xp[r * W + cc] = v.x;
+        xp[W * W + r * W + cc] = v.y;
       }
+    }
+    __syncthreads();
+    if (active && b0 + slot < n_items) {
+      const float* dl = buf + slot * per_item + o * S2;
+      const float* xp = buf + slot * per_item + g.F + c * W * W;
+      for (int i = 0; i < g.side; ++i)
+        for (int j = 0; j < g.side; ++j) {
+          const float d = dl[i * g.side + j];
+          acc += is_bias ? d : d * xp[(i + p) * W + (j + q)];
+        }
     }
   }
   __syncthreads();
@@ -195,18 +240,27 @@ __global__ __launch_bounds__(kCnnThreads) void k_cnn_dwc(CnnGeom g, int64_t n_it
   __syncthreads();
   if (threadIdx.x < nt) {
     float sum = 0.f;
-    for (int k = 0; k < G; ++k) sum += red[k * nt + threadIdx.x];
+    for (int k = 0; k < ipw; ++k) sum += red[k * nt + threadIdx.x];
     cpart[(int64_t)blockIdx.x * nt + threadIdx.x] = sum;
   }
 }
 
-__global__ void k_cnn_dwc_reduce(CnnGeom g, int n_wg, const float* __restrict__ cpart, float* __restrict__ dw) {
+// One workgroup per gradient entry t: thread i sums partials i, i + 256, ... in order,
+// then a fixed tree over the threads (deterministic).
+__global__ __launch_bounds__(256) void k_cnn_dwc_reduce(CnnGeom g, int n_wg, const float* __restrict__ cpart,
+                                                        float* __restrict__ dw) {
+  __shared__ float red[256];
   const int nt = g.n_conv * 2 * g.kc * g.kc + g.n_conv;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nt) return;
+  const int t = blockIdx.x;
   float acc = 0.f;
-  for (int i = 0; i < n_wg; ++i) acc += cpart[(int64_t)i * nt + t];
-  dw[t] = acc;   // conv weights then conv biases (offsets 0 and off_bc are contiguous)
+  for (int i = threadIdx.x; i < n_wg; i += 256) acc += cpart[(int64_t)i * nt + t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w2 = 128; w2 > 0; w2 >>= 1) {
+    if (threadIdx.x < w2) red[threadIdx.x] += red[threadIdx.x + w2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dw[t] = red[0];   // conv weights then conv biases (contiguous from 0)
 }
 
 CnnGeom geom(const CnnDims& d) {
@@ -276,7 +330,7 @@ void launch_cnn_dwconv(const CnnDims& d, int64_t n_items, const float* s, const 
   const CnnGeom g = geom(d);
   const int cg = (int)std::min<int64_t>(n_items, kCnnConvWg);
   k_cnn_dwc<<<cg, kCnnThreads, 0, st>>>(g, n_items, s, dpre, cpart);
-  k_cnn_dwc_reduce<<<1, 256, 0, st>>>(g, cg, cpart, dw);
+  k_cnn_dwc_reduce<<<g.n_conv * 2 * g.kc * g.kc + g.n_conv, 256, 0, st>>>(g, cg, cpart, dw);
 }
 
 }  // namespace dpdmi
