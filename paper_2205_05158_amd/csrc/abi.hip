@@ -834,7 +834,7 @@ size_t dpd_acpr_workspace_size(int64_t n, int32_t nfft) {
   if (nfft < 64 || nfft > 4096 || (nfft & (nfft - 1)) || n < nfft) return 0;
   int64_t nseg = (n - nfft) / (nfft / 2) + 1;
   int64_t groups = std::min<int64_t>(nseg, 1024);
-  return align_up(sizeof(float) * (size_t)groups * nfft);
+  return align_up(sizeof(float) * (size_t)groups * nfft) + align_up(sizeof(float2) * (size_t)kWelchSplits * nfft);
 }
 
 dpd_status cascade_acpr(const float* y, int64_t n, int32_t nfft, int32_t half_bins, float* psd,
@@ -849,8 +849,13 @@ dpd_status cascade_acpr(const float* y, int64_t n, int32_t nfft, int32_t half_bi
   int64_t nseg = (n - nfft) / (nfft / 2) + 1;
   int groups = (int)std::min<int64_t>(nseg, 1024);
   float* seg_part = static_cast<float*>(workspace);
+  float2* sums = reinterpret_cast<float2*>(static_cast<char*>(workspace) +
+                                           align_up(sizeof(float) * (size_t)groups * nfft));
   { DPD_PROF("welch"); launch_welch(y, n, nfft, seg_part, groups, stream); }
-  { DPD_PROF("welch_final"); launch_welch_final(seg_part, groups, (int)nseg, nfft, half_bins, psd, acpr, stream); }
+  {
+    DPD_PROF("welch_final");
+    launch_welch_final(seg_part, groups, (int)nseg, nfft, half_bins, sums, psd, acpr, stream);
+  }
   return launch_status();
 }
 

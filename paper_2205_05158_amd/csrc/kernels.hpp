@@ -141,7 +141,9 @@ void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, con
 // ------------------------------------------------------------------ spectrum
 void launch_welch(const float* y, int64_t n, int nfft, float* seg_part, int n_groups,
                   hipStream_t s);
+// sums: workspace float2[kWelchSplits][nfft] (two-stage sum of the group partials)
+constexpr int kWelchSplits = 32;
 void launch_welch_final(const float* seg_part, int n_groups, int nseg, int nfft, int half_bins,
-                        float* psd, float* acpr, hipStream_t s);
+                        float2* sums, float* psd, float* acpr, hipStream_t s);
 
 }  // namespace dpdmi

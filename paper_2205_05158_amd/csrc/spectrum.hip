@@ -73,14 +73,32 @@ __global__ __launch_bounds__(kFftThreads) void k_welch(const float* __restrict__
 
 // psd[k] = sum over groups (fixed order, Neumaier) / (nseg * sum of Hann^2); one
 // thread per bin.
+// Group partials summed in two fixed-order stages: k_welch_sum adds the groups of split
+// blockIdx.y (compensated) into sums[split][k] (value and compensation), k_welch_sum2
+// adds the splits in order and scales.
 __global__ __launch_bounds__(kFftThreads) void k_welch_sum(const float* __restrict__ part, int G,
-                                                           int nseg, int nfft,
-                                                           float* __restrict__ psd) {
+                                                           int nfft, int splits,
+                                                           float2* __restrict__ sums) {
+  const int k = blockIdx.x * kFftThreads + threadIdx.x;
+  if (k >= nfft) return;
+  const int sp = blockIdx.y;
+  const int g0 = (int)((int64_t)sp * G / splits), g1 = (int)((int64_t)(sp + 1) * G / splits);
+  Comp s;
+  for (int g = g0; g < g1; ++g) s.add(part[(int64_t)g * nfft + k]);
+  sums[(int64_t)sp * nfft + k] = make_float2(s.s, s.c);
+}
+
+__global__ __launch_bounds__(kFftThreads) void k_welch_sum2(const float2* __restrict__ sums, int splits,
+                                                            int nseg, int nfft, float* __restrict__ psd) {
   const int k = blockIdx.x * kFftThreads + threadIdx.x;
   if (k >= nfft) return;
   const float scale = 1.0f / ((float)nseg * 0.375f * (float)nfft);   // sum of Hann^2 = 3 nfft / 8
   Comp s;
-  for (int g = 0; g < G; ++g) s.add(part[(int64_t)g * nfft + k]);
+  for (int sp = 0; sp < splits; ++sp) {
+    const float2 v = sums[(int64_t)sp * nfft + k];
+    s.add(v.x);
+    s.add(v.y);
+  }
   psd[k] = s.value() * scale;
 }
 
@@ -129,9 +147,10 @@ void launch_welch(const float* y, int64_t n, int nfft, float* seg_part, int n_gr
 }
 
 void launch_welch_final(const float* seg_part, int n_groups, int nseg, int nfft, int half_bins,
-                        float* psd, float* acpr, hipStream_t s) {
-  k_welch_sum<<<(nfft + kFftThreads - 1) / kFftThreads, kFftThreads, 0, s>>>(seg_part, n_groups,
-                                                                            nseg, nfft, psd);
+                        float2* sums, float* psd, float* acpr, hipStream_t s) {
+  const int nb = (nfft + kFftThreads - 1) / kFftThreads;
+  k_welch_sum<<<dim3(nb, kWelchSplits), kFftThreads, 0, s>>>(seg_part, n_groups, nfft, kWelchSplits, sums);
+  k_welch_sum2<<<nb, kFftThreads, 0, s>>>(sums, kWelchSplits, nseg, nfft, psd);
   k_welch_final<<<1, kFftThreads, 0, s>>>(psd, nfft, half_bins, acpr);
 }
 
