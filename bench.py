@@ -309,7 +309,6 @@ def bench_fdcnn(args):
     import numpy as np
     import torch
     import dpd_synth as S
-    import oracle.fdcnn as OF
     import paper_2205_05158_amd as D
 
     spec = CNN_WORKLOADS[args.workload]
@@ -366,6 +365,7 @@ def bench_fdcnn(args):
         "kernels_ms_per_step": {k: v / args.steps for k, (c, v) in kern.items()},
     }
     if not args.no_cpu_baseline:
+        import oracle.fdcnn as OF
         ns = n   # the whole batch: the oracle finishes it in about a second
         try:
             from threadpoolctl import threadpool_info
