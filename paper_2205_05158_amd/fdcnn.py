@@ -59,3 +59,23 @@ class FdCnn:
             t += 1
             L.dpd_adam_step(dw, w, m, v, t, lr=lr)
         return losses, (m, v, t)
+
+
+class FdCnnFn(torch.autograd.Function):
+    """out = FD-CNN(s; w) as a torch.autograd.Function of the packed parameters w: any loss
+    written in torch on `out` (for instance through a precoder and channel model) reaches
+    w through the library's reverse mode (fdcnn_backward).  The symbol input s is data (no
+    gradient)."""
+
+    @staticmethod
+    def forward(ctx, w, s, net: FdCnn):
+        out = net.forward(s, w.detach())
+        ctx.save_for_backward(w, s)
+        ctx.net = net
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        w, s = ctx.saved_tensors
+        dw = ctx.net.backward(s, w.detach(), grad_out.contiguous())
+        return dw, None, None

@@ -88,3 +88,33 @@ def test_training_run_matches_oracle():
     dg = w.cpu().numpy().astype(np.float64) - w0
     dr = wr - w0
     assert _rel_l2(dg, dr) <= 1e-2
+
+
+def test_autograd_function_with_a_torch_loss():
+    """FdCnnFn under a loss written in torch (a fixed complex gain per subcarrier applied
+    to the network output, then MSE to target symbols): the gradient torch delivers to w
+    equals the oracle's reverse mode for the same output gradient."""
+    shape = SHAPES[0]
+    items = 24
+    announce(f"fdcnn autograd {shape} items={items}")
+    s = S.fdcnn_symbols(items, shape["n_d"], 256, seed=7)
+    t = S.fdcnn_symbols(items, shape["n_d"], 256, seed=8)
+    w0 = S.xavier_fdcnn(**shape, seed=9)
+    rng = np.random.default_rng(10)
+    hk = (rng.standard_normal(shape["n_d"]) + 1j * rng.standard_normal(shape["n_d"])) / np.sqrt(2)
+    net = D.FdCnn(**shape, max_items=items)
+    w = H.to_dev(w0).requires_grad_(True)
+    out = D.FdCnnFn.apply(w, H.to_dev(s), net)
+    oc = torch.complex(out[..., 0].double(), out[..., 1].double())
+    hkt = torch.tensor(hk, device="cuda")
+    tc = torch.tensor(_cplx(t), device="cuda")
+    loss = ((oc * hkt - tc).abs() ** 2).sum() / oc.numel()
+    loss.backward()
+    torch.cuda.synchronize()
+    ref_out, cache = OF.forward(_cplx(s), w0, **shape)
+    e = ref_out * hk - _cplx(t)
+    g = 2.0 * e * np.conj(hk) / e.size                 # real-convention dL/dout
+    ref = OF.backward(g, cache, **shape)
+    rel = _rel_l2(w.grad.cpu().numpy().astype(np.float64), ref)
+    print(f"  autograd gradient rel err {rel:.2e}", flush=True)
+    assert rel <= H.FP32_GRAD
