@@ -54,6 +54,27 @@ def normal_equations(z_streams, t_streams, K: int, M: int, L: int):
     return G, b
 
 
+def normal_equations_chunked(z: np.ndarray, t: np.ndarray, K: int, M: int, L: int,
+                             chunk: int = 1 << 16):
+    """The same sums as normal_equations for one long stream, accumulated over chunks of
+    rows (bounded memory): the rows of [c0, c1) are the basis of the stream's samples
+    c0..c1-1, built from the window z[c0 - M - L, c1 + L) (zero outside the stream)."""
+    J = K * (M + 1) + 2 * (K - 1) * (M + 1) * L
+    N = z.size
+    G = np.zeros((J, J), dtype=np.complex128)
+    b = np.zeros(J, dtype=np.complex128)
+    back, ahead = M + L, L
+    for c0 in range(0, N, chunk):
+        c1 = min(N, c0 + chunk)
+        lo, hi = max(0, c0 - back), min(N, c1 + ahead)
+        # the window reaches M + L samples back and L ahead of its rows, so its own zero
+        # padding falls only beyond the stream ends
+        Phi = basis_matrix(z[lo:hi], K, M, L)[c0 - lo:c1 - lo]
+        G += Phi.conj().T @ Phi
+        b += Phi.conj().T @ t[c0:c1]
+    return G, b
+
+
 def solve_normal(G: np.ndarray, b: np.ndarray, ridge: float = 0.0) -> np.ndarray:
     J = G.shape[0]
     A = G.copy()

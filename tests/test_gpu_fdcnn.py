@@ -118,3 +118,24 @@ def test_autograd_function_with_a_torch_loss():
     rel = _rel_l2(w.grad.cpu().numpy().astype(np.float64), ref)
     print(f"  autograd gradient rel err {rel:.2e}", flush=True)
     assert rel <= H.FP32_GRAD
+
+
+def test_full_size_fdcnn_8u():
+    """The bench workload: 8 UEs x 1024 symbol vectors, the paper's network, every output
+    and the whole gradient against the oracle."""
+    shape = SHAPES[0]
+    items = 8 * 1024
+    announce(f"fdcnn_8u full size {items} items")
+    s = S.fdcnn_symbols(items, shape["n_d"], 256, seed=1)
+    w = S.xavier_fdcnn(**shape, seed=2)
+    g = (np.random.default_rng(3).standard_normal(s.shape) / items).astype(np.float32)
+    ref_out, cache = OF.forward(_cplx(s), w, **shape)
+    ref_dw = OF.backward(_cplx(g), cache, **shape)
+    net = D.FdCnn(**shape, max_items=items)
+    out = net.forward(H.to_dev(s), H.to_dev(w))
+    dw = net.backward(H.to_dev(s), H.to_dev(w), H.to_dev(g))
+    torch.cuda.synchronize()
+    e = H.per_sample_rel(out.cpu().numpy().reshape(-1, 2), ref_out.reshape(-1))
+    rel = _rel_l2(dw.cpu().numpy().astype(np.float64), ref_dw)
+    print(f"  output rel err {e:.2e}; gradient rel err {rel:.2e}", flush=True)
+    assert e <= H.FP32_SAMPLE and rel <= H.FP32_GRAD

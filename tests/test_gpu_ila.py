@@ -125,3 +125,24 @@ def test_linear_pa_post_inverse_closed_form():
     np.testing.assert_allclose(c[0], [want.real, want.imag], rtol=2e-6)
     assert np.abs(c[1:]).max() < 1e-6
     assert float(hist.cpu()[-1]) < -100.0
+
+
+def test_full_size_ila_4m_normal_equations():
+    """The bench workload (2^22 samples, GMP (7, 5, 3) DPD and PA, identity DPD): the
+    device normal equations against the oracle's, accumulated over chunks of the whole
+    stream (bounded memory)."""
+    announce("ila_4m full size: normal equations of the first ILA iteration")
+    inp = S.make_workload("fwd_4m")
+    orders = (7, 5, 3)
+    u = inp.x                                           # identity DPD
+    y = S.to_interleaved(OI.gmp_apply(u, inp.offsets, inp.coef, *orders)).astype(np.float32)
+    print("  oracle PA output ready", flush=True)
+    ila = D.GmpIla(orders, orders, inp.offsets)
+    coef, info, normal = ila.fit(H.to_dev(y), H.to_dev(u), 0.0, want_normal=True)
+    torch.cuda.synchronize()
+    assert int(info.cpu()[0]) == 0
+    yc = y[:, 0].astype(np.float64) + 1j * y[:, 1]
+    uc = u[:, 0].astype(np.float64) + 1j * u[:, 1]
+    G, b = OI.normal_equations_chunked(yc, uc, *orders, chunk=1 << 16)
+    print("  oracle normal equations ready", flush=True)
+    _check_normal(normal.cpu().numpy()[0], G, b)
