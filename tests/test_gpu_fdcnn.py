@@ -33,7 +33,9 @@ def _rel_l2(got, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
-@pytest.mark.parametrize("shape,items", [(SHAPES[0], 70), (SHAPES[0], 1), (SHAPES[1], 130)])
+@pytest.mark.parametrize("shape,items", [(SHAPES[0], 70), (SHAPES[0], 1), (SHAPES[1], 130),
+                                         (dict(n_d=30, side=6, n_conv=4, kc=1), 65),
+                                         (dict(n_d=9, side=3, n_conv=1, kc=7), 33)])
 def test_forward_and_backward_match_oracle(shape, items):
     """float32 (matrix cores for the output layer, K = 800) against float64: outputs per
     symbol within 1e-5 of max(|ref|, rms(ref)); each parameter tensor's gradient within

@@ -36,7 +36,8 @@ def _check_normal(got, ref_G, ref_b):
 # (7, 5, 3), 6e16 for (9, 7, 4) on this input), so the solution is compared where a ridge
 # bounds the condition number by about J / ridge; the normal equations themselves are
 # compared entry by entry in every case.
-@pytest.mark.parametrize("orders,ridge", [((5, 3, 2), 0.0), ((7, 5, 3), 1e-7), ((9, 7, 4), 1e-7)])
+@pytest.mark.parametrize("orders,ridge", [((5, 3, 2), 0.0), ((7, 5, 3), 1e-7), ((9, 7, 4), 1e-7),
+                                          ((4, 0, 0), 0.0), ((3, 2, 0), 0.0), ((2, 0, 3), 0.0)])
 def test_normal_equations_and_solution_match_oracle(orders, ridge):
     announce(f"ls fit orders={orders} ridge={ridge}")
     inp = S.make_workload("fwd_4m", max_len=20000)
