@@ -27,6 +27,7 @@ __all__ = [
     "qam_constellation", "ofdm_signal", "papr_db", "papr_clip", "gmp_coefficients",
     "xavier_tdnn", "stream_lengths", "Workload", "WORKLOADS", "make_workload",
     "tdnn_param_count", "gmp_coeff_count", "to_interleaved", "fdcnn_symbols", "xavier_fdcnn",
+    "downlink_symbols", "mimo_channel", "awgn_fd", "xavier_fdnn", "antenna_pa_coefficients",
 ]
 
 
@@ -176,6 +177,69 @@ def xavier_fdcnn(n_d: int, side: int, n_conv: int, kc: int, seed: int) -> np.nda
     w = np.concatenate([rng.uniform(-lc, lc, n_conv * 2 * kc * kc), np.zeros(n_conv),
                         rng.uniform(-lf, lf, 2 * n_d * F), np.zeros(2 * n_d)])
     return w.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# multi-user downlink (Sec. II-A): UE symbols, channels, noise, FD-NN weights
+# ---------------------------------------------------------------------------
+def downlink_symbols(n_sym: int, users: int, n_fft: int, n_d: int, qam: int, seed: int):
+    """QAM indices int32 [n_sym][users][n_d] (point i_re sqrt(M) + i_im of
+    qam_constellation) and the UE symbol vectors on the subcarriers, float32
+    [n_sym][users][n_fft][2]: data symbol d on subcarrier 1 + d for d < n_d/2, else
+    n_fft - n_d + d (DC and the outer band stay empty)."""
+    if n_d % 2 or n_d >= n_fft:
+        raise ValueError("n_d must be even and < n_fft")
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, qam, size=(n_sym, users, n_d)).astype(np.int32)
+    h = n_d // 2
+    bins = np.concatenate([np.arange(1, h + 1), np.arange(n_fft - h, n_fft)])
+    S = np.zeros((n_sym, users, n_fft), dtype=np.complex128)
+    S[:, :, bins] = qam_constellation(qam)[idx]
+    return idx, to_interleaved(S).astype(np.float32)
+
+
+def mimo_channel(n_ch: int, taps: int, users: int, antennas: int, eta: float, seed: int):
+    """(true, estimated) tap matrices, float32 [n_ch][taps][users][antennas][2]: entries of
+    the true taps ~ CN(0, 1/taps), estimate sqrt(1 - eta) H + sqrt(eta) H_err with
+    H_err ~ CN(0, 1)."""
+    rng = np.random.default_rng(seed)
+    shp = (n_ch, taps, users, antennas)
+    H = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) / math.sqrt(2.0 * taps)
+    E = (rng.standard_normal(shp) + 1j * rng.standard_normal(shp)) / math.sqrt(2.0)
+    He = math.sqrt(1.0 - eta) * H + math.sqrt(eta) * E
+    return to_interleaved(H).astype(np.float32), to_interleaved(He).astype(np.float32)
+
+
+def awgn_fd(n_sym: int, users: int, n_fft: int, n0: float, seed: int) -> np.ndarray:
+    """Frequency-domain receiver noise CN(0, n0) per UE and subcarrier, float32
+    [n_sym][users][n_fft][2]."""
+    rng = np.random.default_rng(seed)
+    shp = (n_sym, users, n_fft, 2)
+    return (rng.standard_normal(shp) * math.sqrt(n0 / 2.0)).astype(np.float32)
+
+
+def xavier_fdnn(users: int, memory: int, hidden: int, n_hidden: int, seed: int) -> np.ndarray:
+    """Glorot-uniform FD-NN weights, zero biases, packed float32 W1[D][2U(L+1)] b1[D]
+    (W_i[D][D] b_i[D]) Wo[2U][D] bo[2U]."""
+    rng = np.random.default_rng(seed)
+    dims = [2 * users * (memory + 1)] + [hidden] * n_hidden + [2 * users]
+    parts = []
+    for fi, fo in zip(dims[:-1], dims[1:]):
+        lim = math.sqrt(6.0 / (fi + fo))
+        parts += [rng.uniform(-lim, lim, fo * fi), np.zeros(fo)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def antenna_pa_coefficients(antennas: int, K: int, M: int, L: int, seed: int,
+                            scale: float = 1.0) -> np.ndarray:
+    """One GMP coefficient set per antenna (gmp_coefficients with seeds seed + b), every
+    coefficient but a_00 = 1 multiplied by `scale`: float32 [antennas][J][2]."""
+    sets = []
+    for b in range(antennas):
+        c = gmp_coefficients(K, M, L, seed + b).astype(np.float64)
+        c[1:] *= scale
+        sets.append(c)
+    return np.stack(sets).astype(np.float32)
 
 
 def stream_lengths(n_streams: int, lo_log2: float = 14.0, hi_log2: float = 20.0,

@@ -7,7 +7,9 @@ with the HIP library.
 parity pins: every function here is checked by tests/test_oracle_pins.py,
 tests/test_oracle_grad.py, tests/test_oracle_adam.py (the training loop of
 oracle/adam.py), tests/test_oracle_ila.py (the least-squares GMP DPD of
-oracle/ila.py) and tests/test_oracle_fdcnn.py (the FD-CNN of oracle/fdcnn.py) against values fixed independently of the oracle (closed forms,
+oracle/ila.py), tests/test_oracle_fdcnn.py (the FD-CNN of oracle/fdcnn.py) and
+tests/test_oracle_ofdm.py (the FD-NN wrapper, ZF precoding and downlink of
+oracle/ofdm.py) against values fixed independently of the oracle (closed forms,
 library routines, brute force, finite differences).  The whole
 cascade at full workload sizes is trusted by composition of those pinned parts.
 """
