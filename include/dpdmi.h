@@ -262,6 +262,98 @@ dpd_status fdcnn_backward(const dpd_fdcnn_desc* desc, int64_t n_items, const flo
                           const float* w, const float* g_out, float* dw, void* workspace,
                           size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------ OFDM downlink
+ * Multi-user OFDM downlink around the frequency-domain DPDs (Sec. II-A, Sec. III-C):
+ * N = n_fft subcarriers; n_data of them carry data, on subcarriers 1..n_data/2 and
+ * N - n_data/2..N - 1 (data symbol d on 1 + d for d < n_data/2, else N - n_data + d),
+ * the rest (DC, outer band) are guard; U users, B antennas, T channel taps.  Every delay
+ * inside an OFDM symbol is cyclic (index mod N): the frequency-domain channel of
+ * eq. (5) holds exactly only for a cyclic convolution, i.e. a cyclic prefix longer than
+ * every memory.  Complex arrays are interleaved float [..][2]; all pointers device
+ * pointers, 8-byte aligned for complex arrays, workspaces 256-byte aligned. */
+
+/* Batched unitary DFT over `rows` contiguous rows of n_fft points, n_fft a power of two
+ * in [2, 4096]: inverse = 0 gives X_k = N^-1/2 sum_n x_n e^{-2 pi i kn/N}, inverse = 1
+ * the IDFT of eq. (2) (+i, same scale).  in may equal out. */
+dpd_status ofdm_fft(int32_t n_fft, int64_t rows, int32_t inverse, const float* in, float* out,
+                    hipStream_t stream);
+
+/* FD-NN DPD (Sec. III-C): each UE's subcarrier vector to the time domain (unitary IDFT),
+ * delay lines of memory + 1 samples of all U UEs as 2 U (memory + 1) real inputs (input
+ * 2 (u (memory + 1) + t) + {0, 1} = Re, Im of UE u's sample n - t), n_hidden fully
+ * connected ReLU layers of `hidden` neurons, 2 U linear outputs (2u = Re, 2u + 1 = Im of
+ * UE u) and a unitary DFT per UE back to all N subcarriers (guard subcarriers included).
+ * Parameters w (float): W1[hidden][2 U (memory+1)] b1[hidden] (W_i[hidden][hidden]
+ * b_i[hidden])_{i=2..n_hidden} Wo[2U][hidden] bo[2U].
+ * Supported: users <= 8, memory <= 7, 2 users (memory + 1) <= 64, hidden <= 32,
+ * n_hidden 1 or 2, n_fft as ofdm_fft. */
+typedef struct {
+    int32_t n_fft;     /* N */
+    int32_t users;     /* U */
+    int32_t memory;    /* delay-line memory (the paper's L4) */
+    int32_t hidden;    /* D */
+    int32_t n_hidden;  /* K^NN */
+} dpd_fdnn_desc;
+
+/* Parameter count (< 0 for an invalid or unsupported descriptor). */
+int64_t fdnn_param_count(const dpd_fdnn_desc* desc);
+dpd_status fdnn_workspace_size(const dpd_fdnn_desc* desc, int64_t n_sym, size_t* bytes_host);
+/* s, out: float[n_sym][U][N][2] (UE symbol vectors on the subcarriers; out may equal s). */
+dpd_status fdnn_forward(const dpd_fdnn_desc* desc, int64_t n_sym, const float* s, const float* w,
+                        float* out, void* workspace, size_t workspace_bytes, hipStream_t stream);
+/* Reverse mode for the real-convention output gradient g_out = dL/dRe + j dL/dIm
+ * (float[n_sym][U][N][2]): dw (float[param count], packed like w) = dL/dw summed over
+ * every symbol, UE and sample (fixed summation order: deterministic). */
+dpd_status fdnn_backward(const dpd_fdnn_desc* desc, int64_t n_sym, const float* s, const float* w,
+                         const float* g_out, float* dw, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream);
+
+/* Downlink link.  Channel taps h: float[n_ch][T][U][B][2].  OFDM symbol i uses channel
+ * realisation i / sym_per_ch (n_ch = ceil(n_sym / sym_per_ch)).
+ * Supported: users <= 8, antennas <= 256, taps <= 64, qam = m^2 with 2 <= m <= 256, PA
+ * and DPD GMP orders within the DPD_MAX_GMP_* ranges with M + L < n_fft, 2 <= n_data <
+ * n_fft even. */
+typedef struct {
+    int32_t n_fft, n_data, users, antennas, taps, qam;
+    dpd_gmp_desc pa;    /* per-antenna PA model, eq. (9) with cyclic delays */
+    dpd_gmp_desc dpd;   /* per-antenna TD-GMP DPD in front of the PA; dpd.K = 0: none */
+} dpd_link_desc;
+
+dpd_status zf_workspace_size(const dpd_link_desc* desc, int32_t n_ch, size_t* bytes_host);
+/* ZF precoding (eq. (6)) from the estimated taps h_est: for every subcarrier k (guard
+ * included) pt[c][k] = H_k^H (H_k H_k^H)^-1 (float[n_ch][N][B][U][2]), H_k = sum_t
+ * H_t e^{-2 pi i k t / N}, computed in FP64 (H_k H_k^H must be nonsingular); alpha[c]
+ * (float[n_ch]) = sqrt(p_total / mean over the data subcarriers of tr(pt^H pt)), so that
+ * the precoder alpha pt meets the average transmit power p_total with unit-energy
+ * symbols (one alpha per channel realisation). */
+dpd_status zf_precoder(const dpd_link_desc* desc, int32_t n_ch, const float* h_est, float p_total,
+                       float* pt, float* alpha, void* workspace, size_t workspace_bytes,
+                       hipStream_t stream);
+/* x[i][b][k] = alpha[c] sum_u pt[c][k][b][u] s[i][u][k] (eq. (1)) on the data subcarriers
+ * (all_bins = 0) or on every subcarrier (all_bins = 1: the guard-band precoding an FD-NN
+ * output needs), 0 elsewhere.  s: float[n_sym][U][N][2]; x: float[n_sym][B][N][2]; pt and
+ * alpha hold (at least) the ceil(n_sym / sym_per_ch) realisations the symbols use. */
+dpd_status ofdm_precode(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* pt,
+                        const float* alpha, const float* s, int32_t all_bins, float* x,
+                        hipStream_t stream);
+dpd_status link_workspace_size(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch,
+                               size_t* bytes_host);
+/* The precoded x (float[n_sym][B][N][2]) through, per antenna b: unitary IDFT (eq. (2)),
+ * the optional TD-GMP DPD (dpd_coef float[B][Jd][2]), the PA (pa_coef float[B][J][2],
+ * eq. (7)), unitary DFT; then per data subcarrier the true channel h (eq. (5)) plus the
+ * frequency-domain noise (float[n_sym][U][N][2], or NULL for none), equalised by
+ * 1 / (alpha[c] G) with G = g_re + j g_im the PA's linear gain, and decided to the
+ * nearest unit-energy square-QAM point, index i_re m + i_im of the point
+ * ((2 i_re - m + 1) + j (2 i_im - m + 1)) / sqrt(2 (m^2 - 1) / 3).  tx: int32
+ * [n_sym][U][n_data] transmitted indices; r_out (NULL or float[n_sym][U][n_data][2]) the
+ * equalised symbols; errors: int64[U] symbol errors per UE (overwritten).  h and alpha
+ * hold (at least) ceil(n_sym / sym_per_ch) realisations. */
+dpd_status ofdm_link(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* x,
+                     const float* dpd_coef, const float* pa_coef, float g_re, float g_im,
+                     const float* h, const float* alpha, const float* noise, const int32_t* tx,
+                     float* r_out, int64_t* errors, void* workspace, size_t workspace_bytes,
+                     hipStream_t stream);
+
 /* Welch PSD of one stream y [n][2] (nfft-point segments, periodic Hann window,
  * 50 % overlap, no detrending, scaled by 1/sum(w^2)), bins in natural FFT order,
  * and the ACPR with main channel |k| <= half_bins, adjacent channels

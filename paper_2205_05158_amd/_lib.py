@@ -43,6 +43,16 @@ class FdcnnDesc(C.Structure):
     _fields_ = [("n_d", C.c_int32), ("side", C.c_int32), ("n_conv", C.c_int32), ("kc", C.c_int32)]
 
 
+class FdnnDesc(C.Structure):
+    _fields_ = [("n_fft", C.c_int32), ("users", C.c_int32), ("memory", C.c_int32), ("hidden", C.c_int32),
+                ("n_hidden", C.c_int32)]
+
+
+class LinkDesc(C.Structure):
+    _fields_ = [("n_fft", C.c_int32), ("n_data", C.c_int32), ("users", C.c_int32), ("antennas", C.c_int32),
+                ("taps", C.c_int32), ("qam", C.c_int32), ("pa", GmpDesc), ("dpd", GmpDesc)]
+
+
 class Tune(C.Structure):
     _fields_ = [("fwd_waves", C.c_int32), ("fwd_wg_per_cu", C.c_int32),
                 ("bwd_wg_per_cu", C.c_int32), ("gmp_tile", C.c_int32)]
@@ -80,6 +90,17 @@ _SIGS = {
     "fdcnn_workspace_size": (C.c_int, [C.POINTER(FdcnnDesc), C.c_int64, C.POINTER(C.c_size_t)]),
     "fdcnn_forward": (C.c_int, [C.POINTER(FdcnnDesc), C.c_int64, _P, _P, _P, _P, C.c_size_t, _P]),
     "fdcnn_backward": (C.c_int, [C.POINTER(FdcnnDesc), C.c_int64, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "ofdm_fft": (C.c_int, [C.c_int32, C.c_int64, C.c_int32, _P, _P, _P]),
+    "fdnn_param_count": (C.c_int64, [C.POINTER(FdnnDesc)]),
+    "fdnn_workspace_size": (C.c_int, [C.POINTER(FdnnDesc), C.c_int64, C.POINTER(C.c_size_t)]),
+    "fdnn_forward": (C.c_int, [C.POINTER(FdnnDesc), C.c_int64, _P, _P, _P, _P, C.c_size_t, _P]),
+    "fdnn_backward": (C.c_int, [C.POINTER(FdnnDesc), C.c_int64, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "zf_workspace_size": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.POINTER(C.c_size_t)]),
+    "zf_precoder": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, _P, C.c_float, _P, _P, _P, C.c_size_t, _P]),
+    "ofdm_precode": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P]),
+    "link_workspace_size": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
+    "ofdm_link": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, _P, _P, _P, C.c_float, C.c_float, _P, _P,
+                            _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dpd_profile_enable": (C.c_int, [C.c_int32]),
@@ -268,6 +289,75 @@ def fdcnn_backward(desc, n_items, s, w, g_out, dw, workspace, stream=None):
     _check(lib().fdcnn_backward(C.byref(desc), int(n_items), _ptr(s), _ptr(w), _ptr(g_out), _ptr(dw),
                                 _ptr(workspace), workspace.numel() * workspace.element_size(),
                                 _stream(stream)), "fdcnn_backward")
+
+
+def _nbytes(t) -> int:
+    return t.numel() * t.element_size()
+
+
+def ofdm_fft(n_fft, rows, inverse, x, out, stream=None):
+    _check(lib().ofdm_fft(int(n_fft), int(rows), int(bool(inverse)), _ptr(x), _ptr(out), _stream(stream)),
+           "ofdm_fft")
+
+
+def fdnn_desc(n_fft, users, memory, hidden, n_hidden) -> FdnnDesc:
+    return FdnnDesc(int(n_fft), int(users), int(memory), int(hidden), int(n_hidden))
+
+
+def fdnn_param_count(desc) -> int:
+    return lib().fdnn_param_count(C.byref(desc))
+
+
+def fdnn_workspace_size(desc, n_sym) -> int:
+    n = C.c_size_t(0)
+    _check(lib().fdnn_workspace_size(C.byref(desc), int(n_sym), C.byref(n)), "fdnn_workspace_size")
+    return n.value
+
+
+def fdnn_forward(desc, n_sym, s, w, out, workspace, stream=None):
+    _check(lib().fdnn_forward(C.byref(desc), int(n_sym), _ptr(s), _ptr(w), _ptr(out), _ptr(workspace),
+                              _nbytes(workspace), _stream(stream)), "fdnn_forward")
+
+
+def fdnn_backward(desc, n_sym, s, w, g_out, dw, workspace, stream=None):
+    _check(lib().fdnn_backward(C.byref(desc), int(n_sym), _ptr(s), _ptr(w), _ptr(g_out), _ptr(dw),
+                               _ptr(workspace), _nbytes(workspace), _stream(stream)), "fdnn_backward")
+
+
+def link_desc(n_fft, n_data, users, antennas, taps, qam, pa, dpd=None) -> LinkDesc:
+    d = dpd if dpd is not None else GmpDesc(0, 0, 0)
+    return LinkDesc(int(n_fft), int(n_data), int(users), int(antennas), int(taps), int(qam), pa, d)
+
+
+def zf_workspace_size(desc, n_ch) -> int:
+    n = C.c_size_t(0)
+    _check(lib().zf_workspace_size(C.byref(desc), int(n_ch), C.byref(n)), "zf_workspace_size")
+    return n.value
+
+
+def zf_precoder(desc, n_ch, h_est, p_total, pt, alpha, workspace, stream=None):
+    _check(lib().zf_precoder(C.byref(desc), int(n_ch), _ptr(h_est), float(p_total), _ptr(pt), _ptr(alpha),
+                             _ptr(workspace), _nbytes(workspace), _stream(stream)), "zf_precoder")
+
+
+def ofdm_precode(desc, n_sym, sym_per_ch, pt, alpha, s, all_bins, x, stream=None):
+    _check(lib().ofdm_precode(C.byref(desc), int(n_sym), int(sym_per_ch), _ptr(pt), _ptr(alpha), _ptr(s),
+                              int(bool(all_bins)), _ptr(x), _stream(stream)), "ofdm_precode")
+
+
+def link_workspace_size(desc, n_sym, sym_per_ch) -> int:
+    n = C.c_size_t(0)
+    _check(lib().link_workspace_size(C.byref(desc), int(n_sym), int(sym_per_ch), C.byref(n)),
+           "link_workspace_size")
+    return n.value
+
+
+def ofdm_link(desc, n_sym, sym_per_ch, x, dpd_coef, pa_coef, g, h, alpha, noise, tx, r_out, errors, workspace,
+              stream=None):
+    g = complex(g)
+    _check(lib().ofdm_link(C.byref(desc), int(n_sym), int(sym_per_ch), _ptr(x), _ptr(dpd_coef), _ptr(pa_coef),
+                           g.real, g.imag, _ptr(h), _ptr(alpha), _ptr(noise), _ptr(tx), _ptr(r_out),
+                           _ptr(errors), _ptr(workspace), _nbytes(workspace), _stream(stream)), "ofdm_link")
 
 
 def dpd_acpr_workspace_size(n: int, nfft: int) -> int:

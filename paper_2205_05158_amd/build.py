@@ -25,7 +25,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]
-SOURCES = ["abi.hip", "plain.hip", "reduce.hip", "gmp.hip", "tdnn.hip", "spectrum.hip", "adam.hip", "ls.hip", "fdcnn.hip"]
+SOURCES = ["abi.hip", "plain.hip", "reduce.hip", "gmp.hip", "tdnn.hip", "spectrum.hip", "adam.hip", "ls.hip", "fdcnn.hip",
+           "ofdm.hip"]
 PEAKS_SOURCES = ["peaks.hip"]
 # Per-source extra flags.  The TDNN kernels keep every dW accumulator of the deepest
 # model in registers; selecting the VGPR form of the MFMA instructions lets the

@@ -914,3 +914,234 @@ const char* dpd_status_string(dpd_status status) {
 const char* dpd_version(void) { return "dpdmi 0.1 gfx950"; }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ OFDM downlink
+namespace {
+
+constexpr int kNnMaxGroups = 512;    // backward partials of the FD-NN
+
+bool fdnn_check(const dpd_fdnn_desc* d, NnDims* out) {
+  if (!d) return false;
+  const NnDims n = nn_dims(d->n_fft, d->users, d->memory, d->hidden, d->n_hidden);
+  if (!nn_supported(n)) return false;
+  *out = n;
+  return true;
+}
+
+struct NnWs {
+  size_t td = 0, o = 0, part = 0, total = 0;
+};
+NnWs fdnn_ws_layout(const NnDims& d, int64_t n_sym) {
+  NnWs w;
+  size_t pos = 0;
+  auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
+  const size_t row = sizeof(float2) * (size_t)n_sym * d.users * d.n_fft;
+  w.td = take(row);
+  w.o = take(row);
+  w.part = take(sizeof(float) * (size_t)kNnMaxGroups * d.part_floats);
+  w.total = pos;
+  return w;
+}
+
+bool fdnn_sym_ok(const NnDims& d, int64_t n_sym) {
+  // tile counts (128-sample tiles) stay within int
+  return n_sym >= 1 && n_sym * (int64_t)((d.n_fft + 127) / 128) < ((int64_t)1 << 31);
+}
+
+bool link_gmp_ok(const dpd_gmp_desc& g, int n_fft) {
+  return g.K >= 1 && g.K <= DPD_MAX_GMP_K && g.M >= 0 && g.M <= DPD_MAX_GMP_M && g.L >= 0 &&
+         g.L <= DPD_MAX_GMP_L && g.M + g.L < n_fft;
+}
+
+dpd_status link_check(const dpd_link_desc* d) {
+  if (!d) return DPD_ERR_NULL;
+  if (!fft_size_ok(d->n_fft)) return DPD_ERR_SHAPE;
+  if (d->n_data < 2 || d->n_data % 2 || d->n_data >= d->n_fft) return DPD_ERR_SHAPE;
+  if (d->users < 1 || d->antennas < 1 || d->taps < 1 || d->qam < 4) return DPD_ERR_SHAPE;
+  int m = 2;
+  while (m * m < d->qam) ++m;
+  if (m * m != d->qam) return DPD_ERR_SHAPE;
+  if (d->users > 8 || d->antennas > 256 || d->taps > 64 || m > 256) return DPD_ERR_UNSUPPORTED;
+  if (!link_gmp_ok(d->pa, d->n_fft)) return DPD_ERR_SHAPE;
+  if (d->dpd.K != 0 && !link_gmp_ok(d->dpd, d->n_fft)) return DPD_ERR_SHAPE;
+  return DPD_OK;
+}
+
+int qam_side(int qam) {
+  int m = 2;
+  while (m * m < qam) ++m;
+  return m;
+}
+
+struct LinkWs {
+  size_t y = 0, hd = 0, part = 0, total = 0;
+};
+LinkWs link_ws_layout(const dpd_link_desc& d, int n_sym, int n_ch) {
+  LinkWs w;
+  size_t pos = 0;
+  auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
+  w.y = take(sizeof(float2) * (size_t)n_sym * d.antennas * d.n_fft);
+  w.hd = take(sizeof(float2) * (size_t)n_ch * d.n_data * d.users * d.antennas);
+  w.part = take(sizeof(int32_t) * (size_t)link_rx_parts(d.n_data, n_sym) * d.users);
+  w.total = pos;
+  return w;
+}
+
+bool syms_ok(int32_t n_sym, int32_t spc) { return n_sym >= 1 && spc >= 1; }
+int n_channels(int32_t n_sym, int32_t spc) { return (int)((n_sym + (int64_t)spc - 1) / spc); }
+
+}  // namespace
+
+extern "C" {
+
+dpd_status ofdm_fft(int32_t n_fft, int64_t rows, int32_t inverse, const float* in, float* out,
+                    hipStream_t stream) {
+  if (!in || !out) return DPD_ERR_NULL;
+  if (!fft_size_ok(n_fft) || rows < 1 || (inverse != 0 && inverse != 1)) return DPD_ERR_SHAPE;
+  if (!aligned(in, 8) || !aligned(out, 8)) return DPD_ERR_ALIGN;
+  { DPD_PROF("fft"); launch_fft(in, out, n_fft, rows, inverse != 0, device_cus(), stream); }
+  return launch_status();
+}
+
+int64_t fdnn_param_count(const dpd_fdnn_desc* desc) {
+  NnDims d;
+  return fdnn_check(desc, &d) ? d.params : -1;
+}
+
+dpd_status fdnn_workspace_size(const dpd_fdnn_desc* desc, int64_t n_sym, size_t* bytes_host) {
+  NnDims d;
+  if (!desc || !bytes_host) return DPD_ERR_NULL;
+  if (!fdnn_check(desc, &d)) return DPD_ERR_UNSUPPORTED;
+  if (!fdnn_sym_ok(d, n_sym)) return DPD_ERR_SHAPE;
+  *bytes_host = fdnn_ws_layout(d, n_sym).total;
+  return DPD_OK;
+}
+
+dpd_status fdnn_forward(const dpd_fdnn_desc* desc, int64_t n_sym, const float* s, const float* w,
+                        float* out, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  NnDims d;
+  if (!desc || !s || !w || !out || !workspace) return DPD_ERR_NULL;
+  if (!fdnn_check(desc, &d)) return DPD_ERR_UNSUPPORTED;
+  if (!fdnn_sym_ok(d, n_sym)) return DPD_ERR_SHAPE;
+  if (!aligned(s, 8) || !aligned(out, 8) || !aligned(w, 4) || !aligned(workspace, 256)) return DPD_ERR_ALIGN;
+  const NnWs L = fdnn_ws_layout(d, n_sym);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  float* td = at<float>(workspace, L.td);
+  float* o = at<float>(workspace, L.o);
+  const int cus = device_cus();
+  const int64_t rows = n_sym * d.users;
+  { DPD_PROF("fdnn_idft"); launch_fft(s, td, d.n_fft, rows, true, cus, stream); }
+  { DPD_PROF("fdnn_net"); launch_fdnn_fwd(d, n_sym, td, w, o, cus, stream); }
+  { DPD_PROF("fdnn_dft"); launch_fft(o, out, d.n_fft, rows, false, cus, stream); }
+  return launch_status();
+}
+
+dpd_status fdnn_backward(const dpd_fdnn_desc* desc, int64_t n_sym, const float* s, const float* w,
+                         const float* g_out, float* dw, void* workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
+  NnDims d;
+  if (!desc || !s || !w || !g_out || !dw || !workspace) return DPD_ERR_NULL;
+  if (!fdnn_check(desc, &d)) return DPD_ERR_UNSUPPORTED;
+  if (!fdnn_sym_ok(d, n_sym)) return DPD_ERR_SHAPE;
+  if (!aligned(s, 8) || !aligned(g_out, 8) || !aligned(w, 4) || !aligned(dw, 4) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  const NnWs L = fdnn_ws_layout(d, n_sym);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  float* td = at<float>(workspace, L.td);
+  float* gtd = at<float>(workspace, L.o);
+  const int cus = device_cus();
+  const int64_t rows = n_sym * d.users;
+  { DPD_PROF("fdnn_idft"); launch_fft(s, td, d.n_fft, rows, true, cus, stream); }
+  // the adjoint of the unitary DFT is the unitary IDFT
+  { DPD_PROF("fdnn_idft"); launch_fft(g_out, gtd, d.n_fft, rows, true, cus, stream); }
+  { DPD_PROF("fdnn_bwd"); launch_fdnn_bwd(d, n_sym, td, gtd, w, at<float>(workspace, L.part), dw,
+                                          std::min(cus, kNnMaxGroups / 2), stream); }
+  return launch_status();
+}
+
+dpd_status zf_workspace_size(const dpd_link_desc* desc, int32_t n_ch, size_t* bytes_host) {
+  if (!desc || !bytes_host) return DPD_ERR_NULL;
+  const dpd_status st = link_check(desc);
+  if (st != DPD_OK) return st;
+  if (n_ch < 1) return DPD_ERR_SHAPE;
+  *bytes_host = align_up(sizeof(double) * (size_t)n_ch * desc->n_fft);
+  return DPD_OK;
+}
+
+dpd_status zf_precoder(const dpd_link_desc* desc, int32_t n_ch, const float* h_est, float p_total,
+                       float* pt, float* alpha, void* workspace, size_t workspace_bytes,
+                       hipStream_t stream) {
+  if (!desc || !h_est || !pt || !alpha || !workspace) return DPD_ERR_NULL;
+  const dpd_status st = link_check(desc);
+  if (st != DPD_OK) return st;
+  if (n_ch < 1 || !(p_total > 0.f) || n_ch > 65535) return DPD_ERR_SHAPE;
+  if (!aligned(h_est, 8) || !aligned(pt, 8) || !aligned(alpha, 4) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (workspace_bytes < align_up(sizeof(double) * (size_t)n_ch * desc->n_fft)) return DPD_ERR_WORKSPACE;
+  {
+    DPD_PROF("zf");
+    launch_zf(h_est, desc->n_fft, desc->n_data, desc->users, desc->antennas, desc->taps, n_ch, p_total, pt,
+              at<double>(workspace, 0), alpha, stream);
+  }
+  return launch_status();
+}
+
+dpd_status ofdm_precode(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* pt,
+                        const float* alpha, const float* s, int32_t all_bins, float* x, hipStream_t stream) {
+  if (!desc || !pt || !alpha || !s || !x) return DPD_ERR_NULL;
+  const dpd_status st = link_check(desc);
+  if (st != DPD_OK) return st;
+  if (!syms_ok(n_sym, sym_per_ch) || n_sym > 65535 || (all_bins != 0 && all_bins != 1)) return DPD_ERR_SHAPE;
+  if (!aligned(pt, 8) || !aligned(alpha, 4) || !aligned(s, 8) || !aligned(x, 8)) return DPD_ERR_ALIGN;
+  {
+    DPD_PROF("precode");
+    launch_precode(pt, alpha, s, desc->n_fft, desc->n_data, desc->users, desc->antennas, n_sym, sym_per_ch,
+                   all_bins, x, stream);
+  }
+  return launch_status();
+}
+
+dpd_status link_workspace_size(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch,
+                               size_t* bytes_host) {
+  if (!desc || !bytes_host) return DPD_ERR_NULL;
+  const dpd_status st = link_check(desc);
+  if (st != DPD_OK) return st;
+  if (!syms_ok(n_sym, sym_per_ch) || n_sym > 65535) return DPD_ERR_SHAPE;
+  *bytes_host = link_ws_layout(*desc, n_sym, n_channels(n_sym, sym_per_ch)).total;
+  return DPD_OK;
+}
+
+dpd_status ofdm_link(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* x,
+                     const float* dpd_coef, const float* pa_coef, float g_re, float g_im, const float* h,
+                     const float* alpha, const float* noise, const int32_t* tx, float* r_out, int64_t* errors,
+                     void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!desc || !x || !pa_coef || !h || !alpha || !tx || !errors || !workspace) return DPD_ERR_NULL;
+  const dpd_status st = link_check(desc);
+  if (st != DPD_OK) return st;
+  if (desc->dpd.K != 0 && !dpd_coef) return DPD_ERR_NULL;
+  if (!syms_ok(n_sym, sym_per_ch) || n_sym > 65535 || !(g_re * g_re + g_im * g_im > 0.f)) return DPD_ERR_SHAPE;
+  if (!aligned(x, 8) || !aligned(pa_coef, 8) || !aligned(h, 8) || !aligned(alpha, 4) || !aligned(tx, 4) ||
+      !aligned(errors, 8) || !aligned(workspace, 256) || (noise && !aligned(noise, 8)) ||
+      (r_out && !aligned(r_out, 8)) || (dpd_coef && !aligned(dpd_coef, 8)))
+    return DPD_ERR_ALIGN;
+  const int n_ch = n_channels(n_sym, sym_per_ch);
+  const LinkWs L = link_ws_layout(*desc, n_sym, n_ch);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  const dpd_link_desc& d = *desc;
+  float* y = at<float>(workspace, L.y);
+  float* hd = at<float>(workspace, L.hd);
+  { DPD_PROF("link_chan"); launch_chan_data(h, d.n_fft, d.n_data, d.users, d.antennas, d.taps, n_ch, hd, stream); }
+  {
+    DPD_PROF("link_pa");
+    launch_link_pa(x, d.n_fft, d.antennas, (int64_t)n_sym * d.antennas, d.dpd.K ? dpd_coef : nullptr,
+                   d.dpd.K ? &d.dpd : nullptr, pa_coef, d.pa, y, device_cus(), stream);
+  }
+  {
+    DPD_PROF("link_rx");
+    launch_link_rx(y, hd, alpha, g_re, g_im, noise, tx, d.n_fft, d.n_data, d.users, d.antennas, n_sym,
+                   sym_per_ch, qam_side(d.qam), r_out, at<int32_t>(workspace, L.part), errors, stream);
+  }
+  return launch_status();
+}
+
+}  // extern "C"

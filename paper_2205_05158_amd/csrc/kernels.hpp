@@ -146,4 +146,40 @@ constexpr int kWelchSplits = 32;
 void launch_welch_final(const float* seg_part, int n_groups, int nseg, int nfft, int half_bins,
                         float2* sums, float* psd, float* acpr, hipStream_t s);
 
+// ------------------------------------------------------------------ OFDM downlink
+// Batched unitary FFT over rows of n = 2^m points (2 <= n <= 4096): forward
+// X_k = n^-1/2 sum x_j e^{-2 pi i jk/n}, inverse with +i.  in may equal out.
+bool fft_size_ok(int n);
+void launch_fft(const float* in, float* out, int n, int64_t rows, bool inverse, int cus, hipStream_t s);
+
+// FD-NN network dims: F = 2 U (L4+1) <= 64 inputs, hidden <= 32, 1 or 2 hidden layers.
+struct NnDims {
+  int n_fft, users, memory, hidden, n_hidden;
+  int params;        // packed parameter count
+  int part_floats;   // floats of one workgroup's padded dW partial (widest layout)
+};
+NnDims nn_dims(int n_fft, int users, int memory, int hidden, int n_hidden);
+bool nn_supported(const NnDims& d);
+int fdnn_bwd_groups(int cus);   // upper bound of the backward grid (partials)
+// td, o_td: [n_sym][U][N] complex time samples.
+void launch_fdnn_fwd(const NnDims& d, int64_t n_sym, const float* td, const float* w, float* o_td, int cus,
+                     hipStream_t s);
+// g_td: time-sample gradients [n_sym][U][N]; part: fdnn_bwd_groups * part_floats floats.
+void launch_fdnn_bwd(const NnDims& d, int64_t n_sym, const float* td, const float* g_td, const float* w,
+                     float* part, float* dw, int cus, hipStream_t s);
+// ZF: pt [n_ch][N][B][U], trace double [n_ch][N], alpha [n_ch].  U <= 8, B <= 256, T <= 64.
+void launch_zf(const float* h_est, int N, int n_d, int U, int B, int T, int n_ch, float p_total, float* pt,
+               double* trace, float* alpha, hipStream_t s);
+void launch_precode(const float* pt, const float* alpha, const float* sym, int N, int n_d, int U, int B,
+                    int n_sym, int spc, int all_bins, float* x, hipStream_t s);
+// true channel on the data subcarriers: hd [n_ch][n_d][U][B]
+void launch_chan_data(const float* h, int N, int n_d, int U, int B, int T, int n_ch, float* hd, hipStream_t s);
+// rows = n_sym * B rows of x [n_sym][B][N] -> y_fd (same layout); dpd may be null.
+void launch_link_pa(const float* x, int N, int B, int64_t rows, const float* dpd, const dpd_gmp_desc* dd,
+                    const float* pa, const dpd_gmp_desc& pd, float* y_fd, int cus, hipStream_t s);
+int64_t link_rx_parts(int n_d, int n_sym);   // int32 partial counts of U entries each
+void launch_link_rx(const float* y_fd, const float* hd, const float* alpha, float g_re, float g_im,
+                    const float* noise, const int32_t* tx, int N, int n_d, int U, int B, int n_sym, int spc,
+                    int qam_m, float* r_out, int32_t* err_part, int64_t* errors, hipStream_t s);
+
 }  // namespace dpdmi

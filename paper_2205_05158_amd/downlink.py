@@ -1,0 +1,123 @@
+"""Multi-user OFDM downlink on the device (Sec. II-A, Sec. III-C): the FD-NN DPD and the
+ZF-precoded link with per-antenna PAs, channel, noise and QAM decisions.
+
+`FdNn` holds the FD-NN descriptor and a workspace sized for a maximum number of OFDM
+symbols; `FdNnFn` makes its output a torch.autograd.Function of the packed weights.
+`Downlink` holds a link descriptor and runs ZF precoding, precoding and the link (the
+symbol error count per UE).  All arrays are contiguous float32 device tensors with a
+trailing (re, im) axis, except the int32 transmitted QAM indices.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+
+def _check_c(t, shape, name):
+    if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected contiguous float32 {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+
+
+class FdNn:
+    def __init__(self, n_fft=4096, users=8, memory=3, hidden=15, n_hidden=1, max_sym=1, device="cuda"):
+        self.desc = L.fdnn_desc(n_fft, users, memory, hidden, n_hidden)
+        self.P = L.fdnn_param_count(self.desc)
+        if self.P < 0:
+            raise RuntimeError("unsupported FD-NN shape")
+        self.n_fft, self.users = n_fft, users
+        self.max_sym = int(max_sym)
+        self.device = torch.device(device)
+        nb = L.fdnn_workspace_size(self.desc, self.max_sym)
+        self.workspace = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+
+    def _n(self, s):
+        n = s.shape[0]
+        _check_c(s, (n, self.users, self.n_fft, 2), "s")
+        if n > self.max_sym:
+            raise ValueError("more OFDM symbols than the workspace was sized for")
+        return n
+
+    def forward(self, s, w):
+        n = self._n(s)
+        out = torch.empty_like(s)
+        L.fdnn_forward(self.desc, n, s, w, out, self.workspace)
+        return out
+
+    def backward(self, s, w, g_out):
+        n = self._n(s)
+        dw = torch.empty(self.P, dtype=torch.float32, device=self.device)
+        L.fdnn_backward(self.desc, n, s, w, g_out, dw, self.workspace)
+        return dw
+
+
+class FdNnFn(torch.autograd.Function):
+    """out = FD-NN(s; w) as a function of the packed weights w (s is data)."""
+
+    @staticmethod
+    def forward(ctx, w, s, net: FdNn):
+        out = net.forward(s, w.detach())
+        ctx.save_for_backward(w, s)
+        ctx.net = net
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        w, s = ctx.saved_tensors
+        return ctx.net.backward(s, w.detach(), grad_out.contiguous()), None, None
+
+
+class Downlink:
+    def __init__(self, n_fft=4096, n_data=384, users=8, antennas=32, taps=10, qam=256, pa=(7, 3, 1),
+                 dpd=None, device="cuda"):
+        self.desc = L.link_desc(n_fft, n_data, users, antennas, taps, qam, L.GmpDesc(*pa),
+                                L.GmpDesc(*dpd) if dpd else None)
+        self.n_fft, self.n_data, self.users, self.antennas, self.taps = n_fft, n_data, users, antennas, taps
+        self.device = torch.device(device)
+
+    def zf(self, h_est, p_total):
+        """-> (pt [n_ch][N][B][U][2], alpha [n_ch]) from the estimated taps [n_ch][T][U][B][2]."""
+        n_ch = h_est.shape[0]
+        _check_c(h_est, (n_ch, self.taps, self.users, self.antennas, 2), "h_est")
+        pt = torch.empty(n_ch, self.n_fft, self.antennas, self.users, 2, dtype=torch.float32, device=self.device)
+        alpha = torch.empty(n_ch, dtype=torch.float32, device=self.device)
+        ws = torch.empty(max(L.zf_workspace_size(self.desc, n_ch), 256), dtype=torch.uint8, device=self.device)
+        L.zf_precoder(self.desc, n_ch, h_est, p_total, pt, alpha, ws)
+        return pt, alpha
+
+    def _check_channels(self, pt, alpha, n_sym, sym_per_ch, h=None):
+        n_ch = -(-n_sym // sym_per_ch)
+        if pt is not None:
+            _check_c(pt, (pt.shape[0], self.n_fft, self.antennas, self.users, 2), "pt")
+            if pt.shape[0] < n_ch:
+                raise ValueError(f"pt holds {pt.shape[0]} channel realisations, {n_ch} needed")
+        if h is not None:
+            _check_c(h, (h.shape[0], self.taps, self.users, self.antennas, 2), "h")
+            if h.shape[0] < n_ch:
+                raise ValueError(f"h holds {h.shape[0]} channel realisations, {n_ch} needed")
+        if alpha.dtype != torch.float32 or alpha.numel() < n_ch:
+            raise ValueError(f"alpha: float32 with at least {n_ch} entries expected")
+
+    def precode(self, s, pt, alpha, sym_per_ch=1, all_bins=False):
+        """UE symbols on the subcarriers [n_sym][U][N][2] -> antenna subcarriers [n_sym][B][N][2]."""
+        n = s.shape[0]
+        _check_c(s, (n, self.users, self.n_fft, 2), "s")
+        self._check_channels(pt, alpha, n, sym_per_ch)
+        x = torch.empty(n, self.antennas, self.n_fft, 2, dtype=torch.float32, device=self.device)
+        L.ofdm_precode(self.desc, n, sym_per_ch, pt, alpha, s, all_bins, x)
+        return x
+
+    def link(self, x, pa_coef, g, h, alpha, tx, noise=None, dpd_coef=None, sym_per_ch=1, want_r=False):
+        """-> (symbol errors per UE int64 [U], equalised symbols [n_sym][U][n_data][2] or None)."""
+        n = x.shape[0]
+        _check_c(x, (n, self.antennas, self.n_fft, 2), "x")
+        self._check_channels(None, alpha, n, sym_per_ch, h)
+        if tx.dtype != torch.int32 or tuple(tx.shape) != (n, self.users, self.n_data) or not tx.is_contiguous():
+            raise ValueError("tx: expected contiguous int32 [n_sym][U][n_data]")
+        errors = torch.empty(self.users, dtype=torch.int64, device=self.device)
+        r = (torch.empty(n, self.users, self.n_data, 2, dtype=torch.float32, device=self.device)
+             if want_r else None)
+        ws = torch.empty(max(L.link_workspace_size(self.desc, n, sym_per_ch), 256), dtype=torch.uint8,
+                         device=self.device)
+        L.ofdm_link(self.desc, n, sym_per_ch, x, dpd_coef, pa_coef, g, h, alpha, noise, tx, r, errors, ws)
+        return errors, r

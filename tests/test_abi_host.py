@@ -211,3 +211,60 @@ def test_fdcnn_arguments_rejected(dpdlib):
     assert lib.fdcnn_backward(C.byref(d), 4, FAKE, FAKE, C.c_void_p(0x100004), FAKE, FAKE, 1 << 40,
                               None) == L.DPD_ERR_ALIGN
     assert D.fdcnn_workspace_size(d, 100) > D.fdcnn_workspace_size(d, 10)
+
+
+def test_downlink_arguments_rejected(dpdlib):
+    lib = L.lib()
+    OUT = C.c_void_p(0x200000)
+    # FFT: sizes are powers of two in [2, 4096]
+    for n in (0, 1, 3, 96, 8192):
+        assert lib.ofdm_fft(n, 4, 0, FAKE, OUT, None) == L.DPD_ERR_SHAPE
+    assert lib.ofdm_fft(64, 0, 0, FAKE, OUT, None) == L.DPD_ERR_SHAPE
+    assert lib.ofdm_fft(64, 4, 2, FAKE, OUT, None) == L.DPD_ERR_SHAPE
+    assert lib.ofdm_fft(64, 4, 0, None, OUT, None) == L.DPD_ERR_NULL
+    assert lib.ofdm_fft(64, 4, 0, C.c_void_p(0x100004), OUT, None) == L.DPD_ERR_ALIGN
+    # FD-NN: the paper's network (U = 8, L4 = 3, D = 15, one hidden layer)
+    d = L.fdnn_desc(4096, 8, 3, 15, 1)
+    assert D.FdNn.__name__ and L.fdnn_param_count(d) == 15 * 64 + 15 + 16 * 15 + 16
+    assert L.fdnn_param_count(L.fdnn_desc(64, 2, 1, 4, 2)) == 4 * 8 + 4 + 4 * 4 + 4 + 4 * 4 + 4
+    for bad in [L.fdnn_desc(4096, 9, 3, 15, 1), L.fdnn_desc(4096, 8, 4, 15, 1), L.fdnn_desc(4096, 8, 3, 33, 1),
+                L.fdnn_desc(4096, 8, 3, 15, 3), L.fdnn_desc(4000, 8, 3, 15, 1), L.fdnn_desc(4096, 0, 3, 15, 1)]:
+        assert L.fdnn_param_count(bad) == -1
+        assert lib.fdnn_forward(C.byref(bad), 2, FAKE, FAKE, OUT, FAKE, 1 << 40, None) == L.DPD_ERR_UNSUPPORTED
+    assert lib.fdnn_forward(C.byref(d), 0, FAKE, FAKE, OUT, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert lib.fdnn_forward(C.byref(d), 2, None, FAKE, OUT, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    assert lib.fdnn_forward(C.byref(d), 2, FAKE, FAKE, OUT, FAKE, 16, None) == L.DPD_ERR_WORKSPACE
+    assert lib.fdnn_backward(C.byref(d), 2, FAKE, FAKE, FAKE, C.c_void_p(0x100002), FAKE, 1 << 40,
+                             None) == L.DPD_ERR_ALIGN
+    assert L.fdnn_workspace_size(d, 20) > L.fdnn_workspace_size(d, 2)
+    # link: U <= 8, B <= 256, T <= 64, square QAM, GMP orders in range
+    pa = L.GmpDesc(7, 3, 1)
+    ok = L.link_desc(4096, 384, 8, 32, 10, 256, pa)
+    assert L.zf_workspace_size(ok, 3) >= 3 * 4096 * 8
+    cases = [(L.link_desc(4096, 384, 9, 32, 10, 256, pa), L.DPD_ERR_UNSUPPORTED),
+             (L.link_desc(4096, 384, 8, 257, 10, 256, pa), L.DPD_ERR_UNSUPPORTED),
+             (L.link_desc(4096, 384, 8, 32, 65, 256, pa), L.DPD_ERR_UNSUPPORTED),
+             (L.link_desc(4096, 384, 8, 32, 10, 200, pa), L.DPD_ERR_SHAPE),
+             (L.link_desc(4096, 385, 8, 32, 10, 256, pa), L.DPD_ERR_SHAPE),
+             (L.link_desc(4096, 4096, 8, 32, 10, 256, pa), L.DPD_ERR_SHAPE),
+             (L.link_desc(3000, 384, 8, 32, 10, 256, pa), L.DPD_ERR_SHAPE),
+             (L.link_desc(4096, 384, 8, 32, 10, 256, L.GmpDesc(13, 3, 1)), L.DPD_ERR_SHAPE),
+             (L.link_desc(16, 8, 2, 4, 2, 16, L.GmpDesc(3, 15, 1)), L.DPD_ERR_SHAPE),      # M + L >= N
+             (L.link_desc(4096, 384, 8, 32, 10, 256, pa, L.GmpDesc(3, 16, 0)), L.DPD_ERR_SHAPE)]
+    for desc, code in cases:
+        assert lib.zf_precoder(C.byref(desc), 1, FAKE, C.c_float(1.0), OUT, FAKE, FAKE, 1 << 40, None) == code
+        assert lib.ofdm_link(C.byref(desc), 2, 1, FAKE, FAKE, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
+                             None, FAKE, None, FAKE, FAKE, 1 << 40, None) == code
+    assert lib.zf_precoder(C.byref(ok), 1, FAKE, C.c_float(0.0), OUT, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert lib.zf_precoder(C.byref(ok), 2, FAKE, C.c_float(1.0), OUT, FAKE, FAKE, 16, None) == L.DPD_ERR_WORKSPACE
+    assert lib.ofdm_precode(C.byref(ok), 4, 0, FAKE, FAKE, FAKE, 0, OUT, None) == L.DPD_ERR_SHAPE
+    assert lib.ofdm_precode(C.byref(ok), 4, 1, FAKE, FAKE, FAKE, 2, OUT, None) == L.DPD_ERR_SHAPE
+    # a DPD in the descriptor needs its coefficients; a zero gain cannot be equalised
+    withdpd = L.link_desc(4096, 384, 8, 32, 10, 256, pa, L.GmpDesc(5, 2, 1))
+    assert lib.ofdm_link(C.byref(withdpd), 2, 1, FAKE, None, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
+                         None, FAKE, None, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    assert lib.ofdm_link(C.byref(ok), 2, 1, FAKE, None, FAKE, C.c_float(0.0), C.c_float(0.0), FAKE, FAKE,
+                         None, FAKE, None, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert lib.ofdm_link(C.byref(ok), 2, 1, FAKE, None, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
+                         None, FAKE, None, FAKE, FAKE, 64, None) == L.DPD_ERR_WORKSPACE
+    assert L.link_workspace_size(ok, 20, 10) > L.link_workspace_size(ok, 2, 1)

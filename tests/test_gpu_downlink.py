@@ -1,0 +1,250 @@
+"""Downlink path on the device against the FP64 oracle of oracle/ofdm.py: batched unitary
+FFTs, the FD-NN forward and backward, ZF precoding, precoding and the link (per-antenna
+DPD and PA, channel, noise, QAM decisions).  Small shapes that span several tiles with
+ragged tails, degenerate sizes (two-point transforms, one user, one antenna), and the
+paper's configuration (4096 subcarriers, 384 data, 8 UEs, 32 antennas, 10 taps,
+256-QAM, GMP K=7 L3=3 G=1, FD-NN L4=3 D=15)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import dpd_synth as S
+import oracle.ofdm as O
+import paper_2205_05158_amd as D
+from paper_2205_05158_amd import _lib as L
+import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+def announce(msg):
+    print(f"\n[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _c(a):
+    a = np.asarray(a, dtype=np.float64)
+    return a[..., 0] + 1j * a[..., 1]
+
+
+def _rms_rel(got, ref):
+    """max |got - ref| / rms(ref)."""
+    return float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2)))
+
+
+# ---------------------------------------------------------------------------
+# FFT
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,rows", [(2, 3), (4, 1), (8, 5), (64, 33), (128, 7), (2048, 9), (4096, 1100)])
+def test_fft_matches_oracle(n, rows):
+    """FP32 FFT against the FP64 unitary DFT: max error within 1e-5 of the rms (the
+    rounding of log2 n radix passes is ~log2(n) 2^-24)."""
+    announce(f"fft n={n} rows={rows}")
+    rng = np.random.default_rng(n + rows)
+    x = (rng.standard_normal((rows, n, 2)) / math.sqrt(2)).astype(np.float32)
+    xd = H.to_dev(x)
+    for inverse, ref in ((0, O.dft(_c(x))), (1, O.idft(_c(x)))):
+        out = torch.empty_like(xd)
+        L.ofdm_fft(n, rows, inverse, xd, out)
+        torch.cuda.synchronize()
+        assert _rms_rel(_c(out.cpu().numpy()), ref) < 1e-5, (n, rows, inverse)
+    # in place, and the round trip
+    y = xd.clone()
+    L.ofdm_fft(n, rows, 0, y, y)
+    L.ofdm_fft(n, rows, 1, y, y)
+    torch.cuda.synchronize()
+    assert _rms_rel(_c(y.cpu().numpy()), _c(x)) < 2e-5
+
+
+# ---------------------------------------------------------------------------
+# FD-NN
+# ---------------------------------------------------------------------------
+FDNN_CASES = [
+    # (N, U, L4, D, n_hidden, n_sym)
+    (64, 2, 1, 5, 1, 3),          # one tile per symbol, short symbols
+    (512, 3, 2, 15, 2, 2),        # several tiles per symbol, two hidden layers
+    (2, 1, 0, 1, 1, 4),           # degenerate: two samples, one user, no memory, one neuron
+    (256, 8, 3, 32, 2, 2),        # widest inputs (64) and hidden layers (32)
+    (4096, 8, 3, 15, 1, 2),       # the paper's network at the paper's symbol size
+]
+
+
+def _fdnn_inputs(N, U, L4, Dh, nh, n_sym, seed=0):
+    """UE symbol vectors (QAM on 3/32 of the subcarriers, unit time-domain power; plain
+    Gaussian vectors for tiny N), Glorot weights with small non-zero biases."""
+    rng = np.random.default_rng(seed + 2)
+    if N >= 64:
+        n_d = 3 * N // 32
+        _, s = S.downlink_symbols(n_sym, U, N, n_d, 16, seed)
+        s = (s * math.sqrt(N / n_d)).astype(np.float32)
+    else:
+        s = (rng.standard_normal((n_sym, U, N, 2)) / math.sqrt(2)).astype(np.float32)
+    w = S.xavier_fdnn(U, L4, Dh, nh, seed + 1).astype(np.float64)
+    w += 0.05 * rng.standard_normal(w.size) * (w == 0)
+    return s, w.astype(np.float32), rng
+
+
+@pytest.mark.parametrize("case", FDNN_CASES)
+def test_fdnn_forward_and_backward_match_oracle(case):
+    """Outputs within 1e-5 of the rms, gradients within 1e-4 in relative L2 per layer
+    (FP32 FFTs and sums against FP64)."""
+    N, U, L4, Dh, nh, n_sym = case
+    announce(f"fdnn N={N} U={U} L4={L4} D={Dh} nh={nh} n_sym={n_sym}")
+    s, w, rng = _fdnn_inputs(*case)
+    g = (rng.standard_normal(s.shape) / math.sqrt(s.size)).astype(np.float32)
+    ref, cache = O.fdnn_forward(_c(s), w, U, L4, Dh, nh)
+    ref_dw = O.fdnn_backward(_c(g), cache, U, L4)
+    net = D.FdNn(N, U, L4, Dh, nh, max_sym=n_sym)
+    out = net.forward(H.to_dev(s), H.to_dev(w))
+    dw = net.backward(H.to_dev(s), H.to_dev(w), H.to_dev(g))
+    torch.cuda.synchronize()
+    assert _rms_rel(_c(out.cpu().numpy()), ref) < 1e-5
+    got = dw.cpu().numpy().astype(np.float64)
+    F = 2 * U * (L4 + 1)
+    sizes = [Dh * F, Dh] + [Dh * Dh, Dh] * (nh - 1) + [2 * U * Dh, 2 * U]
+    cuts = np.concatenate([[0], np.cumsum(sizes)])
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        r = ref_dw[a:b]
+        assert np.linalg.norm(got[a:b] - r) <= 1e-4 * np.linalg.norm(r) + 1e-7, (a, b)
+
+
+def test_fdnn_routing_network_delays_exactly():
+    """The routing network (UE u+1's sample n - t to UE u) on the device: the output is
+    the input subcarriers times exp(-j 2 pi k t / N)."""
+    U, L4, N, t = 3, 3, 128, 2
+    announce("fdnn routing network")
+    rng = np.random.default_rng(4)
+    s = (rng.standard_normal((2, U, N, 2)) / math.sqrt(2)).astype(np.float32)
+    F, Dh = 2 * U * (L4 + 1), 4 * U
+    W1 = np.zeros((Dh, F))
+    Wo = np.zeros((2 * U, Dh))
+    for u in range(U):
+        j = 2 * (((u + 1) % U) * (L4 + 1) + t)
+        W1[4 * u, j], W1[4 * u + 1, j], W1[4 * u + 2, j + 1], W1[4 * u + 3, j + 1] = 1, -1, 1, -1
+        Wo[2 * u, 4 * u], Wo[2 * u, 4 * u + 1], Wo[2 * u + 1, 4 * u + 2], Wo[2 * u + 1, 4 * u + 3] = 1, -1, 1, -1
+    w = np.concatenate([W1.reshape(-1), np.zeros(Dh), Wo.reshape(-1), np.zeros(2 * U)]).astype(np.float32)
+    net = D.FdNn(N, U, L4, Dh, 1, max_sym=2)
+    out = _c(net.forward(H.to_dev(s), H.to_dev(w)).cpu().numpy())
+    ramp = np.exp(-2j * np.pi * np.arange(N) * t / N)
+    ref = _c(s)[:, [(u + 1) % U for u in range(U)], :] * ramp
+    assert _rms_rel(out, ref) < 1e-5
+
+
+def test_fdnn_autograd_function():
+    N, U, L4, Dh, nh, n_sym = 256, 4, 2, 8, 1, 3
+    announce("fdnn autograd")
+    s, w, rng = _fdnn_inputs(N, U, L4, Dh, nh, n_sym, seed=5)
+    target = (rng.standard_normal(s.shape) * 0.5).astype(np.float32)
+    net = D.FdNn(N, U, L4, Dh, nh, max_sym=n_sym)
+    wd = H.to_dev(w).requires_grad_(True)
+    out = D.FdNnFn.apply(wd, H.to_dev(s), net)
+    loss = ((out - H.to_dev(target)) ** 2).sum() / out.numel()
+    loss.backward()
+    ref, cache = O.fdnn_forward(_c(s), w, U, L4, Dh, nh)
+    e = ref - _c(target)
+    ref_dw = O.fdnn_backward(e * (2.0 / out.numel()), cache, U, L4)     # numel counts Re and Im
+    got = wd.grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref_dw) <= 1e-4 * np.linalg.norm(ref_dw)
+
+
+# ---------------------------------------------------------------------------
+# ZF precoding, precoding, link
+# ---------------------------------------------------------------------------
+LINK_CASES = [
+    # (N, n_d, U, B, T, qam, spc, n_sym, pa (K, M, L), dpd or None)
+    (64, 48, 4, 8, 4, 16, 2, 4, (3, 1, 1), None),
+    (256, 96, 3, 5, 6, 64, 3, 7, (5, 2, 1), (3, 1, 1)),    # ragged last channel block
+    (4, 2, 1, 1, 1, 4, 1, 2, (2, 0, 0), None),             # degenerate: N = 4, one UE, one antenna
+    (4096, 384, 8, 32, 10, 256, 2, 4, (7, 3, 1), None),    # the paper's link
+]
+
+
+def _link_inputs(case, seed=0, pa_scale=0.3):
+    """Transmit power set so that each antenna's time-domain signal has rms 0.5 (where the
+    synthetic PAs are visibly nonlinear); weak receiver noise (N0 = 1e-4)."""
+    N, n_d, U, B, T, qam, spc, n_sym, pa, dpd = case
+    n_ch = -(-n_sym // spc)
+    idx, s = S.downlink_symbols(n_sym, U, N, n_d, qam, seed)
+    h, he = S.mimo_channel(n_ch, T, U, B, 0.001, seed + 1)
+    pa_c = S.antenna_pa_coefficients(B, *pa, seed + 10, scale=pa_scale)
+    dpd_c = S.antenna_pa_coefficients(B, *dpd, seed + 20, scale=0.1) if dpd else None
+    noise = S.awgn_fd(n_sym, U, N, 1e-4, seed + 3)
+    return dict(idx=idx, s=s, h=h, he=he, pa=pa_c, dpd=dpd_c, noise=noise, p_total=0.25 * B * N / n_d)
+
+
+@pytest.mark.parametrize("case", LINK_CASES)
+def test_zf_precode_link_match_oracle(case):
+    """ZF (FP64 on the device) within 1e-6 of max |Pt| and alpha within 1e-6; precoded
+    subcarriers and equalised symbols within 1e-5 of the rms; every decision equals the
+    exhaustive nearest-point search on the device's own equalised symbols (away from
+    decision boundaries, where the FP32 and FP64 roundings may differ), and the error
+    counts agree with the oracle's up to the symbols that sit that close to a boundary."""
+    N, n_d, U, B, T, qam, spc, n_sym, pa, dpd = case
+    announce(f"link N={N} n_d={n_d} U={U} B={B} T={T} qam={qam} spc={spc} n_sym={n_sym} pa={pa} dpd={dpd}")
+    inp = _link_inputs(case)
+    n_ch = -(-n_sym // spc)
+    G = 1.0
+    ref_pt, ref_alpha = O.zf_precoder(_c(inp["he"]), N, n_d, inp["p_total"])
+    ref_x = O.precode(_c(inp["s"]), ref_pt, ref_alpha, n_d, False, spc)
+    ref_r, ref_dec, ref_err = O.link(ref_x, _c(inp["h"]), ref_alpha, inp["pa"], pa, G, _c(inp["noise"]),
+                                     inp["idx"], qam, n_d, spc, dpd_coef=inp["dpd"], dpd_orders=dpd)
+    dl = D.Downlink(N, n_d, U, B, T, qam, pa=pa, dpd=dpd)
+    pt, alpha = dl.zf(H.to_dev(inp["he"]), inp["p_total"])
+    x = dl.precode(H.to_dev(inp["s"]), pt, alpha, sym_per_ch=spc)
+    err, r = dl.link(x, H.to_dev(inp["pa"]), G, H.to_dev(inp["h"]), alpha,
+                     torch.from_numpy(inp["idx"]).cuda(), noise=H.to_dev(inp["noise"]),
+                     dpd_coef=H.to_dev(inp["dpd"]) if dpd else None, sym_per_ch=spc, want_r=True)
+    torch.cuda.synchronize()
+    g_pt = _c(pt.cpu().numpy())
+    assert np.max(np.abs(g_pt - ref_pt)) <= 1e-6 * np.max(np.abs(ref_pt))
+    np.testing.assert_allclose(alpha.cpu().numpy(), ref_alpha, rtol=1e-6)
+    # the precoder inverts the estimated channel on every subcarrier
+    Hk = O.channel_fd(_c(inp["he"]), N)
+    assert np.max(np.abs(Hk @ g_pt - np.eye(U))) < 1e-4
+    assert _rms_rel(_c(x.cpu().numpy()), ref_x) < 1e-5
+    g_r = _c(r.cpu().numpy())
+    assert _rms_rel(g_r, ref_r) < 1e-5
+    # decisions on the device's own symbols
+    m = int(round(math.sqrt(qam)))
+    qs = math.sqrt(2.0 * (qam - 1) / 3.0)
+    v = np.stack([g_r.real, g_r.imag], -1) * qs + m       # decision boundaries at v = 2k, 1 <= k < m
+    k = np.round(v / 2)
+    near = np.any((np.abs(v / 2 - k) < 1e-3) & (k >= 1) & (k <= m - 1), axis=-1)
+    dec = O.qam_decide(g_r, qam)
+    amb = near.sum(axis=(0, 2))
+    got_err = err.cpu().numpy()
+    assert np.all(np.abs(got_err - (dec != inp["idx"]).sum(axis=(0, 2))) <= amb)
+    # against the oracle's own decisions: any disagreement sits at a boundary
+    assert np.all(near[dec != ref_dec])
+    assert np.all(np.abs(got_err - ref_err) <= amb)
+
+
+def test_link_transparent_linear_pa_and_ser_closed_form():
+    """Linear PA, perfect CSI: with no noise the equalised symbols are the transmitted
+    ones (no errors); with AWGN the error count matches the closed-form QAM SER within
+    5 standard deviations."""
+    N, n_d, U, B, T, qam, spc, n_sym = 256, 192, 4, 16, 6, 16, 8, 8
+    announce("link linear PA / SER")
+    idx, s = S.downlink_symbols(n_sym, U, N, n_d, qam, 3)
+    h, _ = S.mimo_channel(1, T, U, B, 0.0, 4)
+    pa = np.zeros((B, S.gmp_coeff_count(2, 0, 0), 2), dtype=np.float32)
+    pa[:, 0, 0] = 0.8
+    dl = D.Downlink(N, n_d, U, B, T, qam, pa=(2, 0, 0))
+    pt, alpha = dl.zf(H.to_dev(h), 4.0)
+    x = dl.precode(H.to_dev(s), pt, alpha, sym_per_ch=spc)
+    tx = torch.from_numpy(idx).cuda()
+    err, r = dl.link(x, H.to_dev(pa), 0.8, H.to_dev(h), alpha, tx, sym_per_ch=spc, want_r=True)
+    torch.cuda.synchronize()
+    assert int(err.sum()) == 0
+    db = O.data_bins(N, n_d)
+    assert _rms_rel(_c(r.cpu().numpy()), _c(s)[:, :, db]) < 1e-5
+    a = float(alpha.cpu()[0])
+    snr = 10 ** (13.0 / 10)
+    noise = S.awgn_fd(n_sym, U, N, (a * 0.8) ** 2 / snr, 8)
+    err, _ = dl.link(x, H.to_dev(pa), 0.8, H.to_dev(h), alpha, tx, noise=H.to_dev(noise), sym_per_ch=spc)
+    n = n_sym * U * n_d
+    p = O.qam_ser_awgn(qam, snr)
+    assert abs(int(err.sum()) / n - p) < 5 * math.sqrt(p * (1 - p) / n)
