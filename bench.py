@@ -32,6 +32,18 @@ PEAK = {  # MI355X published peaks
 ILA_WORKLOADS = {"ila_4m": dict(signal="fwd_4m", dpd=(7, 5, 3))}
 # FD-CNN: U = 8 UEs x 1024 OFDM symbols of the 5G n257 numerology (384 data subcarriers,
 # 256-QAM), the network of Sec. V-A (20 x 20 grid, two 3 x 3 kernels, 800 -> 768)
+# Downlink of the paper's simulation setup (Sec. V-A): 4096 subcarriers, 384 data, 8 UEs,
+# 256-QAM; the FD-NN of the paper (L4 = 3, one hidden layer of 15, ReLU) over 1024 OFDM
+# symbols; the ZF link with 32 antennas, 10 taps, eta = 0.001, GMP PAs K = 7, L3 = 3, G = 1
+# and a new channel per OFDM symbol over 64 symbols (eta = 1e-4 and PA memory/nonlinear
+# terms scaled by 0.05 keep the synthetic link's SER near 1e-2 at a per-antenna rms of 0.3).
+DL_WORKLOADS = {
+    "fdnn_8u": dict(kind="fdnn", n_sym=1024, n_fft=4096, n_d=384, users=8, memory=3, hidden=15,
+                    n_hidden=1, qam=256, cpu_sym=1024),
+    "link_8u32b": dict(kind="link", n_sym=64, sym_per_ch=1, n_fft=4096, n_d=384, users=8, antennas=32,
+                       taps=10, eta=1e-4, n0=1e-3, qam=256, pa=(7, 3, 1), pa_scale=0.05, rms=0.3,
+                       cpu_sym=64),
+}
 CNN_WORKLOADS = {"fdcnn_8u": dict(items=8 * 1024, n_d=384, side=20, n_conv=2, kc=3, qam=256)}
 
 
@@ -392,6 +404,175 @@ def bench_fdcnn(args):
     print(json.dumps(out))
 
 
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        return 1
+
+
+def _fdnn_flops(U, L4, Dh, nh):
+    """Per time sample (all U UEs): forward network, and the backward kernel's work
+    (forward recompute, deltas through the hidden layers, dW outer products, bias sums)."""
+    F = 2 * U * (L4 + 1)
+    fwd = 2 * (F * Dh + (nh - 1) * Dh * Dh + Dh * 2 * U)
+    delta = 2 * (2 * U * Dh + (nh - 1) * Dh * Dh)
+    dw = 2 * (F * Dh + (nh - 1) * Dh * Dh + Dh * 2 * U)
+    bias = nh * Dh + 2 * U
+    return fwd, fwd + delta + dw + bias
+
+
+def bench_downlink(args):
+    """fdnn_8u: one step = FD-NN forward + reverse mode (fixed output gradient) over
+    n_sym OFDM symbols of U UEs.  link_8u32b: one step = ZF precoders of every channel
+    realisation (one per OFDM symbol), precoding and the link (IDFT, PA, DFT per antenna,
+    channel, noise, decisions)."""
+    import numpy as np
+    import torch
+    import dpd_synth as S
+    import paper_2205_05158_amd as D
+    from paper_2205_05158_amd import flops as FL
+
+    spec = DL_WORKLOADS[args.workload]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    N, n_d, U, n_sym = spec["n_fft"], spec["n_d"], spec["users"], spec["n_sym"]
+    state = {}
+    if spec["kind"] == "fdnn":
+        L4, Dh, nh = spec["memory"], spec["hidden"], spec["n_hidden"]
+        idx, s_np = S.downlink_symbols(n_sym, U, N, n_d, spec["qam"], 1)
+        s_np = (s_np * np.sqrt(N / n_d)).astype(np.float32)     # unit-power time samples
+        w_np = S.xavier_fdnn(U, L4, Dh, nh, 2)
+        g_np = (np.random.default_rng(3).standard_normal(s_np.shape) / np.sqrt(s_np.size)).astype(np.float32)
+        s, w, g = dev(s_np), dev(w_np), dev(g_np)
+        net = D.FdNn(N, U, L4, Dh, nh, max_sym=n_sym)
+
+        def step():
+            state["out"] = net.forward(s, w)
+            state["dw"] = net.backward(s, w, g)
+    else:
+        B, T, spc = spec["antennas"], spec["taps"], spec["sym_per_ch"]
+        n_ch = -(-n_sym // spc)
+        idx, s_np = S.downlink_symbols(n_sym, U, N, n_d, spec["qam"], 1)
+        h_np, he_np = S.mimo_channel(n_ch, T, U, B, spec["eta"], 2)
+        pa_np = S.antenna_pa_coefficients(B, *spec["pa"], 10, scale=spec["pa_scale"])
+        noise_np = S.awgn_fd(n_sym, U, N, spec["n0"], 3)
+        s, h, he, pa, noise = dev(s_np), dev(h_np), dev(he_np), dev(pa_np), dev(noise_np)
+        tx = torch.from_numpy(idx).cuda()
+        p_total = spec["rms"] ** 2 * B * N / n_d     # per-antenna time-domain rms
+        dl = D.Downlink(N, n_d, U, B, T, spec["qam"], pa=spec["pa"])
+
+        def step():
+            pt, alpha = dl.zf(he, p_total)
+            x = dl.precode(s, pt, alpha, sym_per_ch=spc)
+            state["err"], _ = dl.link(x, pa, 1.0, h, alpha, tx, noise=noise, sym_per_ch=spc)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    D.dpd_profile_report()
+    D.dpd_profile_enable(True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    D.dpd_profile_enable(False)
+    kern = D.dpd_profile_report()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    per_k = {k: v / c for k, (c, v) in kern.items()}
+    value = n_sym * U * n_d / (ms_per_step / 1e3) / 1e6
+    out = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+           "data": "synthetic", "value": value, "unit": "Msymbols/s",
+           "kernels_ms_per_step": {k: v / args.steps for k, (c, v) in kern.items()}}
+    if spec["kind"] == "fdnn":
+        fwd_f, bwd_f = _fdnn_flops(U, L4, Dh, nh)
+        samples = n_sym * N
+        # the backward kernel is bound by the vector ALU (its arithmetic intensity,
+        # ~40 FLOP/byte of time samples, is above the HBM ridge of ~20)
+        dom = "fdnn_bwd"
+        ach = bwd_f * samples / (per_k[dom] / 1e3) / 1e12
+        out["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK["valu_fp32_tflops"], "unit": "TFLOP/s",
+                           "frac": ach / PEAK["valu_fp32_tflops"], "traffic": profiled_traffic(args.workload, dom),
+                           "kernel": dom, "kernel_ms": per_k[dom], "flops_per_sample": bwd_f,
+                           "samples_per_launch": samples}
+        fft_bytes = 16 * n_sym * U * N          # one read and one write of every complex point
+        out["fft_roofline"] = {"bound": "hbm", "kernel": "fdnn_idft",
+                               "achieved": fft_bytes / (per_k["fdnn_idft"] / 1e3) / 1e9,
+                               "peak": PEAK["hbm_gbs"], "unit": "GB/s", "bytes_per_launch": fft_bytes}
+        out["fft_roofline"]["frac"] = out["fft_roofline"]["achieved"] / PEAK["hbm_gbs"]
+        out["metric"] = "Msymbols/s of FD-NN DPD forward+backward (UE data-subcarrier symbols); % roofline"
+        out["config"] = {"workload": args.workload, "n_sym": n_sym, "n_fft": N, "n_d": n_d, "users": U,
+                         "memory": L4, "hidden": Dh, "n_hidden": nh, "qam": spec["qam"],
+                         "step": "fdnn_forward + fdnn_backward", "parallelism": "single GPU"}
+        out["paper_flops_per_ue_symbol_eq14"] = FL.fd_nn_per_ue_symbol(N, n_d, 32, U, L4, Dh, nh)
+    else:
+        K, M, Lg = spec["pa"]
+        rows = n_sym * B
+        fl_row = N * FL.gmp_flops_fig3(K, M, Lg) + 2 * 5 * N * np.log2(N)
+        dom = max(("link_pa", "zf"), key=lambda k: per_k[k])
+        if dom == "link_pa":
+            ach = fl_row * rows / (per_k[dom] / 1e3) / 1e12
+            out["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK["valu_fp32_tflops"],
+                               "unit": "TFLOP/s", "frac": ach / PEAK["valu_fp32_tflops"],
+                               "traffic": profiled_traffic(args.workload, dom), "kernel": dom,
+                               "kernel_ms": per_k[dom], "flops_per_row": fl_row, "rows_per_launch": rows}
+        else:
+            zf_f = 8 * U * B * T + 8 * U * U * B + 16 * U ** 3 + 8 * B * U * U
+            ach = zf_f * N * n_ch / (per_k[dom] / 1e3) / 1e12
+            out["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK["mfma_fp64_tflops"],
+                               "unit": "TFLOP/s", "frac": ach / PEAK["mfma_fp64_tflops"],
+                               "traffic": profiled_traffic(args.workload, dom), "kernel": dom,
+                               "kernel_ms": per_k[dom], "flops_per_subcarrier": zf_f,
+                               "subcarriers_per_launch": N * n_ch}
+        errs = int(state["err"].sum())
+        out["metric"] = "Msymbols/s of the ZF-precoded downlink (UE data symbols through ZF, precoding, PA, channel, decisions); % roofline"
+        out["config"] = {"workload": args.workload, "n_sym": n_sym, "n_fft": N, "n_d": n_d, "users": U,
+                         "antennas": B, "taps": T, "qam": spec["qam"], "pa": list(spec["pa"]),
+                         "sym_per_ch": spc, "step": "zf_precoder + ofdm_precode + ofdm_link",
+                         "parallelism": "single GPU"}
+        out["ser"] = errs / (n_sym * U * n_d)
+    if not args.no_cpu_baseline:
+        import oracle.ofdm as OO
+        threads = _threads()
+        cx = lambda a: a[..., 0].astype(np.float64) + 1j * a[..., 1]
+        ns = spec["cpu_sym"]
+        t0 = time.perf_counter()
+        if spec["kind"] == "fdnn":
+            ref, cache = OO.fdnn_forward(cx(s_np[:ns]), w_np, U, L4, Dh, nh)
+            ref_dw = OO.fdnn_backward(cx(g_np[:ns]), cache, U, L4)
+        else:
+            pt_r, al_r = OO.zf_precoder(cx(he_np[:-(-ns // spc)]), N, n_d, p_total)
+            x_r = OO.precode(cx(s_np[:ns]), pt_r, al_r, n_d, False, spc)
+            r_r, _, e_r = OO.link(x_r, cx(h_np), al_r, pa_np, spec["pa"], 1.0, cx(noise_np[:ns]), idx[:ns],
+                                  spec["qam"], n_d, spc)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": ns * U * n_d / dt / 1e6, "unit": "Msymbols/s", "cores": int(threads),
+                               "kind": "oracle",
+                               "sample": f"first {ns} of {n_sym} OFDM symbols; FP64 NumPy; BLAS threads "
+                                         f"{threads}; {dt:.2f} s"}
+        if spec["kind"] == "fdnn":
+            snet = D.FdNn(N, U, L4, Dh, nh, max_sym=ns)
+            o2 = snet.forward(s[:ns].contiguous(), w).cpu().double().numpy()
+            d2 = snet.backward(s[:ns].contiguous(), w, g[:ns].contiguous()).cpu().double().numpy()
+            out["parity"] = {"sample_sym": ns,
+                             "out_rel_err": float(np.max(np.abs(cx(o2) - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))),
+                             "grad_rel_err": float(np.linalg.norm(d2 - ref_dw) / np.linalg.norm(ref_dw))}
+        else:
+            pt, alpha = dl.zf(he[:-(-ns // spc)].contiguous(), p_total)
+            x = dl.precode(s[:ns].contiguous(), pt, alpha, sym_per_ch=spc)
+            e2, r2 = dl.link(x, pa, 1.0, h, alpha, tx[:ns].contiguous(), noise=noise[:ns].contiguous(),
+                             sym_per_ch=spc, want_r=True)
+            r2 = cx(r2.cpu().double().numpy())
+            out["parity"] = {"sample_sym": ns, "errors_gpu": int(e2.sum()), "errors_oracle": int(e_r.sum()),
+                             "r_rel_err": float(np.max(np.abs(r2 - r_r)) / np.sqrt(np.mean(np.abs(r_r) ** 2)))}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -403,6 +584,12 @@ def main():
             print(json.dumps({"error": "this build runs on one GPU only", "n_gpus": args.gpus}))
             sys.exit(2)
         return bench_fdcnn(args)
+    if args.workload in DL_WORKLOADS:
+        world = int(os.environ.get("WORLD_SIZE", "1"))
+        if args.gpus != 1 or world != 1:
+            print(json.dumps({"error": "this build runs on one GPU only", "n_gpus": args.gpus}))
+            sys.exit(2)
+        return bench_downlink(args)
     if args.workload in ILA_WORKLOADS:
         world = int(os.environ.get("WORLD_SIZE", "1"))
         if args.gpus != 1 or world != 1:

@@ -320,14 +320,15 @@ typedef struct {
 } dpd_link_desc;
 
 dpd_status zf_workspace_size(const dpd_link_desc* desc, int32_t n_ch, size_t* bytes_host);
-/* ZF precoding (eq. (6)) from the estimated taps h_est: for every subcarrier k (guard
- * included) pt[c][k] = H_k^H (H_k H_k^H)^-1 (float[n_ch][N][B][U][2]), H_k = sum_t
- * H_t e^{-2 pi i k t / N}, computed in FP64 (H_k H_k^H must be nonsingular); alpha[c]
- * (float[n_ch]) = sqrt(p_total / mean over the data subcarriers of tr(pt^H pt)), so that
- * the precoder alpha pt meets the average transmit power p_total with unit-energy
- * symbols (one alpha per channel realisation). */
+/* ZF precoding (eq. (6)) from the estimated taps h_est: pt[c][k] = H_k^H (H_k H_k^H)^-1
+ * (float[n_ch][N][B][U][2]), H_k = sum_t H_t e^{-2 pi i k t / N}, computed in FP64
+ * (H_k H_k^H must be nonsingular), on the data subcarriers (all_bins = 0; the guard
+ * entries of pt are not written) or on every subcarrier (all_bins = 1, for guard-band
+ * precoding); alpha[c] (float[n_ch]) = sqrt(p_total / mean over the data subcarriers of
+ * tr(pt^H pt)), so that the precoder alpha pt meets the average transmit power p_total
+ * with unit-energy symbols (one alpha per channel realisation). */
 dpd_status zf_precoder(const dpd_link_desc* desc, int32_t n_ch, const float* h_est, float p_total,
-                       float* pt, float* alpha, void* workspace, size_t workspace_bytes,
+                       int32_t all_bins, float* pt, float* alpha, void* workspace, size_t workspace_bytes,
                        hipStream_t stream);
 /* x[i][b][k] = alpha[c] sum_u pt[c][k][b][u] s[i][u][k] (eq. (1)) on the data subcarriers
  * (all_bins = 0) or on every subcarrier (all_bins = 1: the guard-band precoding an FD-NN

@@ -96,7 +96,8 @@ _SIGS = {
     "fdnn_forward": (C.c_int, [C.POINTER(FdnnDesc), C.c_int64, _P, _P, _P, _P, C.c_size_t, _P]),
     "fdnn_backward": (C.c_int, [C.POINTER(FdnnDesc), C.c_int64, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "zf_workspace_size": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.POINTER(C.c_size_t)]),
-    "zf_precoder": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, _P, C.c_float, _P, _P, _P, C.c_size_t, _P]),
+    "zf_precoder": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, _P, C.c_float, C.c_int32, _P, _P, _P, C.c_size_t,
+                              _P]),
     "ofdm_precode": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P]),
     "link_workspace_size": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "ofdm_link": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, _P, _P, _P, C.c_float, C.c_float, _P, _P,
@@ -335,9 +336,9 @@ def zf_workspace_size(desc, n_ch) -> int:
     return n.value
 
 
-def zf_precoder(desc, n_ch, h_est, p_total, pt, alpha, workspace, stream=None):
-    _check(lib().zf_precoder(C.byref(desc), int(n_ch), _ptr(h_est), float(p_total), _ptr(pt), _ptr(alpha),
-                             _ptr(workspace), _nbytes(workspace), _stream(stream)), "zf_precoder")
+def zf_precoder(desc, n_ch, h_est, p_total, all_bins, pt, alpha, workspace, stream=None):
+    _check(lib().zf_precoder(C.byref(desc), int(n_ch), _ptr(h_est), float(p_total), int(bool(all_bins)), _ptr(pt),
+                             _ptr(alpha), _ptr(workspace), _nbytes(workspace), _stream(stream)), "zf_precoder")
 
 
 def ofdm_precode(desc, n_sym, sym_per_ch, pt, alpha, s, all_bins, x, stream=None):

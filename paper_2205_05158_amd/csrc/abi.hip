@@ -1069,19 +1069,19 @@ dpd_status zf_workspace_size(const dpd_link_desc* desc, int32_t n_ch, size_t* by
 }
 
 dpd_status zf_precoder(const dpd_link_desc* desc, int32_t n_ch, const float* h_est, float p_total,
-                       float* pt, float* alpha, void* workspace, size_t workspace_bytes,
+                       int32_t all_bins, float* pt, float* alpha, void* workspace, size_t workspace_bytes,
                        hipStream_t stream) {
   if (!desc || !h_est || !pt || !alpha || !workspace) return DPD_ERR_NULL;
   const dpd_status st = link_check(desc);
   if (st != DPD_OK) return st;
-  if (n_ch < 1 || !(p_total > 0.f) || n_ch > 65535) return DPD_ERR_SHAPE;
+  if (n_ch < 1 || !(p_total > 0.f) || n_ch > 65535 || (all_bins != 0 && all_bins != 1)) return DPD_ERR_SHAPE;
   if (!aligned(h_est, 8) || !aligned(pt, 8) || !aligned(alpha, 4) || !aligned(workspace, 256))
     return DPD_ERR_ALIGN;
   if (workspace_bytes < align_up(sizeof(double) * (size_t)n_ch * desc->n_fft)) return DPD_ERR_WORKSPACE;
   {
     DPD_PROF("zf");
-    launch_zf(h_est, desc->n_fft, desc->n_data, desc->users, desc->antennas, desc->taps, n_ch, p_total, pt,
-              at<double>(workspace, 0), alpha, stream);
+    launch_zf(h_est, desc->n_fft, desc->n_data, all_bins, desc->users, desc->antennas, desc->taps, n_ch, p_total,
+              pt, at<double>(workspace, 0), alpha, stream);
   }
   return launch_status();
 }

@@ -167,9 +167,10 @@ void launch_fdnn_fwd(const NnDims& d, int64_t n_sym, const float* td, const floa
 // g_td: time-sample gradients [n_sym][U][N]; part: fdnn_bwd_groups * part_floats floats.
 void launch_fdnn_bwd(const NnDims& d, int64_t n_sym, const float* td, const float* g_td, const float* w,
                      float* part, float* dw, int cus, hipStream_t s);
-// ZF: pt [n_ch][N][B][U], trace double [n_ch][N], alpha [n_ch].  U <= 8, B <= 256, T <= 64.
-void launch_zf(const float* h_est, int N, int n_d, int U, int B, int T, int n_ch, float p_total, float* pt,
-               double* trace, float* alpha, hipStream_t s);
+// ZF: pt [n_ch][N][B][U] (data subcarriers only unless all_bins), trace double [n_ch][N],
+// alpha [n_ch].  U <= 8, B <= 256, T <= 64.
+void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, int T, int n_ch, float p_total,
+               float* pt, double* trace, float* alpha, hipStream_t s);
 void launch_precode(const float* pt, const float* alpha, const float* sym, int N, int n_d, int U, int B,
                     int n_sym, int spc, int all_bins, float* x, hipStream_t s);
 // true channel on the data subcarriers: hd [n_ch][n_d][U][B]

@@ -124,6 +124,104 @@ __device__ void fft_lds(float2* buf, const float2* tw, int n, int log2n) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 4096-point path (the paper's OFDM symbol): three radix-16 Stockham passes, one
+// butterfly per thread per pass (256 threads) with its sixteen values in registers;
+// passes exchange through a padded LDS row (one float2 gap after every 16, so the
+// stride-16 writes of the first pass spread over all 64 banks).  Global memory is read
+// straight into the first pass and written straight from the last.  The inverse is the
+// forward transform of the conjugate, conjugated.
+// ---------------------------------------------------------------------------
+constexpr int kF16Row = kFftMax + kFftMax / 16;
+__device__ __forceinline__ int p16(int i) { return i + (i >> 4); }
+
+__device__ __forceinline__ void dft4f(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), d = csub(a1, a3);
+  const float2 t3 = make_float2(d.y, -d.x);     // (a1 - a3) (-i)
+  a0 = cadd(t0, t2);
+  a1 = cadd(t1, t3);
+  a2 = csub(t0, t2);
+  a3 = csub(t1, t3);
+}
+
+// Forward 16-point DFT in place as 4 x 4: X[k] ends in v[4 (k mod 4) + k / 4] (X16).
+__device__ __forceinline__ void dft16f(float2 (&v)[16]) {
+  constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508978f, rh = 0.70710678118654752f;
+  // exp(-2 pi i m / 16), m = 0..9 (the products q p of the middle twiddles)
+  const float2 w[10] = {{1.f, 0.f}, {c1, -s1}, {rh, -rh}, {s1, -c1}, {0.f, -1.f},
+                        {-s1, -c1}, {-rh, -rh}, {-c1, -s1}, {-1.f, 0.f}, {-c1, s1}};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dft4f(v[q], v[q + 4], v[q + 8], v[q + 12]);
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+#pragma unroll
+    for (int p = 1; p < 4; ++p) v[q + 4 * p] = cmul(v[q + 4 * p], w[q * p]);
+#pragma unroll
+  for (int p = 0; p < 4; ++p) dft4f(v[4 * p], v[4 * p + 1], v[4 * p + 2], v[4 * p + 3]);
+}
+#define X16(v, k) (v)[4 * ((k) & 3) + ((k) >> 2)]
+
+// First pass (sub-transform length 1): v[r] = x[t + 256 r] on entry.
+__device__ __forceinline__ void f16_pass1(float2* buf, float2 (&v)[16]) {
+  const int t = threadIdx.x;
+  dft16f(v);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) buf[p16(t * 16 + r)] = X16(v, r);
+}
+
+// Second pass (length 16), in place; the caller's barrier precedes it and follows it.
+__device__ __forceinline__ void f16_pass2(float2* buf, const float2* tw) {
+  const int t = threadIdx.x, k = t & 15;
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = buf[p16(t + 256 * r)];
+  __syncthreads();
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<false>(tw, 16 * r * k, kFftMax));
+  dft16f(v);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) buf[p16((t - k) * 16 + k + 16 * r)] = X16(v, r);
+}
+
+// Last pass (length 256): X16(v, r) is transform output t + 256 r on return.
+__device__ __forceinline__ void f16_pass3(const float2* buf, const float2* tw, float2 (&v)[16]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = buf[p16(t + 256 * r)];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<false>(tw, r * t, kFftMax));
+  dft16f(v);
+}
+
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+// 4096-point rows (in may equal out: each thread reads and writes the same indices).
+template <bool INV>
+__global__ __launch_bounds__(kFftThreads) void k_fft4096(const float2* in, float2* out, float scale, int64_t rows) {
+  __shared__ float2 buf[kF16Row];
+  __shared__ float2 tw[kFftMax / 2];
+  fft_twiddles(tw, kFftMax);
+  const int t = threadIdx.x;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const float2* src = in + row * kFftMax;
+    float2* dst = out + row * kFftMax;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = INV ? conjf2(src[t + 256 * r]) : src[t + 256 * r];
+    __syncthreads();                       // the previous row's last-pass reads are done
+    f16_pass1(buf, v);
+    __syncthreads();
+    f16_pass2(buf, tw);
+    __syncthreads();
+    f16_pass3(buf, tw, v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float2 a = X16(v, r);
+      dst[t + 256 * r] = make_float2(a.x * scale, (INV ? -a.y : a.y) * scale);
+    }
+  }
+}
+
 // Batched unitary transform of `rows` contiguous rows of n points (in may equal out).
 // Persistent: workgroup g takes rows g, g + G, ...; the twiddle table is built once.
 template <bool INV>
@@ -514,6 +612,11 @@ __device__ __forceinline__ double2 zmulc(double2 a, double2 b) {   // conj(a) b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// Subcarrier of data symbol d: 1 + d for d < n_d / 2, else N - n_d + d.
+__device__ __forceinline__ int data_bin(int d, int N, int n_d) {
+  return d < n_d / 2 ? 1 + d : N - n_d + d;
+}
+
 // e^{-2 pi i (k t mod N) / N} in double.
 __device__ __forceinline__ double2 unit_phase(int64_t k, int t, int N) {
   const int64_t e = (k * t) % N;
@@ -523,14 +626,19 @@ __device__ __forceinline__ double2 unit_phase(int64_t k, int t, int N) {
 }
 
 // Pt_k = H_k^H (H_k H_k^H)^-1 with H_k = sum_t H_t e^{-2 pi i k t / N}; tr(Pt^H Pt) -> trace.
-__global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, int U, int B, int T,
-                                           float2* __restrict__ pt, double* __restrict__ trace) {
-  __shared__ double2 ph[kZfMaxT];
-  __shared__ double2 hk[kZfMaxU * kZfMaxB];
+// Subcarrier k = blockIdx.x (all_bins) or the data subcarrier blockIdx.x.  Dynamic LDS:
+// the T phases and H_k [U][B] (sized to the problem, so small antenna counts keep many
+// waves resident).
+__global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, int n_d, int all_bins, int U,
+                                           int B, int T, float2* __restrict__ pt, double* __restrict__ trace) {
+  extern __shared__ double2 zf_dyn[];
+  double2* ph = zf_dyn;
+  double2* hk = zf_dyn + T;
   __shared__ double2 A[kZfMaxU][kZfMaxU], I[kZfMaxU][kZfMaxU];
   __shared__ double red[64];
   const int lane = threadIdx.x;
-  const int k = blockIdx.x, c = blockIdx.y;
+  const int k = all_bins ? (int)blockIdx.x : data_bin((int)blockIdx.x, N, n_d);
+  const int c = blockIdx.y;
   for (int t = lane; t < T; t += 64) ph[t] = unit_phase(k, t, N);
   __syncthreads();
   const float2* hc = h + (int64_t)c * T * U * B;
@@ -602,10 +710,6 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
     __syncthreads();
   }
   if (lane == 0) trace[(int64_t)c * N + k] = red[0];
-}
-
-__device__ __forceinline__ int data_bin(int d, int N, int n_d) {
-  return d < n_d / 2 ? 1 + d : N - n_d + d;
 }
 
 // alpha[c] = sqrt(P_T / mean over data subcarriers of trace[c][k]) (fixed-order tree).
@@ -715,38 +819,59 @@ __device__ void gmp_cyclic_lds(const float2* buf, const float* r, int N, const f
 }
 
 // One workgroup per (symbol, antenna) row, persistent: x (precoded subcarriers) -> IDFT
-// -> optional DPD -> PA -> DFT -> y_fd.  Both transforms unitary.
+// -> optional DPD -> PA -> DFT -> y_fd.  Both transforms unitary.  For 4096-point symbols
+// the radix-16 passes run in registers; the PA's output samples (t + 256 m of thread t)
+// are already the first pass's inputs.
 __global__ __launch_bounds__(kFftThreads) void k_link_pa(const float2* __restrict__ x, int N, int log2n,
                                                          float scale, int B, int64_t rows,
                                                          const float2* __restrict__ dpd, int Kd, int Md, int Ld,
                                                          int Jd, const float2* __restrict__ pa, int Kp, int Mp,
                                                          int Lp, int Jp, float2* __restrict__ y_fd) {
-  __shared__ float2 buf[kFftMax];
+  __shared__ float2 buf[kF16Row];
   __shared__ float2 tw[kFftMax / 2];
   __shared__ float r[kFftMax];
   fft_twiddles(tw, N);
+  const int t = threadIdx.x;
+  const bool f16 = N == kFftMax;
   for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
     const int b = (int)(row % B);
-    __syncthreads();
-    for (int i = threadIdx.x; i < N; i += kFftThreads) buf[i] = x[row * N + i];
-    __syncthreads();
-    fft_lds<true>(buf, tw, N, log2n);
-    for (int i = threadIdx.x; i < N; i += kFftThreads) {
-      const float2 v = make_float2(buf[i].x * scale, buf[i].y * scale);
-      buf[i] = v;
-      r[i] = sqrtf(v.x * v.x + v.y * v.y);
+    if (f16) {
+      float2 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = conjf2(x[row * N + t + 256 * q]);
+      __syncthreads();                     // the previous row is done with buf
+      f16_pass1(buf, v);
+      __syncthreads();
+      f16_pass2(buf, tw);
+      __syncthreads();
+      f16_pass3(buf, tw, v);
+      __syncthreads();                     // every last-pass read precedes the sample writes
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float2 a = X16(v, q);
+        const float2 u = make_float2(a.x * scale, -a.y * scale);
+        buf[t + 256 * q] = u;
+        r[t + 256 * q] = sqrtf(u.x * u.x + u.y * u.y);
+      }
+    } else {
+      __syncthreads();
+      for (int i = t; i < N; i += kFftThreads) buf[i] = x[row * N + i];
+      __syncthreads();
+      fft_lds<true>(buf, tw, N, log2n);
+      for (int i = t; i < N; i += kFftThreads) {
+        const float2 v = make_float2(buf[i].x * scale, buf[i].y * scale);
+        buf[i] = v;
+        r[i] = sqrtf(v.x * v.x + v.y * v.y);
+      }
     }
     __syncthreads();
     float2 y[kFftMax / kFftThreads];
-    for (int pass = 0; pass < 2; ++pass) {
-      const bool is_dpd = pass == 0;
-      if (is_dpd && !dpd) continue;
-      if (is_dpd) gmp_cyclic_lds(buf, r, N, dpd + (int64_t)b * Jd, Kd, Md, Ld, y);
-      else gmp_cyclic_lds(buf, r, N, pa + (int64_t)b * Jp, Kp, Mp, Lp, y);
+    if (dpd) {
+      gmp_cyclic_lds(buf, r, N, dpd + (int64_t)b * Jd, Kd, Md, Ld, y);
       __syncthreads();
 #pragma unroll
       for (int m = 0; m < kFftMax / kFftThreads; ++m) {
-        const int n = threadIdx.x + m * kFftThreads;
+        const int n = t + m * kFftThreads;
         if (n < N) {
           buf[n] = y[m];
           r[n] = sqrtf(y[m].x * y[m].x + y[m].y * y[m].y);
@@ -754,9 +879,30 @@ __global__ __launch_bounds__(kFftThreads) void k_link_pa(const float2* __restric
       }
       __syncthreads();
     }
-    fft_lds<false>(buf, tw, N, log2n);
-    for (int i = threadIdx.x; i < N; i += kFftThreads)
-      y_fd[row * N + i] = make_float2(buf[i].x * scale, buf[i].y * scale);
+    gmp_cyclic_lds(buf, r, N, pa + (int64_t)b * Jp, Kp, Mp, Lp, y);
+    __syncthreads();                       // the GMP's neighbour reads precede the FFT writes
+    if (f16) {
+      f16_pass1(buf, y);                   // y[m] is sample t + 256 m
+      __syncthreads();
+      f16_pass2(buf, tw);
+      __syncthreads();
+      f16_pass3(buf, tw, y);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float2 a = X16(y, q);
+        y_fd[row * N + t + 256 * q] = make_float2(a.x * scale, a.y * scale);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < kFftMax / kFftThreads; ++m) {
+        const int n = t + m * kFftThreads;
+        if (n < N) buf[n] = y[m];
+      }
+      __syncthreads();
+      fft_lds<false>(buf, tw, N, log2n);
+      for (int i = t; i < N; i += kFftThreads)
+        y_fd[row * N + i] = make_float2(buf[i].x * scale, buf[i].y * scale);
+    }
   }
 }
 
@@ -907,6 +1053,11 @@ void launch_fft(const float* in, float* out, int n, int64_t rows, bool inverse, 
   const float scale = (float)(1.0 / sqrt((double)n));
   const float2* i2 = reinterpret_cast<const float2*>(in);
   float2* o2 = reinterpret_cast<float2*>(out);
+  if (n == kFftMax) {
+    if (inverse) k_fft4096<true><<<G, kFftThreads, 0, s>>>(i2, o2, scale, rows);
+    else k_fft4096<false><<<G, kFftThreads, 0, s>>>(i2, o2, scale, rows);
+    return;
+  }
   if (inverse) k_fft<true><<<G, kFftThreads, 0, s>>>(i2, o2, n, ilog2(n), scale, rows);
   else k_fft<false><<<G, kFftThreads, 0, s>>>(i2, o2, n, ilog2(n), scale, rows);
 }
@@ -927,10 +1078,11 @@ void launch_fdnn_bwd(const NnDims& d, int64_t n_sym, const float* td, const floa
   else nn_dispatch<2>(d, n_sym, t2, g2, w, nullptr, part, dw, cus, s);
 }
 
-void launch_zf(const float* h_est, int N, int n_d, int U, int B, int T, int n_ch, float p_total, float* pt,
-               double* trace, float* alpha, hipStream_t s) {
-  k_zf<<<dim3(N, n_ch), 64, 0, s>>>(reinterpret_cast<const float2*>(h_est), N, U, B, T,
-                                    reinterpret_cast<float2*>(pt), trace);
+void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, int T, int n_ch, float p_total,
+               float* pt, double* trace, float* alpha, hipStream_t s) {
+  const size_t lds = sizeof(double2) * (size_t)(T + U * B);
+  k_zf<<<dim3(all_bins ? N : n_d, n_ch), 64, lds, s>>>(reinterpret_cast<const float2*>(h_est), N, n_d, all_bins,
+                                                       U, B, T, reinterpret_cast<float2*>(pt), trace);
   k_zf_alpha<<<n_ch, 256, 0, s>>>(trace, N, n_d, p_total, alpha);
 }
 

@@ -75,14 +75,17 @@ class Downlink:
         self.n_fft, self.n_data, self.users, self.antennas, self.taps = n_fft, n_data, users, antennas, taps
         self.device = torch.device(device)
 
-    def zf(self, h_est, p_total):
-        """-> (pt [n_ch][N][B][U][2], alpha [n_ch]) from the estimated taps [n_ch][T][U][B][2]."""
+    def zf(self, h_est, p_total, all_bins=False):
+        """-> (pt [n_ch][N][B][U][2], alpha [n_ch]) from the estimated taps [n_ch][T][U][B][2];
+        pt is written on the data subcarriers only unless all_bins (guard entries are zero
+        then, as allocated here)."""
         n_ch = h_est.shape[0]
         _check_c(h_est, (n_ch, self.taps, self.users, self.antennas, 2), "h_est")
-        pt = torch.empty(n_ch, self.n_fft, self.antennas, self.users, 2, dtype=torch.float32, device=self.device)
+        alloc = torch.empty if all_bins else torch.zeros
+        pt = alloc(n_ch, self.n_fft, self.antennas, self.users, 2, dtype=torch.float32, device=self.device)
         alpha = torch.empty(n_ch, dtype=torch.float32, device=self.device)
         ws = torch.empty(max(L.zf_workspace_size(self.desc, n_ch), 256), dtype=torch.uint8, device=self.device)
-        L.zf_precoder(self.desc, n_ch, h_est, p_total, pt, alpha, ws)
+        L.zf_precoder(self.desc, n_ch, h_est, p_total, all_bins, pt, alpha, ws)
         return pt, alpha
 
     def _check_channels(self, pt, alpha, n_sym, sym_per_ch, h=None):

@@ -252,11 +252,12 @@ def test_downlink_arguments_rejected(dpdlib):
              (L.link_desc(16, 8, 2, 4, 2, 16, L.GmpDesc(3, 15, 1)), L.DPD_ERR_SHAPE),      # M + L >= N
              (L.link_desc(4096, 384, 8, 32, 10, 256, pa, L.GmpDesc(3, 16, 0)), L.DPD_ERR_SHAPE)]
     for desc, code in cases:
-        assert lib.zf_precoder(C.byref(desc), 1, FAKE, C.c_float(1.0), OUT, FAKE, FAKE, 1 << 40, None) == code
+        assert lib.zf_precoder(C.byref(desc), 1, FAKE, C.c_float(1.0), 0, OUT, FAKE, FAKE, 1 << 40, None) == code
         assert lib.ofdm_link(C.byref(desc), 2, 1, FAKE, FAKE, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
                              None, FAKE, None, FAKE, FAKE, 1 << 40, None) == code
-    assert lib.zf_precoder(C.byref(ok), 1, FAKE, C.c_float(0.0), OUT, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
-    assert lib.zf_precoder(C.byref(ok), 2, FAKE, C.c_float(1.0), OUT, FAKE, FAKE, 16, None) == L.DPD_ERR_WORKSPACE
+    assert lib.zf_precoder(C.byref(ok), 1, FAKE, C.c_float(0.0), 0, OUT, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert lib.zf_precoder(C.byref(ok), 2, FAKE, C.c_float(1.0), 0, OUT, FAKE, FAKE, 16, None) == L.DPD_ERR_WORKSPACE
+    assert lib.zf_precoder(C.byref(ok), 1, FAKE, C.c_float(1.0), 2, OUT, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
     assert lib.ofdm_precode(C.byref(ok), 4, 0, FAKE, FAKE, FAKE, 0, OUT, None) == L.DPD_ERR_SHAPE
     assert lib.ofdm_precode(C.byref(ok), 4, 1, FAKE, FAKE, FAKE, 2, OUT, None) == L.DPD_ERR_SHAPE
     # a DPD in the descriptor needs its coefficients; a zero gain cannot be equalised

@@ -198,12 +198,17 @@ def test_zf_precode_link_match_oracle(case):
                      torch.from_numpy(inp["idx"]).cuda(), noise=H.to_dev(inp["noise"]),
                      dpd_coef=H.to_dev(inp["dpd"]) if dpd else None, sym_per_ch=spc, want_r=True)
     torch.cuda.synchronize()
+    db = O.data_bins(N, n_d)
     g_pt = _c(pt.cpu().numpy())
-    assert np.max(np.abs(g_pt - ref_pt)) <= 1e-6 * np.max(np.abs(ref_pt))
+    assert np.max(np.abs(g_pt[:, db] - ref_pt[:, db])) <= 1e-6 * np.max(np.abs(ref_pt))
     np.testing.assert_allclose(alpha.cpu().numpy(), ref_alpha, rtol=1e-6)
-    # the precoder inverts the estimated channel on every subcarrier
+    # with all_bins the guard subcarriers too; the precoder inverts the estimated channel
+    pt_all, alpha_all = dl.zf(H.to_dev(inp["he"]), inp["p_total"], all_bins=True)
+    g_all = _c(pt_all.cpu().numpy())
+    assert np.max(np.abs(g_all - ref_pt)) <= 1e-6 * np.max(np.abs(ref_pt))
+    assert torch.equal(alpha_all, alpha)
     Hk = O.channel_fd(_c(inp["he"]), N)
-    assert np.max(np.abs(Hk @ g_pt - np.eye(U))) < 1e-4
+    assert np.max(np.abs(Hk @ g_all - np.eye(U))) < 1e-4
     assert _rms_rel(_c(x.cpu().numpy()), ref_x) < 1e-5
     g_r = _c(r.cpu().numpy())
     assert _rms_rel(g_r, ref_r) < 1e-5
