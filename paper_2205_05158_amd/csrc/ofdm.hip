@@ -731,7 +731,7 @@ __global__ __launch_bounds__(256) void k_zf_alpha(const double* __restrict__ tra
 // x[i][b][k] = alpha_c sum_u Pt[c][k][b][u] s[i][u][k] on the precoded subcarriers, else 0.
 __global__ __launch_bounds__(256) void k_precode(const float2* __restrict__ pt, const float* __restrict__ alpha,
                                                  const float2* __restrict__ s, int N, int n_d, int U, int B,
-                                                 int spc, int all_bins, float2* __restrict__ x) {
+                                                 int spc, int all_bins, int vec, float2* __restrict__ x) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   const int i = blockIdx.y;
   if (k >= N) return;
@@ -749,6 +749,23 @@ __global__ __launch_bounds__(256) void k_precode(const float2* __restrict__ pt, 
     sv[u] = u < U ? s[((int64_t)i * U + u) * N + k] : make_float2(0.f, 0.f);
   const float a = alpha[c];
   const float2* pk = pt + ((int64_t)c * N + k) * B * U;
+  if (vec) {
+    // even U and a 16-byte aligned pt: each row of Pt_k is U/2 aligned 16-byte pairs
+    const float4* pk4 = reinterpret_cast<const float4*>(pk);
+    for (int b = 0; b < B; ++b) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
+        if (2 * u2 < U) {
+          const float4 q = pk4[b * (U / 2) + u2];
+          acc = cadd(acc, cmul(make_float2(q.x, q.y), sv[2 * u2]));
+          acc = cadd(acc, cmul(make_float2(q.z, q.w), sv[2 * u2 + 1]));
+        }
+      }
+      xi[(int64_t)b * N] = make_float2(a * acc.x, a * acc.y);
+    }
+    return;
+  }
   for (int b = 0; b < B; ++b) {
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
@@ -761,25 +778,26 @@ __global__ __launch_bounds__(256) void k_precode(const float2* __restrict__ pt, 
 // ---------------------------------------------------------------------------
 // Link
 // ---------------------------------------------------------------------------
-// True channel on the data subcarriers: hd[c][d][u][b] = sum_t H_t[u][b] e^{-2 pi i k_d t / N}.
+// True channel on the data subcarriers: hd[c][d][u][b] = sum_t H_t[u][b] e^{-2 pi i k_d t / N};
+// one workgroup per (data subcarrier, realisation), the T phases shared through LDS.
 __global__ __launch_bounds__(256) void k_chan_data(const float2* __restrict__ h, int N, int n_d, int U, int B,
-                                                   int T, int64_t total, float2* __restrict__ hd) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total) return;
-  const int ub = (int)(e % ((int64_t)U * B));
-  const int64_t cd = e / ((int64_t)U * B);
-  const int d = (int)(cd % n_d);
-  const int c = (int)(cd / n_d);
+                                                   int T, float2* __restrict__ hd) {
+  __shared__ double2 ph[kZfMaxT];
+  const int d = blockIdx.x, c = blockIdx.y;
   const int k = data_bin(d, N, n_d);
-  const float2* hc = h + (int64_t)c * T * U * B + ub;
-  double re = 0.0, im = 0.0;
-  for (int t = 0; t < T; ++t) {
-    const double2 p = unit_phase(k, t, N);
-    const float2 v = hc[(int64_t)t * U * B];
-    re += (double)v.x * p.x - (double)v.y * p.y;
-    im += (double)v.x * p.y + (double)v.y * p.x;
+  for (int t = threadIdx.x; t < T; t += 256) ph[t] = unit_phase(k, t, N);
+  __syncthreads();
+  const float2* hc = h + (int64_t)c * T * U * B;
+  float2* dst = hd + ((int64_t)c * n_d + d) * U * B;
+  for (int e = threadIdx.x; e < U * B; e += 256) {
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < T; ++t) {
+      const float2 v = hc[(int64_t)t * U * B + e];
+      re += (double)v.x * ph[t].x - (double)v.y * ph[t].y;
+      im += (double)v.x * ph[t].y + (double)v.y * ph[t].x;
+    }
+    dst[e] = make_float2((float)re, (float)im);
   }
-  hd[e] = make_float2((float)re, (float)im);
 }
 
 // GMP of eq. (9) with cyclic delays on the LDS symbol buf (magnitudes in r), results to
@@ -1088,15 +1106,15 @@ void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, i
 
 void launch_precode(const float* pt, const float* alpha, const float* sym, int N, int n_d, int U, int B,
                     int n_sym, int spc, int all_bins, float* x, hipStream_t s) {
+  const int vec = (U % 2 == 0) && ((uintptr_t)pt % 16 == 0);
   k_precode<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt), alpha,
                                                          reinterpret_cast<const float2*>(sym), N, n_d, U, B,
-                                                         spc, all_bins, reinterpret_cast<float2*>(x));
+                                                         spc, all_bins, vec, reinterpret_cast<float2*>(x));
 }
 
 void launch_chan_data(const float* h, int N, int n_d, int U, int B, int T, int n_ch, float* hd, hipStream_t s) {
-  const int64_t total = (int64_t)n_ch * n_d * U * B;
-  k_chan_data<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(reinterpret_cast<const float2*>(h), N, n_d, U, B,
-                                                              T, total, reinterpret_cast<float2*>(hd));
+  k_chan_data<<<dim3(n_d, n_ch), 256, 0, s>>>(reinterpret_cast<const float2*>(h), N, n_d, U, B, T,
+                                               reinterpret_cast<float2*>(hd));
 }
 
 void launch_link_pa(const float* x, int N, int B, int64_t rows, const float* dpd, const dpd_gmp_desc* dd,
