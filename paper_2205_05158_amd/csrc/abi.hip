@@ -918,8 +918,6 @@ const char* dpd_version(void) { return "dpdmi 0.1 gfx950"; }
 // ------------------------------------------------------------------ OFDM downlink
 namespace {
 
-constexpr int kNnMaxGroups = 512;    // backward partials of the FD-NN
-
 bool fdnn_check(const dpd_fdnn_desc* d, NnDims* out) {
   if (!d) return false;
   const NnDims n = nn_dims(d->n_fft, d->users, d->memory, d->hidden, d->n_hidden);
@@ -938,7 +936,7 @@ NnWs fdnn_ws_layout(const NnDims& d, int64_t n_sym) {
   const size_t row = sizeof(float2) * (size_t)n_sym * d.users * d.n_fft;
   w.td = take(row);
   w.o = take(row);
-  w.part = take(sizeof(float) * (size_t)kNnMaxGroups * d.part_floats);
+  w.part = take(sizeof(float) * ((size_t)kFdnnMaxGroups * d.part_floats + d.mid_floats));
   w.total = pos;
   return w;
 }
@@ -1054,8 +1052,9 @@ dpd_status fdnn_backward(const dpd_fdnn_desc* desc, int64_t n_sym, const float* 
   { DPD_PROF("fdnn_idft"); launch_fft(s, td, d.n_fft, rows, true, cus, stream); }
   // the adjoint of the unitary DFT is the unitary IDFT
   { DPD_PROF("fdnn_idft"); launch_fft(g_out, gtd, d.n_fft, rows, true, cus, stream); }
-  { DPD_PROF("fdnn_bwd"); launch_fdnn_bwd(d, n_sym, td, gtd, w, at<float>(workspace, L.part), dw,
-                                          std::min(cus, kNnMaxGroups / 2), stream); }
+  float* part = at<float>(workspace, L.part);
+  { DPD_PROF("fdnn_bwd"); launch_fdnn_bwd(d, n_sym, td, gtd, w, part, cus, stream); }
+  { DPD_PROF("fdnn_reduce"); launch_fdnn_reduce(d, n_sym, part, dw, cus, stream); }
   return launch_status();
 }
 

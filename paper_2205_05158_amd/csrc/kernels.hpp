@@ -157,16 +157,20 @@ struct NnDims {
   int n_fft, users, memory, hidden, n_hidden;
   int params;        // packed parameter count
   int part_floats;   // floats of one workgroup's padded dW partial (widest layout)
+  int mid_floats;    // floats of the reduction's split sums
 };
+constexpr int kFdnnMaxGroups = 2048;   // backward workgroups (partials) at most
 NnDims nn_dims(int n_fft, int users, int memory, int hidden, int n_hidden);
 bool nn_supported(const NnDims& d);
-int fdnn_bwd_groups(int cus);   // upper bound of the backward grid (partials)
+int fdnn_bwd_groups(int cus);   // backward grid for `cus` CUs (<= kFdnnMaxGroups partials)
 // td, o_td: [n_sym][U][N] complex time samples.
 void launch_fdnn_fwd(const NnDims& d, int64_t n_sym, const float* td, const float* w, float* o_td, int cus,
                      hipStream_t s);
-// g_td: time-sample gradients [n_sym][U][N]; part: fdnn_bwd_groups * part_floats floats.
+// g_td: time-sample gradients [n_sym][U][N]; part: kFdnnMaxGroups * part_floats floats
+// (one partial per backward workgroup) followed by mid_floats.  The reduction writes dw.
 void launch_fdnn_bwd(const NnDims& d, int64_t n_sym, const float* td, const float* g_td, const float* w,
-                     float* part, float* dw, int cus, hipStream_t s);
+                     float* part, int cus, hipStream_t s);
+void launch_fdnn_reduce(const NnDims& d, int64_t n_sym, float* part, float* dw, int cus, hipStream_t s);
 // ZF: pt [n_ch][N][B][U] (data subcarriers only unless all_bins), trace double [n_ch][N],
 // alpha [n_ch].  U <= 8, B <= 256, T <= 64.
 void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, int T, int n_ch, float p_total,

@@ -586,18 +586,32 @@ __global__ __launch_bounds__(kNnBwdT) void k_fdnn_bwd(const float2* __restrict__
   if (tid >= 64 && tid < 64 + kNnOut) out[Ly::bo + tid - 64] = ab;
 }
 
-// dw[p] = sum over workgroup partials g = 0..G-1 (this order) of part[g][padded(p)].
+// Fixed-order sum of the workgroup partials in two stages: mid[sp][p] = sum over the
+// partials g of split sp (in order) of part[g][padded(p)]; dw[p] = sum over the splits in
+// order.
+constexpr int kNnSplits = 32;
 template <int FM, int DM, int NH>
-__global__ __launch_bounds__(256) void k_fdnn_reduce(const float* __restrict__ part, int G, int F, int D,
-                                                     int U, int P, float* __restrict__ dw) {
+__global__ __launch_bounds__(256) void k_fdnn_reduce1(const float* __restrict__ part, int G, int F, int D,
+                                                      int U, int P, float* __restrict__ mid) {
   using Ly = NnLayout<FM, DM, NH>;
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= P) return;
+  const int sp = blockIdx.y;
+  const int g0 = (int)((int64_t)sp * G / kNnSplits), g1 = (int)((int64_t)(sp + 1) * G / kNnSplits);
   const int q = nn_padded_index<FM, DM, NH>(p, F, D, U);
   float acc = 0.f;
-  for (int g = 0; g < G; ++g) acc += part[(int64_t)g * Ly::total + q];
+  for (int g = g0; g < g1; ++g) acc += part[(int64_t)g * Ly::total + q];
+  mid[(int64_t)sp * P + p] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_fdnn_reduce2(const float* __restrict__ mid, int P, float* __restrict__ dw) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= P) return;
+  float acc = 0.f;
+  for (int sp = 0; sp < kNnSplits; ++sp) acc += mid[(int64_t)sp * P + p];
   dw[p] = acc;
 }
+
 // ---------------------------------------------------------------------------
 // ZF precoder: one single-wave workgroup per (channel, subcarrier); FP64 throughout.
 // ---------------------------------------------------------------------------
@@ -1006,38 +1020,53 @@ int ilog2(int n) {
   return l;
 }
 
+// mode 0: forward network; 1: backward kernel (partials); 2: reduction of the partials.
 template <int FM, int DM, int NH>
-void nn_launch(const NnDims& d, int64_t n_sym, const float2* td, const float2* g_td, const float* w,
+void nn_launch(int mode, const NnDims& d, int64_t n_sym, const float2* td, const float2* g_td, const float* w,
                float2* o_td, float* part, float* dw, int cus, hipStream_t s) {
   const int F = 2 * d.users * (d.memory + 1);
-  if (!g_td) {
+  if (mode == 0) {
     const int tps = (d.n_fft + kNnFwdT - 1) / kNnFwdT;
     const int n_tiles = (int)(n_sym * tps);
     const int G = std::min(n_tiles, 4 * cus);
     k_fdnn_fwd<FM, DM, NH><<<G, kNnFwdT, 0, s>>>(td, w, o_td, d.n_fft, d.users, d.memory, d.hidden,
                                                   d.params, tps, n_tiles);
-  } else {
-    const int tps = (d.n_fft + kNnBwdT - 1) / kNnBwdT;
-    const int n_tiles = (int)(n_sym * tps);
-    const int G = std::min(n_tiles, fdnn_bwd_groups(cus));
+    return;
+  }
+  const int tps = (d.n_fft + kNnBwdT - 1) / kNnBwdT;
+  const int n_tiles = (int)(n_sym * tps);
+  const int G = std::min(n_tiles, fdnn_bwd_groups(cus));
+  if (mode == 1) {
     k_fdnn_bwd<FM, DM, NH><<<G, kNnBwdT, 0, s>>>(td, g_td, w, part, d.n_fft, d.users, d.memory, d.hidden,
                                                   d.params, tps, n_tiles);
-    k_fdnn_reduce<FM, DM, NH><<<(d.params + 255) / 256, 256, 0, s>>>(part, G, F, d.hidden, d.users,
-                                                                      d.params, dw);
+    return;
   }
+  float* mid = part + (int64_t)kFdnnMaxGroups * d.part_floats;
+  const int pb = (d.params + 255) / 256;
+  k_fdnn_reduce1<FM, DM, NH><<<dim3(pb, kNnSplits), 256, 0, s>>>(part, G, F, d.hidden, d.users, d.params, mid);
+  k_fdnn_reduce2<<<pb, 256, 0, s>>>(mid, d.params, dw);
 }
 
 template <int NH>
-void nn_dispatch(const NnDims& d, int64_t n_sym, const float2* td, const float2* g_td, const float* w,
+void nn_dispatch(int mode, const NnDims& d, int64_t n_sym, const float2* td, const float2* g_td, const float* w,
                  float2* o_td, float* part, float* dw, int cus, hipStream_t s) {
   const int F = 2 * d.users * (d.memory + 1);
   if (F <= 32) {
-    if (d.hidden <= 16) nn_launch<32, 16, NH>(d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
-    else nn_launch<32, 32, NH>(d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
+    if (d.hidden <= 16) nn_launch<32, 16, NH>(mode, d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
+    else nn_launch<32, 32, NH>(mode, d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
   } else {
-    if (d.hidden <= 16) nn_launch<64, 16, NH>(d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
-    else nn_launch<64, 32, NH>(d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
+    if (d.hidden <= 16) nn_launch<64, 16, NH>(mode, d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
+    else nn_launch<64, 32, NH>(mode, d, n_sym, td, g_td, w, o_td, part, dw, cus, s);
   }
+}
+
+void nn_run(int mode, const NnDims& d, int64_t n_sym, const float* td, const float* g_td, const float* w,
+            float* o_td, float* part, float* dw, int cus, hipStream_t s) {
+  const float2* t2 = reinterpret_cast<const float2*>(td);
+  const float2* g2 = reinterpret_cast<const float2*>(g_td);
+  float2* o2 = reinterpret_cast<float2*>(o_td);
+  if (d.n_hidden == 1) nn_dispatch<1>(mode, d, n_sym, t2, g2, w, o2, part, dw, cus, s);
+  else nn_dispatch<2>(mode, d, n_sym, t2, g2, w, o2, part, dw, cus, s);
 }
 
 }  // namespace
@@ -1051,8 +1080,10 @@ NnDims nn_dims(int n_fft, int users, int memory, int hidden, int n_hidden) {
   d.n_hidden = n_hidden;
   const int F = 2 * users * (memory + 1);
   d.params = hidden * F + hidden + (n_hidden - 1) * (hidden * hidden + hidden) + 2 * users * hidden + 2 * users;
-  // padded partial size of the widest instantiation
+  // padded partial size of the widest instantiation; the reduction's split sums follow
+  // the partials
   d.part_floats = 32 * 64 + 32 + 32 * 32 + 32 + kNnOut * 32 + kNnOut;
+  d.mid_floats = kNnSplits * d.params;
   return d;
 }
 
@@ -1062,7 +1093,8 @@ bool nn_supported(const NnDims& d) {
          F <= 64 && d.hidden >= 1 && d.hidden <= 32 && (d.n_hidden == 1 || d.n_hidden == 2);
 }
 
-int fdnn_bwd_groups(int cus) { return 2 * cus; }
+// Backward grid: four workgroups (eight waves) per CU; each writes one partial.
+int fdnn_bwd_groups(int cus) { return std::min(4 * cus, kFdnnMaxGroups); }
 
 bool fft_size_ok(int n) { return n >= 2 && n <= kFftMax && (n & (n - 1)) == 0; }
 
@@ -1082,18 +1114,16 @@ void launch_fft(const float* in, float* out, int n, int64_t rows, bool inverse, 
 
 void launch_fdnn_fwd(const NnDims& d, int64_t n_sym, const float* td, const float* w, float* o_td, int cus,
                      hipStream_t s) {
-  const float2* t2 = reinterpret_cast<const float2*>(td);
-  float2* o2 = reinterpret_cast<float2*>(o_td);
-  if (d.n_hidden == 1) nn_dispatch<1>(d, n_sym, t2, nullptr, w, o2, nullptr, nullptr, cus, s);
-  else nn_dispatch<2>(d, n_sym, t2, nullptr, w, o2, nullptr, nullptr, cus, s);
+  nn_run(0, d, n_sym, td, nullptr, w, o_td, nullptr, nullptr, cus, s);
 }
 
 void launch_fdnn_bwd(const NnDims& d, int64_t n_sym, const float* td, const float* g_td, const float* w,
-                     float* part, float* dw, int cus, hipStream_t s) {
-  const float2* t2 = reinterpret_cast<const float2*>(td);
-  const float2* g2 = reinterpret_cast<const float2*>(g_td);
-  if (d.n_hidden == 1) nn_dispatch<1>(d, n_sym, t2, g2, w, nullptr, part, dw, cus, s);
-  else nn_dispatch<2>(d, n_sym, t2, g2, w, nullptr, part, dw, cus, s);
+                     float* part, int cus, hipStream_t s) {
+  nn_run(1, d, n_sym, td, g_td, w, nullptr, part, nullptr, cus, s);
+}
+
+void launch_fdnn_reduce(const NnDims& d, int64_t n_sym, float* part, float* dw, int cus, hipStream_t s) {
+  nn_run(2, d, n_sym, nullptr, nullptr, nullptr, nullptr, part, dw, cus, s);
 }
 
 void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, int T, int n_ch, float p_total,
