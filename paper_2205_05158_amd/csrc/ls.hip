@@ -12,7 +12,9 @@
 // Q = P^T P, from which
 //   Phi^H Phi = (A^T A + B^T B) + i (A^T B - B^T A),
 //   Phi^H t   = (A^T t_r + B^T t_i) + i (A^T t_i - B^T t_r).
-// Q is computed in 128 x 128 blocks of its upper block triangle; each workgroup (8 waves,
+// Q is computed in 128 x 128 blocks of its upper block triangle (the last block row and
+// column are 64 wide when NCP is an odd multiple of 64; the waves whose tiles fall past
+// them skip their MFMAs); each workgroup (8 waves,
 // each 2 x 4 tiles of 16 x 16) owns one block and a contiguous range of 32-sample chunks,
 // builds the basis values of its block's row and column sets (one set on the diagonal)
 // for each chunk in LDS (from the stream's z window and |z|^k table) and runs 16x16x4 f64
@@ -90,6 +92,8 @@ __global__ __launch_bounds__(kLsThreads) void k_ls_gram(StreamTable st, LsGeom g
   blk_of(blockIdx.x, gm.nb, bi, bj);
   const bool diag = bi == bj;                  // row and column sets coincide
   const int tr0 = 2 * (wave % 4), tc0 = 4 * (wave / 4);   // the wave's tile rows / columns
+  // the last block row / column may be 64 wide: waves whose tiles lie past it skip the MFMAs
+  const bool active = 16 * tr0 < min(kLsBlk, gm.NCP - kLsBlk * bi) && 16 * tc0 < min(kLsBlk, gm.NCP - kLsBlk * bj);
   const int split = blockIdx.y;
   const int t_begin = wg_tile_start(split, n_splits, st.n_tiles);
   const int t_end = wg_tile_start(split + 1, n_splits, st.n_tiles);
@@ -188,6 +192,7 @@ __global__ __launch_bounds__(kLsThreads) void k_ls_gram(StreamTable st, LsGeom g
     // Q block += P[chunk][rows]^T P[chunk][cols]: A[i][k] = P[4 kk + k][row 16 tr + i] from
     // lane i + 16 k, B[k][j] = P[4 kk + k][col 16 tc + j] from lane j + 16 k
     const double(*pcol)[kLsRow] = pb[diag ? 0 : 1];
+    if (!active) continue;
 #pragma unroll
     for (int kk = 0; kk < kLsChunk / 4; ++kk) {
       const int smp = 4 * kk + lane / 16;
@@ -364,8 +369,9 @@ __global__ __launch_bounds__(256) void k_ls_solve(LsGeom gm, const double2* __re
 LsDims ls_dims(int K, int M, int L) {
   LsDims d;
   d.J = K * (M + 1) + 2 * (K - 1) * (M + 1) * L;
-  d.NCP = round_up(2 * d.J + 2, kLsBlk);
-  d.nb = d.NCP / kLsBlk;
+  // columns padded to a multiple of 64: the last block row / column may be half a block
+  d.NCP = round_up(2 * d.J + 2, kLsBlk / 2);
+  d.nb = (d.NCP + kLsBlk - 1) / kLsBlk;
   d.nblk = d.nb * (d.nb + 1) / 2;
   d.chunk = kLsChunk;
   return d;
