@@ -54,7 +54,7 @@ struct LsDims {
   int nblk;    // blocks of the upper block triangle
   int chunk;   // samples per basis chunk (stream-table tile)
 };
-constexpr int kLsMaxSplits = 64;   // sample splits per Gram block (sizes the slots)
+constexpr int kLsMaxSplits = 128;  // sample splits per Gram block (sizes the slots)
 constexpr int kLsGramBlk = 128;    // Gram block edge
 constexpr int kLsMaxJ = 1024;
 LsDims ls_dims(int K, int M, int L);

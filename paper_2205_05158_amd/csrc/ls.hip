@@ -29,7 +29,7 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLsThreads = 512;     // 8 waves
-constexpr int kLsChunk = 32;        // samples per basis chunk (8 MFMA K steps)
+constexpr int kLsChunk = 16;        // samples per basis chunk (4 MFMA K steps)
 constexpr int kLsBlk = kLsGramBlk;  // Gram block edge (128)
 // LDS row stride (doubles) of a chunk's basis rows: 144 doubles = 288 banks, 32 mod 64, so
 // the two sample rows a 32-lane half of an operand read touches use disjoint banks
@@ -378,7 +378,7 @@ LsDims ls_dims(int K, int M, int L) {
 }
 
 int ls_splits(const LsDims& d, int n_tiles, int cus) {
-  const int want = (4 * cus + d.nblk - 1) / d.nblk;
+  const int want = (8 * cus + d.nblk - 1) / d.nblk;   // about four rounds of two workgroups per CU
   return std::max(1, std::min(n_tiles, std::min(want, kLsMaxSplits)));
 }
 
