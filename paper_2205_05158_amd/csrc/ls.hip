@@ -256,28 +256,32 @@ __device__ inline double2 cmulc_d(double2 a, double2 b) {   // a * conj(b)
 // positive definite, by a right-looking complex Cholesky factorisation H = L L^H in the
 // work copy (lower triangle), then L w = rhs and L^H c = w.  info[set] = 0, or k + 1 when
 // pivot k is not positive (c is then left zero).
-__global__ __launch_bounds__(256) void k_ls_solve(LsGeom gm, const double2* __restrict__ normal,
+constexpr int kLsSolveThreads = 512;
+
+__global__ __launch_bounds__(kLsSolveThreads) void k_ls_solve(LsGeom gm, const double2* __restrict__ normal,
                                                   double ridge, double2* __restrict__ work,
                                                   float* __restrict__ coef, int* __restrict__ info) {
   const int set = blockIdx.x, tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
   const int J = gm.J;
+  __shared__ double2 lk[kLsMaxJ];
   const double2* Hn = normal + (int64_t)set * J * (J + 1);
   double2* A = work + (int64_t)set * J * (J + 1);          // [J][J], column J = right-hand side
-  __shared__ double red[256];
+  __shared__ double red[kLsSolveThreads];
   __shared__ double lam;
   __shared__ int bad;
   // ridge: lambda = ridge * tr(H) / J
   double tr = 0.0;
-  for (int i = tid; i < J; i += 256) tr += Hn[(int64_t)i * (J + 1) + i].x;
+  for (int i = tid; i < J; i += kLsSolveThreads) tr += Hn[(int64_t)i * (J + 1) + i].x;
   red[tid] = tr;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kLsSolveThreads / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
   if (tid == 0) { lam = ridge * red[0] / J; bad = 0; }
   __syncthreads();
-  for (int64_t e = tid; e < (int64_t)J * (J + 1); e += 256) {
+  for (int64_t e = tid; e < (int64_t)J * (J + 1); e += kLsSolveThreads) {
     double2 v = Hn[e];
     const int r = (int)(e / (J + 1)), c = (int)(e % (J + 1));
     if (r == c) v.x += lam;
@@ -294,31 +298,29 @@ __global__ __launch_bounds__(256) void k_ls_solve(LsGeom gm, const double2* __re
     __syncthreads();
     if (bad) break;
     const double inv = 1.0 / A[(int64_t)k * ld + k].x;
-    for (int i = k + 1 + tid; i < J; i += 256) {
+    for (int i = k + 1 + tid; i < J; i += kLsSolveThreads) {
       double2 v = A[(int64_t)i * ld + k];
-      A[(int64_t)i * ld + k] = make_double2(v.x * inv, v.y * inv);
+      v = make_double2(v.x * inv, v.y * inv);
+      A[(int64_t)i * ld + k] = v;
+      lk[i] = v;                            // column k of L, shared for the update
     }
     __syncthreads();
-    // trailing lower triangle: A[i][j] -= L[i][k] conj(L[j][k]), k < j <= i
-    const int m = J - k - 1;
-    const int64_t cnt = (int64_t)m * (m + 1) / 2;
-    for (int64_t e = tid; e < cnt; e += 256) {
-      // e -> (i, j) with 0 <= j <= i < m, row-major over the lower triangle
-      int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-      while ((int64_t)(i + 1) * (i + 2) / 2 <= e) ++i;
-      while ((int64_t)i * (i + 1) / 2 > e) --i;
-      const int j = (int)(e - (int64_t)i * (i + 1) / 2);
-      const int ii = k + 1 + i, jj = k + 1 + j;
-      const double2 lik = A[(int64_t)ii * ld + k], ljk = A[(int64_t)jj * ld + k];
-      const double2 p = cmulc_d(lik, ljk);
-      double2 v = A[(int64_t)ii * ld + jj];
-      A[(int64_t)ii * ld + jj] = make_double2(v.x - p.x, v.y - p.y);
+    // trailing lower triangle: A[i][j] -= L[i][k] conj(L[j][k]), k < j <= i; one wave per
+    // row (rows interleaved over the waves), lanes over the row's columns (coalesced)
+    for (int ii = k + 1 + wave; ii < J; ii += kLsSolveThreads / 64) {
+      const double2 lik = lk[ii];
+      double2* row = A + (int64_t)ii * ld;
+      for (int jj = k + 1 + lane; jj <= ii; jj += 64) {
+        const double2 p = cmulc_d(lik, lk[jj]);
+        const double2 v = row[jj];
+        row[jj] = make_double2(v.x - p.x, v.y - p.y);
+      }
     }
     __syncthreads();
   }
   float* cout = coef + (int64_t)set * 2 * J;
   if (bad) {
-    for (int i = tid; i < 2 * J; i += 256) cout[i] = 0.f;
+    for (int i = tid; i < 2 * J; i += kLsSolveThreads) cout[i] = 0.f;
     if (tid == 0) info[set] = bad;
     return;
   }
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void k_ls_solve(LsGeom gm, const double2* __re
     }
     __syncthreads();
     const double2 wk = A[(int64_t)k * ld + J];
-    for (int i = k + 1 + tid; i < J; i += 256) {
+    for (int i = k + 1 + tid; i < J; i += kLsSolveThreads) {
       const double2 p = cmul_d(A[(int64_t)i * ld + k], wk);
       double2 b = A[(int64_t)i * ld + J];
       A[(int64_t)i * ld + J] = make_double2(b.x - p.x, b.y - p.y);
@@ -347,7 +349,7 @@ __global__ __launch_bounds__(256) void k_ls_solve(LsGeom gm, const double2* __re
     }
     __syncthreads();
     const double2 ck = A[(int64_t)k * ld + J];
-    for (int i = tid; i < k; i += 256) {
+    for (int i = tid; i < k; i += kLsSolveThreads) {
       // (L^H)[i][k] = conj(L[k][i])
       const double2 p = cmulc_d(ck, A[(int64_t)k * ld + i]);
       double2 b = A[(int64_t)i * ld + J];
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(256) void k_ls_solve(LsGeom gm, const double2* __re
     }
     __syncthreads();
   }
-  for (int i = tid; i < J; i += 256) {
+  for (int i = tid; i < J; i += kLsSolveThreads) {
     const double2 c = A[(int64_t)i * ld + J];
     cout[2 * i] = (float)c.x;
     cout[2 * i + 1] = (float)c.y;
@@ -405,7 +407,7 @@ void launch_ls_reduce(const dpd_gmp_desc& g, const StreamTable& st, int n_splits
 
 void launch_ls_solve(const dpd_gmp_desc& g, int n_sets, const double2* normal, double ridge,
                      double2* work, float* coef, int* info, hipStream_t s) {
-  k_ls_solve<<<n_sets, 256, 0, s>>>(geom_of(g), normal, ridge, work, coef, info);
+  k_ls_solve<<<n_sets, kLsSolveThreads, 0, s>>>(geom_of(g), normal, ridge, work, coef, info);
 }
 
 }  // namespace dpdmi
