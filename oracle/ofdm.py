@@ -20,6 +20,8 @@ Passages followed (arXiv 2205.05158):
     samples of all U UEs as 2 U (L4 + 1) real inputs, K^NN fully connected ReLU layers
     of D neurons, 2 U linear outputs, and a DFT per UE back to the subcarriers .. Sec. III-C
   * symbol error rate over the QAM symbols of the data subcarriers ....... Sec. V-B
+  * supervised training of the frequency-domain DPDs through all simulated blocks with a
+    loss at the receiver: the adjoints of precoding and of the link ........ Sec. V-A-2
 Readings where the paper is silent or loose:
   * data subcarriers are +-1..+-N_d/2 (DC and the outer band are guard), as for the
     time-domain signals;
@@ -200,6 +202,69 @@ def gmp_cyclic(x: np.ndarray, coef, K: int, M: int, L: int) -> np.ndarray:
                 y += b[k - 1, l, g - 1] * ul * np.roll(r, l + g, axis=-1) ** k
                 y += c[k - 1, l, g - 1] * ul * np.roll(r, l - g, axis=-1) ** k
     return y
+
+
+def gmp_cyclic_backward(x: np.ndarray, g_y: np.ndarray, coef, K: int, M: int, L: int) -> np.ndarray:
+    """Real-convention gradient (dL/dRe + j dL/dIm) with respect to x of a real loss through
+    gmp_cyclic, given g_y for its output: each monomial c x[n - l] |x[n - q]|^k of eq. (9)
+    differentiated on its own, delays mod N.  The multiplied sample gives
+    conj(c |x[n - q]|^k) g_y[n] at n - l; the envelope (k >= 1) gives
+    k |x[n - q]|^(k-1) Re(conj(g_y[n]) c x[n - l]) x[n - q] / |x[n - q]| at n - q (0 at x = 0)."""
+    a, b, c = unpack_gmp(coef, K, M, L)
+    x = np.asarray(x, dtype=np.complex128)
+    r = np.abs(x)
+    unit = np.zeros_like(x)
+    nz = r > 0
+    unit[nz] = x[nz] / r[nz]
+    terms = [(a[k, l], k, l, l) for l in range(M + 1) for k in range(K)]
+    terms += [(b[k - 1, l, g - 1], k, l, l + g) for k in range(1, K) for l in range(M + 1) for g in range(1, L + 1)]
+    terms += [(c[k - 1, l, g - 1], k, l, l - g) for k in range(1, K) for l in range(M + 1) for g in range(1, L + 1)]
+    out = np.zeros_like(x)
+    for cf, k, l, q in terms:
+        rq = np.roll(r, q, axis=-1)                                  # |x[n - q]|
+        out += np.roll(np.conj(cf) * rq ** k * g_y, -l, axis=-1)    # to index n - l
+        if k >= 1:
+            s = k * np.real(np.conj(g_y) * cf * np.roll(x, l, axis=-1))
+            out += np.roll(s, -q, axis=-1) * r ** (k - 1) * unit    # to index n - q
+    return out
+
+
+def link_backward(g_r, x_fd, h_taps, alpha, pa_coef, pa_orders, G: complex, n_d: int, sym_per_ch: int = 1):
+    """Adjoint of `link` (no DPD, no decisions) for the real-convention gradient g_r of a
+    real loss with respect to the equalised data symbols (complex [n_sym][U][N_d]): the
+    gradient with respect to the precoded antenna subcarriers x_fd ([n_sym][B][N]).
+    Equalisation and channel are complex-linear (adjoint: the conjugate transpose), the
+    unitary DFT's adjoint is the IDFT and vice versa, the PA goes through
+    gmp_cyclic_backward."""
+    x_fd = np.asarray(x_fd, dtype=np.complex128)
+    n_sym, B, N = x_fd.shape
+    K, M, L = pa_orders
+    u = idft(x_fd)
+    db = data_bins(N, n_d)
+    H = channel_fd(h_taps, N, db)                           # [n_ch][N_d][U][B]
+    g_y = np.zeros_like(x_fd)
+    for i in range(n_sym):
+        c = i // sym_per_ch
+        g_z = np.conj(1.0 / (alpha[c] * G)) * np.asarray(g_r)[i]       # [U][N_d]
+        g_y[i][:, db] = np.einsum("kub,uk->bk", np.conj(H[c]), g_z)
+    g_y_td = idft(g_y)
+    g_u = np.stack([gmp_cyclic_backward(u[:, b], g_y_td[:, b], pa_coef[b], K, M, L) for b in range(B)], axis=1)
+    return dft(g_u)
+
+
+def precode_backward(g_x, Pt, alpha, n_d: int, all_bins: bool = False, sym_per_ch: int = 1):
+    """Adjoint of `precode`: g_s[i][:, k] = alpha Pt_k^H g_x[i][:, k] on the precoded
+    subcarriers, 0 elsewhere ([n_sym][B][N] -> [n_sym][U][N])."""
+    g_x = np.asarray(g_x, dtype=np.complex128)
+    n_sym, B, N = g_x.shape
+    U = Pt.shape[3]
+    g_s = np.zeros((n_sym, U, N), dtype=np.complex128)
+    bins = np.arange(N) if all_bins else data_bins(N, n_d)
+    for i in range(n_sym):
+        c = i // sym_per_ch
+        for k in bins:
+            g_s[i, :, k] = alpha[c] * (np.conj(Pt[c, k]).T @ g_x[i, :, k])
+    return g_s
 
 
 def qam_points(qam: int) -> np.ndarray:

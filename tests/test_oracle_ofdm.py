@@ -327,3 +327,71 @@ def test_link_nonlinear_pa_adds_distortion_and_keeps_the_decisions_valid():
     assert np.sqrt(np.mean(np.abs(err) ** 2)) > 1e-3      # the PA distorts
     assert np.all(dec == ofdm.qam_decide(r, qam))
     assert errs.sum() == np.sum(dec != idx)
+
+
+# ---------------------------------------------------------------------------
+# adjoints (receiver-side training through the link)
+# ---------------------------------------------------------------------------
+def _fd_grad(f, z, eps=1e-6):
+    """Real-convention gradient dL/dRe + j dL/dIm of a real f at complex z by central
+    differences."""
+    g = np.zeros_like(z)
+    for idx in np.ndindex(z.shape):
+        for unit in (1.0, 1j):
+            zp = z.copy()
+            zm = z.copy()
+            zp[idx] += eps * unit
+            zm[idx] -= eps * unit
+            d = (f(zp) - f(zm)) / (2 * eps)
+            g[idx] += d * unit
+    return g
+
+
+def test_gmp_cyclic_backward_finite_differences_and_tiling():
+    rng = np.random.default_rng(31)
+    K, M, L, N = 4, 2, 2, 9
+    coef = syn.gmp_coefficients(K, M, L, 7)
+    x = _rand_c(rng, N) * 0.6
+    w = _rand_c(rng, N)
+    f = lambda v: float(np.sum((np.conj(w) * ofdm.gmp_cyclic(v, coef, K, M, L)).real))
+    g = ofdm.gmp_cyclic_backward(x, w, coef, K, M, L)
+    np.testing.assert_allclose(g, _fd_grad(f, x), atol=1e-6)
+    # chain rule through the thrice-tiled zero-padded GMP (pinned gmp_backward)
+    a, b, c = dpd_pa.unpack_gmp(coef, K, M, L)
+    gy = np.concatenate([np.zeros(N), w, np.zeros(N)])
+    gt = dpd_pa.gmp_backward(np.tile(x, 3), gy, a, b, c)
+    np.testing.assert_allclose(g, gt[:N] + gt[N:2 * N] + gt[2 * N:], atol=1e-12)
+
+
+def test_link_backward_finite_differences():
+    rng = np.random.default_rng(32)
+    n_sym, U, B, N, n_d, T = 2, 2, 3, 8, 4, 2
+    idx, S = _link_case(n_sym, U, B, N, n_d, T, qam=4, spc=1, seed=9)[:2]
+    _, _, H, He = _link_case(n_sym, U, B, N, n_d, T, qam=4, spc=1, seed=9)
+    Pt, alpha = ofdm.zf_precoder(He, N, n_d, 3.0)
+    x = ofdm.precode(S, Pt, alpha, n_d, True, 1) + 0.1 * _rand_c(rng, n_sym, B, N)
+    K, M, L = 3, 1, 1
+    pa = syn.antenna_pa_coefficients(B, K, M, L, 5, scale=0.4).astype(np.float64)
+    G = 0.9 + 0.2j
+    w = _rand_c(rng, n_sym, U, n_d)
+    noise = np.zeros((n_sym, U, N), dtype=complex)
+
+    def f(v):
+        r, _, _ = ofdm.link(v, H, alpha, pa, (K, M, L), G, noise, idx, 4, n_d, 1)
+        return float(np.sum((np.conj(w) * r).real))
+
+    g = ofdm.link_backward(w, x, H, alpha, pa, (K, M, L), G, n_d, 1)
+    np.testing.assert_allclose(g, _fd_grad(f, x), atol=1e-5)
+
+
+@pytest.mark.parametrize("all_bins", [False, True])
+def test_precode_backward_is_the_adjoint(all_bins):
+    rng = np.random.default_rng(33)
+    n_sym, U, B, N, n_d, spc = 3, 2, 4, 16, 6, 2
+    _, _, _, He = _link_case(n_sym, U, B, N, n_d, 3, qam=4, spc=spc, seed=4)
+    Pt, alpha = ofdm.zf_precoder(He, N, n_d, 2.0)
+    s = _rand_c(rng, n_sym, U, N)
+    gx = _rand_c(rng, n_sym, B, N)
+    lhs = np.vdot(gx, ofdm.precode(s, Pt, alpha, n_d, all_bins, spc))
+    rhs = np.vdot(ofdm.precode_backward(gx, Pt, alpha, n_d, all_bins, spc), s)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12)
