@@ -355,6 +355,23 @@ dpd_status ofdm_link(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_c
                      float* r_out, int64_t* errors, void* workspace, size_t workspace_bytes,
                      hipStream_t stream);
 
+/* Reverse mode of the link for a real loss on the equalised symbols (receiver-side
+ * training, Sec. V-A-2): given g_r = dL/dRe + j dL/dIm of r_out (float[n_sym][U][n_data][2]),
+ * g_x (float[n_sym][B][N][2], not aliasing x) = the gradient with respect to the precoded
+ * x of ofdm_link: the adjoints of equalisation and channel, of the DFT (the IDFT), of the
+ * PA (eq. (9) differentiated, cyclic delays, d|u|/du = 0 at u = 0) and of the IDFT (the
+ * DFT).  Decisions and noise do not enter; desc.dpd.K must be 0 (DPD_ERR_UNSUPPORTED
+ * otherwise).  Workspace as link_workspace_size. */
+dpd_status ofdm_link_backward(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* x,
+                              const float* pa_coef, float g_re, float g_im, const float* h, const float* alpha,
+                              const float* g_r, float* g_x, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream);
+/* Adjoint of ofdm_precode: g_s[i][u][k] = alpha[c] sum_b conj(pt[c][k][b][u]) g_x[i][b][k]
+ * on the precoded subcarriers (as all_bins), 0 elsewhere; g_s float[n_sym][U][N][2]. */
+dpd_status ofdm_precode_backward(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* pt,
+                                 const float* alpha, const float* g_x, int32_t all_bins, float* g_s,
+                                 hipStream_t stream);
+
 /* Welch PSD of one stream y [n][2] (nfft-point segments, periodic Hann window,
  * 50 % overlap, no detrending, scaled by 1/sum(w^2)), bins in natural FFT order,
  * and the ACPR with main channel |k| <= half_bins, adjacent channels

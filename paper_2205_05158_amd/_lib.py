@@ -102,6 +102,10 @@ _SIGS = {
     "link_workspace_size": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]),
     "ofdm_link": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, _P, _P, _P, C.c_float, C.c_float, _P, _P,
                             _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "ofdm_link_backward": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, _P, _P, C.c_float, C.c_float, _P,
+                                     _P, _P, _P, _P, C.c_size_t, _P]),
+    "ofdm_precode_backward": (C.c_int, [C.POINTER(LinkDesc), C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P,
+                                        _P]),
     "cascade_acpr": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32, _P, _P, _P, C.c_size_t, _P]),
     "dpd_acpr_workspace_size": (C.c_size_t, [C.c_int64, C.c_int32]),
     "dpd_profile_enable": (C.c_int, [C.c_int32]),
@@ -359,6 +363,18 @@ def ofdm_link(desc, n_sym, sym_per_ch, x, dpd_coef, pa_coef, g, h, alpha, noise,
     _check(lib().ofdm_link(C.byref(desc), int(n_sym), int(sym_per_ch), _ptr(x), _ptr(dpd_coef), _ptr(pa_coef),
                            g.real, g.imag, _ptr(h), _ptr(alpha), _ptr(noise), _ptr(tx), _ptr(r_out),
                            _ptr(errors), _ptr(workspace), _nbytes(workspace), _stream(stream)), "ofdm_link")
+
+
+def ofdm_link_backward(desc, n_sym, sym_per_ch, x, pa_coef, g, h, alpha, g_r, g_x, workspace, stream=None):
+    g = complex(g)
+    _check(lib().ofdm_link_backward(C.byref(desc), int(n_sym), int(sym_per_ch), _ptr(x), _ptr(pa_coef), g.real,
+                                    g.imag, _ptr(h), _ptr(alpha), _ptr(g_r), _ptr(g_x), _ptr(workspace),
+                                    _nbytes(workspace), _stream(stream)), "ofdm_link_backward")
+
+
+def ofdm_precode_backward(desc, n_sym, sym_per_ch, pt, alpha, g_x, all_bins, g_s, stream=None):
+    _check(lib().ofdm_precode_backward(C.byref(desc), int(n_sym), int(sym_per_ch), _ptr(pt), _ptr(alpha), _ptr(g_x),
+                                       int(bool(all_bins)), _ptr(g_s), _stream(stream)), "ofdm_precode_backward")
 
 
 def dpd_acpr_workspace_size(n: int, nfft: int) -> int:

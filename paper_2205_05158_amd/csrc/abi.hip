@@ -1100,6 +1100,22 @@ dpd_status ofdm_precode(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_pe
   return launch_status();
 }
 
+dpd_status ofdm_precode_backward(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* pt,
+                                 const float* alpha, const float* g_x, int32_t all_bins, float* g_s,
+                                 hipStream_t stream) {
+  if (!desc || !pt || !alpha || !g_x || !g_s) return DPD_ERR_NULL;
+  const dpd_status st = link_check(desc);
+  if (st != DPD_OK) return st;
+  if (!syms_ok(n_sym, sym_per_ch) || n_sym > 65535 || (all_bins != 0 && all_bins != 1)) return DPD_ERR_SHAPE;
+  if (!aligned(pt, 8) || !aligned(alpha, 4) || !aligned(g_x, 8) || !aligned(g_s, 8)) return DPD_ERR_ALIGN;
+  {
+    DPD_PROF("precode_bwd");
+    launch_precode_bwd(pt, alpha, g_x, desc->n_fft, desc->n_data, desc->users, desc->antennas, n_sym, sym_per_ch,
+                       all_bins, g_s, stream);
+  }
+  return launch_status();
+}
+
 dpd_status link_workspace_size(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch,
                                size_t* bytes_host) {
   if (!desc || !bytes_host) return DPD_ERR_NULL;
@@ -1139,6 +1155,33 @@ dpd_status ofdm_link(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_c
     DPD_PROF("link_rx");
     launch_link_rx(y, hd, alpha, g_re, g_im, noise, tx, d.n_fft, d.n_data, d.users, d.antennas, n_sym,
                    sym_per_ch, qam_side(d.qam), r_out, at<int32_t>(workspace, L.part), errors, stream);
+  }
+  return launch_status();
+}
+
+dpd_status ofdm_link_backward(const dpd_link_desc* desc, int32_t n_sym, int32_t sym_per_ch, const float* x,
+                              const float* pa_coef, float g_re, float g_im, const float* h, const float* alpha,
+                              const float* g_r, float* g_x, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream) {
+  if (!desc || !x || !pa_coef || !h || !alpha || !g_r || !g_x || !workspace) return DPD_ERR_NULL;
+  const dpd_status st = link_check(desc);
+  if (st != DPD_OK) return st;
+  if (desc->dpd.K != 0) return DPD_ERR_UNSUPPORTED;
+  if (!syms_ok(n_sym, sym_per_ch) || n_sym > 65535 || !(g_re * g_re + g_im * g_im > 0.f)) return DPD_ERR_SHAPE;
+  if (!aligned(x, 8) || !aligned(pa_coef, 8) || !aligned(h, 8) || !aligned(alpha, 4) || !aligned(g_r, 8) ||
+      !aligned(g_x, 8) || !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (x == g_x) return DPD_ERR_SHAPE;
+  const int n_ch = n_channels(n_sym, sym_per_ch);
+  const LinkWs L = link_ws_layout(*desc, n_sym, n_ch);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  const dpd_link_desc& d = *desc;
+  float* hd = at<float>(workspace, L.hd);
+  { DPD_PROF("link_chan"); launch_chan_data(h, d.n_fft, d.n_data, d.users, d.antennas, d.taps, n_ch, hd, stream); }
+  {
+    DPD_PROF("link_bwd");
+    launch_link_bwd(x, hd, alpha, g_re, g_im, g_r, d.n_fft, d.n_data, d.users, d.antennas, n_sym, sym_per_ch,
+                    pa_coef, d.pa, at<float>(workspace, L.y), g_x, device_cus(), stream);
   }
   return launch_status();
 }

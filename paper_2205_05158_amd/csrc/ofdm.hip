@@ -938,6 +938,239 @@ __global__ __launch_bounds__(kFftThreads) void k_link_pa(const float2* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// Reverse mode of the link (receiver-side training of the frequency-domain DPDs)
+// ---------------------------------------------------------------------------
+// Index of data symbol on subcarrier k, or -1 for a guard subcarrier.
+__device__ __forceinline__ int data_index(int k, int N, int n_d) {
+  const int h = n_d / 2;
+  if (k >= 1 && k <= h) return k - 1;
+  if (k >= N - h) return k - (N - n_d);
+  return -1;
+}
+
+// g_y[i][b][k] = sum_u conj(H_k[u][b]) conj(1 / (alpha G)) g_r[i][u][d(k)] on data
+// subcarriers, 0 on guard subcarriers (adjoint of channel and equalisation).
+__global__ __launch_bounds__(256) void k_link_rx_bwd(const float2* __restrict__ hd, const float* __restrict__ alpha,
+                                                     float g_re, float g_im, const float2* __restrict__ g_r, int N,
+                                                     int n_d, int U, int B, int spc, float2* __restrict__ g_y) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= N) return;
+  float2* gi = g_y + (int64_t)i * B * N + k;
+  const int d = data_index(k, N, n_d);
+  if (d < 0) {
+    for (int b = 0; b < B; ++b) gi[(int64_t)b * N] = make_float2(0.f, 0.f);
+    return;
+  }
+  const int c = i / spc;
+  // conj(1 / (alpha G)) = G / (alpha |G|^2)
+  const float den = alpha[c] * (g_re * g_re + g_im * g_im);
+  const float2 cj = make_float2(g_re / den, g_im / den);
+  float2 gz[kZfMaxU];
+#pragma unroll
+  for (int u = 0; u < kZfMaxU; ++u)
+    gz[u] = u < U ? cmul(cj, g_r[((int64_t)i * U + u) * n_d + d]) : make_float2(0.f, 0.f);
+  const float2* hk = hd + ((int64_t)c * n_d + d) * U * B;
+  for (int b = 0; b < B; ++b) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < kZfMaxU; ++u) {
+      if (u < U) {
+        const float2 h = hk[u * B + b];
+        // conj(h) gz
+        acc.x += h.x * gz[u].x + h.y * gz[u].y;
+        acc.y += h.x * gz[u].y - h.y * gz[u].x;
+      }
+    }
+    gi[(int64_t)b * N] = acc;
+  }
+}
+
+// Unitary IDFT of one global row into dst (LDS, natural order), through the scratch row.
+// dst may alias scratch.  Ends with a barrier.
+__device__ void row_idft(const float2* __restrict__ src, float2* scratch, const float2* tw, float2* dst, int N,
+                         int log2n, float scale) {
+  const int t = threadIdx.x;
+  if (N == kFftMax) {
+    float2 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = conjf2(src[t + 256 * q]);
+    __syncthreads();
+    f16_pass1(scratch, v);
+    __syncthreads();
+    f16_pass2(scratch, tw);
+    __syncthreads();
+    f16_pass3(scratch, tw, v);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const float2 a = X16(v, q);
+      dst[t + 256 * q] = make_float2(a.x * scale, -a.y * scale);
+    }
+  } else {
+    __syncthreads();
+    for (int i = t; i < N; i += kFftThreads) scratch[i] = src[i];
+    __syncthreads();
+    fft_lds<true>(scratch, tw, N, log2n);
+    for (int i = t; i < N; i += kFftThreads) {
+      const float2 v = scratch[i];
+      dst[i] = make_float2(v.x * scale, v.y * scale);     // dst == scratch: same index
+    }
+  }
+  __syncthreads();
+}
+
+// Cyclic GMP reverse mode, gather form, for samples m = t + 256 q (registers g[q]):
+// g[m] = sum_l conj(Q_l(m)) gy[m + l]
+//        + x[m] / |x[m]| sum over the monomials whose envelope sample is m of
+//          k |x[m]|^(k-1) Re(conj(gy[n]) c x[n - l]),
+// Q_l(p) = sum_k a_kl r[p]^k + sum_{g,k>=1} (b_klg r[p - g]^k + c_klg r[p + g]^k).
+__device__ void gmp_cyclic_bwd_lds(const float2* x, const float* r, const float2* gy, int N,
+                                   const float2* __restrict__ coef, int K, int M, int L,
+                                   float2 (&g)[kFftMax / kFftThreads]) {
+  const int na = K * (M + 1), nb = (K - 1) * (M + 1) * L;
+  const int sb = (M + 1) * L;                  // stride of k in the b / c blocks
+#pragma unroll
+  for (int q = 0; q < kFftMax / kFftThreads; ++q) {
+    const int m = threadIdx.x + q * kFftThreads;
+    if (m >= N) break;
+    const float rm = r[m];
+    const float2 xm = x[m];
+    float2 hol = make_float2(0.f, 0.f);
+    float env = 0.f;
+    for (int l = 0; l <= M; ++l) {
+      const float2 gyl = gy[(m + l) % N];
+      // Q_l(m) and the derivative of its a-part in r[m]
+      float2 poly = coef[(K - 1) * (M + 1) + l];
+      float2 dpa = make_float2(0.f, 0.f);
+      for (int k = K - 1; k >= 1; --k) {
+        const float2 a = coef[k * (M + 1) + l];
+        dpa = make_float2(fmaf(dpa.x, rm, (float)k * a.x), fmaf(dpa.y, rm, (float)k * a.y));
+      }
+      for (int k = K - 2; k >= 0; --k) {
+        const float2 a = coef[k * (M + 1) + l];
+        poly = make_float2(fmaf(poly.x, rm, a.x), fmaf(poly.y, rm, a.y));
+      }
+      // envelope of the a-monomials at m: n = m + l, multiplied sample x[m]
+      {
+        const float2 w = cmul(dpa, xm);
+        env += gyl.x * w.x + gyl.y * w.y;     // Re(conj(gy) w)
+      }
+      for (int gg = 1; K > 1 && gg <= L; ++gg) {
+        const int ib = na + l * L + (gg - 1), ic = ib + nb;
+        const float rb = r[((m - gg) % N + N) % N], rc = r[(m + gg) % N];
+        float2 pb = coef[ib + (K - 2) * sb], pc = coef[ic + (K - 2) * sb];
+        float2 db = make_float2((float)(K - 1) * pb.x, (float)(K - 1) * pb.y);
+        float2 dc = make_float2((float)(K - 1) * pc.x, (float)(K - 1) * pc.y);
+        for (int k = K - 2; k >= 1; --k) {
+          const float2 bb = coef[ib + (k - 1) * sb], cc = coef[ic + (k - 1) * sb];
+          pb = make_float2(fmaf(pb.x, rb, bb.x), fmaf(pb.y, rb, bb.y));
+          pc = make_float2(fmaf(pc.x, rc, cc.x), fmaf(pc.y, rc, cc.y));
+          db = make_float2(fmaf(db.x, rm, (float)k * bb.x), fmaf(db.y, rm, (float)k * bb.y));
+          dc = make_float2(fmaf(dc.x, rm, (float)k * cc.x), fmaf(dc.y, rm, (float)k * cc.y));
+        }
+        poly = make_float2(fmaf(pb.x, rb, fmaf(pc.x, rc, poly.x)), fmaf(pb.y, rb, fmaf(pc.y, rc, poly.y)));
+        // envelope sample m of b_{k,l,g}: n = m + l + g, multiplied sample x[m + g]
+        const float2 gyb = gy[(m + l + gg) % N];
+        const float2 wb = cmul(db, x[(m + gg) % N]);
+        env += gyb.x * wb.x + gyb.y * wb.y;
+        // of c_{k,l,g}: n = m + l - g, multiplied sample x[m - g]
+        const float2 gyc = gy[((m + l - gg) % N + N) % N];
+        const float2 wc = cmul(dc, x[((m - gg) % N + N) % N]);
+        env += gyc.x * wc.x + gyc.y * wc.y;
+      }
+      // conj(Q_l(m)) gy[m + l]
+      hol.x += poly.x * gyl.x + poly.y * gyl.y;
+      hol.y += poly.x * gyl.y - poly.y * gyl.x;
+    }
+    const float2 unit = rm > 0.f ? make_float2(xm.x / rm, xm.y / rm) : make_float2(0.f, 0.f);
+    g[q] = make_float2(fmaf(env, unit.x, hol.x), fmaf(env, unit.y, hol.y));
+  }
+}
+
+// One workgroup per (symbol, antenna) row, persistent: u = IDFT(x), gy = IDFT(g_y) (the
+// adjoint of the DFT), g_u by the cyclic GMP reverse mode, g_x = DFT(g_u) (the adjoint of
+// the IDFT).
+__global__ __launch_bounds__(kFftThreads) void k_link_pa_bwd(const float2* __restrict__ x,
+                                                             const float2* __restrict__ g_y, int N, int log2n,
+                                                             float scale, int B, int64_t rows,
+                                                             const float2* __restrict__ pa, int Kp, int Mp, int Lp,
+                                                             int Jp, float2* __restrict__ g_x) {
+  __shared__ float2 scratch[kF16Row];      // transforms; afterwards the gy row
+  __shared__ float2 xs[kFftMax];
+  __shared__ float2 tw[kFftMax / 2];
+  __shared__ float r[kFftMax];
+  fft_twiddles(tw, N);
+  const int t = threadIdx.x;
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const int b = (int)(row % B);
+    row_idft(x + row * N, scratch, tw, xs, N, log2n, scale);
+    for (int i = t; i < N; i += kFftThreads) r[i] = sqrtf(xs[i].x * xs[i].x + xs[i].y * xs[i].y);
+    row_idft(g_y + row * N, scratch, tw, scratch, N, log2n, scale);
+    float2 g[kFftMax / kFftThreads];
+    gmp_cyclic_bwd_lds(xs, r, scratch, N, pa + (int64_t)b * Jp, Kp, Mp, Lp, g);
+    __syncthreads();                       // gy (in scratch) and x are read before reuse
+    if (N == kFftMax) {
+      f16_pass1(scratch, g);
+      __syncthreads();
+      f16_pass2(scratch, tw);
+      __syncthreads();
+      f16_pass3(scratch, tw, g);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const float2 a = X16(g, q);
+        g_x[row * N + t + 256 * q] = make_float2(a.x * scale, a.y * scale);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kFftMax / kFftThreads; ++q) {
+        const int n = t + q * kFftThreads;
+        if (n < N) scratch[n] = g[q];
+      }
+      __syncthreads();
+      fft_lds<false>(scratch, tw, N, log2n);
+      for (int i = t; i < N; i += kFftThreads)
+        g_x[row * N + i] = make_float2(scratch[i].x * scale, scratch[i].y * scale);
+    }
+    __syncthreads();                       // this row is done with the LDS rows
+  }
+}
+
+// g_s[i][u][k] = alpha_c sum_b conj(Pt[c][k][b][u]) g_x[i][b][k] on the precoded
+// subcarriers, 0 elsewhere (adjoint of k_precode).
+__global__ __launch_bounds__(256) void k_precode_bwd(const float2* __restrict__ pt, const float* __restrict__ alpha,
+                                                     const float2* __restrict__ g_x, int N, int n_d, int U, int B,
+                                                     int spc, int all_bins, float2* __restrict__ g_s) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int i = blockIdx.y;
+  if (k >= N) return;
+  const int c = i / spc;
+  const bool on = all_bins || data_index(k, N, n_d) >= 0;
+  float2 acc[kZfMaxU];
+#pragma unroll
+  for (int u = 0; u < kZfMaxU; ++u) acc[u] = make_float2(0.f, 0.f);
+  if (on) {
+    const float2* pk = pt + ((int64_t)c * N + k) * B * U;
+    const float2* gx = g_x + (int64_t)i * B * N + k;
+    for (int b = 0; b < B; ++b) {
+      const float2 v = gx[(int64_t)b * N];
+#pragma unroll
+      for (int u = 0; u < kZfMaxU; ++u) {
+        if (u < U) {
+          const float2 p = pk[b * U + u];
+          acc[u].x += p.x * v.x + p.y * v.y;     // conj(p) v
+          acc[u].y += p.x * v.y - p.y * v.x;
+        }
+      }
+    }
+  }
+  const float a = on ? alpha[c] : 0.f;
+#pragma unroll
+  for (int u = 0; u < kZfMaxU; ++u)
+    if (u < U) g_s[((int64_t)i * U + u) * N + k] = make_float2(a * acc[u].x, a * acc[u].y);
+}
+
 // Receiver: thread per (symbol i, data symbol d): y = H_k x_pa + w, r = y / (alpha G),
 // nearest QAM point, errors counted per UE into the workgroup's partial.
 __global__ __launch_bounds__(256) void k_link_rx(const float2* __restrict__ y_fd, const float2* __restrict__ hd,
@@ -1157,6 +1390,28 @@ void launch_link_pa(const float* x, int N, int B, int64_t rows, const float* dpd
                                       reinterpret_cast<const float2*>(dpd), dd ? dd->K : 0, dd ? dd->M : 0,
                                       dd ? dd->L : 0, Jd, reinterpret_cast<const float2*>(pa), pd.K, pd.M, pd.L,
                                       Jp, reinterpret_cast<float2*>(y_fd));
+}
+
+void launch_link_bwd(const float* x, const float* hd, const float* alpha, float g_re, float g_im, const float* g_r,
+                     int N, int n_d, int U, int B, int n_sym, int spc, const float* pa, const dpd_gmp_desc& pd,
+                     float* g_y, float* g_x, int cus, hipStream_t s) {
+  k_link_rx_bwd<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(hd), alpha, g_re, g_im,
+                                                             reinterpret_cast<const float2*>(g_r), N, n_d, U, B, spc,
+                                                             reinterpret_cast<float2*>(g_y));
+  const int64_t rows = (int64_t)n_sym * B;
+  const int G = (int)std::min<int64_t>(rows, 2 * (int64_t)cus);
+  const float scale = (float)(1.0 / sqrt((double)N));
+  const int Jp = pd.K * (pd.M + 1) + 2 * (pd.K - 1) * (pd.M + 1) * pd.L;
+  k_link_pa_bwd<<<G, kFftThreads, 0, s>>>(reinterpret_cast<const float2*>(x), reinterpret_cast<const float2*>(g_y), N,
+                                          ilog2(N), scale, B, rows, reinterpret_cast<const float2*>(pa), pd.K, pd.M,
+                                          pd.L, Jp, reinterpret_cast<float2*>(g_x));
+}
+
+void launch_precode_bwd(const float* pt, const float* alpha, const float* g_x, int N, int n_d, int U, int B,
+                        int n_sym, int spc, int all_bins, float* g_s, hipStream_t s) {
+  k_precode_bwd<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt), alpha,
+                                                             reinterpret_cast<const float2*>(g_x), N, n_d, U, B, spc,
+                                                             all_bins, reinterpret_cast<float2*>(g_s));
 }
 
 int64_t link_rx_parts(int n_d, int n_sym) { return (int64_t)((n_d + 255) / 256) * n_sym; }

@@ -124,3 +124,25 @@ class Downlink:
                          device=self.device)
         L.ofdm_link(self.desc, n, sym_per_ch, x, dpd_coef, pa_coef, g, h, alpha, noise, tx, r, errors, ws)
         return errors, r
+
+    def link_backward(self, x, pa_coef, g, h, alpha, g_r, sym_per_ch=1):
+        """Gradient with respect to the precoded subcarriers x of a real loss on the
+        equalised symbols, given its gradient g_r [n_sym][U][n_data][2]."""
+        n = x.shape[0]
+        _check_c(x, (n, self.antennas, self.n_fft, 2), "x")
+        _check_c(g_r, (n, self.users, self.n_data, 2), "g_r")
+        self._check_channels(None, alpha, n, sym_per_ch, h)
+        g_x = torch.empty_like(x)
+        ws = torch.empty(max(L.link_workspace_size(self.desc, n, sym_per_ch), 256), dtype=torch.uint8,
+                         device=self.device)
+        L.ofdm_link_backward(self.desc, n, sym_per_ch, x, pa_coef, g, h, alpha, g_r, g_x, ws)
+        return g_x
+
+    def precode_backward(self, g_x, pt, alpha, sym_per_ch=1, all_bins=False):
+        """Adjoint of precode: [n_sym][B][N][2] -> [n_sym][U][N][2]."""
+        n = g_x.shape[0]
+        _check_c(g_x, (n, self.antennas, self.n_fft, 2), "g_x")
+        self._check_channels(pt, alpha, n, sym_per_ch)
+        g_s = torch.empty(n, self.users, self.n_fft, 2, dtype=torch.float32, device=self.device)
+        L.ofdm_precode_backward(self.desc, n, sym_per_ch, pt, alpha, g_x, all_bins, g_s)
+        return g_s

@@ -269,3 +269,11 @@ def test_downlink_arguments_rejected(dpdlib):
     assert lib.ofdm_link(C.byref(ok), 2, 1, FAKE, None, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
                          None, FAKE, None, FAKE, FAKE, 64, None) == L.DPD_ERR_WORKSPACE
     assert L.link_workspace_size(ok, 20, 10) > L.link_workspace_size(ok, 2, 1)
+    # reverse mode: no DPD in the descriptor, x and g_x distinct
+    assert lib.ofdm_link_backward(C.byref(withdpd), 2, 1, FAKE, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
+                                  FAKE, OUT, FAKE, 1 << 40, None) == L.DPD_ERR_UNSUPPORTED
+    assert lib.ofdm_link_backward(C.byref(ok), 2, 1, FAKE, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
+                                  FAKE, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert lib.ofdm_link_backward(C.byref(ok), 2, 1, FAKE, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
+                                  None, OUT, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    assert lib.ofdm_precode_backward(C.byref(ok), 2, 1, FAKE, FAKE, FAKE, 3, OUT, None) == L.DPD_ERR_SHAPE

@@ -253,3 +253,84 @@ def test_link_transparent_linear_pa_and_ser_closed_form():
     n = n_sym * U * n_d
     p = O.qam_ser_awgn(qam, snr)
     assert abs(int(err.sum()) / n - p) < 5 * math.sqrt(p * (1 - p) / n)
+
+
+# ---------------------------------------------------------------------------
+# reverse mode of the link and precoding; receiver-side FD-NN gradient
+# ---------------------------------------------------------------------------
+BWD_CASES = [
+    # (N, n_d, U, B, T, qam, spc, n_sym, pa)
+    (64, 48, 4, 8, 4, 16, 2, 4, (3, 1, 1)),
+    (256, 96, 3, 5, 6, 64, 3, 7, (5, 2, 1)),
+    (4, 2, 1, 1, 1, 4, 1, 2, (2, 0, 0)),
+    (4096, 384, 8, 32, 10, 256, 2, 2, (7, 3, 1)),
+]
+
+
+@pytest.mark.parametrize("case", BWD_CASES)
+def test_link_and_precode_backward_match_oracle(case):
+    """FP32 adjoints against the FP64 oracle (pinned by finite differences): gradients with
+    respect to the precoded subcarriers and the UE symbols within 1e-5 of their rms."""
+    N, n_d, U, B, T, qam, spc, n_sym, pa = case
+    announce(f"link backward N={N} U={U} B={B} n_sym={n_sym} pa={pa}")
+    inp = _link_inputs(case + (None,))
+    G = 0.9 + 0.1j
+    rng = np.random.default_rng(N + B)
+    g_r = (rng.standard_normal((n_sym, U, n_d, 2)) / math.sqrt(n_sym * U * n_d)).astype(np.float32)
+    ref_pt, ref_alpha = O.zf_precoder(_c(inp["he"]), N, n_d, inp["p_total"])
+    dl = D.Downlink(N, n_d, U, B, T, qam, pa=pa)
+    pt, alpha = dl.zf(H.to_dev(inp["he"]), inp["p_total"], all_bins=True)
+    for all_bins in (False, True):
+        x = dl.precode(H.to_dev(inp["s"]), pt, alpha, sym_per_ch=spc, all_bins=all_bins)
+        x_np = _c(x.cpu().numpy())
+        g_x = dl.link_backward(x, H.to_dev(inp["pa"]), G, H.to_dev(inp["h"]), alpha, H.to_dev(g_r), sym_per_ch=spc)
+        g_s = dl.precode_backward(g_x, pt, alpha, sym_per_ch=spc, all_bins=all_bins)
+        torch.cuda.synchronize()
+        # the oracle on the device's own precoded input (the link's input is data here)
+        ref_gx = O.link_backward(_c(g_r), x_np, _c(inp["h"]), alpha.cpu().numpy().astype(np.float64), inp["pa"],
+                                 pa, G, n_d, spc)
+        assert _rms_rel(_c(g_x.cpu().numpy()), ref_gx) < 1e-5, all_bins
+        ref_gs = O.precode_backward(_c(g_x.cpu().numpy()), _c(pt.cpu().numpy()),
+                                    alpha.cpu().numpy().astype(np.float64), n_d, all_bins, spc)
+        assert _rms_rel(_c(g_s.cpu().numpy()), ref_gs) < 1e-5, all_bins
+
+
+def test_fdnn_receiver_side_gradient():
+    """The paper's supervised training signal for the FD-NN (Sec. V-A-2): MSE between the
+    equalised and transmitted symbols, through FD-NN, guard-band ZF precoding, PAs and
+    channel; the weight gradient against the oracle's chain of adjoints within 1e-4."""
+    N, n_d, U, B, T, qam, spc, n_sym, pa = 256, 96, 4, 8, 4, 16, 2, 4, (5, 2, 1)
+    L4, Dh = 2, 12
+    announce("fdnn receiver-side gradient")
+    inp = _link_inputs((N, n_d, U, B, T, qam, spc, n_sym, pa, None))
+    w = S.xavier_fdnn(U, L4, Dh, 1, 9)
+    G = 1.0
+    dl = D.Downlink(N, n_d, U, B, T, qam, pa=pa)
+    net = D.FdNn(N, U, L4, Dh, 1, max_sym=n_sym)
+    s, wd = H.to_dev(inp["s"]), H.to_dev(w)
+    pt, alpha = dl.zf(H.to_dev(inp["he"]), inp["p_total"], all_bins=True)
+    v = net.forward(s, wd)
+    x = dl.precode(v, pt, alpha, sym_per_ch=spc, all_bins=True)
+    tx = torch.from_numpy(inp["idx"]).cuda()
+    _, r = dl.link(x, H.to_dev(inp["pa"]), G, H.to_dev(inp["h"]), alpha, tx, sym_per_ch=spc, want_r=True)
+    db = torch.from_numpy(O.data_bins(N, n_d)).cuda()
+    target = s[:, :, db, :]
+    n = n_sym * U * n_d
+    g_r = (2.0 / n) * (r - target)
+    g_x = dl.link_backward(x, H.to_dev(inp["pa"]), G, H.to_dev(inp["h"]), alpha, g_r.contiguous(), sym_per_ch=spc)
+    g_v = dl.precode_backward(g_x, pt, alpha, sym_per_ch=spc, all_bins=True)
+    dw = net.backward(s, wd, g_v)
+    torch.cuda.synchronize()
+    # oracle chain
+    ref_pt, ref_alpha = O.zf_precoder(_c(inp["he"]), N, n_d, inp["p_total"])
+    ref_v, cache = O.fdnn_forward(_c(inp["s"]), w, U, L4, Dh, 1)
+    ref_x = O.precode(ref_v, ref_pt, ref_alpha, n_d, True, spc)
+    zero = np.zeros((n_sym, U, N), dtype=complex)
+    ref_r, _, _ = O.link(ref_x, _c(inp["h"]), ref_alpha, inp["pa"], pa, G, zero, inp["idx"], qam, n_d, spc)
+    assert _rms_rel(_c(r.cpu().numpy()), ref_r) < 1e-4
+    ref_gr = (2.0 / n) * (ref_r - _c(inp["s"])[:, :, O.data_bins(N, n_d)])
+    ref_gx = O.link_backward(ref_gr, ref_x, _c(inp["h"]), ref_alpha, inp["pa"], pa, G, n_d, spc)
+    ref_gv = O.precode_backward(ref_gx, ref_pt, ref_alpha, n_d, True, spc)
+    ref_dw = O.fdnn_backward(ref_gv, cache, U, L4)
+    got = dw.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref_dw) <= 1e-4 * np.linalg.norm(ref_dw)
