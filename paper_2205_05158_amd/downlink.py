@@ -146,3 +146,44 @@ class Downlink:
         g_s = torch.empty(n, self.users, self.n_fft, 2, dtype=torch.float32, device=self.device)
         L.ofdm_precode_backward(self.desc, n, sym_per_ch, pt, alpha, g_x, all_bins, g_s)
         return g_s
+
+
+def receiver_loss_grad(dl: Downlink, net: FdNn, s, tx, w, pt, alpha, pa_coef, g, h, sym_per_ch=1):
+    """The supervised criterion of Sec. V-A-2 for the FD-NN, on the device: the UE symbols s
+    through the FD-NN, guard-band ZF precoding (every subcarrier), the link (PAs, channel)
+    to the equalised data symbols r; L = sum |r - s_data|^2 / (n_sym U N_d).
+    Returns (L as a device scalar, dL/dw, symbol errors per UE)."""
+    n = s.shape[0] * dl.users * dl.n_data
+    v = net.forward(s, w)
+    x = dl.precode(v, pt, alpha, sym_per_ch=sym_per_ch, all_bins=True)
+    errors, r = dl.link(x, pa_coef, g, h, alpha, tx, sym_per_ch=sym_per_ch, want_r=True)
+    bins = torch.as_tensor(_data_bins(dl.n_fft, dl.n_data), device=s.device)
+    e = r - s.index_select(2, bins)
+    loss = (e * e).sum() / n
+    g_x = dl.link_backward(x, pa_coef, g, h, alpha, ((2.0 / n) * e).contiguous(), sym_per_ch=sym_per_ch)
+    g_v = dl.precode_backward(g_x, pt, alpha, sym_per_ch=sym_per_ch, all_bins=True)
+    return loss, net.backward(s, w, g_v), errors
+
+
+def train_receiver(dl: Downlink, net: FdNn, s, tx, w, pt, alpha, pa_coef, g, h, steps, lr=1e-3,
+                   sym_per_ch=1, state=None):
+    """`steps` device Adam updates of w in place on the receiver-side loss (the paper trains
+    the FD-NN this way, Adam with learning rate 0.001).  Returns the loss before each step
+    (device [steps]), the symbol errors before each step (device [steps][U]) and the
+    optimiser state (m, v, t)."""
+    m, v, t = (torch.zeros_like(w), torch.zeros_like(w), 0) if state is None else state
+    losses = torch.empty(steps, dtype=torch.float32, device=w.device)
+    errs = torch.empty(steps, dl.users, dtype=torch.int64, device=w.device)
+    for i in range(steps):
+        loss, dw, e = receiver_loss_grad(dl, net, s, tx, w, pt, alpha, pa_coef, g, h, sym_per_ch)
+        losses[i] = loss
+        errs[i] = e
+        t += 1
+        L.dpd_adam_step(dw, w, m, v, t, lr=lr)
+    return losses, errs, (m, v, t)
+
+
+def _data_bins(n_fft, n_d):
+    """Subcarriers of the data symbols in symbol order: 1..n_d/2, then n_fft - n_d/2.."""
+    h = n_d // 2
+    return list(range(1, h + 1)) + list(range(n_fft - h, n_fft))

@@ -334,3 +334,43 @@ def test_fdnn_receiver_side_gradient():
     ref_dw = O.fdnn_backward(ref_gv, cache, U, L4)
     got = dw.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(got - ref_dw) <= 1e-4 * np.linalg.norm(ref_dw)
+
+
+def test_fdnn_receiver_training_matches_oracle():
+    """Four device Adam steps of the FD-NN on the receiver-side loss against the same loop
+    in FP64 (oracle chain + oracle Adam): the loss before every step within 1e-4
+    (relative) and the total weight change within 1 % in relative L2."""
+    import oracle.adam as OA
+    N, n_d, U, B, T, qam, spc, n_sym, pa = 256, 96, 4, 8, 4, 16, 2, 4, (5, 2, 1)
+    L4, Dh, steps, lr = 2, 12, 4, 1e-3
+    announce("fdnn receiver training")
+    inp = _link_inputs((N, n_d, U, B, T, qam, spc, n_sym, pa, None))
+    w0 = S.xavier_fdnn(U, L4, Dh, 1, 9)
+    dl = D.Downlink(N, n_d, U, B, T, qam, pa=pa)
+    net = D.FdNn(N, U, L4, Dh, 1, max_sym=n_sym)
+    s = H.to_dev(inp["s"])
+    pt, alpha = dl.zf(H.to_dev(inp["he"]), inp["p_total"], all_bins=True)
+    w = H.to_dev(w0)
+    tx = torch.from_numpy(inp["idx"]).cuda()
+    losses, errs, _ = D.train_receiver(dl, net, s, tx, w, pt, alpha, H.to_dev(inp["pa"]), 1.0, H.to_dev(inp["h"]),
+                                       steps, lr=lr, sym_per_ch=spc)
+    torch.cuda.synchronize()
+    ref_pt, ref_alpha = O.zf_precoder(_c(inp["he"]), N, n_d, inp["p_total"])
+    db = O.data_bins(N, n_d)
+    n = n_sym * U * n_d
+    zero = np.zeros((n_sym, U, N), dtype=complex)
+    wr, m, v = w0.astype(np.float64), np.zeros(w0.size), np.zeros(w0.size)
+    ref_losses = []
+    for t in range(1, steps + 1):
+        ref_v, cache = O.fdnn_forward(_c(inp["s"]), wr, U, L4, Dh, 1)
+        ref_x = O.precode(ref_v, ref_pt, ref_alpha, n_d, True, spc)
+        ref_r, _, _ = O.link(ref_x, _c(inp["h"]), ref_alpha, inp["pa"], pa, 1.0, zero, inp["idx"], qam, n_d, spc)
+        e = ref_r - _c(inp["s"])[:, :, db]
+        ref_losses.append(float(np.sum(np.abs(e) ** 2) / n))
+        gx = O.link_backward(2.0 * e / n, ref_x, _c(inp["h"]), ref_alpha, inp["pa"], pa, 1.0, n_d, spc)
+        dw = O.fdnn_backward(O.precode_backward(gx, ref_pt, ref_alpha, n_d, True, spc), cache, U, L4)
+        wr, m, v = OA.adam_step(wr, m, v, dw, t, lr=lr)
+    np.testing.assert_allclose(losses.cpu().numpy(), ref_losses, rtol=1e-4)
+    got = w.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm((got - w0) - (wr - w0)) <= 1e-2 * np.linalg.norm(wr - w0)
+    assert errs.shape == (steps, U)
