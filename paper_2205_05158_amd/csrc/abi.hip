@@ -1178,11 +1178,13 @@ dpd_status ofdm_link_backward(const dpd_link_desc* desc, int32_t n_sym, int32_t 
   const dpd_link_desc& d = *desc;
   float* hd = at<float>(workspace, L.hd);
   { DPD_PROF("link_chan"); launch_chan_data(h, d.n_fft, d.n_data, d.users, d.antennas, d.taps, n_ch, hd, stream); }
+  float* g_y = at<float>(workspace, L.y);
   {
-    DPD_PROF("link_bwd");
-    launch_link_bwd(x, hd, alpha, g_re, g_im, g_r, d.n_fft, d.n_data, d.users, d.antennas, n_sym, sym_per_ch,
-                    pa_coef, d.pa, at<float>(workspace, L.y), g_x, device_cus(), stream);
+    DPD_PROF("link_rx_bwd");
+    launch_link_rx_bwd(hd, alpha, g_re, g_im, g_r, d.n_fft, d.n_data, d.users, d.antennas, n_sym, sym_per_ch, g_y,
+                       stream);
   }
+  { DPD_PROF("link_pa_bwd"); launch_link_pa_bwd(x, g_y, d.n_fft, d.antennas, n_sym, pa_coef, d.pa, g_x, device_cus(), stream); }
   return launch_status();
 }
 

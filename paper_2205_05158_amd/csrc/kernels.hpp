@@ -184,9 +184,10 @@ void launch_link_pa(const float* x, int N, int B, int64_t rows, const float* dpd
                     const float* pa, const dpd_gmp_desc& pd, float* y_fd, int cus, hipStream_t s);
 // Reverse mode of the link without a DPD: g_r [n_sym][U][n_d] -> g_y (workspace,
 // [n_sym][B][N]) -> g_x [n_sym][B][N]; hd as for the receiver.
-void launch_link_bwd(const float* x, const float* hd, const float* alpha, float g_re, float g_im, const float* g_r,
-                     int N, int n_d, int U, int B, int n_sym, int spc, const float* pa, const dpd_gmp_desc& pd,
-                     float* g_y, float* g_x, int cus, hipStream_t s);
+void launch_link_rx_bwd(const float* hd, const float* alpha, float g_re, float g_im, const float* g_r, int N, int n_d,
+                        int U, int B, int n_sym, int spc, float* g_y, hipStream_t s);
+void launch_link_pa_bwd(const float* x, const float* g_y, int N, int B, int n_sym, const float* pa,
+                        const dpd_gmp_desc& pd, float* g_x, int cus, hipStream_t s);
 void launch_precode_bwd(const float* pt, const float* alpha, const float* g_x, int N, int n_d, int U, int B,
                         int n_sym, int spc, int all_bins, float* g_s, hipStream_t s);
 int64_t link_rx_parts(int n_d, int n_sym);   // int32 partial counts of U entries each

@@ -651,79 +651,85 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
   __shared__ double2 A[kZfMaxU][kZfMaxU], I[kZfMaxU][kZfMaxU];
   __shared__ double red[64];
   const int lane = threadIdx.x;
-  const int k = all_bins ? (int)blockIdx.x : data_bin((int)blockIdx.x, N, n_d);
   const int c = blockIdx.y;
-  for (int t = lane; t < T; t += 64) ph[t] = unit_phase(k, t, N);
-  __syncthreads();
-  const float2* hc = h + (int64_t)c * T * U * B;
-  for (int e = lane; e < U * B; e += 64) {
-    double2 acc = make_double2(0.0, 0.0);
-    for (int t = 0; t < T; ++t) {
-      const float2 v = hc[(int64_t)t * U * B + e];
-      acc = make_double2(acc.x + (double)v.x * ph[t].x - (double)v.y * ph[t].y,
-                         acc.y + (double)v.x * ph[t].y + (double)v.y * ph[t].x);
-    }
-    hk[e] = acc;
-  }
-  __syncthreads();
-  const int i = lane / kZfMaxU, j = lane % kZfMaxU;
-  const bool own = i < U && j < U;
-  if (own) {
-    double2 g = make_double2(0.0, 0.0);
-    for (int b = 0; b < B; ++b) {          // G[i][j] = sum_b H[i][b] conj(H[j][b])
-      const double2 x = hk[i * B + b], y = hk[j * B + b];
-      g.x += x.x * y.x + x.y * y.y;
-      g.y += x.y * y.x - x.x * y.y;
-    }
-    A[i][j] = g;
-    I[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  // Gauss-Jordan on [A | I] without pivoting (A is Hermitian positive definite)
-  for (int p = 0; p < U; ++p) {
-    double2 na = make_double2(0.0, 0.0), ni = na;
-    if (own) {
-      const double2 piv = A[p][p];
-      const double m2 = piv.x * piv.x + piv.y * piv.y;
-      const double2 inv = make_double2(piv.x / m2, -piv.y / m2);
-      if (i == p) {
-        na = zmul(A[p][j], inv);
-        ni = zmul(I[p][j], inv);
-      } else {
-        const double2 fct = zmul(A[i][p], inv);
-        const double2 x = zmul(fct, A[p][j]), y = zmul(fct, I[p][j]);
-        na = make_double2(A[i][j].x - x.x, A[i][j].y - x.y);
-        ni = make_double2(I[i][j].x - y.x, I[i][j].y - y.y);
+  const int nbins = all_bins ? N : n_d;
+  // one subcarrier per workgroup (grid-stride form; looping over several per workgroup
+  // measured slower)
+  for (int kb = blockIdx.x; kb < nbins; kb += gridDim.x) {
+    const int k = all_bins ? kb : data_bin(kb, N, n_d);
+    __syncthreads();                         // the previous subcarrier is done with the LDS
+    for (int t = lane; t < T; t += 64) ph[t] = unit_phase(k, t, N);
+    __syncthreads();
+    const float2* hc = h + (int64_t)c * T * U * B;
+    for (int e = lane; e < U * B; e += 64) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int t = 0; t < T; ++t) {
+        const float2 v = hc[(int64_t)t * U * B + e];
+        acc = make_double2(acc.x + (double)v.x * ph[t].x - (double)v.y * ph[t].y,
+                           acc.y + (double)v.x * ph[t].y + (double)v.y * ph[t].x);
       }
+      hk[e] = acc;
     }
     __syncthreads();
+    const int i = lane / kZfMaxU, j = lane % kZfMaxU;
+    const bool own = i < U && j < U;
     if (own) {
-      A[i][j] = na;
-      I[i][j] = ni;
+      double2 g = make_double2(0.0, 0.0);
+      for (int b = 0; b < B; ++b) {          // G[i][j] = sum_b H[i][b] conj(H[j][b])
+        const double2 x = hk[i * B + b], y = hk[j * B + b];
+        g.x += x.x * y.x + x.y * y.y;
+        g.y += x.y * y.x - x.x * y.y;
+      }
+      A[i][j] = g;
+      I[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-  }
-  // Pt[b][u] = sum_j conj(H[j][b]) Ginv[j][u]
-  double tr = 0.0;
-  float2* dst = pt + ((int64_t)c * N + k) * B * U;
-  for (int e = lane; e < B * U; e += 64) {
-    const int b = e / U, u = e % U;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int jj = 0; jj < U; ++jj) {
-      const double2 v = zmulc(hk[jj * B + b], I[jj][u]);
-      acc.x += v.x;
-      acc.y += v.y;
+    // Gauss-Jordan on [A | I] without pivoting (A is Hermitian positive definite)
+    for (int p = 0; p < U; ++p) {
+      double2 na = make_double2(0.0, 0.0), ni = na;
+      if (own) {
+        const double2 piv = A[p][p];
+        const double m2 = piv.x * piv.x + piv.y * piv.y;
+        const double2 inv = make_double2(piv.x / m2, -piv.y / m2);
+        if (i == p) {
+          na = zmul(A[p][j], inv);
+          ni = zmul(I[p][j], inv);
+        } else {
+          const double2 fct = zmul(A[i][p], inv);
+          const double2 x = zmul(fct, A[p][j]), y = zmul(fct, I[p][j]);
+          na = make_double2(A[i][j].x - x.x, A[i][j].y - x.y);
+          ni = make_double2(I[i][j].x - y.x, I[i][j].y - y.y);
+        }
+      }
+      __syncthreads();
+      if (own) {
+        A[i][j] = na;
+        I[i][j] = ni;
+      }
+      __syncthreads();
     }
-    dst[e] = make_float2((float)acc.x, (float)acc.y);
-    tr += acc.x * acc.x + acc.y * acc.y;
-  }
-  red[lane] = tr;
-  __syncthreads();
-  for (int w = 32; w > 0; w >>= 1) {
-    if (lane < w) red[lane] += red[lane + w];
+    // Pt[b][u] = sum_j conj(H[j][b]) Ginv[j][u]
+    double tr = 0.0;
+    float2* dst = pt + ((int64_t)c * N + k) * B * U;
+    for (int e = lane; e < B * U; e += 64) {
+      const int b = e / U, u = e % U;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int jj = 0; jj < U; ++jj) {
+        const double2 v = zmulc(hk[jj * B + b], I[jj][u]);
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+      dst[e] = make_float2((float)acc.x, (float)acc.y);
+      tr += acc.x * acc.x + acc.y * acc.y;
+    }
+    red[lane] = tr;
     __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+      if (lane < w) red[lane] += red[lane + w];
+      __syncthreads();
+    }
+    if (lane == 0) trace[(int64_t)c * N + k] = red[0];
   }
-  if (lane == 0) trace[(int64_t)c * N + k] = red[0];
 }
 
 // alpha[c] = sqrt(P_T / mean over data subcarriers of trace[c][k]) (fixed-order tree).
@@ -1141,7 +1147,7 @@ __global__ __launch_bounds__(kFftThreads) void k_link_pa_bwd(const float2* __res
 // subcarriers, 0 elsewhere (adjoint of k_precode).
 __global__ __launch_bounds__(256) void k_precode_bwd(const float2* __restrict__ pt, const float* __restrict__ alpha,
                                                      const float2* __restrict__ g_x, int N, int n_d, int U, int B,
-                                                     int spc, int all_bins, float2* __restrict__ g_s) {
+                                                     int spc, int all_bins, int vec, float2* __restrict__ g_s) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   const int i = blockIdx.y;
   if (k >= N) return;
@@ -1153,14 +1159,32 @@ __global__ __launch_bounds__(256) void k_precode_bwd(const float2* __restrict__ 
   if (on) {
     const float2* pk = pt + ((int64_t)c * N + k) * B * U;
     const float2* gx = g_x + (int64_t)i * B * N + k;
-    for (int b = 0; b < B; ++b) {
-      const float2 v = gx[(int64_t)b * N];
+    if (vec) {
+      // even U and a 16-byte aligned pt: Pt_k rows as U/2 aligned pairs
+      const float4* pk4 = reinterpret_cast<const float4*>(pk);
+      for (int b = 0; b < B; ++b) {
+        const float2 v = gx[(int64_t)b * N];
 #pragma unroll
-      for (int u = 0; u < kZfMaxU; ++u) {
-        if (u < U) {
-          const float2 p = pk[b * U + u];
-          acc[u].x += p.x * v.x + p.y * v.y;     // conj(p) v
-          acc[u].y += p.x * v.y - p.y * v.x;
+        for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
+          if (2 * u2 < U) {
+            const float4 p = pk4[b * (U / 2) + u2];
+            acc[2 * u2].x += p.x * v.x + p.y * v.y;     // conj(p) v
+            acc[2 * u2].y += p.x * v.y - p.y * v.x;
+            acc[2 * u2 + 1].x += p.z * v.x + p.w * v.y;
+            acc[2 * u2 + 1].y += p.z * v.y - p.w * v.x;
+          }
+        }
+      }
+    } else {
+      for (int b = 0; b < B; ++b) {
+        const float2 v = gx[(int64_t)b * N];
+#pragma unroll
+        for (int u = 0; u < kZfMaxU; ++u) {
+          if (u < U) {
+            const float2 p = pk[b * U + u];
+            acc[u].x += p.x * v.x + p.y * v.y;     // conj(p) v
+            acc[u].y += p.x * v.y - p.y * v.x;
+          }
         }
       }
     }
@@ -1362,8 +1386,9 @@ void launch_fdnn_reduce(const NnDims& d, int64_t n_sym, float* part, float* dw, 
 void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, int T, int n_ch, float p_total,
                float* pt, double* trace, float* alpha, hipStream_t s) {
   const size_t lds = sizeof(double2) * (size_t)(T + U * B);
-  k_zf<<<dim3(all_bins ? N : n_d, n_ch), 64, lds, s>>>(reinterpret_cast<const float2*>(h_est), N, n_d, all_bins,
-                                                       U, B, T, reinterpret_cast<float2*>(pt), trace);
+  const int nbins = all_bins ? N : n_d;
+  k_zf<<<dim3(nbins, n_ch), 64, lds, s>>>(reinterpret_cast<const float2*>(h_est), N, n_d, all_bins, U, B, T,
+                                           reinterpret_cast<float2*>(pt), trace);
   k_zf_alpha<<<n_ch, 256, 0, s>>>(trace, N, n_d, p_total, alpha);
 }
 
@@ -1392,12 +1417,15 @@ void launch_link_pa(const float* x, int N, int B, int64_t rows, const float* dpd
                                       Jp, reinterpret_cast<float2*>(y_fd));
 }
 
-void launch_link_bwd(const float* x, const float* hd, const float* alpha, float g_re, float g_im, const float* g_r,
-                     int N, int n_d, int U, int B, int n_sym, int spc, const float* pa, const dpd_gmp_desc& pd,
-                     float* g_y, float* g_x, int cus, hipStream_t s) {
+void launch_link_rx_bwd(const float* hd, const float* alpha, float g_re, float g_im, const float* g_r, int N, int n_d,
+                        int U, int B, int n_sym, int spc, float* g_y, hipStream_t s) {
   k_link_rx_bwd<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(hd), alpha, g_re, g_im,
                                                              reinterpret_cast<const float2*>(g_r), N, n_d, U, B, spc,
                                                              reinterpret_cast<float2*>(g_y));
+}
+
+void launch_link_pa_bwd(const float* x, const float* g_y, int N, int B, int n_sym, const float* pa,
+                        const dpd_gmp_desc& pd, float* g_x, int cus, hipStream_t s) {
   const int64_t rows = (int64_t)n_sym * B;
   const int G = (int)std::min<int64_t>(rows, 2 * (int64_t)cus);
   const float scale = (float)(1.0 / sqrt((double)N));
@@ -1409,9 +1437,10 @@ void launch_link_bwd(const float* x, const float* hd, const float* alpha, float 
 
 void launch_precode_bwd(const float* pt, const float* alpha, const float* g_x, int N, int n_d, int U, int B,
                         int n_sym, int spc, int all_bins, float* g_s, hipStream_t s) {
+  const int vec = (U % 2 == 0) && ((uintptr_t)pt % 16 == 0);
   k_precode_bwd<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt), alpha,
                                                              reinterpret_cast<const float2*>(g_x), N, n_d, U, B, spc,
-                                                             all_bins, reinterpret_cast<float2*>(g_s));
+                                                             all_bins, vec, reinterpret_cast<float2*>(g_s));
 }
 
 int64_t link_rx_parts(int n_d, int n_sym) { return (int64_t)((n_d + 255) / 256) * n_sym; }
