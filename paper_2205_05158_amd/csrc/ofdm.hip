@@ -647,8 +647,9 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
                                            int B, int T, float2* __restrict__ pt, double* __restrict__ trace) {
   extern __shared__ double2 zf_dyn[];
   double2* ph = zf_dyn;
-  double2* hk = zf_dyn + T;
-  __shared__ double2 A[kZfMaxU][kZfMaxU], I[kZfMaxU][kZfMaxU];
+  double2* hk = zf_dyn + T;                 // H_k rows of B + 1 (the pad spreads rows over the banks)
+  const int hs = B + 1;
+  __shared__ double2 A[kZfMaxU][kZfMaxU + 1], I[kZfMaxU][kZfMaxU + 1];   // padded rows: column reads hit distinct banks
   __shared__ double red[64];
   const int lane = threadIdx.x;
   const int c = blockIdx.y;
@@ -662,13 +663,14 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
     __syncthreads();
     const float2* hc = h + (int64_t)c * T * U * B;
     for (int e = lane; e < U * B; e += 64) {
+      const int eu = e / B, eb = e % B;
       double2 acc = make_double2(0.0, 0.0);
       for (int t = 0; t < T; ++t) {
         const float2 v = hc[(int64_t)t * U * B + e];
         acc = make_double2(acc.x + (double)v.x * ph[t].x - (double)v.y * ph[t].y,
                            acc.y + (double)v.x * ph[t].y + (double)v.y * ph[t].x);
       }
-      hk[e] = acc;
+      hk[eu * hs + eb] = acc;
     }
     __syncthreads();
     const int i = lane / kZfMaxU, j = lane % kZfMaxU;
@@ -676,7 +678,7 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
     if (own) {
       double2 g = make_double2(0.0, 0.0);
       for (int b = 0; b < B; ++b) {          // G[i][j] = sum_b H[i][b] conj(H[j][b])
-        const double2 x = hk[i * B + b], y = hk[j * B + b];
+        const double2 x = hk[i * hs + b], y = hk[j * hs + b];
         g.x += x.x * y.x + x.y * y.y;
         g.y += x.y * y.x - x.x * y.y;
       }
@@ -715,7 +717,7 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
       const int b = e / U, u = e % U;
       double2 acc = make_double2(0.0, 0.0);
       for (int jj = 0; jj < U; ++jj) {
-        const double2 v = zmulc(hk[jj * B + b], I[jj][u]);
+        const double2 v = zmulc(hk[jj * hs + b], I[jj][u]);
         acc.x += v.x;
         acc.y += v.y;
       }
@@ -1385,7 +1387,7 @@ void launch_fdnn_reduce(const NnDims& d, int64_t n_sym, float* part, float* dw, 
 
 void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, int T, int n_ch, float p_total,
                float* pt, double* trace, float* alpha, hipStream_t s) {
-  const size_t lds = sizeof(double2) * (size_t)(T + U * B);
+  const size_t lds = sizeof(double2) * (size_t)(T + U * (B + 1));
   const int nbins = all_bins ? N : n_d;
   k_zf<<<dim3(nbins, n_ch), 64, lds, s>>>(reinterpret_cast<const float2*>(h_est), N, n_d, all_bins, U, B, T,
                                            reinterpret_cast<float2*>(pt), trace);
