@@ -11,7 +11,8 @@ from ._lib import (DPD_BF16, DPD_FP32, DPD_IMPL_PLAIN, DPD_IMPL_TUNED, EXPORTS, 
 from .cascade import Cascade, CascadeFn
 from .ila import GmpIla
 from .fdcnn import FdCnn, FdCnnFn
-from .downlink import Downlink, FdNn, FdNnFn, receiver_loss_grad, train_receiver
+from .downlink import (Downlink, FdNn, FdNnFn, receiver_loss_grad, receiver_loss_grad_fdcnn,
+                       train_receiver)
 
 __all__ = [
     "DPD_BF16", "DPD_FP32", "DPD_IMPL_PLAIN", "DPD_IMPL_TUNED", "EXPORTS", "LIB_PATH", "Batch",
@@ -21,5 +22,6 @@ __all__ = [
     "dpd_version", "dpd_workspace_size", "fdcnn_backward", "fdcnn_forward", "fdcnn_param_count",
     "fdcnn_workspace_size", "gmp_desc", "gmp_ls_fit", "gmp_ls_workspace_size", "lib",
     "make_batch", "pa_gmp_forward", "status_string", "tdnn_desc", "Cascade", "CascadeFn", "GmpIla",
-    "FdCnn", "FdCnnFn", "Downlink", "FdNn", "FdNnFn", "receiver_loss_grad", "train_receiver",
+    "FdCnn", "FdCnnFn", "Downlink", "FdNn", "FdNnFn", "receiver_loss_grad",
+    "receiver_loss_grad_fdcnn", "train_receiver",
 ]

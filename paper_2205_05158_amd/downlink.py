@@ -165,17 +165,42 @@ def receiver_loss_grad(dl: Downlink, net: FdNn, s, tx, w, pt, alpha, pa_coef, g,
     return loss, net.backward(s, w, g_v), errors
 
 
+def receiver_loss_grad_fdcnn(dl: Downlink, net, s, tx, w, pt, alpha, pa_coef, g, h, sym_per_ch=1):
+    """The same criterion for the FD-CNN (Sec. IV-C, trained like the FD-NN, Sec. V-A-2):
+    each UE's N_d data symbols (items = n_sym x U symbol vectors) through the FD-CNN, back
+    on the data subcarriers, data-only ZF precoding, the link; L as above.  `net` is an
+    FdCnn for n_d = dl.n_data.  Returns (L, dL/dw, symbol errors per UE)."""
+    n_sym = s.shape[0]
+    n = n_sym * dl.users * dl.n_data
+    bins = torch.as_tensor(_data_bins(dl.n_fft, dl.n_data), device=s.device)
+    s_data = s.index_select(2, bins).contiguous()                       # [n_sym][U][N_d][2]
+    items = s_data.view(n_sym * dl.users, dl.n_data, 2)
+    v = net.forward(items, w).view(n_sym, dl.users, dl.n_data, 2)
+    v_full = torch.zeros_like(s)
+    v_full.index_copy_(2, bins, v)
+    x = dl.precode(v_full, pt, alpha, sym_per_ch=sym_per_ch, all_bins=False)
+    errors, r = dl.link(x, pa_coef, g, h, alpha, tx, sym_per_ch=sym_per_ch, want_r=True)
+    e = r - s_data
+    loss = (e * e).sum() / n
+    g_x = dl.link_backward(x, pa_coef, g, h, alpha, ((2.0 / n) * e).contiguous(), sym_per_ch=sym_per_ch)
+    g_v = dl.precode_backward(g_x, pt, alpha, sym_per_ch=sym_per_ch, all_bins=False)
+    g_items = g_v.index_select(2, bins).contiguous().view(n_sym * dl.users, dl.n_data, 2)
+    return loss, net.backward(items, w, g_items), errors
+
+
 def train_receiver(dl: Downlink, net: FdNn, s, tx, w, pt, alpha, pa_coef, g, h, steps, lr=1e-3,
                    sym_per_ch=1, state=None):
     """`steps` device Adam updates of w in place on the receiver-side loss (the paper trains
-    the FD-NN this way, Adam with learning rate 0.001).  Returns the loss before each step
+    the FD-NN and the FD-CNN this way, Adam with learning rate 0.001); `net` is an FdNn
+    (precoding on every subcarrier) or an FdCnn (data subcarriers).  Returns the loss before each step
     (device [steps]), the symbol errors before each step (device [steps][U]) and the
     optimiser state (m, v, t)."""
     m, v, t = (torch.zeros_like(w), torch.zeros_like(w), 0) if state is None else state
     losses = torch.empty(steps, dtype=torch.float32, device=w.device)
     errs = torch.empty(steps, dl.users, dtype=torch.int64, device=w.device)
+    crit = receiver_loss_grad if isinstance(net, FdNn) else receiver_loss_grad_fdcnn
     for i in range(steps):
-        loss, dw, e = receiver_loss_grad(dl, net, s, tx, w, pt, alpha, pa_coef, g, h, sym_per_ch)
+        loss, dw, e = crit(dl, net, s, tx, w, pt, alpha, pa_coef, g, h, sym_per_ch)
         losses[i] = loss
         errs[i] = e
         t += 1

@@ -2,9 +2,9 @@
 
 `FdCnn` holds the descriptor and a workspace sized for a maximum batch (allocated once
 through torch) and exposes forward, backward (parameter gradient for a given output
-gradient) and a training loop against a target (MSE, Adam on the device) — the loss of
-the paper's supervised training needs the precoder/channel chain around the network,
-which is not part of this build, so the loop takes the target symbols directly.
+gradient) and a training loop against given target symbols (MSE, Adam on the device).
+The paper's supervised training with the loss at the receiver, through ZF precoding,
+PAs and channel, is `downlink.train_receiver` with an FdCnn.
 """
 from __future__ import annotations
 

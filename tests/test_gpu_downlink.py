@@ -374,3 +374,46 @@ def test_fdnn_receiver_training_matches_oracle():
     got = w.cpu().numpy().astype(np.float64)
     assert np.linalg.norm((got - w0) - (wr - w0)) <= 1e-2 * np.linalg.norm(wr - w0)
     assert errs.shape == (steps, U)
+
+
+def test_fdcnn_receiver_training_matches_oracle():
+    """The FD-CNN (Sec. IV-C: each UE's data symbols on a side x side grid) trained at the
+    receiver through data-only ZF precoding, PAs and channel: three device Adam steps
+    against the FP64 loop (oracle FD-CNN, precoding, link and their adjoints, Adam)."""
+    import oracle.adam as OA
+    import oracle.fdcnn as OF
+    N, n_d, U, B, T, qam, spc, n_sym, pa = 256, 96, 4, 8, 4, 16, 2, 4, (5, 2, 1)
+    side, n_conv, kc, steps, lr = 10, 2, 3, 3, 1e-3
+    announce("fdcnn receiver training")
+    inp = _link_inputs((N, n_d, U, B, T, qam, spc, n_sym, pa, None))
+    w0 = S.xavier_fdcnn(n_d, side, n_conv, kc, 5)
+    dl = D.Downlink(N, n_d, U, B, T, qam, pa=pa)
+    net = D.FdCnn(n_d, side, n_conv, kc, max_items=n_sym * U)
+    s = H.to_dev(inp["s"])
+    pt, alpha = dl.zf(H.to_dev(inp["he"]), inp["p_total"])
+    w = H.to_dev(w0)
+    tx = torch.from_numpy(inp["idx"]).cuda()
+    losses, _, _ = D.train_receiver(dl, net, s, tx, w, pt, alpha, H.to_dev(inp["pa"]), 1.0, H.to_dev(inp["h"]),
+                                    steps, lr=lr, sym_per_ch=spc)
+    torch.cuda.synchronize()
+    ref_pt, ref_alpha = O.zf_precoder(_c(inp["he"]), N, n_d, inp["p_total"])
+    db = O.data_bins(N, n_d)
+    n = n_sym * U * n_d
+    zero = np.zeros((n_sym, U, N), dtype=complex)
+    s_data = _c(inp["s"])[:, :, db]
+    wr, m, v = w0.astype(np.float64), np.zeros(w0.size), np.zeros(w0.size)
+    ref_losses = []
+    for t in range(1, steps + 1):
+        out, cache = OF.forward(s_data.reshape(n_sym * U, n_d), wr, n_d, side, n_conv, kc)
+        vf = np.zeros((n_sym, U, N), dtype=complex)
+        vf[:, :, db] = out.reshape(n_sym, U, n_d)
+        ref_x = O.precode(vf, ref_pt, ref_alpha, n_d, False, spc)
+        ref_r, _, _ = O.link(ref_x, _c(inp["h"]), ref_alpha, inp["pa"], pa, 1.0, zero, inp["idx"], qam, n_d, spc)
+        e = ref_r - s_data
+        ref_losses.append(float(np.sum(np.abs(e) ** 2) / n))
+        gx = O.link_backward(2.0 * e / n, ref_x, _c(inp["h"]), ref_alpha, inp["pa"], pa, 1.0, n_d, spc)
+        gv = O.precode_backward(gx, ref_pt, ref_alpha, n_d, False, spc)[:, :, db].reshape(n_sym * U, n_d)
+        wr, m, v = OA.adam_step(wr, m, v, OF.backward(gv, cache, n_d, side, n_conv, kc), t, lr=lr)
+    np.testing.assert_allclose(losses.cpu().numpy(), ref_losses, rtol=1e-4)
+    got = w.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm((got - w0) - (wr - w0)) <= 1e-2 * np.linalg.norm(wr - w0)
