@@ -136,3 +136,16 @@ def test_planted_mistakes_are_caught(monkeypatch, mistake):
         except AssertionError:
             caught += 1
     assert caught > 0
+
+
+def test_identity_start_of_the_receiver_training_is_the_identity():
+    """The FD-CNN identity weights of the receiver-side training driver map unit-energy
+    256-QAM symbol vectors to themselves exactly (checked with the oracle's forward)."""
+    import dpd_synth as S
+    from paper_2205_05158_amd.train_downlink import identity_fdcnn
+    n_d, side, kc = 384, 20, 3
+    w = identity_fdcnn(n_d, side, kc)
+    s = S.fdcnn_symbols(6, n_d, 256, seed=2)
+    z = s[..., 0].astype(np.float64) + 1j * s[..., 1]
+    out, _ = F.forward(z, w, n_d, side, 2, kc)
+    np.testing.assert_allclose(out, z, atol=1e-6)
