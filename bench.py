@@ -579,13 +579,14 @@ def bench_downlink(args):
                                "traffic": profiled_traffic(args.workload, dom), "kernel": dom,
                                "kernel_ms": per_k[dom], "flops_per_row": fl_row, "rows_per_launch": rows}
         else:
+            # ZF on the data subcarriers only (the link precodes no guard subcarrier)
             zf_f = 8 * U * B * T + 8 * U * U * B + 16 * U ** 3 + 8 * B * U * U
-            ach = zf_f * N * n_ch / (per_k[dom] / 1e3) / 1e12
+            ach = zf_f * n_d * n_ch / (per_k[dom] / 1e3) / 1e12
             out["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK["mfma_fp64_tflops"],
                                "unit": "TFLOP/s", "frac": ach / PEAK["mfma_fp64_tflops"],
                                "traffic": profiled_traffic(args.workload, dom), "kernel": dom,
                                "kernel_ms": per_k[dom], "flops_per_subcarrier": zf_f,
-                               "subcarriers_per_launch": N * n_ch}
+                               "subcarriers_per_launch": n_d * n_ch}
         errs = int(state["err"].sum())
         out["metric"] = "Msymbols/s of the ZF-precoded downlink (UE data symbols through ZF, precoding, PA, channel, decisions); % roofline"
         out["config"] = {"workload": args.workload, "n_sym": n_sym, "n_fft": N, "n_d": n_d, "users": U,

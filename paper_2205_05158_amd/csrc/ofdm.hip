@@ -823,38 +823,88 @@ __global__ __launch_bounds__(256) void k_chan_data(const float2* __restrict__ h,
 }
 
 // GMP of eq. (9) with cyclic delays on the LDS symbol buf (magnitudes in r), results to
-// the registers y[m] for samples tid + m kFftThreads.  coef: this antenna's [J] set.
+// the registers y[m] for samples t + m kFftThreads.  coef: this antenna's [J] set.  N is a
+// power of two, so every cyclic index is a mask.  Samples go in batches of Q with the
+// coefficient loops outside: each (wave-uniform) coefficient is read once per batch, and
+// the batch's Horner chains run side by side.
+template <int Q>
+__device__ __forceinline__ void gmp_cyclic_batch(const float2* buf, const float* r, int N,
+                                                 const float2* __restrict__ coef, int K, int M, int L, int q0,
+                                                 float2 (&y)[kFftMax / kFftThreads]) {
+  const int na = K * (M + 1), nb = (K - 1) * (M + 1) * L, sb = (M + 1) * L;
+  const int mask = N - 1;
+  int nn[Q];
+  float2 acc[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    nn[j] = threadIdx.x + (q0 + j) * kFftThreads;
+    acc[j] = make_float2(0.f, 0.f);
+  }
+  for (int l = 0; l <= M; ++l) {
+    float rl[Q];
+    float2 ul[Q], poly[Q];
+    const float2 top = coef[(K - 1) * (M + 1) + l];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const int nl = (nn[j] - l) & mask;
+      rl[j] = r[nl];
+      ul[j] = buf[nl];
+      poly[j] = top;
+    }
+    for (int k = K - 2; k >= 0; --k) {                  // Horner over k of a_{k,l} r^k
+      const float2 a = coef[k * (M + 1) + l];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) poly[j] = make_float2(fmaf(poly[j].x, rl[j], a.x), fmaf(poly[j].y, rl[j], a.y));
+    }
+    for (int g = 1; K > 1 && g <= L; ++g) {
+      const int ib = na + l * L + (g - 1), ic = ib + nb;
+      const float2 tb = coef[ib + (K - 2) * sb], tc = coef[ic + (K - 2) * sb];
+      float rb[Q], rc[Q];
+      float2 pb[Q], pc[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        rb[j] = r[(nn[j] - l - g) & mask];
+        rc[j] = r[(nn[j] - l + g) & mask];
+        pb[j] = tb;
+        pc[j] = tc;
+      }
+      for (int k = K - 2; k >= 1; --k) {                // b_{k,l,g}, c_{k,l,g} at k - 1 of [K-1]
+        const float2 bb = coef[ib + (k - 1) * sb], cc = coef[ic + (k - 1) * sb];
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          pb[j] = make_float2(fmaf(pb[j].x, rb[j], bb.x), fmaf(pb[j].y, rb[j], bb.y));
+          pc[j] = make_float2(fmaf(pc[j].x, rc[j], cc.x), fmaf(pc[j].y, rc[j], cc.y));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < Q; ++j)
+        poly[j] = make_float2(fmaf(pb[j].x, rb[j], fmaf(pc[j].x, rc[j], poly[j].x)),
+                              fmaf(pb[j].y, rb[j], fmaf(pc[j].y, rc[j], poly[j].y)));
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) acc[j] = cadd(acc[j], cmul(ul[j], poly[j]));
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) y[q0 + j] = acc[j];
+}
+
 __device__ void gmp_cyclic_lds(const float2* buf, const float* r, int N, const float2* __restrict__ coef,
                                int K, int M, int L, float2 (&y)[kFftMax / kFftThreads]) {
-  const int na = K * (M + 1), nb = (K - 1) * (M + 1) * L;
+  constexpr int kQ = 8;
+  constexpr int kMaxQ = kFftMax / kFftThreads;
+  const int nq = (N + kFftThreads - 1) / kFftThreads;  // samples per thread (<= 16)
+  // fully unrolled, so that y is indexed by constants only (a runtime index would put it
+  // in scratch memory)
 #pragma unroll
-  for (int m = 0; m < kFftMax / kFftThreads; ++m) {
-    const int n = threadIdx.x + m * kFftThreads;
-    if (n >= N) break;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int l = 0; l <= M; ++l) {
-      const int nl = ((n - l) % N + N) % N;
-      const float2 ul = buf[nl];
-      const float rl = r[nl];
-      float2 poly = coef[(K - 1) * (M + 1) + l];            // Horner over k of a_{k,l} r^k
-      for (int k = K - 2; k >= 0; --k) {
-        const float2 a = coef[k * (M + 1) + l];
-        poly = make_float2(fmaf(poly.x, rl, a.x), fmaf(poly.y, rl, a.y));
-      }
-      for (int g = 1; K > 1 && g <= L; ++g) {
-        const float rb = r[((nl - g) % N + N) % N], rc = r[(nl + g) % N];
-        const int ib = na + l * L + (g - 1), ic = ib + nb;
-        float2 pb = coef[ib + (K - 2) * (M + 1) * L], pc = coef[ic + (K - 2) * (M + 1) * L];
-        for (int k = K - 2; k >= 1; --k) {                  // b_{k,l,g} at k - 1 of [K-1]
-          const float2 bb = coef[ib + (k - 1) * (M + 1) * L], cc = coef[ic + (k - 1) * (M + 1) * L];
-          pb = make_float2(fmaf(pb.x, rb, bb.x), fmaf(pb.y, rb, bb.y));
-          pc = make_float2(fmaf(pc.x, rc, cc.x), fmaf(pc.y, rc, cc.y));
-        }
-        poly = make_float2(fmaf(pb.x, rb, fmaf(pc.x, rc, poly.x)), fmaf(pb.y, rb, fmaf(pc.y, rc, poly.y)));
-      }
-      acc = cadd(acc, cmul(ul, poly));
+  for (int q0 = 0; q0 < kMaxQ; q0 += kQ) {
+    if (q0 + kQ <= nq) {
+      gmp_cyclic_batch<kQ>(buf, r, N, coef, K, M, L, q0, y);
+    } else if (q0 < nq) {
+      // short symbols: one sample at a time (thread t's samples t + 256 q below N only)
+#pragma unroll
+      for (int q = q0; q < q0 + kQ; ++q)
+        if (q < nq && threadIdx.x + q * kFftThreads < N) gmp_cyclic_batch<1>(buf, r, N, coef, K, M, L, q, y);
     }
-    y[m] = acc;
   }
 }
 
@@ -1039,6 +1089,7 @@ __device__ void gmp_cyclic_bwd_lds(const float2* x, const float* r, const float2
                                    float2 (&g)[kFftMax / kFftThreads]) {
   const int na = K * (M + 1), nb = (K - 1) * (M + 1) * L;
   const int sb = (M + 1) * L;                  // stride of k in the b / c blocks
+  const int mask = N - 1;                      // N is a power of two: cyclic index = mask
 #pragma unroll
   for (int q = 0; q < kFftMax / kFftThreads; ++q) {
     const int m = threadIdx.x + q * kFftThreads;
@@ -1048,7 +1099,7 @@ __device__ void gmp_cyclic_bwd_lds(const float2* x, const float* r, const float2
     float2 hol = make_float2(0.f, 0.f);
     float env = 0.f;
     for (int l = 0; l <= M; ++l) {
-      const float2 gyl = gy[(m + l) % N];
+      const float2 gyl = gy[(m + l) & mask];
       // Q_l(m) and the derivative of its a-part in r[m]
       float2 poly = coef[(K - 1) * (M + 1) + l];
       float2 dpa = make_float2(0.f, 0.f);
@@ -1067,7 +1118,7 @@ __device__ void gmp_cyclic_bwd_lds(const float2* x, const float* r, const float2
       }
       for (int gg = 1; K > 1 && gg <= L; ++gg) {
         const int ib = na + l * L + (gg - 1), ic = ib + nb;
-        const float rb = r[((m - gg) % N + N) % N], rc = r[(m + gg) % N];
+        const float rb = r[(m - gg) & mask], rc = r[(m + gg) & mask];
         float2 pb = coef[ib + (K - 2) * sb], pc = coef[ic + (K - 2) * sb];
         float2 db = make_float2((float)(K - 1) * pb.x, (float)(K - 1) * pb.y);
         float2 dc = make_float2((float)(K - 1) * pc.x, (float)(K - 1) * pc.y);
@@ -1080,12 +1131,12 @@ __device__ void gmp_cyclic_bwd_lds(const float2* x, const float* r, const float2
         }
         poly = make_float2(fmaf(pb.x, rb, fmaf(pc.x, rc, poly.x)), fmaf(pb.y, rb, fmaf(pc.y, rc, poly.y)));
         // envelope sample m of b_{k,l,g}: n = m + l + g, multiplied sample x[m + g]
-        const float2 gyb = gy[(m + l + gg) % N];
-        const float2 wb = cmul(db, x[(m + gg) % N]);
+        const float2 gyb = gy[(m + l + gg) & mask];
+        const float2 wb = cmul(db, x[(m + gg) & mask]);
         env += gyb.x * wb.x + gyb.y * wb.y;
         // of c_{k,l,g}: n = m + l - g, multiplied sample x[m - g]
-        const float2 gyc = gy[((m + l - gg) % N + N) % N];
-        const float2 wc = cmul(dc, x[((m - gg) % N + N) % N]);
+        const float2 gyc = gy[(m + l - gg) & mask];
+        const float2 wc = cmul(dc, x[(m - gg) & mask]);
         env += gyc.x * wc.x + gyc.y * wc.y;
       }
       // conj(Q_l(m)) gy[m + l]
