@@ -1084,67 +1084,120 @@ __device__ void row_idft(const float2* __restrict__ src, float2* scratch, const 
 //        + x[m] / |x[m]| sum over the monomials whose envelope sample is m of
 //          k |x[m]|^(k-1) Re(conj(gy[n]) c x[n - l]),
 // Q_l(p) = sum_k a_kl r[p]^k + sum_{g,k>=1} (b_klg r[p - g]^k + c_klg r[p + g]^k).
+// Batches of Q samples with the coefficient loops outside (as gmp_cyclic_batch); N is a
+// power of two.
+template <int Q>
+__device__ __forceinline__ void gmp_cyclic_bwd_batch(const float2* x, const float* r, const float2* gy, int N,
+                                                     const float2* __restrict__ coef, int K, int M, int L, int q0,
+                                                     float2 (&g)[kFftMax / kFftThreads]) {
+  const int na = K * (M + 1), nb = (K - 1) * (M + 1) * L;
+  const int sb = (M + 1) * L;                  // stride of k in the b / c blocks
+  const int mask = N - 1;
+  int nn[Q];
+  float rm[Q], env[Q];
+  float2 xm[Q], hol[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    nn[j] = threadIdx.x + (q0 + j) * kFftThreads;
+    rm[j] = r[nn[j]];
+    xm[j] = x[nn[j]];
+    hol[j] = make_float2(0.f, 0.f);
+    env[j] = 0.f;
+  }
+  for (int l = 0; l <= M; ++l) {
+    float2 gyl[Q], poly[Q], dpa[Q];
+    const float2 top = coef[(K - 1) * (M + 1) + l];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      gyl[j] = gy[(nn[j] + l) & mask];
+      poly[j] = top;
+      dpa[j] = make_float2(0.f, 0.f);
+    }
+    // Q_l's a-part and its derivative in r[m], one pass over k
+    for (int k = K - 1; k >= 0; --k) {
+      const float2 a = coef[k * (M + 1) + l];
+      const float fk = (float)k;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        if (k >= 1) dpa[j] = make_float2(fmaf(dpa[j].x, rm[j], fk * a.x), fmaf(dpa[j].y, rm[j], fk * a.y));
+        if (k <= K - 2) poly[j] = make_float2(fmaf(poly[j].x, rm[j], a.x), fmaf(poly[j].y, rm[j], a.y));
+      }
+    }
+    // envelope of the a-monomials at m: n = m + l, multiplied sample x[m]
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const float2 w = cmul(dpa[j], xm[j]);
+      env[j] += gyl[j].x * w.x + gyl[j].y * w.y;     // Re(conj(gy) w)
+    }
+    for (int gg = 1; K > 1 && gg <= L; ++gg) {
+      const int ib = na + l * L + (gg - 1), ic = ib + nb;
+      const float2 tb = coef[ib + (K - 2) * sb], tc = coef[ic + (K - 2) * sb];
+      const float fk1 = (float)(K - 1);
+      float rb[Q], rc[Q];
+      float2 pb[Q], pc[Q], db[Q], dc[Q];
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        rb[j] = r[(nn[j] - gg) & mask];
+        rc[j] = r[(nn[j] + gg) & mask];
+        pb[j] = tb;
+        pc[j] = tc;
+        db[j] = make_float2(fk1 * tb.x, fk1 * tb.y);
+        dc[j] = make_float2(fk1 * tc.x, fk1 * tc.y);
+      }
+      for (int k = K - 2; k >= 1; --k) {
+        const float2 bb = coef[ib + (k - 1) * sb], cc = coef[ic + (k - 1) * sb];
+        const float fk = (float)k;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          pb[j] = make_float2(fmaf(pb[j].x, rb[j], bb.x), fmaf(pb[j].y, rb[j], bb.y));
+          pc[j] = make_float2(fmaf(pc[j].x, rc[j], cc.x), fmaf(pc[j].y, rc[j], cc.y));
+          db[j] = make_float2(fmaf(db[j].x, rm[j], fk * bb.x), fmaf(db[j].y, rm[j], fk * bb.y));
+          dc[j] = make_float2(fmaf(dc[j].x, rm[j], fk * cc.x), fmaf(dc[j].y, rm[j], fk * cc.y));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        poly[j] = make_float2(fmaf(pb[j].x, rb[j], fmaf(pc[j].x, rc[j], poly[j].x)),
+                              fmaf(pb[j].y, rb[j], fmaf(pc[j].y, rc[j], poly[j].y)));
+        // envelope sample m of b_{k,l,g}: n = m + l + g, multiplied sample x[m + g]
+        const float2 gyb = gy[(nn[j] + l + gg) & mask];
+        const float2 wb = cmul(db[j], x[(nn[j] + gg) & mask]);
+        env[j] += gyb.x * wb.x + gyb.y * wb.y;
+        // of c_{k,l,g}: n = m + l - g, multiplied sample x[m - g]
+        const float2 gyc = gy[(nn[j] + l - gg) & mask];
+        const float2 wc = cmul(dc[j], x[(nn[j] - gg) & mask]);
+        env[j] += gyc.x * wc.x + gyc.y * wc.y;
+      }
+    }
+    // conj(Q_l(m)) gy[m + l]
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      hol[j].x += poly[j].x * gyl[j].x + poly[j].y * gyl[j].y;
+      hol[j].y += poly[j].x * gyl[j].y - poly[j].y * gyl[j].x;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const float2 unit = rm[j] > 0.f ? make_float2(xm[j].x / rm[j], xm[j].y / rm[j]) : make_float2(0.f, 0.f);
+    g[q0 + j] = make_float2(fmaf(env[j], unit.x, hol[j].x), fmaf(env[j], unit.y, hol[j].y));
+  }
+}
+
 __device__ void gmp_cyclic_bwd_lds(const float2* x, const float* r, const float2* gy, int N,
                                    const float2* __restrict__ coef, int K, int M, int L,
                                    float2 (&g)[kFftMax / kFftThreads]) {
-  const int na = K * (M + 1), nb = (K - 1) * (M + 1) * L;
-  const int sb = (M + 1) * L;                  // stride of k in the b / c blocks
-  const int mask = N - 1;                      // N is a power of two: cyclic index = mask
+  constexpr int kQ = 8;
+  constexpr int kMaxQ = kFftMax / kFftThreads;
+  const int nq = (N + kFftThreads - 1) / kFftThreads;
 #pragma unroll
-  for (int q = 0; q < kFftMax / kFftThreads; ++q) {
-    const int m = threadIdx.x + q * kFftThreads;
-    if (m >= N) break;
-    const float rm = r[m];
-    const float2 xm = x[m];
-    float2 hol = make_float2(0.f, 0.f);
-    float env = 0.f;
-    for (int l = 0; l <= M; ++l) {
-      const float2 gyl = gy[(m + l) & mask];
-      // Q_l(m) and the derivative of its a-part in r[m]
-      float2 poly = coef[(K - 1) * (M + 1) + l];
-      float2 dpa = make_float2(0.f, 0.f);
-      for (int k = K - 1; k >= 1; --k) {
-        const float2 a = coef[k * (M + 1) + l];
-        dpa = make_float2(fmaf(dpa.x, rm, (float)k * a.x), fmaf(dpa.y, rm, (float)k * a.y));
-      }
-      for (int k = K - 2; k >= 0; --k) {
-        const float2 a = coef[k * (M + 1) + l];
-        poly = make_float2(fmaf(poly.x, rm, a.x), fmaf(poly.y, rm, a.y));
-      }
-      // envelope of the a-monomials at m: n = m + l, multiplied sample x[m]
-      {
-        const float2 w = cmul(dpa, xm);
-        env += gyl.x * w.x + gyl.y * w.y;     // Re(conj(gy) w)
-      }
-      for (int gg = 1; K > 1 && gg <= L; ++gg) {
-        const int ib = na + l * L + (gg - 1), ic = ib + nb;
-        const float rb = r[(m - gg) & mask], rc = r[(m + gg) & mask];
-        float2 pb = coef[ib + (K - 2) * sb], pc = coef[ic + (K - 2) * sb];
-        float2 db = make_float2((float)(K - 1) * pb.x, (float)(K - 1) * pb.y);
-        float2 dc = make_float2((float)(K - 1) * pc.x, (float)(K - 1) * pc.y);
-        for (int k = K - 2; k >= 1; --k) {
-          const float2 bb = coef[ib + (k - 1) * sb], cc = coef[ic + (k - 1) * sb];
-          pb = make_float2(fmaf(pb.x, rb, bb.x), fmaf(pb.y, rb, bb.y));
-          pc = make_float2(fmaf(pc.x, rc, cc.x), fmaf(pc.y, rc, cc.y));
-          db = make_float2(fmaf(db.x, rm, (float)k * bb.x), fmaf(db.y, rm, (float)k * bb.y));
-          dc = make_float2(fmaf(dc.x, rm, (float)k * cc.x), fmaf(dc.y, rm, (float)k * cc.y));
-        }
-        poly = make_float2(fmaf(pb.x, rb, fmaf(pc.x, rc, poly.x)), fmaf(pb.y, rb, fmaf(pc.y, rc, poly.y)));
-        // envelope sample m of b_{k,l,g}: n = m + l + g, multiplied sample x[m + g]
-        const float2 gyb = gy[(m + l + gg) & mask];
-        const float2 wb = cmul(db, x[(m + gg) & mask]);
-        env += gyb.x * wb.x + gyb.y * wb.y;
-        // of c_{k,l,g}: n = m + l - g, multiplied sample x[m - g]
-        const float2 gyc = gy[(m + l - gg) & mask];
-        const float2 wc = cmul(dc, x[(m - gg) & mask]);
-        env += gyc.x * wc.x + gyc.y * wc.y;
-      }
-      // conj(Q_l(m)) gy[m + l]
-      hol.x += poly.x * gyl.x + poly.y * gyl.y;
-      hol.y += poly.x * gyl.y - poly.y * gyl.x;
+  for (int q0 = 0; q0 < kMaxQ; q0 += kQ) {
+    if (q0 + kQ <= nq) {
+      gmp_cyclic_bwd_batch<kQ>(x, r, gy, N, coef, K, M, L, q0, g);
+    } else if (q0 < nq) {
+#pragma unroll
+      for (int q = q0; q < q0 + kQ; ++q)
+        if (q < nq && threadIdx.x + q * kFftThreads < N) gmp_cyclic_bwd_batch<1>(x, r, gy, N, coef, K, M, L, q, g);
     }
-    const float2 unit = rm > 0.f ? make_float2(xm.x / rm, xm.y / rm) : make_float2(0.f, 0.f);
-    g[q] = make_float2(fmaf(env, unit.x, hol.x), fmaf(env, unit.y, hol.y));
   }
 }
 
