@@ -1456,8 +1456,9 @@ bool nn_supported(const NnDims& d) {
          F <= 64 && d.hidden >= 1 && d.hidden <= 32 && (d.n_hidden == 1 || d.n_hidden == 2);
 }
 
-// Backward grid: four workgroups (eight waves) per CU; each writes one partial.
-int fdnn_bwd_groups(int cus) { return std::min(4 * cus, kFdnnMaxGroups); }
+// Backward grid: five workgroups (ten waves) per CU, as many as the LDS holds (30 KB
+// each for the paper's network); each writes one partial.
+int fdnn_bwd_groups(int cus) { return std::min(5 * cus, kFdnnMaxGroups); }
 
 bool fft_size_ok(int n) { return n >= 2 && n <= kFftMax && (n & (n - 1)) == 0; }
 
