@@ -159,6 +159,7 @@ LINK_CASES = [
     (256, 96, 3, 5, 6, 64, 3, 7, (5, 2, 1), (3, 1, 1)),    # ragged last channel block
     (4, 2, 1, 1, 1, 4, 1, 2, (2, 0, 0), None),             # degenerate: N = 4, one UE, one antenna
     (4096, 384, 8, 32, 10, 256, 2, 4, (7, 3, 1), None),    # the paper's link
+    (4096, 384, 4, 16, 10, 64, 1, 2, (7, 3, 1), (5, 2, 1)),  # 4096-point path with a TD-GMP DPD
 ]
 
 
