@@ -43,6 +43,9 @@ DL_WORKLOADS = {
     "fdnn_rx_8u32b": dict(kind="fdnn_rx", n_sym=64, sym_per_ch=1, n_fft=4096, n_d=384, users=8, antennas=32,
                           taps=10, eta=1e-4, qam=256, pa=(7, 3, 1), pa_scale=0.05, rms=0.3, memory=3, hidden=15,
                           n_hidden=1, cpu_sym=16),
+    "fdcnn_rx_8u32b": dict(kind="fdcnn_rx", n_sym=64, sym_per_ch=1, n_fft=4096, n_d=384, users=8, antennas=32,
+                           taps=10, eta=1e-4, qam=256, pa=(7, 3, 1), pa_scale=0.05, rms=0.3, side=20, n_conv=2,
+                           kc=3, cpu_sym=16),
     "link_8u32b": dict(kind="link", n_sym=64, sym_per_ch=1, n_fft=4096, n_d=384, users=8, antennas=32,
                        taps=10, eta=1e-4, n0=1e-3, qam=256, pa=(7, 3, 1), pa_scale=0.05, rms=0.3,
                        cpu_sym=64),
@@ -476,6 +479,29 @@ def bench_downlink(args):
             state["t"] += 1
             D.dpd_adam_step(dw, w, m_, v_, state["t"], lr=1e-3)
             state["loss"] = loss
+    elif spec["kind"] == "fdcnn_rx":
+        B, T, spc = spec["antennas"], spec["taps"], spec["sym_per_ch"]
+        side, n_conv, kc = spec["side"], spec["n_conv"], spec["kc"]
+        n_ch = -(-n_sym // spc)
+        idx, s_np = S.downlink_symbols(n_sym, U, N, n_d, spec["qam"], 1)
+        h_np, he_np = S.mimo_channel(n_ch, T, U, B, spec["eta"], 2)
+        pa_np = S.antenna_pa_coefficients(B, *spec["pa"], 10, scale=spec["pa_scale"])
+        w_np = S.xavier_fdcnn(n_d, side, n_conv, kc, 4)
+        s, h, he, pa = dev(s_np), dev(h_np), dev(he_np), dev(pa_np)
+        tx = torch.from_numpy(idx).cuda()
+        p_total = spec["rms"] ** 2 * B * N / n_d
+        dl = D.Downlink(N, n_d, U, B, T, spec["qam"], pa=spec["pa"])
+        net = D.FdCnn(n_d, side, n_conv, kc, max_items=n_sym * U)
+        w = dev(w_np)
+        m_, v_ = torch.zeros_like(w), torch.zeros_like(w)
+        state["t"] = 0
+
+        def step():
+            pt, alpha = dl.zf(he, p_total)
+            loss, dw, _ = D.receiver_loss_grad_fdcnn(dl, net, s, tx, w, pt, alpha, pa, 1.0, h, spc)
+            state["t"] += 1
+            D.dpd_adam_step(dw, w, m_, v_, state["t"], lr=1e-3)
+            state["loss"] = loss
     else:
         B, T, spc = spec["antennas"], spec["taps"], spec["sym_per_ch"]
         n_ch = -(-n_sym // spc)
@@ -536,7 +562,7 @@ def bench_downlink(args):
                          "memory": L4, "hidden": Dh, "n_hidden": nh, "qam": spec["qam"],
                          "step": "fdnn_forward + fdnn_backward", "parallelism": "single GPU"}
         out["paper_flops_per_ue_symbol_eq14"] = FL.fd_nn_per_ue_symbol(N, n_d, 32, U, L4, Dh, nh)
-    elif spec["kind"] == "fdnn_rx":
+    elif spec["kind"] in ("fdnn_rx", "fdcnn_rx"):
         K, M, Lg = spec["pa"]
         rows = n_sym * B
         # reverse mode of the PA per sample: two passes of the forward monomials (the
@@ -545,12 +571,13 @@ def bench_downlink(args):
         dom = max(("zf", "link_pa_bwd"), key=lambda k: per_k[k] * kern[k][0])
         if dom == "zf":
             zf_f = 8 * U * B * T + 8 * U * U * B + 16 * U ** 3 + 8 * B * U * U
-            ach = zf_f * N * n_ch / (per_k[dom] / 1e3) / 1e12
+            nb_zf = N if spec["kind"] == "fdnn_rx" else n_d      # FD-CNN: data subcarriers only
+            ach = zf_f * nb_zf * n_ch / (per_k[dom] / 1e3) / 1e12
             out["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK["mfma_fp64_tflops"],
                                "unit": "TFLOP/s", "frac": ach / PEAK["mfma_fp64_tflops"],
                                "traffic": profiled_traffic(args.workload, dom), "kernel": dom,
                                "kernel_ms": per_k[dom], "flops_per_subcarrier": zf_f,
-                               "subcarriers_per_launch": N * n_ch, "note": "FP64, every subcarrier (guard-band precoding)"}
+                               "subcarriers_per_launch": nb_zf * n_ch, "note": "FP64"}
         elif dom == "link_pa_bwd":
             ach = fl_row * rows / (per_k[dom] / 1e3) / 1e12
             out["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK["valu_fp32_tflops"], "unit": "TFLOP/s",
@@ -558,14 +585,24 @@ def bench_downlink(args):
                                "traffic": profiled_traffic(args.workload, dom), "kernel": dom,
                                "kernel_ms": per_k[dom], "flops_per_row": fl_row, "rows_per_launch": rows,
                                "note": "per antenna row: IDFT x2, PA reverse mode, DFT"}
-        out["metric"] = ("Msymbols/s of receiver-side FD-NN training (FD-NN, guard-band ZF precoding, PAs, "
-                         "channel, loss at the receiver, reverse mode, Adam); % roofline")
-        out["config"] = {"workload": args.workload, "n_sym": n_sym, "n_fft": N, "n_d": n_d, "users": U,
-                         "antennas": B, "taps": T, "qam": spec["qam"], "pa": list(spec["pa"]), "memory": L4,
-                         "hidden": Dh, "n_hidden": nh, "sym_per_ch": spc,
-                         "step": "zf_precoder(all bins) + fdnn_forward + ofdm_precode + ofdm_link + "
-                                 "ofdm_link_backward + ofdm_precode_backward + fdnn_backward + dpd_adam_step",
-                         "parallelism": "single GPU"}
+        if spec["kind"] == "fdnn_rx":
+            out["metric"] = ("Msymbols/s of receiver-side FD-NN training (FD-NN, guard-band ZF precoding, PAs, "
+                             "channel, loss at the receiver, reverse mode, Adam); % roofline")
+            out["config"] = {"workload": args.workload, "n_sym": n_sym, "n_fft": N, "n_d": n_d, "users": U,
+                             "antennas": B, "taps": T, "qam": spec["qam"], "pa": list(spec["pa"]), "memory": L4,
+                             "hidden": Dh, "n_hidden": nh, "sym_per_ch": spc,
+                             "step": "zf_precoder(all bins) + fdnn_forward + ofdm_precode + ofdm_link + "
+                                     "ofdm_link_backward + ofdm_precode_backward + fdnn_backward + dpd_adam_step",
+                             "parallelism": "single GPU"}
+        else:
+            out["metric"] = ("Msymbols/s of receiver-side FD-CNN training (FD-CNN, data-subcarrier ZF precoding, "
+                             "PAs, channel, loss at the receiver, reverse mode, Adam); % roofline")
+            out["config"] = {"workload": args.workload, "n_sym": n_sym, "n_fft": N, "n_d": n_d, "users": U,
+                             "antennas": B, "taps": T, "qam": spec["qam"], "pa": list(spec["pa"]),
+                             "side": spec["side"], "n_conv": spec["n_conv"], "kc": spec["kc"], "sym_per_ch": spc,
+                             "step": "zf_precoder(data) + fdcnn_forward + ofdm_precode + ofdm_link + "
+                                     "ofdm_link_backward + ofdm_precode_backward + fdcnn_backward + dpd_adam_step",
+                             "parallelism": "single GPU"}
         out["loss_last_step"] = float(state["loss"])
     else:
         K, M, Lg = spec["pa"]
@@ -619,6 +656,28 @@ def bench_downlink(args):
             gx_r = OO.link_backward(2.0 * e_r / nn_, x_r, cx(h_np[:nch]), al_r, pa_np, spec["pa"], 1.0, n_d, spc)
             dw_r = OO.fdnn_backward(OO.precode_backward(gx_r, pt_r, al_r, n_d, True, spc), cache, U, L4)
             OA.adam_step(w_np, np.zeros(w_np.size), np.zeros(w_np.size), dw_r, 1)
+        elif spec["kind"] == "fdcnn_rx":
+            import oracle.adam as OA
+            import oracle.fdcnn as OFC
+            nch = -(-ns // spc)
+            pt_r, al_r = OO.zf_precoder(cx(he_np[:nch]), N, n_d, p_total)
+            db = OO.data_bins(N, n_d)
+            sd = cx(s_np[:ns])[:, :, db]
+            shp = dict(n_d=n_d, side=spec["side"], n_conv=spec["n_conv"], kc=spec["kc"])
+            o_r, cache = OFC.forward(sd.reshape(ns * U, n_d), w_np, **shp)
+            vf = np.zeros((ns, U, N), dtype=complex)
+            vf[:, :, db] = o_r.reshape(ns, U, n_d)
+            x_r = OO.precode(vf, pt_r, al_r, n_d, False, spc)
+            zero = np.zeros((ns, U, N), dtype=complex)
+            r_r, _, _ = OO.link(x_r, cx(h_np[:nch]), al_r, pa_np, spec["pa"], 1.0, zero, idx[:ns], spec["qam"], n_d,
+                                spc)
+            e_r = r_r - sd
+            nn_ = ns * U * n_d
+            loss_r = float(np.sum(np.abs(e_r) ** 2) / nn_)
+            gx_r = OO.link_backward(2.0 * e_r / nn_, x_r, cx(h_np[:nch]), al_r, pa_np, spec["pa"], 1.0, n_d, spc)
+            gv = OO.precode_backward(gx_r, pt_r, al_r, n_d, False, spc)[:, :, db].reshape(ns * U, n_d)
+            dw_r = OFC.backward(gv, cache, **shp)
+            OA.adam_step(w_np, np.zeros(w_np.size), np.zeros(w_np.size), dw_r, 1)
         else:
             pt_r, al_r = OO.zf_precoder(cx(he_np[:-(-ns // spc)]), N, n_d, p_total)
             x_r = OO.precode(cx(s_np[:ns]), pt_r, al_r, n_d, False, spc)
@@ -629,12 +688,18 @@ def bench_downlink(args):
                                "kind": "oracle",
                                "sample": f"first {ns} of {n_sym} OFDM symbols; FP64 NumPy; BLAS threads "
                                          f"{threads}; {dt:.2f} s"}
-        if spec["kind"] == "fdnn_rx":
+        if spec["kind"] in ("fdnn_rx", "fdcnn_rx"):
             nch = -(-ns // spc)
-            snet = D.FdNn(N, U, L4, Dh, nh, max_sym=ns)
-            pt2, al2 = dl.zf(he[:nch].contiguous(), p_total, all_bins=True)
-            l2, d2, _ = D.receiver_loss_grad(dl, snet, s[:ns].contiguous(), tx[:ns].contiguous(), dev(w_np), pt2, al2,
-                                             pa, 1.0, h[:nch].contiguous(), spc)
+            if spec["kind"] == "fdnn_rx":
+                snet = D.FdNn(N, U, L4, Dh, nh, max_sym=ns)
+                pt2, al2 = dl.zf(he[:nch].contiguous(), p_total, all_bins=True)
+                crit = D.receiver_loss_grad
+            else:
+                snet = D.FdCnn(n_d, spec["side"], spec["n_conv"], spec["kc"], max_items=ns * U)
+                pt2, al2 = dl.zf(he[:nch].contiguous(), p_total)
+                crit = D.receiver_loss_grad_fdcnn
+            l2, d2, _ = crit(dl, snet, s[:ns].contiguous(), tx[:ns].contiguous(), dev(w_np), pt2, al2,
+                             pa, 1.0, h[:nch].contiguous(), spc)
             d2 = d2.cpu().double().numpy()
             out["parity"] = {"sample_sym": ns, "loss_gpu": float(l2), "loss_oracle": loss_r,
                              "grad_rel_err": float(np.linalg.norm(d2 - dw_r) / np.linalg.norm(dw_r))}
