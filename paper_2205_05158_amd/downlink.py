@@ -1,11 +1,14 @@
 """Multi-user OFDM downlink on the device (Sec. II-A, Sec. III-C): the FD-NN DPD and the
-ZF-precoded link with per-antenna PAs, channel, noise and QAM decisions.
+ZF-precoded link with per-antenna PAs, channel, noise and QAM decisions, their reverse
+modes, and the receiver-side training of the frequency-domain DPDs (Sec. V-A-2).
 
 `FdNn` holds the FD-NN descriptor and a workspace sized for a maximum number of OFDM
 symbols; `FdNnFn` makes its output a torch.autograd.Function of the packed weights.
-`Downlink` holds a link descriptor and runs ZF precoding, precoding and the link (the
-symbol error count per UE).  All arrays are contiguous float32 device tensors with a
-trailing (re, im) axis, except the int32 transmitted QAM indices.
+`Downlink` holds a link descriptor and runs ZF precoding, precoding, the link (the
+symbol error count per UE) and the adjoints of the last two.  `receiver_loss_grad*` and
+`train_receiver` compose them into the supervised criterion and its Adam loop.  All
+arrays are contiguous float32 device tensors with a trailing (re, im) axis, except the
+int32 transmitted QAM indices.
 """
 from __future__ import annotations
 
@@ -110,10 +113,22 @@ class Downlink:
         L.ofdm_precode(self.desc, n, sym_per_ch, pt, alpha, s, all_bins, x)
         return x
 
+    def _check_coef(self, coef, orders, name):
+        K, M, L_ = orders
+        J = K * (M + 1) + 2 * (K - 1) * (M + 1) * L_
+        _check_c(coef, (self.antennas, J, 2), name)
+
     def link(self, x, pa_coef, g, h, alpha, tx, noise=None, dpd_coef=None, sym_per_ch=1, want_r=False):
         """-> (symbol errors per UE int64 [U], equalised symbols [n_sym][U][n_data][2] or None)."""
         n = x.shape[0]
         _check_c(x, (n, self.antennas, self.n_fft, 2), "x")
+        self._check_coef(pa_coef, (self.desc.pa.K, self.desc.pa.M, self.desc.pa.L), "pa_coef")
+        if self.desc.dpd.K:
+            if dpd_coef is None:
+                raise ValueError("this link has a DPD: dpd_coef is required")
+            self._check_coef(dpd_coef, (self.desc.dpd.K, self.desc.dpd.M, self.desc.dpd.L), "dpd_coef")
+        if noise is not None:
+            _check_c(noise, (n, self.users, self.n_fft, 2), "noise")
         self._check_channels(None, alpha, n, sym_per_ch, h)
         if tx.dtype != torch.int32 or tuple(tx.shape) != (n, self.users, self.n_data) or not tx.is_contiguous():
             raise ValueError("tx: expected contiguous int32 [n_sym][U][n_data]")
@@ -131,6 +146,7 @@ class Downlink:
         n = x.shape[0]
         _check_c(x, (n, self.antennas, self.n_fft, 2), "x")
         _check_c(g_r, (n, self.users, self.n_data, 2), "g_r")
+        self._check_coef(pa_coef, (self.desc.pa.K, self.desc.pa.M, self.desc.pa.L), "pa_coef")
         self._check_channels(None, alpha, n, sym_per_ch, h)
         g_x = torch.empty_like(x)
         ws = torch.empty(max(L.link_workspace_size(self.desc, n, sym_per_ch), 256), dtype=torch.uint8,
