@@ -754,17 +754,14 @@ __global__ __launch_bounds__(256) void k_zf_alpha(const double* __restrict__ tra
 __global__ __launch_bounds__(256) void k_precode(const float2* __restrict__ pt, const float* __restrict__ alpha,
                                                  const float2* __restrict__ s, int N, int n_d, int U, int B,
                                                  int spc, int all_bins, int vec, float2* __restrict__ x) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
+  // thread -> subcarrier k (all_bins) or data symbol (the guard subcarriers were zeroed
+  // beforehand by zero_complex: per-thread zero loops at a stride of N were several times slower)
+  const int e = blockIdx.x * 256 + threadIdx.x;
   const int i = blockIdx.y;
-  if (k >= N) return;
+  if (e >= (all_bins ? N : n_d)) return;
+  const int k = all_bins ? e : data_bin(e, N, n_d);
   const int c = i / spc;
-  const int h = n_d / 2;
-  const bool on = all_bins || (k >= 1 && k <= h) || (k >= N - h);
   float2* xi = x + (int64_t)i * B * N + k;
-  if (!on) {
-    for (int b = 0; b < B; ++b) xi[(int64_t)b * N] = make_float2(0.f, 0.f);
-    return;
-  }
   float2 sv[kZfMaxU];
 #pragma unroll
   for (int u = 0; u < kZfMaxU; ++u)
@@ -1007,20 +1004,17 @@ __device__ __forceinline__ int data_index(int k, int N, int n_d) {
   return -1;
 }
 
-// g_y[i][b][k] = sum_u conj(H_k[u][b]) conj(1 / (alpha G)) g_r[i][u][d(k)] on data
-// subcarriers, 0 on guard subcarriers (adjoint of channel and equalisation).
+// g_y[i][b][k_d] = sum_u conj(H_k[u][b]) conj(1 / (alpha G)) g_r[i][u][d] for data symbol
+// d (adjoint of channel and equalisation); one thread per (symbol, data symbol), as the
+// receiver.  The guard subcarriers of g_y are zeroed beforehand by zero_complex.
 __global__ __launch_bounds__(256) void k_link_rx_bwd(const float2* __restrict__ hd, const float* __restrict__ alpha,
                                                      float g_re, float g_im, const float2* __restrict__ g_r, int N,
                                                      int n_d, int U, int B, int spc, float2* __restrict__ g_y) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
+  const int d = blockIdx.x * 256 + threadIdx.x;
   const int i = blockIdx.y;
-  if (k >= N) return;
+  if (d >= n_d) return;
+  const int k = data_bin(d, N, n_d);
   float2* gi = g_y + (int64_t)i * B * N + k;
-  const int d = data_index(k, N, n_d);
-  if (d < 0) {
-    for (int b = 0; b < B; ++b) gi[(int64_t)b * N] = make_float2(0.f, 0.f);
-    return;
-  }
   const int c = i / spc;
   // conj(1 / (alpha G)) = G / (alpha |G|^2)
   const float den = alpha[c] * (g_re * g_re + g_im * g_im);
@@ -1042,6 +1036,25 @@ __global__ __launch_bounds__(256) void k_link_rx_bwd(const float2* __restrict__ 
       }
     }
     gi[(int64_t)b * N] = acc;
+  }
+}
+
+// p[0, n) = 0 (grid-stride; V = float4 for 16-byte aligned buffers, else float2).
+template <typename V>
+__global__ __launch_bounds__(256) void k_zero(V* __restrict__ p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) p[e] = V{};
+}
+
+// Zeroes n2 complex values (float2) at p: 16-byte stores when p is 16-byte aligned and n2 even.
+static void zero_complex(float* p, int64_t n2, hipStream_t s) {
+  if (n2 <= 0) return;
+  if ((uintptr_t)p % 16 == 0 && n2 % 2 == 0) {
+    const int64_t n4 = n2 / 2;
+    k_zero<float4><<<(unsigned)std::min<int64_t>((n4 + 255) / 256, 8192), 256, 0, s>>>(reinterpret_cast<float4*>(p),
+                                                                                       n4);
+  } else {
+    k_zero<float2><<<(unsigned)std::min<int64_t>((n2 + 255) / 256, 8192), 256, 0, s>>>(reinterpret_cast<float2*>(p),
+                                                                                       n2);
   }
 }
 
@@ -1254,48 +1267,47 @@ __global__ __launch_bounds__(kFftThreads) void k_link_pa_bwd(const float2* __res
 __global__ __launch_bounds__(256) void k_precode_bwd(const float2* __restrict__ pt, const float* __restrict__ alpha,
                                                      const float2* __restrict__ g_x, int N, int n_d, int U, int B,
                                                      int spc, int all_bins, int vec, float2* __restrict__ g_s) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
+  // thread -> subcarrier k (all_bins) or data symbol; guard subcarriers zeroed beforehand
+  const int e = blockIdx.x * 256 + threadIdx.x;
   const int i = blockIdx.y;
-  if (k >= N) return;
+  if (e >= (all_bins ? N : n_d)) return;
+  const int k = all_bins ? e : data_bin(e, N, n_d);
   const int c = i / spc;
-  const bool on = all_bins || data_index(k, N, n_d) >= 0;
   float2 acc[kZfMaxU];
 #pragma unroll
   for (int u = 0; u < kZfMaxU; ++u) acc[u] = make_float2(0.f, 0.f);
-  if (on) {
-    const float2* pk = pt + ((int64_t)c * N + k) * B * U;
-    const float2* gx = g_x + (int64_t)i * B * N + k;
-    if (vec) {
-      // even U and a 16-byte aligned pt: Pt_k rows as U/2 aligned pairs
-      const float4* pk4 = reinterpret_cast<const float4*>(pk);
-      for (int b = 0; b < B; ++b) {
-        const float2 v = gx[(int64_t)b * N];
+  const float2* pk = pt + ((int64_t)c * N + k) * B * U;
+  const float2* gx = g_x + (int64_t)i * B * N + k;
+  if (vec) {
+    // even U and a 16-byte aligned pt: Pt_k rows as U/2 aligned pairs
+    const float4* pk4 = reinterpret_cast<const float4*>(pk);
+    for (int b = 0; b < B; ++b) {
+      const float2 v = gx[(int64_t)b * N];
 #pragma unroll
-        for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
-          if (2 * u2 < U) {
-            const float4 p = pk4[b * (U / 2) + u2];
-            acc[2 * u2].x += p.x * v.x + p.y * v.y;     // conj(p) v
-            acc[2 * u2].y += p.x * v.y - p.y * v.x;
-            acc[2 * u2 + 1].x += p.z * v.x + p.w * v.y;
-            acc[2 * u2 + 1].y += p.z * v.y - p.w * v.x;
-          }
+      for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
+        if (2 * u2 < U) {
+          const float4 p = pk4[b * (U / 2) + u2];
+          acc[2 * u2].x += p.x * v.x + p.y * v.y;     // conj(p) v
+          acc[2 * u2].y += p.x * v.y - p.y * v.x;
+          acc[2 * u2 + 1].x += p.z * v.x + p.w * v.y;
+          acc[2 * u2 + 1].y += p.z * v.y - p.w * v.x;
         }
       }
-    } else {
-      for (int b = 0; b < B; ++b) {
-        const float2 v = gx[(int64_t)b * N];
+    }
+  } else {
+    for (int b = 0; b < B; ++b) {
+      const float2 v = gx[(int64_t)b * N];
 #pragma unroll
-        for (int u = 0; u < kZfMaxU; ++u) {
-          if (u < U) {
-            const float2 p = pk[b * U + u];
-            acc[u].x += p.x * v.x + p.y * v.y;     // conj(p) v
-            acc[u].y += p.x * v.y - p.y * v.x;
-          }
+      for (int u = 0; u < kZfMaxU; ++u) {
+        if (u < U) {
+          const float2 p = pk[b * U + u];
+          acc[u].x += p.x * v.x + p.y * v.y;     // conj(p) v
+          acc[u].y += p.x * v.y - p.y * v.x;
         }
       }
     }
   }
-  const float a = on ? alpha[c] : 0.f;
+  const float a = alpha[c];
 #pragma unroll
   for (int u = 0; u < kZfMaxU; ++u)
     if (u < U) g_s[((int64_t)i * U + u) * N + k] = make_float2(a * acc[u].x, a * acc[u].y);
@@ -1502,7 +1514,8 @@ void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, i
 void launch_precode(const float* pt, const float* alpha, const float* sym, int N, int n_d, int U, int B,
                     int n_sym, int spc, int all_bins, float* x, hipStream_t s) {
   const int vec = (U % 2 == 0) && ((uintptr_t)pt % 16 == 0);
-  k_precode<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt), alpha,
+  if (!all_bins) zero_complex(x, (int64_t)n_sym * B * N, s);
+  k_precode<<<dim3(((all_bins ? N : n_d) + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt), alpha,
                                                          reinterpret_cast<const float2*>(sym), N, n_d, U, B,
                                                          spc, all_bins, vec, reinterpret_cast<float2*>(x));
 }
@@ -1526,9 +1539,10 @@ void launch_link_pa(const float* x, int N, int B, int64_t rows, const float* dpd
 
 void launch_link_rx_bwd(const float* hd, const float* alpha, float g_re, float g_im, const float* g_r, int N, int n_d,
                         int U, int B, int n_sym, int spc, float* g_y, hipStream_t s) {
-  k_link_rx_bwd<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(hd), alpha, g_re, g_im,
-                                                             reinterpret_cast<const float2*>(g_r), N, n_d, U, B, spc,
-                                                             reinterpret_cast<float2*>(g_y));
+  zero_complex(g_y, (int64_t)n_sym * B * N, s);
+  k_link_rx_bwd<<<dim3((n_d + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(hd), alpha, g_re,
+                                                               g_im, reinterpret_cast<const float2*>(g_r), N, n_d, U,
+                                                               B, spc, reinterpret_cast<float2*>(g_y));
 }
 
 void launch_link_pa_bwd(const float* x, const float* g_y, int N, int B, int n_sym, const float* pa,
@@ -1545,7 +1559,9 @@ void launch_link_pa_bwd(const float* x, const float* g_y, int N, int B, int n_sy
 void launch_precode_bwd(const float* pt, const float* alpha, const float* g_x, int N, int n_d, int U, int B,
                         int n_sym, int spc, int all_bins, float* g_s, hipStream_t s) {
   const int vec = (U % 2 == 0) && ((uintptr_t)pt % 16 == 0);
-  k_precode_bwd<<<dim3((N + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt), alpha,
+  if (!all_bins) zero_complex(g_s, (int64_t)n_sym * U * N, s);
+  k_precode_bwd<<<dim3(((all_bins ? N : n_d) + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt),
+                                                                               alpha,
                                                              reinterpret_cast<const float2*>(g_x), N, n_d, U, B, spc,
                                                              all_bins, vec, reinterpret_cast<float2*>(g_s));
 }
