@@ -751,46 +751,64 @@ __global__ __launch_bounds__(256) void k_zf_alpha(const double* __restrict__ tra
 }
 
 // x[i][b][k] = alpha_c sum_u Pt[c][k][b][u] s[i][u][k] on the precoded subcarriers, else 0.
+// One workgroup per (tile of tw precoded subcarriers, symbol i); the guard subcarriers are
+// zeroed beforehand by zero_complex.  Three phases: the tile's symbols into LDS; one thread per
+// (subcarrier, antenna) with the antenna fastest, so a wave reads consecutive rows of Pt; the
+// outputs leave through an LDS tile [B][tw+1] with the subcarrier fastest (contiguous
+// tw-wide runs of each antenna row of x).
+constexpr int kPcTile = 32;
+
+// Tile width in subcarriers: kPcTile, halved for more than 128 antennas so that the LDS
+// tiles stay within 64 KiB.
+inline int precode_tile(int B) { return B <= 128 ? kPcTile : kPcTile / 2; }
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_precode(const float2* __restrict__ pt, const float* __restrict__ alpha,
                                                  const float2* __restrict__ s, int N, int n_d, int U, int B,
-                                                 int spc, int all_bins, int vec, float2* __restrict__ x) {
-  // thread -> subcarrier k (all_bins) or data symbol (the guard subcarriers were zeroed
-  // beforehand by zero_complex: per-thread zero loops at a stride of N were several times slower)
-  const int e = blockIdx.x * 256 + threadIdx.x;
+                                                 int spc, int all_bins, int tw, float2* __restrict__ x) {
+  extern __shared__ float2 pc_lds[];
+  float2* st = pc_lds;                  // [kZfMaxU][tw]
+  float2* xt = pc_lds + kZfMaxU * tw;   // [B][tw + 1]
+  const int XS = tw + 1;
   const int i = blockIdx.y;
-  if (e >= (all_bins ? N : n_d)) return;
-  const int k = all_bins ? e : data_bin(e, N, n_d);
   const int c = i / spc;
-  float2* xi = x + (int64_t)i * B * N + k;
-  float2 sv[kZfMaxU];
-#pragma unroll
-  for (int u = 0; u < kZfMaxU; ++u)
-    sv[u] = u < U ? s[((int64_t)i * U + u) * N + k] : make_float2(0.f, 0.f);
+  const int e0 = blockIdx.x * tw;
+  const int nb = min(tw, (all_bins ? N : n_d) - e0);
   const float a = alpha[c];
-  const float2* pk = pt + ((int64_t)c * N + k) * B * U;
-  if (vec) {
-    // even U and a 16-byte aligned pt: each row of Pt_k is U/2 aligned 16-byte pairs
-    const float4* pk4 = reinterpret_cast<const float4*>(pk);
-    for (int b = 0; b < B; ++b) {
-      float2 acc = make_float2(0.f, 0.f);
+  const float2* si = s + (int64_t)i * U * N;
+  for (int j = threadIdx.x; j < U * tw; j += 256) {
+    const int u = j / tw, el = j % tw;
+    if (el < nb) st[j] = si[(int64_t)u * N + (all_bins ? e0 + el : data_bin(e0 + el, N, n_d))];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nb * B; j += 256) {
+    const int el = j / B, b = j - el * B;
+    const int k = all_bins ? e0 + el : data_bin(e0 + el, N, n_d);
+    const float2* row = pt + (((int64_t)c * N + k) * B + b) * U;
+    float2 acc = make_float2(0.f, 0.f);
+    if (VEC) {
+      // even U and a 16-byte aligned pt: the row is U/2 aligned 16-byte pairs
+      const float4* row4 = reinterpret_cast<const float4*>(row);
 #pragma unroll
       for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
         if (2 * u2 < U) {
-          const float4 q = pk4[b * (U / 2) + u2];
-          acc = cadd(acc, cmul(make_float2(q.x, q.y), sv[2 * u2]));
-          acc = cadd(acc, cmul(make_float2(q.z, q.w), sv[2 * u2 + 1]));
+          const float4 q = row4[u2];
+          acc = cadd(acc, cmul(make_float2(q.x, q.y), st[(2 * u2) * tw + el]));
+          acc = cadd(acc, cmul(make_float2(q.z, q.w), st[(2 * u2 + 1) * tw + el]));
         }
       }
-      xi[(int64_t)b * N] = make_float2(a * acc.x, a * acc.y);
-    }
-    return;
-  }
-  for (int b = 0; b < B; ++b) {
-    float2 acc = make_float2(0.f, 0.f);
+    } else {
 #pragma unroll
-    for (int u = 0; u < kZfMaxU; ++u)
-      if (u < U) acc = cadd(acc, cmul(pk[b * U + u], sv[u]));
-    xi[(int64_t)b * N] = make_float2(a * acc.x, a * acc.y);
+      for (int u = 0; u < kZfMaxU; ++u)
+        if (u < U) acc = cadd(acc, cmul(row[u], st[u * tw + el]));
+    }
+    xt[b * XS + el] = make_float2(a * acc.x, a * acc.y);
+  }
+  __syncthreads();
+  float2* xi = x + (int64_t)i * B * N;
+  for (int j = threadIdx.x; j < nb * B; j += 256) {
+    const int b = j / nb, el = j - b * nb;
+    xi[(int64_t)b * N + (all_bins ? e0 + el : data_bin(e0 + el, N, n_d))] = xt[b * XS + el];
   }
 }
 
@@ -1263,54 +1281,48 @@ __global__ __launch_bounds__(kFftThreads) void k_link_pa_bwd(const float2* __res
 }
 
 // g_s[i][u][k] = alpha_c sum_b conj(Pt[c][k][b][u]) g_x[i][b][k] on the precoded
-// subcarriers, 0 elsewhere (adjoint of k_precode).
+// subcarriers, 0 elsewhere (adjoint of k_precode; the guard subcarriers are zeroed beforehand).
+// Same tiling: the tile of g_x enters LDS with the subcarrier fastest, one thread per
+// (subcarrier, UE) with the UE fastest accumulates over the antennas, the outputs leave through
+// an LDS tile [U][tw+1].
 __global__ __launch_bounds__(256) void k_precode_bwd(const float2* __restrict__ pt, const float* __restrict__ alpha,
                                                      const float2* __restrict__ g_x, int N, int n_d, int U, int B,
-                                                     int spc, int all_bins, int vec, float2* __restrict__ g_s) {
-  // thread -> subcarrier k (all_bins) or data symbol; guard subcarriers zeroed beforehand
-  const int e = blockIdx.x * 256 + threadIdx.x;
+                                                     int spc, int all_bins, int tw, float2* __restrict__ g_s) {
+  extern __shared__ float2 pc_lds[];
+  const int XS = tw + 1;
+  float2* gt = pc_lds;              // [B][tw + 1]
+  float2* ot = pc_lds + B * XS;     // [kZfMaxU][tw + 1]
   const int i = blockIdx.y;
-  if (e >= (all_bins ? N : n_d)) return;
-  const int k = all_bins ? e : data_bin(e, N, n_d);
   const int c = i / spc;
-  float2 acc[kZfMaxU];
-#pragma unroll
-  for (int u = 0; u < kZfMaxU; ++u) acc[u] = make_float2(0.f, 0.f);
-  const float2* pk = pt + ((int64_t)c * N + k) * B * U;
-  const float2* gx = g_x + (int64_t)i * B * N + k;
-  if (vec) {
-    // even U and a 16-byte aligned pt: Pt_k rows as U/2 aligned pairs
-    const float4* pk4 = reinterpret_cast<const float4*>(pk);
-    for (int b = 0; b < B; ++b) {
-      const float2 v = gx[(int64_t)b * N];
-#pragma unroll
-      for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
-        if (2 * u2 < U) {
-          const float4 p = pk4[b * (U / 2) + u2];
-          acc[2 * u2].x += p.x * v.x + p.y * v.y;     // conj(p) v
-          acc[2 * u2].y += p.x * v.y - p.y * v.x;
-          acc[2 * u2 + 1].x += p.z * v.x + p.w * v.y;
-          acc[2 * u2 + 1].y += p.z * v.y - p.w * v.x;
-        }
-      }
-    }
-  } else {
-    for (int b = 0; b < B; ++b) {
-      const float2 v = gx[(int64_t)b * N];
-#pragma unroll
-      for (int u = 0; u < kZfMaxU; ++u) {
-        if (u < U) {
-          const float2 p = pk[b * U + u];
-          acc[u].x += p.x * v.x + p.y * v.y;     // conj(p) v
-          acc[u].y += p.x * v.y - p.y * v.x;
-        }
-      }
-    }
+  const int e0 = blockIdx.x * tw;
+  const int nb = min(tw, (all_bins ? N : n_d) - e0);
+  const float2* gi = g_x + (int64_t)i * B * N;
+  for (int j = threadIdx.x; j < nb * B; j += 256) {
+    const int b = j / nb, el = j - b * nb;
+    gt[b * XS + el] = gi[(int64_t)b * N + (all_bins ? e0 + el : data_bin(e0 + el, N, n_d))];
   }
+  __syncthreads();
   const float a = alpha[c];
-#pragma unroll
-  for (int u = 0; u < kZfMaxU; ++u)
-    if (u < U) g_s[((int64_t)i * U + u) * N + k] = make_float2(a * acc[u].x, a * acc[u].y);
+  for (int j = threadIdx.x; j < nb * U; j += 256) {
+    const int el = j / U, u = j - el * U;
+    const int k = all_bins ? e0 + el : data_bin(e0 + el, N, n_d);
+    const float2* col = pt + ((int64_t)c * N + k) * B * U + u;
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll 8
+    for (int b = 0; b < B; ++b) {
+      const float2 p = col[(int64_t)b * U];
+      const float2 v = gt[b * XS + el];
+      acc.x += p.x * v.x + p.y * v.y;     // conj(p) v
+      acc.y += p.x * v.y - p.y * v.x;
+    }
+    ot[u * XS + el] = make_float2(a * acc.x, a * acc.y);
+  }
+  __syncthreads();
+  float2* gs = g_s + (int64_t)i * U * N;
+  for (int j = threadIdx.x; j < nb * U; j += 256) {
+    const int u = j / nb, el = j - u * nb;
+    gs[(int64_t)u * N + (all_bins ? e0 + el : data_bin(e0 + el, N, n_d))] = ot[u * XS + el];
+  }
 }
 
 // Receiver: thread per (symbol i, data symbol d): y = H_k x_pa + w, r = y / (alpha G),
@@ -1513,11 +1525,17 @@ void launch_zf(const float* h_est, int N, int n_d, int all_bins, int U, int B, i
 
 void launch_precode(const float* pt, const float* alpha, const float* sym, int N, int n_d, int U, int B,
                     int n_sym, int spc, int all_bins, float* x, hipStream_t s) {
-  const int vec = (U % 2 == 0) && ((uintptr_t)pt % 16 == 0);
   if (!all_bins) zero_complex(x, (int64_t)n_sym * B * N, s);
-  k_precode<<<dim3(((all_bins ? N : n_d) + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt), alpha,
-                                                         reinterpret_cast<const float2*>(sym), N, n_d, U, B,
-                                                         spc, all_bins, vec, reinterpret_cast<float2*>(x));
+  const int tw = precode_tile(B);
+  const dim3 grid(((all_bins ? N : n_d) + tw - 1) / tw, n_sym);
+  const size_t lds = sizeof(float2) * (size_t)(kZfMaxU * tw + B * (tw + 1));
+  const auto* p2 = reinterpret_cast<const float2*>(pt);
+  const auto* s2 = reinterpret_cast<const float2*>(sym);
+  auto* x2 = reinterpret_cast<float2*>(x);
+  if (U % 2 == 0 && (uintptr_t)pt % 16 == 0)
+    k_precode<true><<<grid, 256, lds, s>>>(p2, alpha, s2, N, n_d, U, B, spc, all_bins, tw, x2);
+  else
+    k_precode<false><<<grid, 256, lds, s>>>(p2, alpha, s2, N, n_d, U, B, spc, all_bins, tw, x2);
 }
 
 void launch_chan_data(const float* h, int N, int n_d, int U, int B, int T, int n_ch, float* hd, hipStream_t s) {
@@ -1558,12 +1576,12 @@ void launch_link_pa_bwd(const float* x, const float* g_y, int N, int B, int n_sy
 
 void launch_precode_bwd(const float* pt, const float* alpha, const float* g_x, int N, int n_d, int U, int B,
                         int n_sym, int spc, int all_bins, float* g_s, hipStream_t s) {
-  const int vec = (U % 2 == 0) && ((uintptr_t)pt % 16 == 0);
   if (!all_bins) zero_complex(g_s, (int64_t)n_sym * U * N, s);
-  k_precode_bwd<<<dim3(((all_bins ? N : n_d) + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(pt),
-                                                                               alpha,
-                                                             reinterpret_cast<const float2*>(g_x), N, n_d, U, B, spc,
-                                                             all_bins, vec, reinterpret_cast<float2*>(g_s));
+  const int tw = precode_tile(B);
+  const dim3 grid(((all_bins ? N : n_d) + tw - 1) / tw, n_sym);
+  const size_t lds = sizeof(float2) * (size_t)((B + kZfMaxU) * (tw + 1));
+  k_precode_bwd<<<grid, 256, lds, s>>>(reinterpret_cast<const float2*>(pt), alpha, reinterpret_cast<const float2*>(g_x),
+                                       N, n_d, U, B, spc, all_bins, tw, reinterpret_cast<float2*>(g_s));
 }
 
 int64_t link_rx_parts(int n_d, int n_sym) { return (int64_t)((n_d + 255) / 256) * n_sym; }
