@@ -618,6 +618,8 @@ __global__ __launch_bounds__(256) void k_fdnn_reduce2(const float* __restrict__ 
 constexpr int kZfMaxU = 8;
 constexpr int kZfMaxB = 256;
 constexpr int kZfMaxT = 64;
+constexpr int kZfE = 2;     // H_k elements per lane and pass
+constexpr int kZfTc = 8;    // taps per batch of loads
 
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -662,15 +664,36 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
     for (int t = lane; t < T; t += 64) ph[t] = unit_phase(k, t, N);
     __syncthreads();
     const float2* hc = h + (int64_t)c * T * U * B;
-    for (int e = lane; e < U * B; e += 64) {
-      const int eu = e / B, eb = e % B;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int t = 0; t < T; ++t) {
-        const float2 v = hc[(int64_t)t * U * B + e];
-        acc = make_double2(acc.x + (double)v.x * ph[t].x - (double)v.y * ph[t].y,
-                           acc.y + (double)v.x * ph[t].y + (double)v.y * ph[t].x);
+    for (int e0 = lane; e0 < U * B; e0 += 64 * kZfE) {
+      double2 acc[kZfE];
+#pragma unroll
+      for (int q = 0; q < kZfE; ++q) acc[q] = make_double2(0.0, 0.0);
+      for (int t0 = 0; t0 < T; t0 += kZfTc) {
+        // the chunk's kZfE x kZfTc tap loads are issued together (one wait per chunk, not per tap)
+        // (unconditional loads from clamped, in-bounds indices: a guarded load is a branch
+        // that ends in its own wait; the taps past T are skipped below, lanes past U B unused)
+        float2 v[kZfE][kZfTc];
+#pragma unroll
+        for (int q = 0; q < kZfE; ++q)
+#pragma unroll
+          for (int tt = 0; tt < kZfTc; ++tt)
+            v[q][tt] = hc[(int64_t)min(t0 + tt, T - 1) * U * B + min(e0 + 64 * q, U * B - 1)];
+#pragma unroll
+        for (int tt = 0; tt < kZfTc; ++tt) {
+          if (t0 + tt < T) {
+            const double2 p = ph[t0 + tt];
+#pragma unroll
+            for (int q = 0; q < kZfE; ++q)
+              acc[q] = make_double2(acc[q].x + (double)v[q][tt].x * p.x - (double)v[q][tt].y * p.y,
+                                    acc[q].y + (double)v[q][tt].x * p.y + (double)v[q][tt].y * p.x);
+          }
+        }
       }
-      hk[eu * hs + eb] = acc;
+#pragma unroll
+      for (int q = 0; q < kZfE; ++q) {
+        const int e = e0 + 64 * q;
+        if (e < U * B) hk[(e / B) * hs + e % B] = acc[q];
+      }
     }
     __syncthreads();
     const int i = lane / kZfMaxU, j = lane % kZfMaxU;
@@ -691,8 +714,8 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
       double2 na = make_double2(0.0, 0.0), ni = na;
       if (own) {
         const double2 piv = A[p][p];
-        const double m2 = piv.x * piv.x + piv.y * piv.y;
-        const double2 inv = make_double2(piv.x / m2, -piv.y / m2);
+        const double r2 = 1.0 / (piv.x * piv.x + piv.y * piv.y);   // one FP64 division per pivot
+        const double2 inv = make_double2(piv.x * r2, -piv.y * r2);
         if (i == p) {
           na = zmul(A[p][j], inv);
           ni = zmul(I[p][j], inv);
@@ -828,10 +851,18 @@ __global__ __launch_bounds__(256) void k_chan_data(const float2* __restrict__ h,
   float2* dst = hd + ((int64_t)c * n_d + d) * U * B;
   for (int e = threadIdx.x; e < U * B; e += 256) {
     double re = 0.0, im = 0.0;
-    for (int t = 0; t < T; ++t) {
-      const float2 v = hc[(int64_t)t * U * B + e];
-      re += (double)v.x * ph[t].x - (double)v.y * ph[t].y;
-      im += (double)v.x * ph[t].y + (double)v.y * ph[t].x;
+    for (int t0 = 0; t0 < T; t0 += kZfTc) {
+      float2 v[kZfTc];     // one batch of tap loads in flight (clamped indices, no branches)
+#pragma unroll
+      for (int tt = 0; tt < kZfTc; ++tt) v[tt] = hc[(int64_t)min(t0 + tt, T - 1) * U * B + e];
+#pragma unroll
+      for (int tt = 0; tt < kZfTc; ++tt) {
+        if (t0 + tt < T) {
+          const double2 p = ph[t0 + tt];
+          re += (double)v[tt].x * p.x - (double)v[tt].y * p.y;
+          im += (double)v[tt].x * p.y + (double)v[tt].y * p.x;
+        }
+      }
     }
     dst[e] = make_float2((float)re, (float)im);
   }
