@@ -624,9 +624,6 @@ constexpr int kZfTc = 8;    // taps per batch of loads
 __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 zmulc(double2 a, double2 b) {   // conj(a) b
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
 
 // Subcarrier of data symbol d: 1 + d for d < n_d / 2, else N - n_d + d.
 __device__ __forceinline__ int data_bin(int d, int N, int n_d) {
@@ -639,6 +636,17 @@ __device__ __forceinline__ double2 unit_phase(int64_t k, int t, int N) {
   double s, c;
   sincospi(-2.0 * (double)e / (double)N, &s, &c);
   return make_double2(c, s);
+}
+
+// (r, k) -> the (row, column) of the element 64 further on in a row-major array of C
+// columns (q = 64 / C, m = 64 % C).
+__device__ __forceinline__ void step64(int& r, int& k, int q, int m, int C) {
+  r += q;
+  k += m;
+  if (k >= C) {
+    k -= C;
+    ++r;
+  }
 }
 
 // Pt_k = H_k^H (H_k H_k^H)^-1 with H_k = sum_t H_t e^{-2 pi i k t / N}; tr(Pt^H Pt) -> trace.
@@ -656,6 +664,10 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
   const int lane = threadIdx.x;
   const int c = blockIdx.y;
   const int nbins = all_bins ? N : n_d;
+  // element e = lane + 64 m of a row-major [R][C] array sits at (e / C, e % C); the lanes
+  // step through m with a carry instead of integer divisions
+  const int qB = 64 / B, rB = 64 % B, hu0 = lane / B, hb0 = lane % B;
+  const int qU = 64 / U, rU = 64 % U, pb0 = lane / U, pu0 = lane % U;
   // one subcarrier per workgroup (grid-stride form; looping over several per workgroup
   // measured slower)
   for (int kb = blockIdx.x; kb < nbins; kb += gridDim.x) {
@@ -664,6 +676,7 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
     for (int t = lane; t < T; t += 64) ph[t] = unit_phase(k, t, N);
     __syncthreads();
     const float2* hc = h + (int64_t)c * T * U * B;
+    int hu = hu0, hb = hb0;                  // (row, column) of H_k element lane + 64 m
     for (int e0 = lane; e0 < U * B; e0 += 64 * kZfE) {
       double2 acc[kZfE];
 #pragma unroll
@@ -691,8 +704,8 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
       }
 #pragma unroll
       for (int q = 0; q < kZfE; ++q) {
-        const int e = e0 + 64 * q;
-        if (e < U * B) hk[(e / B) * hs + e % B] = acc[q];
+        if (e0 + 64 * q < U * B) hk[hu * hs + hb] = acc[q];
+        step64(hu, hb, qB, rB, B);
       }
     }
     __syncthreads();
@@ -702,8 +715,10 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
       double2 g = make_double2(0.0, 0.0);
       for (int b = 0; b < B; ++b) {          // G[i][j] = sum_b H[i][b] conj(H[j][b])
         const double2 x = hk[i * hs + b], y = hk[j * hs + b];
-        g.x += x.x * y.x + x.y * y.y;
-        g.y += x.y * y.x - x.x * y.y;
+        g.x = fma(x.x, y.x, g.x);
+        g.x = fma(x.y, y.y, g.x);
+        g.y = fma(x.y, y.x, g.y);
+        g.y = fma(-x.x, y.y, g.y);
       }
       A[i][j] = g;
       I[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
@@ -736,16 +751,19 @@ __global__ __launch_bounds__(64) void k_zf(const float2* __restrict__ h, int N, 
     // Pt[b][u] = sum_j conj(H[j][b]) Ginv[j][u]
     double tr = 0.0;
     float2* dst = pt + ((int64_t)c * N + k) * B * U;
+    int b = pb0, u = pu0;                    // (b, u) of element e of Pt_k [B][U]
     for (int e = lane; e < B * U; e += 64) {
-      const int b = e / U, u = e % U;
       double2 acc = make_double2(0.0, 0.0);
-      for (int jj = 0; jj < U; ++jj) {
-        const double2 v = zmulc(hk[jj * hs + b], I[jj][u]);
-        acc.x += v.x;
-        acc.y += v.y;
+      for (int jj = 0; jj < U; ++jj) {         // conj(H[jj][b]) Ginv[jj][u]
+        const double2 hv = hk[jj * hs + b], q = I[jj][u];
+        acc.x = fma(hv.x, q.x, acc.x);
+        acc.x = fma(hv.y, q.y, acc.x);
+        acc.y = fma(hv.x, q.y, acc.y);
+        acc.y = fma(-hv.y, q.x, acc.y);
       }
       dst[e] = make_float2((float)acc.x, (float)acc.y);
       tr += acc.x * acc.x + acc.y * acc.y;
+      step64(b, u, qU, rU, U);
     }
     red[lane] = tr;
     __syncthreads();
@@ -849,20 +867,14 @@ __global__ __launch_bounds__(256) void k_chan_data(const float2* __restrict__ h,
   __syncthreads();
   const float2* hc = h + (int64_t)c * T * U * B;
   float2* dst = hd + ((int64_t)c * n_d + d) * U * B;
+  // (a plain loop over the taps: with four waves per workgroup and many workgroups resident,
+  // batching the tap loads as in k_zf measured 15 % slower here)
   for (int e = threadIdx.x; e < U * B; e += 256) {
     double re = 0.0, im = 0.0;
-    for (int t0 = 0; t0 < T; t0 += kZfTc) {
-      float2 v[kZfTc];     // one batch of tap loads in flight (clamped indices, no branches)
-#pragma unroll
-      for (int tt = 0; tt < kZfTc; ++tt) v[tt] = hc[(int64_t)min(t0 + tt, T - 1) * U * B + e];
-#pragma unroll
-      for (int tt = 0; tt < kZfTc; ++tt) {
-        if (t0 + tt < T) {
-          const double2 p = ph[t0 + tt];
-          re += (double)v[tt].x * p.x - (double)v[tt].y * p.y;
-          im += (double)v[tt].x * p.y + (double)v[tt].y * p.x;
-        }
-      }
+    for (int t = 0; t < T; ++t) {
+      const float2 v = hc[(int64_t)t * U * B + e];
+      re += (double)v.x * ph[t].x - (double)v.y * ph[t].y;
+      im += (double)v.x * ph[t].y + (double)v.y * ph[t].x;
     }
     dst[e] = make_float2((float)re, (float)im);
   }
