@@ -822,28 +822,47 @@ __global__ __launch_bounds__(256) void k_precode(const float2* __restrict__ pt, 
     if (el < nb) st[j] = si[(int64_t)u * N + (all_bins ? e0 + el : data_bin(e0 + el, N, n_d))];
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < nb * B; j += 256) {
-    const int el = j / B, b = j - el * B;
-    const int k = all_bins ? e0 + el : data_bin(e0 + el, N, n_d);
-    const float2* row = pt + (((int64_t)c * N + k) * B + b) * U;
-    float2 acc = make_float2(0.f, 0.f);
-    if (VEC) {
-      // even U and a 16-byte aligned pt: the row is U/2 aligned 16-byte pairs
-      const float4* row4 = reinterpret_cast<const float4*>(row);
-#pragma unroll
-      for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
-        if (2 * u2 < U) {
-          const float4 q = row4[u2];
-          acc = cadd(acc, cmul(make_float2(q.x, q.y), st[(2 * u2) * tw + el]));
-          acc = cadd(acc, cmul(make_float2(q.z, q.w), st[(2 * u2 + 1) * tw + el]));
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < kZfMaxU; ++u)
-        if (u < U) acc = cadd(acc, cmul(row[u], st[u * tw + el]));
+  if (VEC && U == kZfMaxU) {
+    // eight UEs: four lanes per 64-byte row of Pt, one 16-byte piece each, so a wave's load
+    // is 1 KB of consecutive rows; the four partial sums meet by two xor shuffles (the loop
+    // bound is a multiple of 4, so a lane group is active or idle as a whole)
+    for (int j = threadIdx.x; j < nb * B * 4; j += 256) {
+      const int r = j >> 2, q = j & 3;
+      const int el = r / B, b = r - el * B;
+      const int k = all_bins ? e0 + el : data_bin(e0 + el, N, n_d);
+      const float4 v = reinterpret_cast<const float4*>(pt + (((int64_t)c * N + k) * B + b) * kZfMaxU)[q];
+      float2 acc = cmul(make_float2(v.x, v.y), st[(2 * q) * tw + el]);
+      acc = cadd(acc, cmul(make_float2(v.z, v.w), st[(2 * q + 1) * tw + el]));
+      acc.x += __shfl_xor(acc.x, 1);
+      acc.y += __shfl_xor(acc.y, 1);
+      acc.x += __shfl_xor(acc.x, 2);
+      acc.y += __shfl_xor(acc.y, 2);
+      if (q == 0) xt[b * XS + el] = make_float2(a * acc.x, a * acc.y);
     }
-    xt[b * XS + el] = make_float2(a * acc.x, a * acc.y);
+  } else {
+    for (int j = threadIdx.x; j < nb * B; j += 256) {
+      const int el = j / B, b = j - el * B;
+      const int k = all_bins ? e0 + el : data_bin(e0 + el, N, n_d);
+      const float2* row = pt + (((int64_t)c * N + k) * B + b) * U;
+      float2 acc = make_float2(0.f, 0.f);
+      if (VEC) {
+        // even U and a 16-byte aligned pt: the row is U/2 aligned 16-byte pairs
+        const float4* row4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+        for (int u2 = 0; u2 < kZfMaxU / 2; ++u2) {
+          if (2 * u2 < U) {
+            const float4 q = row4[u2];
+            acc = cadd(acc, cmul(make_float2(q.x, q.y), st[(2 * u2) * tw + el]));
+            acc = cadd(acc, cmul(make_float2(q.z, q.w), st[(2 * u2 + 1) * tw + el]));
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kZfMaxU; ++u)
+          if (u < U) acc = cadd(acc, cmul(row[u], st[u * tw + el]));
+      }
+      xt[b * XS + el] = make_float2(a * acc.x, a * acc.y);
+    }
   }
   __syncthreads();
   float2* xi = x + (int64_t)i * B * N;
