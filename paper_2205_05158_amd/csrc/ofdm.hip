@@ -1085,12 +1085,16 @@ __device__ __forceinline__ int data_index(int k, int N, int n_d) {
 }
 
 // g_y[i][b][k_d] = sum_u conj(H_k[u][b]) conj(1 / (alpha G)) g_r[i][u][d] for data symbol
-// d (adjoint of channel and equalisation); one thread per (symbol, data symbol), as the
-// receiver.  The guard subcarriers of g_y are zeroed beforehand by zero_complex.
+// d (adjoint of channel and equalisation).  A workgroup holds kRxbD data symbols (fastest,
+// so the g_y stores are contiguous) x 4 antenna groups, each thread the antennas b of its
+// group; the guard subcarriers of g_y are zeroed beforehand by zero_complex.
+constexpr int kRxbD = 64;
+
 __global__ __launch_bounds__(256) void k_link_rx_bwd(const float2* __restrict__ hd, const float* __restrict__ alpha,
                                                      float g_re, float g_im, const float2* __restrict__ g_r, int N,
                                                      int n_d, int U, int B, int spc, float2* __restrict__ g_y) {
-  const int d = blockIdx.x * 256 + threadIdx.x;
+  const int d = blockIdx.x * kRxbD + threadIdx.x % kRxbD;
+  const int bg = threadIdx.x / kRxbD;
   const int i = blockIdx.y;
   if (d >= n_d) return;
   const int k = data_bin(d, N, n_d);
@@ -1103,8 +1107,8 @@ __global__ __launch_bounds__(256) void k_link_rx_bwd(const float2* __restrict__ 
 #pragma unroll
   for (int u = 0; u < kZfMaxU; ++u)
     gz[u] = u < U ? cmul(cj, g_r[((int64_t)i * U + u) * n_d + d]) : make_float2(0.f, 0.f);
-  const float2* hk = hd + ((int64_t)c * n_d + d) * U * B;
-  for (int b = 0; b < B; ++b) {
+  const float2* hk = hd + ((int64_t)c * n_d + d) * U * B;   // hd[c][d][u][b]
+  for (int b = bg; b < B; b += 256 / kRxbD) {
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int u = 0; u < kZfMaxU; ++u) {
@@ -1387,62 +1391,49 @@ __global__ __launch_bounds__(256) void k_precode_bwd(const float2* __restrict__ 
   }
 }
 
-// Receiver: thread per (symbol i, data symbol d): y = H_k x_pa + w, r = y / (alpha G),
-// nearest QAM point, errors counted per UE into the workgroup's partial.
+// Receiver: thread per (symbol i, data symbol d, UE u): y = sum_b H_k[u][b] x_pa[b] + w,
+// r = y / (alpha G), nearest QAM point; the workgroup's errors per UE into its partial.  A
+// workgroup holds kRxD data symbols x kZfMaxU UE slots (UE fastest): eight times the threads
+// of a thread-per-data-symbol receiver (which left most of the chip idle at 64 symbols), each
+// thread summing one contiguous 256-byte row of H_k.
+constexpr int kRxD = 256 / kZfMaxU;
+
 __global__ __launch_bounds__(256) void k_link_rx(const float2* __restrict__ y_fd, const float2* __restrict__ hd,
                                                  const float* __restrict__ alpha, float g_re, float g_im,
                                                  const float2* __restrict__ noise, const int32_t* __restrict__ tx,
                                                  int N, int n_d, int U, int B, int spc, int qam_m,
                                                  float2* __restrict__ r_out, int32_t* __restrict__ err_part) {
-  __shared__ int32_t cnt[kZfMaxU][256];
-  const int d = blockIdx.x * 256 + threadIdx.x;
+  __shared__ int32_t cnt[256];
+  const int dl = threadIdx.x / kZfMaxU, u = threadIdx.x % kZfMaxU;
+  const int d = blockIdx.x * kRxD + dl;
   const int i = blockIdx.y;
-  int e[kZfMaxU];
-#pragma unroll
-  for (int u = 0; u < kZfMaxU; ++u) e[u] = 0;
-  if (d < n_d) {
+  int e = 0;
+  if (d < n_d && u < U) {
     const int c = i / spc;
     const int k = data_bin(d, N, n_d);
-    float2 acc[kZfMaxU];
-#pragma unroll
-    for (int u = 0; u < kZfMaxU; ++u) acc[u] = make_float2(0.f, 0.f);
-    const float2* hk = hd + ((int64_t)c * n_d + d) * U * B;
+    const float2* hk = hd + (((int64_t)c * n_d + d) * U + u) * B;   // hd[c][d][u][b]
     const float2* yi = y_fd + (int64_t)i * B * N + k;
-    for (int b = 0; b < B; ++b) {
-      const float2 v = yi[(int64_t)b * N];
-#pragma unroll
-      for (int u = 0; u < kZfMaxU; ++u)
-        if (u < U) acc[u] = cadd(acc[u], cmul(hk[u * B + b], v));
-    }
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b = 0; b < B; ++b) acc = cadd(acc, cmul(hk[b], yi[(int64_t)b * N]));
     // 1 / (alpha G) = conj(G) / (alpha |G|^2)
-    const float a = alpha[c];
-    const float den = a * (g_re * g_re + g_im * g_im);
+    const float den = alpha[c] * (g_re * g_re + g_im * g_im);
     const float2 inv = make_float2(g_re / den, -g_im / den);
     const float qs = sqrtf(2.0f * (float)(qam_m * qam_m - 1) / 3.0f);   // unit-energy scale
-#pragma unroll
-    for (int u = 0; u < kZfMaxU; ++u) {
-      if (u < U) {
-        float2 yv = acc[u];
-        if (noise) yv = cadd(yv, noise[((int64_t)i * U + u) * N + k]);
-        const float2 rv = cmul(yv, inv);
-        if (r_out) r_out[((int64_t)i * U + u) * n_d + d] = rv;
-        const int ire = min(max((int)floorf((rv.x * qs + (float)qam_m) * 0.5f), 0), qam_m - 1);
-        const int iim = min(max((int)floorf((rv.y * qs + (float)qam_m) * 0.5f), 0), qam_m - 1);
-        e[u] = (ire * qam_m + iim) != tx[((int64_t)i * U + u) * n_d + d];
-      }
-    }
+    if (noise) acc = cadd(acc, noise[((int64_t)i * U + u) * N + k]);
+    const float2 rv = cmul(acc, inv);
+    if (r_out) r_out[((int64_t)i * U + u) * n_d + d] = rv;
+    const int ire = min(max((int)floorf((rv.x * qs + (float)qam_m) * 0.5f), 0), qam_m - 1);
+    const int iim = min(max((int)floorf((rv.y * qs + (float)qam_m) * 0.5f), 0), qam_m - 1);
+    e = (ire * qam_m + iim) != tx[((int64_t)i * U + u) * n_d + d];
   }
-#pragma unroll
-  for (int u = 0; u < kZfMaxU; ++u) cnt[u][threadIdx.x] = e[u];
+  cnt[threadIdx.x] = e;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-#pragma unroll
-      for (int u = 0; u < kZfMaxU; ++u) cnt[u][threadIdx.x] += cnt[u][threadIdx.x + w];
+  for (int w = kRxD / 2; w > 0; w >>= 1) {   // over the data symbols, per UE slot
+    if (dl < w) cnt[threadIdx.x] += cnt[threadIdx.x + w * kZfMaxU];
     __syncthreads();
   }
   if (threadIdx.x < U)
-    err_part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * U + threadIdx.x] = cnt[threadIdx.x][0];
+    err_part[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * U + threadIdx.x] = cnt[threadIdx.x];
 }
 
 // errors[u] = sum over the partials in order (int64).
@@ -1620,7 +1611,7 @@ void launch_link_pa(const float* x, int N, int B, int64_t rows, const float* dpd
 void launch_link_rx_bwd(const float* hd, const float* alpha, float g_re, float g_im, const float* g_r, int N, int n_d,
                         int U, int B, int n_sym, int spc, float* g_y, hipStream_t s) {
   zero_complex(g_y, (int64_t)n_sym * B * N, s);
-  k_link_rx_bwd<<<dim3((n_d + 255) / 256, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(hd), alpha, g_re,
+  k_link_rx_bwd<<<dim3((n_d + kRxbD - 1) / kRxbD, n_sym), 256, 0, s>>>(reinterpret_cast<const float2*>(hd), alpha, g_re,
                                                                g_im, reinterpret_cast<const float2*>(g_r), N, n_d, U,
                                                                B, spc, reinterpret_cast<float2*>(g_y));
 }
@@ -1646,12 +1637,12 @@ void launch_precode_bwd(const float* pt, const float* alpha, const float* g_x, i
                                        N, n_d, U, B, spc, all_bins, tw, reinterpret_cast<float2*>(g_s));
 }
 
-int64_t link_rx_parts(int n_d, int n_sym) { return (int64_t)((n_d + 255) / 256) * n_sym; }
+int64_t link_rx_parts(int n_d, int n_sym) { return (int64_t)((n_d + kRxD - 1) / kRxD) * n_sym; }
 
 void launch_link_rx(const float* y_fd, const float* hd, const float* alpha, float g_re, float g_im,
                     const float* noise, const int32_t* tx, int N, int n_d, int U, int B, int n_sym, int spc,
                     int qam_m, float* r_out, int32_t* err_part, int64_t* errors, hipStream_t s) {
-  k_link_rx<<<dim3((n_d + 255) / 256, n_sym), 256, 0, s>>>(
+  k_link_rx<<<dim3((n_d + kRxD - 1) / kRxD, n_sym), 256, 0, s>>>(
       reinterpret_cast<const float2*>(y_fd), reinterpret_cast<const float2*>(hd), alpha, g_re, g_im,
       reinterpret_cast<const float2*>(noise), tx, N, n_d, U, B, spc, qam_m, reinterpret_cast<float2*>(r_out),
       err_part);
