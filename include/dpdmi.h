@@ -208,7 +208,7 @@ dpd_status dpd_adam_step(const float* grad, float* w, float* m, float* v, int64_
 
 /* Least-squares fit of a GMP DPD by indirect learning: the TD-GMP benchmark of the
  * paper (the per-antenna DPD with the monomials of eq. (9), coefficients found by
- * mean-square-error estimation, Sec. IV-B) identified as a post-inverse at the PA output
+ * mean-square-error estimation, Sec. III-B) identified as a post-inverse at the PA output
  * (least squares between the post-distorter output and the PA input, Sec. V-A-2).
  * For every parameter set p (per stream, or one pooled over all streams):
  *   z = y / G,  Phi = the eq. (9) monomials of z (flat coefficient order a, b, c; zero
@@ -231,7 +231,7 @@ dpd_status gmp_ls_fit(const dpd_gmp_desc* gmp, const dpd_batch* batch, const flo
                       int32_t* info, double* normal_out, void* workspace,
                       size_t workspace_bytes, hipStream_t stream);
 
-/* FD-CNN DPD, the paper's proposed frequency-domain network (Sec. IV-C; Sec. V-A uses
+/* FD-CNN DPD, the paper's proposed frequency-domain network (Sec. IV-A; Sec. V-A uses
  * n_d = 384 data subcarriers, side = 20, n_conv = 2, kc = 3, ReLU), applied to a batch of
  * n_items UE symbol vectors (one UE's N_d data-subcarrier symbols of one OFDM symbol):
  * the vector fills a side x side grid row-major (zero padded); its Re and Im planes

@@ -6,12 +6,12 @@ CPU-baseline leg may import this module.  It shares no code with the HIP path.
 
 Passages followed (arXiv 2205.05158):
   * a UE's data-subcarrier symbol vector (N_d complex) is written into a side x side
-    matrix, side = ceil(sqrt(N_d)), in contiguous order with zero padding ... Sec. IV-C
+    matrix, side = ceil(sqrt(N_d)), in contiguous order with zero padding ... Sec. IV-A
   * its real and imaginary parts are 2 L_U real planes, convolved by N^Conv kernels of
-    size K_C (stride 1 here), zero padding keeping the plane size ............ Sec. IV-C, Sec. V-A
+    size K_C (stride 1 here), zero padding keeping the plane size ............ Sec. IV-A, Sec. V-A
   * an element-wise activation (ReLU), flattening, and a linear fully connected output
     layer of 2 N_d neurons: the real and imaginary parts of the predistorted symbol
-    vector ...................................................................... Sec. IV-C, Sec. V-A
+    vector ...................................................................... Sec. IV-A, Sec. V-A
 Readings where the paper is silent: L_U = 1 (the paper's setting; the planes are the
 UE's own Re and Im); each kernel spans all input planes (a standard multi-channel
 convolution, cross-correlation orientation) and has a bias; the output layer has a

@@ -7,7 +7,7 @@ CPU-baseline leg may import this module.  It shares no code with the HIP path.
 Passages followed (arXiv 2205.05158):
   * the per-antenna GMP DPD, the same monomials as eq. (9) with the DPD input in
     place of the PA input, coefficients found by mean-square-error estimation
-    ......................................................... Sec. IV-B, eq. (9)
+    ......................................................... Sec. III-B, eq. (9)
   * indirect learning: a post-distorter is fitted by least squares at the output of
     each PA (PA output in, PA input as the target) and copied in front of the PA
     ......................................................... Sec. V-A-2

@@ -1,4 +1,4 @@
-// FD-CNN DPD (the paper's proposed frequency-domain CNN, Sec. IV-C; configuration of
+// FD-CNN DPD (the paper's proposed frequency-domain CNN, Sec. IV-A; configuration of
 // Sec. V-A) applied to a batch of UE symbol vectors: forward and reverse mode.
 //
 // Per item: the N_d data-subcarrier symbols fill a side x side grid row-major (zero

@@ -1,6 +1,6 @@
 // Least-squares identification of a GMP DPD by indirect learning: the TD-GMP benchmark
 // of the paper (the per-antenna DPD of eq. (9), coefficients by mean-square-error
-// estimation, Sec. IV-B) fitted as a post-inverse at the PA output (Sec. V-A-2).
+// estimation, Sec. III-B) fitted as a post-inverse at the PA output (Sec. V-A-2).
 //
 // The normal equations Phi^H Phi c = Phi^H t are accumulated on the FP64 matrix cores
 // (the basis is badly conditioned: powers |z|^k of one envelope; float32 sums would not

@@ -182,7 +182,7 @@ def receiver_loss_grad(dl: Downlink, net: FdNn, s, tx, w, pt, alpha, pa_coef, g,
 
 
 def receiver_loss_grad_fdcnn(dl: Downlink, net, s, tx, w, pt, alpha, pa_coef, g, h, sym_per_ch=1):
-    """The same criterion for the FD-CNN (Sec. IV-C, trained like the FD-NN, Sec. V-A-2):
+    """The same criterion for the FD-CNN (Sec. IV-A, trained like the FD-NN, Sec. V-A-2):
     each UE's N_d data symbols (items = n_sym x U symbol vectors) through the FD-CNN, back
     on the data subcarriers, data-only ZF precoding, the link; L as above.  `net` is an
     FdCnn for n_d = dl.n_data.  Returns (L, dL/dw, symbol errors per UE)."""

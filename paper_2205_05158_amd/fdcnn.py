@@ -1,4 +1,4 @@
-"""FD-CNN DPD (Sec. IV-C) over a batch of UE symbol vectors, on the device.
+"""FD-CNN DPD (Sec. IV-A) over a batch of UE symbol vectors, on the device.
 
 `FdCnn` holds the descriptor and a workspace sized for a maximum batch (allocated once
 through torch) and exposes forward, backward (parameter gradient for a given output

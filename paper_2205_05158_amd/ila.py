@@ -1,7 +1,7 @@
 """TD-GMP benchmark DPD identified by indirect learning with least squares, on the device.
 
 `GmpIla` holds the DPD and PA GMP descriptors, the batch and a workspace (allocated once
-through torch).  One ILA iteration (Sec. V-A-2 with the GMP DPD of Sec. IV-B, eq. (9)):
+through torch).  One ILA iteration (Sec. V-A-2 with the GMP DPD of Sec. III-B, eq. (9)):
 u = DPD(x) (pa_gmp_forward with the DPD coefficients), y = PA(u) (pa_gmp_forward with
 the PA coefficients), NMSE of y against G x (cascade_nmse), then the post-inverse fit
 gmp_ls_fit(z = y / G -> t = u) gives the next DPD coefficients.

@@ -406,7 +406,7 @@ def test_fdnn_receiver_training_matches_oracle():
 
 
 def test_fdcnn_receiver_training_matches_oracle():
-    """The FD-CNN (Sec. IV-C: each UE's data symbols on a side x side grid) trained at the
+    """The FD-CNN (Sec. IV-A: each UE's data symbols on a side x side grid) trained at the
     receiver through data-only ZF precoding, PAs and channel: three device Adam steps
     against the FP64 loop (oracle FD-CNN, precoding, link and their adjoints, Adam)."""
     import oracle.adam as OA

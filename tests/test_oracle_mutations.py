@@ -103,3 +103,72 @@ def test_gmp_backward_missing_envelope_term_is_caught(monkeypatch):
             g_u += OC.advance(np.conj(cf) * OC.delay(r, d) ** k * g_y, l)
         return g_u
     assert _caught(monkeypatch, OC, "gmp_backward", bad)
+
+
+# ---------------------------------------------------------------- ACPR plan, ridge
+import oracle.spectrum as OS
+import test_oracle_ila as TI
+
+
+def _acpr_pins():
+    return ([lambda k=k, b=b: TP.test_band_plan_single_bin_membership(k, b)
+             for k, b in [(0, "M"), (20, "M"), (-20, "M"), (21, "U"), (60, "U"), (-21, "L"),
+                          (-60, "L"), (61, None), (-61, None)]]
+            + [TP.test_band_plan_exact_sums_of_distinct_bins, TP.test_acpr_of_tones_in_known_channels])
+
+
+def _plan(main_hi, up_lo, up_hi, lo_lo, lo_hi, swap=False):
+    """A band_powers variant: main |k| <= main_hi, upper up_lo <= k <= up_hi, lower
+    lo_lo <= k <= lo_hi (bins as signed indices), optionally with L and U swapped."""
+    def bp(psd, h):
+        nfft = psd.size
+        k = np.arange(nfft)
+        ks = np.where(k < nfft // 2, k, k - nfft)
+        main = psd[np.abs(ks) <= main_hi(h)].sum()
+        up = psd[(ks >= up_lo(h)) & (ks <= up_hi(h))].sum()
+        lo = psd[(ks >= lo_lo(h)) & (ks <= lo_hi(h))].sum()
+        return (float(up), float(main), float(lo)) if swap else (float(lo), float(main), float(up))
+    return bp
+
+
+@pytest.mark.parametrize("name,variant", [
+    ("adjacent width h", _plan(lambda h: h, lambda h: h + 1, lambda h: 2 * h, lambda h: -2 * h, lambda h: -h - 1)),
+    ("L and U swapped", _plan(lambda h: h, lambda h: h + 1, lambda h: 3 * h, lambda h: -3 * h, lambda h: -h - 1, swap=True)),
+    ("main edge |k| < h", _plan(lambda h: h - 1, lambda h: h, lambda h: 3 * h, lambda h: -3 * h, lambda h: -h)),
+    ("main edge |k| <= h + 1", _plan(lambda h: h + 1, lambda h: h + 2, lambda h: 3 * h, lambda h: -3 * h, lambda h: -h - 2)),
+    ("outer edge 3h excluded", _plan(lambda h: h, lambda h: h + 1, lambda h: 3 * h - 1, lambda h: -3 * h + 1, lambda h: -h - 1)),
+    ("outer edge 3h + 1 included", _plan(lambda h: h, lambda h: h + 1, lambda h: 3 * h + 1, lambda h: -3 * h - 1, lambda h: -h - 1)),
+])
+def test_acpr_plan_mistakes_are_caught(monkeypatch, name, variant):
+    monkeypatch.setattr(OS, "band_powers", variant)
+    caught = [p for p in _acpr_pins() if _fails(p)]
+    monkeypatch.undo()
+    assert caught, name
+
+
+def test_acpr_plan_pins_pass_unmutated():
+    assert not [p for p in _acpr_pins() if _fails(p)]
+
+
+@pytest.mark.parametrize("name", ["no /J", "Frobenius of G", "ridge on the right-hand side"])
+def test_ridge_mistakes_are_caught(monkeypatch, name):
+    import oracle.ila as I
+
+    def bad(G, b, ridge=0.0):
+        J = G.shape[0]
+        A = G.copy()
+        rhs = b.copy()
+        if ridge:
+            if name == "no /J":
+                A += ridge * np.trace(G).real * np.eye(J)
+            elif name == "Frobenius of G":
+                A += ridge * np.linalg.norm(G) / J * np.eye(J)
+            else:
+                A += ridge * np.trace(G).real / J * np.eye(J)
+                rhs = rhs * (1 + ridge)
+        return np.linalg.solve(A, rhs)
+    monkeypatch.setattr(I, "solve_normal", bad)
+    pins = [lambda r=r: TI.test_ridge_equals_least_squares_on_augmented_system(r) for r in (1e-3, 0.3)]
+    caught = [p for p in pins if _fails(p)]
+    monkeypatch.undo()
+    assert caught, name

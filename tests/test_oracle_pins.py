@@ -304,3 +304,53 @@ def test_acpr_grows_with_third_order_distortion():
     psd = O.welch_psd(x, 4096)
     lo, mn, up = O.band_powers(psd, 512)
     assert 0.999 < (lo + mn + up) / psd.sum() <= 1.0
+
+
+# ACPR channel plan (the reading of the ACPR the paper names in Sec. I without an
+# estimator): main channel |k| <= h, upper adjacent h < k <= 3h, lower -3h <= k < -h.
+# These pins fix each edge and the side of each adjacent channel with hand-built inputs.
+def _bands_of_single_bin(k, nfft, h):
+    import oracle.spectrum as OS
+    psd = np.zeros(nfft)
+    psd[k % nfft] = 1.0
+    return OS.band_powers(psd, h)
+
+
+@pytest.mark.parametrize("k,band", [
+    (0, "M"), (7, "M"), (20, "M"), (-20, "M"),           # |k| <= h (h = 20), DC included
+    (21, "U"), (40, "U"), (60, "U"),                      # h < k <= 3h
+    (-21, "L"), (-40, "L"), (-60, "L"),                   # -3h <= k < -h
+    (61, None), (-61, None), (127, None), (-128, None),   # beyond 3h: no channel
+])
+def test_band_plan_single_bin_membership(k, band):
+    """Unit power in one PSD bin lands in exactly the channel the plan assigns."""
+    lo, mn, up = _bands_of_single_bin(k, 256, 20)
+    expect = {"L": (1.0, 0.0, 0.0), "M": (0.0, 1.0, 0.0), "U": (0.0, 0.0, 1.0), None: (0.0, 0.0, 0.0)}[band]
+    assert (lo, mn, up) == expect
+
+
+def test_band_plan_exact_sums_of_distinct_bins():
+    """Every bin carries a distinct power of two, so each channel sum identifies the exact
+    set of bins it took: main = bins -h..h, upper = h+1..3h, lower = -3h..-h-1."""
+    import oracle.spectrum as OS
+    nfft, h = 64, 5
+    ks = np.where(np.arange(nfft) < nfft // 2, np.arange(nfft), np.arange(nfft) - nfft)
+    psd = 2.0 ** (ks + 32)                                   # exact in float64
+    lo, mn, up = OS.band_powers(psd, h)
+    assert mn == sum(2.0 ** (k + 32) for k in range(-h, h + 1))
+    assert up == sum(2.0 ** (k + 32) for k in range(h + 1, 3 * h + 1))
+    assert lo == sum(2.0 ** (k + 32) for k in range(-3 * h, -h))
+
+
+def test_acpr_of_tones_in_known_channels():
+    """Tones on bin centres: a unit tone at DC (main), one of power 1e-2 at k = 5h/2
+    (upper adjacent, beyond 2h) and one of power 1e-4 at k = -5h/2 (lower).  Each tone's
+    Hann leakage (bins k0 - 1, k0, k0 + 1) stays inside its channel, so ACPR_U = -20 dB and
+    ACPR_L = -40 dB exactly (up to rounding): pins the sides of L and U and the 2h width."""
+    import oracle.spectrum as OS
+    nfft, h = 1024, 40
+    n = np.arange(nfft * 6)
+    y = (1.0 + 0.1 * np.exp(2j * np.pi * (5 * h // 2) * n / nfft)
+         + 0.01 * np.exp(-2j * np.pi * (5 * h // 2) * n / nfft))
+    aL, aU, amax = OS.acpr_db(OS.welch_psd(y, nfft), h)
+    np.testing.assert_allclose([aL, aU, amax], [-40.0, -20.0, -20.0], atol=1e-9)
