@@ -51,7 +51,9 @@ typedef enum {
     DPD_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement        */
     DPD_ERR_WORKSPACE = -4,    /* workspace smaller than dpd_workspace_size() says    */
     DPD_ERR_LAUNCH = -5,       /* the HIP runtime reported an error                   */
-    DPD_ERR_ALIGN = -6         /* a pointer is not aligned as documented              */
+    DPD_ERR_ALIGN = -6,        /* a pointer is not aligned as documented              */
+    DPD_ERR_NONFINITE = -7     /* an NMSE record reports non-finite samples
+                                  (dpd_nmse_status, on host copies of the records)    */
 } dpd_status;
 
 typedef enum { DPD_FP32 = 0, DPD_BF16 = 1 } dpd_precision;
@@ -115,10 +117,26 @@ dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch,
 dpd_status pa_gmp_forward(const dpd_gmp_desc* gmp, const dpd_batch* batch,
                           const float* u, const float* coef, float* y, hipStream_t stream);
 
-/* NMSE of y against the linear target G x (Sec. II-B), per stream and pooled per
- * parameter set.  out: device float[3*(S+1)]: for s < S, (E_s, R_s, NMSE_dB_s);
- * at s = S the triple pooled over all streams.  E = sum|y-Gx|^2, R = sum|Gx|^2,
- * accumulated in float32 with compensated (Neumaier) sums. */
+/* NMSE records.  The NMSE of y against the linear target G x (Sec. II-B) is reported
+ * as one record of DPD_NMSE_FIELDS floats per stream plus one pooled over all streams:
+ *   (E, R, NMSE_dB, n_nonfinite),  E = sum|y-Gx|^2, R = sum|Gx|^2, NMSE_dB = 10 log10(E/R),
+ * accumulated in float32 with compensated (Neumaier) sums.  n_nonfinite counts the
+ * samples whose |y-Gx|^2 or |Gx|^2 is not a finite float32 (NaN or infinite inputs or
+ * outputs, or squares beyond the float32 range); such samples still enter E and R, so
+ * E, NMSE_dB and the loss of their stream and parameter set are then not finite.  The
+ * count is exact below 2^24 samples per record.  Records are written on the device
+ * without synchronising; dpd_nmse_status checks host copies of them. */
+enum { DPD_NMSE_FIELDS = 4 };
+
+/* Host only, no HIP call: DPD_ERR_NONFINITE if any of the n_records records at
+ * nmse_host (host float[n_records][DPD_NMSE_FIELDS]) has n_nonfinite > 0, a non-finite
+ * E or R, or an NMSE_dB that is NaN or +inf (-inf, the exact match E = 0, is accepted);
+ * DPD_OK otherwise; DPD_ERR_NULL / DPD_ERR_SHAPE for a null pointer or n_records < 1. */
+dpd_status dpd_nmse_status(const float* nmse_host, int64_t n_records);
+
+/* NMSE of y against the linear target G x (Sec. II-B), per stream and pooled.
+ * out: device float[(S+1)][DPD_NMSE_FIELDS]: record s < S of stream s, record S
+ * pooled over all streams. */
 dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x,
                         float g_re, float g_im, float* out,
                         void* workspace, size_t workspace_bytes, hipStream_t stream);
@@ -128,14 +146,16 @@ dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x,
  * loss[p] = sum_{s in p} E_s / sum_{s in p} R_s and dw[p] = d loss[p] / d w_p
  * (same packed layout as w).  loss: device float[n_sets]; dw: device float[n_sets*P].
  * d|u|/du is taken as 0 at u = 0.  Deterministic: identical inputs give bitwise
- * identical results for a given launch shape. */
+ * identical results for a given launch shape.  A set whose streams hold non-finite
+ * samples (see the NMSE records) gets a non-finite loss and dw; other sets are not
+ * affected. */
 dpd_status dpd_backward(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                         const dpd_batch* batch, const float* x, const float* w,
                         const float* coef, float g_re, float g_im, float* dw, float* loss,
                         void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* The whole cascade in one call: optional u and y outputs (NULL to skip),
- * per-stream NMSE triples as cascade_nmse (nmse: device float[3*(S+1)], may be
+ * NMSE records as cascade_nmse (nmse: device float[(S+1)][DPD_NMSE_FIELDS], may be
  * NULL), and when dw is non-NULL the gradient and pooled loss as dpd_backward
  * (loss required with dw). */
 dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
@@ -188,6 +208,18 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                         const float* coef, float g_re, float g_im, int32_t reps,
                         void* workspace, size_t workspace_bytes, hipStream_t stream,
                         dpd_tune* out_host);
+
+/* Mean squared error of complex symbols: the supervised criterion the paper trains its
+ * frequency-domain DPDs with (Sec. V-A-2), for n complex values z_i (e.g. equalised
+ * received symbols) against targets t_i (the transmitted symbols):
+ *   loss = sum_i |z_i - t_i|^2 / n,  grad_i = 2 (z_i - t_i) / n  (= dloss/dRe + j dloss/dIm),
+ * summed in float32 with compensated sums in a fixed order (deterministic).
+ * z, t: device float[n][2]; out: device float[2] = (loss, count of i whose |z_i - t_i|^2
+ * is not finite); grad: device float[n][2] (not aliasing z or t) or NULL.  The
+ * workspace (dpd_symbol_mse_workspace_size) holds per-tile partial sums. */
+dpd_status dpd_symbol_mse_workspace_size(int64_t n, size_t* bytes_host);
+dpd_status dpd_symbol_mse(int64_t n, const float* z, const float* t, float* out, float* grad,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* One Adam step on n float32 parameters in place: the optimiser the paper trains its
  * DPD networks with (Sec. V-A-2, learning rate 0.001), with the update rule of

@@ -18,8 +18,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdpdmi.so")
 
 DPD_OK = 0
-DPD_ERR_NULL, DPD_ERR_SHAPE, DPD_ERR_UNSUPPORTED, DPD_ERR_WORKSPACE, DPD_ERR_LAUNCH, DPD_ERR_ALIGN = \
-    -1, -2, -3, -4, -5, -6
+DPD_ERR_NULL, DPD_ERR_SHAPE, DPD_ERR_UNSUPPORTED, DPD_ERR_WORKSPACE, DPD_ERR_LAUNCH, DPD_ERR_ALIGN, \
+    DPD_ERR_NONFINITE = -1, -2, -3, -4, -5, -6, -7
+DPD_NMSE_FIELDS = 4    # (E, R, NMSE dB, non-finite count) per NMSE record
 DPD_FP32, DPD_BF16 = 0, 1
 DPD_IMPL_TUNED, DPD_IMPL_PLAIN = 0, 1
 DPD_MAX_STREAMS = 128
@@ -81,6 +82,9 @@ _SIGS = {
     "dpd_tune_set": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(Tune)]),
     "dpd_autotune": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
                                C.c_float, C.c_float, C.c_int32, _P, C.c_size_t, _P, C.POINTER(Tune)]),
+    "dpd_nmse_status": (C.c_int, [C.POINTER(C.c_float), C.c_int64]),
+    "dpd_symbol_mse_workspace_size": (C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
+    "dpd_symbol_mse": (C.c_int, [C.c_int64, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "dpd_adam_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int32, C.c_double, C.c_double,
                                 C.c_double, C.c_double, _P]),
     "gmp_ls_workspace_size": (C.c_int, [C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(C.c_size_t)]),
@@ -208,6 +212,30 @@ def cascade_nmse(batch, y, x, g, out, workspace, stream=None):
     _check(lib().cascade_nmse(C.byref(batch), _ptr(y), _ptr(x), g.real, g.imag, _ptr(out),
                               _ptr(workspace), workspace.numel() * workspace.element_size(),
                               _stream(stream)), "cascade_nmse")
+
+
+def dpd_nmse_status(records) -> int:
+    """Status of NMSE records (host array-like [n][DPD_NMSE_FIELDS] or flat): DPD_OK or
+    DPD_ERR_NONFINITE.  Runs on the host; copy device records first."""
+    a = np.ascontiguousarray(np.asarray(records, dtype=np.float32).reshape(-1))
+    if a.size == 0 or a.size % DPD_NMSE_FIELDS:
+        raise ValueError("records must hold whole DPD_NMSE_FIELDS-float records")
+    code = lib().dpd_nmse_status(a.ctypes.data_as(C.POINTER(C.c_float)), a.size // DPD_NMSE_FIELDS)
+    if code not in (DPD_OK, DPD_ERR_NONFINITE):
+        _check(code, "dpd_nmse_status")
+    return code
+
+
+def dpd_symbol_mse_workspace_size(n) -> int:
+    b = C.c_size_t(0)
+    _check(lib().dpd_symbol_mse_workspace_size(int(n), C.byref(b)), "dpd_symbol_mse_workspace_size")
+    return b.value
+
+
+def dpd_symbol_mse(n, z, t, out, grad, workspace, stream=None):
+    _check(lib().dpd_symbol_mse(int(n), _ptr(z), _ptr(t), _ptr(out), _ptr(grad), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream)),
+           "dpd_symbol_mse")
 
 
 def dpd_backward(tdnn, gmp, batch, x, w, coef, g, dw, loss, workspace, stream=None):

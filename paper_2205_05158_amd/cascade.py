@@ -58,10 +58,12 @@ class Cascade:
         return y
 
     def nmse(self, y, x):
+        """NMSE records [S + 1][DPD_NMSE_FIELDS]: (E, R, NMSE dB, non-finite count) per
+        stream, then pooled."""
         self._chk(y, (self.n_total, 2)); self._chk(x, (self.n_total, 2))
-        out = torch.empty(3 * (self.S + 1), dtype=torch.float32, device=self.device)
+        out = torch.empty((self.S + 1, L.DPD_NMSE_FIELDS), dtype=torch.float32, device=self.device)
         L.cascade_nmse(self.batch, y, x, self.gain, out, self.workspace)
-        return out.view(self.S + 1, 3)
+        return out
 
     def run(self, x, w, coef, want_u=True, want_y=True, want_nmse=True, want_grad=True):
         """One pass of the whole cascade; returns dict of the requested outputs."""
@@ -69,13 +71,22 @@ class Cascade:
         dev = self.device
         u = torch.empty_like(x) if want_u else None
         y = torch.empty_like(x) if want_y else None
-        nm = torch.empty(3 * (self.S + 1), dtype=torch.float32, device=dev) if want_nmse else None
+        nm = (torch.empty((self.S + 1, L.DPD_NMSE_FIELDS), dtype=torch.float32, device=dev)
+              if want_nmse else None)
         dw = torch.empty(self._w_shape(), dtype=torch.float32, device=dev) if want_grad else None
         loss = torch.empty(self.n_sets, dtype=torch.float32, device=dev) if want_grad else None
         L.dpd_cascade(self.tdnn, self.gmp, self.batch, x, w, coef, self.gain, u, y, nm, dw, loss,
                       self.workspace)
-        return {"u": u, "y": y, "nmse": None if nm is None else nm.view(self.S + 1, 3),
-                "dw": dw, "loss": loss}
+        return {"u": u, "y": y, "nmse": nm, "dw": dw, "loss": loss}
+
+    def loss(self, x, w, coef):
+        """Pooled loss per parameter set (device [n_sets]) computed by the library
+        (forward, GMP, NMSE; no reverse mode)."""
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape()); self._chk(coef, self._c_shape())
+        loss = torch.empty(self.n_sets, dtype=torch.float32, device=self.device)
+        L.dpd_cascade(self.tdnn, self.gmp, self.batch, x, w, coef, self.gain, None, None, None, None,
+                      loss, self.workspace)
+        return loss
 
     def autotune(self, x, w, coef, reps=3):
         """Pick this problem's launch shapes by timing on these inputs (blocks until
@@ -130,12 +141,7 @@ class CascadeFn(torch.autograd.Function):
             loss, dw = cascade.backward(x, w.detach(), coef)
             ctx.save_for_backward(dw)
         else:
-            nm = cascade.run(x, w, coef, want_u=False, want_y=False, want_nmse=True,
-                             want_grad=False)["nmse"]
-            if cascade.n_sets > 1:
-                loss = nm[:-1, 0] / nm[:-1, 1]
-            else:
-                loss = (nm[-1, 0] / nm[-1, 1]).reshape(1)
+            loss = cascade.loss(x, w.detach(), coef)
         return loss
 
     @staticmethod

@@ -202,7 +202,7 @@ Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
   size_t pos = 0;
   auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
   int64_t max_tiles = p.n_total / 32 + p.S + 1;   // any tile size >= 32
-  w.tile_part = take(sizeof(float2) * max_tiles);
+  w.tile_part = take(sizeof(float4) * max_tiles);
   w.inv_r = take(sizeof(float) * p.n_sets);
   w.loss_tmp = take(sizeof(float) * p.n_sets);
   w.u_buf = take(sizeof(float2) * p.n_total);
@@ -450,6 +450,42 @@ dpd_status pa_gmp_forward(const dpd_gmp_desc* gmp, const dpd_batch* batch, const
   return launch_status();
 }
 
+dpd_status dpd_symbol_mse_workspace_size(int64_t n, size_t* bytes_host) {
+  if (!bytes_host) return DPD_ERR_NULL;
+  if (n < 1) return DPD_ERR_SHAPE;
+  *bytes_host = align_up(sizeof(float4) * (size_t)mse_tiles(n));
+  return DPD_OK;
+}
+
+dpd_status dpd_symbol_mse(int64_t n, const float* z, const float* t, float* out, float* grad,
+                          void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (n < 1) return DPD_ERR_SHAPE;
+  if (!z || !t || !out || !workspace) return DPD_ERR_NULL;
+  if (!aligned(z, 8) || !aligned(t, 8) || !aligned(out, 4) || (grad && !aligned(grad, 8)) ||
+      !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (grad && (grad == z || grad == t)) return DPD_ERR_SHAPE;
+  if (workspace_bytes < align_up(sizeof(float4) * (size_t)mse_tiles(n))) return DPD_ERR_WORKSPACE;
+  {
+    DPD_PROF("symbol_mse");
+    launch_mse(n, z, t, (float)(2.0 / (double)n), grad, static_cast<float4*>(workspace), out, stream);
+  }
+  return launch_status();
+}
+
+dpd_status dpd_nmse_status(const float* nmse_host, int64_t n_records) {
+  if (!nmse_host) return DPD_ERR_NULL;
+  if (n_records < 1) return DPD_ERR_SHAPE;
+  for (int64_t r = 0; r < n_records; ++r) {
+    const float* rec = nmse_host + r * DPD_NMSE_FIELDS;
+    // NMSE_dB = -inf is the exact match E = 0 (a finite result); NaN or +inf is not
+    if (!(rec[3] == 0.f) || !isfinite(rec[0]) || !isfinite(rec[1]) || isnan(rec[2]) ||
+        (isinf(rec[2]) && rec[2] > 0.f))
+      return DPD_ERR_NONFINITE;
+  }
+  return DPD_OK;
+}
+
 dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x, float g_re,
                         float g_im, float* out, void* workspace, size_t workspace_bytes,
                         hipStream_t stream) {
@@ -463,7 +499,7 @@ dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x, 
   Ws L = ws_layout(nullptr, nullptr, p);
   if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
   StreamTable tab = make_table(p, kNmseTile);
-  float2* part = at<float2>(workspace, L.tile_part);
+  float4* part = at<float4>(workspace, L.tile_part);
   { DPD_PROF("nmse_tiles"); launch_nmse_tiles(tab, y, x, g_re, g_im, part, stream); }
   { DPD_PROF("nmse_final"); launch_nmse_final(tab, part, out, nullptr, nullptr, stream); }
   return launch_status();
@@ -491,7 +527,7 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   float* ubuf = u ? u : at<float>(workspace, L.u_buf);
   float* inv_r = at<float>(workspace, L.inv_r);
   float* lossp = loss ? loss : at<float>(workspace, L.loss_tmp);
-  float2* part = at<float2>(workspace, L.tile_part);
+  float4* part = at<float4>(workspace, L.tile_part);
   int64_t P = param_count(*tdnn);
   if (tdnn->impl == DPD_IMPL_PLAIN) {
     float* ybuf = y ? y : at<float>(workspace, L.y_buf);
@@ -596,7 +632,7 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
   float* ubuf = at<float>(workspace, L.u_buf);
   float* gub = at<float>(workspace, L.gu_buf);
   float2* gtab = at<float2>(workspace, L.gmp_tab);
-  float2* part = at<float2>(workspace, L.tile_part);
+  float4* part = at<float4>(workspace, L.tile_part);
   float* slots = at<float>(workspace, L.slots);
   const dpd_tune def = default_tune(td);
   const StreamTable btab = make_table(p, td.tile);
@@ -907,6 +943,7 @@ const char* dpd_status_string(dpd_status status) {
     case DPD_ERR_WORKSPACE: return "DPD_ERR_WORKSPACE: workspace too small";
     case DPD_ERR_LAUNCH: return "DPD_ERR_LAUNCH: the HIP runtime reported an error";
     case DPD_ERR_ALIGN: return "DPD_ERR_ALIGN: misaligned pointer";
+    case DPD_ERR_NONFINITE: return "DPD_ERR_NONFINITE: non-finite samples in the NMSE records";
   }
   return "unknown dpd_status";
 }

@@ -69,9 +69,10 @@ __host__ __device__ inline int wg_of_tile(int t, int G, int n_tiles) {
 // Maclaurin series of tanh through x^11 (coefficients 1, -1/3, 2/15, -17/315,
 // 62/2835, -1382/155925; truncation error < 3e-10 relative for |x| < 1/4).  Sign
 // restored; saturates to +-1 for |x| > 10 (tanh rounds to 1 in float32 beyond ~9.01).
+// A NaN argument gives NaN (the clamp is a comparison, which keeps NaN, not fminf).
 __device__ __forceinline__ float tanh_f32(float x) {
   float ax = fabsf(x);
-  float e = __builtin_amdgcn_exp2f(fminf(ax, 10.0f) * 2.8853900817779268f);   // 2 log2(e)
+  float e = __builtin_amdgcn_exp2f((ax > 10.0f ? 10.0f : ax) * 2.8853900817779268f);   // 2 log2(e)
   float big = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
   float x2 = ax * ax;
   float p = -8.8632355299e-3f;                  // -1382/155925

@@ -82,13 +82,14 @@ __global__ void k_gmp_table(const float* __restrict__ coef, float2* __restrict__
 // coefficients are read from the table (wave-uniform addresses: scalar loads into
 // SGPRs, used directly as FMA operands):
 //   y = GMP(u) (stored when y_out is not null), g_y = 2 (y - G x) inside the stream,
-//   the tile's E = sum |y - G x|^2 and R = sum |G x|^2 (fixed reduction tree), and
+//   the tile's E = sum |y - G x|^2, R = sum |G x|^2 and count of samples where either
+//   square is not finite (fixed reduction tree), and
 //   g_u[m] = dL/du[m] of L = sum |y - G x|^2 (the gather form in gmp.hpp).
 template <int K, int M, int L, int S>
 __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __restrict__ x,
                                                             const float* __restrict__ u,
                                                             const float2* __restrict__ tab, float g_re,
-                                                            float g_im, float2* __restrict__ tile_part,
+                                                            float g_im, float4* __restrict__ tile_part,
                                                             float* __restrict__ gu_out,
                                                             float* __restrict__ y_out) {
   using G = Gmp<K, M, L>;
@@ -103,6 +104,7 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
   __shared__ float2 qw[QW][M + 1];
   __shared__ float2 gyw[YW];
   __shared__ float red[4 * S];
+  __shared__ uint32_t redn[S];
 
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
@@ -133,6 +135,7 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
   __syncthreads();
   // y and g_y on [t0 - L, t0 + S + M + L); E and R on the tile's own samples
   Comp Ec, Rc;
+  uint32_t nf = 0;
   for (int i = tid; i < YW; i += S) {
     const int64_t n = t0 - L + i;
     float2 gyv = make_float2(0.f, 0.f);
@@ -149,14 +152,17 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
       const float er = y.x - tr, ei = y.y - ti;
       gyv = make_float2(2.f * er, 2.f * ei);
       if (i >= L && i < L + S) {
-        Ec.add(er * er + ei * ei);
-        Rc.add(tr * tr + ti * ti);
+        const float e2 = er * er + ei * ei, r2 = tr * tr + ti * ti;
+        nf += !isfinite(e2 + r2);
+        Ec.add(e2);
+        Rc.add(r2);
         if (y_out) st2(y_out, n, y);
       }
     }
     gyw[i] = gyv;
   }
   red[tid] = Ec.s; red[S + tid] = Ec.c; red[2 * S + tid] = Rc.s; red[3 * S + tid] = Rc.c;
+  redn[tid] = nf;
   __syncthreads();
   for (int w2 = S / 2; w2 > 0; w2 >>= 1) {
     if (tid < w2) {
@@ -164,10 +170,11 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
       a.add(red[tid + w2]); a.add(red[S + tid + w2]);
       b.add(red[2 * S + tid + w2]); b.add(red[3 * S + tid + w2]);
       red[tid] = a.s; red[S + tid] = a.c; red[2 * S + tid] = b.s; red[3 * S + tid] = b.c;
+      redn[tid] += redn[tid + w2];
     }
     __syncthreads();
   }
-  if (tid == 0) tile_part[t] = make_float2(red[0] + red[S], red[2 * S] + red[3 * S]);
+  if (tid == 0) tile_part[t] = make_float4(red[0] + red[S], red[2 * S] + red[3 * S], (float)redn[0], 0.f);
   // g_u at the tile's own samples
   const int64_t m = t0 + tid;
   if (m < hi) {
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
 }  // namespace
 
 void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
-                    const float* coef, float2* tab, float g_re, float g_im, float2* tile_part,
+                    const float* coef, float2* tab, float g_re, float g_im, float4* tile_part,
                     float* gu, float* y, hipStream_t s) {
   gmp_dispatch(g.K, g.M, g.L, [&]<int K, int M, int L>() {
     const int n_sets = st.per_stream ? st.n : 1;

@@ -11,13 +11,20 @@
 namespace dpdmi {
 
 // ------------------------------------------------------------------ shared
-// E/R partial per tile of the stream table (tile = table.tile samples).
+// (E, R, non-finite count, 0) partial per tile of the stream table (tile = table.tile
+// samples).
 void launch_nmse_tiles(const StreamTable& st, const float* y, const float* x, float g_re,
-                       float g_im, float2* tile_part, hipStream_t s);
-// Per-stream and pooled (E, R, NMSE dB) from the tile partials; optional per-set
-// pooled loss and 1/R per set (inv_r may be null).
-void launch_nmse_final(const StreamTable& st, const float2* tile_part, float* out3, float* loss,
+                       float g_im, float4* tile_part, hipStream_t s);
+// Per-stream and pooled NMSE records (E, R, NMSE dB, non-finite count) from the tile
+// partials (rec may be null); optional per-set pooled loss and 1/R per set (inv_r may
+// be null).
+void launch_nmse_final(const StreamTable& st, const float4* tile_part, float* rec, float* loss,
                        float* inv_r, hipStream_t s);
+// Symbol MSE of n complex values: out[0] = sum |z - t|^2 / n, out[1] = non-finite count,
+// grad (may be null) = scale (z - t); part holds mse_tiles(n) tile partials.
+int mse_tiles(int64_t n);
+void launch_mse(int64_t n, const float* z, const float* t, float scale, float* grad, float4* part,
+                float* out, hipStream_t s);
 
 // ------------------------------------------------------------------ plain path
 void launch_plain_features(const float* x, int64_t lo, int64_t c0, int cn, int taps, float* F,
@@ -130,7 +137,7 @@ void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u
 // tab: workspace of 2 * J float2 per parameter set (the coefficients and their
 // derivative-weighted copy, written first on the same stream).
 void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
-                    const float* coef, float2* tab, float g_re, float g_im, float2* tile_part,
+                    const float* coef, float2* tab, float g_re, float g_im, float4* tile_part,
                     float* gu, float* y, hipStream_t s);
 // TDNN recompute + reverse mode from g_u: dW partial slots per (workgroup, stream).
 void launch_tdnn_bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu,

@@ -1,7 +1,8 @@
-// NMSE against the linear-gain target (Sec. II-B): E = sum|y - Gx|^2, R = sum|Gx|^2.
-// Per-tile partials (one workgroup per tile, fixed tree) and a single-workgroup
-// final pass that sums each stream's tiles in a fixed order with Neumaier
-// compensation, so results are deterministic and accurate in float32.
+// NMSE against the linear-gain target (Sec. II-B): E = sum|y - Gx|^2, R = sum|Gx|^2,
+// and the count of samples whose |y - Gx|^2 or |Gx|^2 is not finite.  Per-tile
+// partials (one workgroup per tile, fixed tree) and a single-workgroup final pass
+// that sums each stream's tiles in a fixed order with Neumaier compensation, so
+// results are deterministic and accurate in float32.
 #include "kernels.hpp"
 
 namespace dpdmi {
@@ -9,6 +10,7 @@ namespace dpdmi {
 namespace {
 
 constexpr int kRedThreads = 256;
+constexpr int kMseTile = 4096;   // values per symbol-MSE tile
 
 __device__ void block_reduce2(Comp& a, Comp& b, float* sh) {
   // sh: 4 * kRedThreads floats
@@ -31,48 +33,76 @@ __device__ void block_reduce2(Comp& a, Comp& b, float* sh) {
   __syncthreads();
 }
 
+// Sum of one unsigned count per thread (fixed tree); every thread gets the total.
+__device__ uint32_t block_sum_u32(uint32_t v, uint32_t* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const uint32_t r = sh[0];
+  __syncthreads();
+  return r;
+}
+
 __global__ __launch_bounds__(kRedThreads) void k_nmse_tiles(StreamTable st, const float* __restrict__ y,
                                                             const float* __restrict__ x, float g_re,
-                                                            float g_im, float2* __restrict__ part) {
+                                                            float g_im, float4* __restrict__ part) {
   __shared__ float sh[4 * kRedThreads];
+  __shared__ uint32_t shn[kRedThreads];
   int t = blockIdx.x;
   int s = stream_of_tile(st, t);
   int64_t lo = st.off[s], hi = st.off[s + 1];
   int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * st.tile;
   int64_t t1 = min(hi, t0 + st.tile);
   Comp E, R;
+  uint32_t nf = 0;
   for (int64_t n = t0 + threadIdx.x; n < t1; n += kRedThreads) {
     float2 yv = ld2(y, n), xv = ld2(x, n);
     float tr = g_re * xv.x - g_im * xv.y, ti = g_re * xv.y + g_im * xv.x;
     float er = yv.x - tr, ei = yv.y - ti;
-    E.add(er * er + ei * ei);
-    R.add(tr * tr + ti * ti);
+    const float e2 = er * er + ei * ei, r2 = tr * tr + ti * ti;
+    nf += !isfinite(e2 + r2);
+    E.add(e2);
+    R.add(r2);
   }
   block_reduce2(E, R, sh);
-  if (threadIdx.x == 0) part[t] = make_float2(E.value(), R.value());
+  nf = block_sum_u32(nf, shn);
+  if (threadIdx.x == 0) part[t] = make_float4(E.value(), R.value(), (float)nf, 0.f);
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_nmse_final(StreamTable st, const float2* __restrict__ part,
-                                                            float* __restrict__ out3,
+// Records of DPD_NMSE_FIELDS floats: (E, R, NMSE dB, non-finite count).
+__global__ __launch_bounds__(kRedThreads) void k_nmse_final(StreamTable st, const float4* __restrict__ part,
+                                                            float* __restrict__ rec,
                                                             float* __restrict__ loss,
                                                             float* __restrict__ inv_r) {
+  constexpr int F = DPD_NMSE_FIELDS;
   __shared__ float sh[4 * kRedThreads];
+  __shared__ uint32_t shn[kRedThreads];
   Comp Et, Rt;   // pooled over all streams
+  uint32_t nft = 0;
   for (int s = 0; s < st.n; ++s) {
     Comp E, R;
+    uint32_t nf = 0;
     for (int t = st.tile0[s] + threadIdx.x; t < st.tile0[s + 1]; t += kRedThreads) {
-      float2 v = part[t];
+      float4 v = part[t];
       E.add(v.x);
       R.add(v.y);
+      nf += (uint32_t)v.z;
     }
     block_reduce2(E, R, sh);
+    nf = block_sum_u32(nf, shn);
     float e = E.value(), r = R.value();
     if (threadIdx.x == 0) {
-      if (out3) {
-        out3[3 * s] = e;
-        out3[3 * s + 1] = r;
-        out3[3 * s + 2] = 10.f * log10f(e / r);
+      if (rec) {
+        rec[F * s] = e;
+        rec[F * s + 1] = r;
+        rec[F * s + 2] = 10.f * log10f(e / r);
+        rec[F * s + 3] = (float)nf;
       }
+      nft += nf;
       Et.add(E.s); Et.add(E.c);
       Rt.add(R.s); Rt.add(R.c);
       if (st.per_stream) {
@@ -83,10 +113,11 @@ __global__ __launch_bounds__(kRedThreads) void k_nmse_final(StreamTable st, cons
   }
   if (threadIdx.x == 0) {
     float e = Et.value(), r = Rt.value();
-    if (out3) {
-      out3[3 * st.n] = e;
-      out3[3 * st.n + 1] = r;
-      out3[3 * st.n + 2] = 10.f * log10f(e / r);
+    if (rec) {
+      rec[F * st.n] = e;
+      rec[F * st.n + 1] = r;
+      rec[F * st.n + 2] = 10.f * log10f(e / r);
+      rec[F * st.n + 3] = (float)nft;
     }
     if (!st.per_stream) {
       if (loss) loss[0] = e / r;
@@ -95,16 +126,71 @@ __global__ __launch_bounds__(kRedThreads) void k_nmse_final(StreamTable st, cons
   }
 }
 
+// Symbol MSE: per tile of kMseTile values the compensated sum of |z - t|^2 and the
+// count of non-finite terms, and (when grad is not null) grad = scale (z - t).
+__global__ __launch_bounds__(kRedThreads) void k_mse_tiles(int64_t n, const float* __restrict__ z,
+                                                           const float* __restrict__ tg, float scale,
+                                                           float* __restrict__ grad,
+                                                           float4* __restrict__ part) {
+  __shared__ float sh[4 * kRedThreads];
+  __shared__ uint32_t shn[kRedThreads];
+  const int64_t t0 = (int64_t)blockIdx.x * kMseTile;
+  const int64_t t1 = min(n, t0 + kMseTile);
+  Comp E, dummy;
+  uint32_t nf = 0;
+  for (int64_t i = t0 + threadIdx.x; i < t1; i += kRedThreads) {
+    const float2 zv = ld2(z, i), tv = ld2(tg, i);
+    const float er = zv.x - tv.x, ei = zv.y - tv.y;
+    const float e2 = er * er + ei * ei;
+    nf += !isfinite(e2);
+    E.add(e2);
+    if (grad) st2(grad, i, make_float2(scale * er, scale * ei));
+  }
+  block_reduce2(E, dummy, sh);
+  nf = block_sum_u32(nf, shn);
+  if (threadIdx.x == 0) part[blockIdx.x] = make_float4(E.value(), 0.f, (float)nf, 0.f);
+}
+
+// out[0] = (sum over the tiles, fixed order) / n, out[1] = non-finite count.
+__global__ __launch_bounds__(kRedThreads) void k_mse_final(int n_tiles, int64_t n,
+                                                           const float4* __restrict__ part,
+                                                           float* __restrict__ out) {
+  __shared__ float sh[4 * kRedThreads];
+  __shared__ uint32_t shn[kRedThreads];
+  Comp E, dummy;
+  uint32_t nf = 0;
+  for (int t = threadIdx.x; t < n_tiles; t += kRedThreads) {
+    const float4 v = part[t];
+    E.add(v.x);
+    nf += (uint32_t)v.z;
+  }
+  block_reduce2(E, dummy, sh);
+  nf = block_sum_u32(nf, shn);
+  if (threadIdx.x == 0) {
+    out[0] = (float)((double)E.value() / (double)n);
+    out[1] = (float)nf;
+  }
+}
+
 }  // namespace
 
+int mse_tiles(int64_t n) { return (int)ceil_div64(n, kMseTile); }
+
+void launch_mse(int64_t n, const float* z, const float* t, float scale, float* grad, float4* part,
+                float* out, hipStream_t s) {
+  const int nt = mse_tiles(n);
+  k_mse_tiles<<<nt, kRedThreads, 0, s>>>(n, z, t, scale, grad, part);
+  k_mse_final<<<1, kRedThreads, 0, s>>>(nt, n, part, out);
+}
+
 void launch_nmse_tiles(const StreamTable& st, const float* y, const float* x, float g_re,
-                       float g_im, float2* tile_part, hipStream_t s) {
+                       float g_im, float4* tile_part, hipStream_t s) {
   k_nmse_tiles<<<st.n_tiles, kRedThreads, 0, s>>>(st, y, x, g_re, g_im, tile_part);
 }
 
-void launch_nmse_final(const StreamTable& st, const float2* tile_part, float* out3, float* loss,
+void launch_nmse_final(const StreamTable& st, const float4* tile_part, float* rec, float* loss,
                        float* inv_r, hipStream_t s) {
-  k_nmse_final<<<1, kRedThreads, 0, s>>>(st, tile_part, out3, loss, inv_r);
+  k_nmse_final<<<1, kRedThreads, 0, s>>>(st, tile_part, rec, loss, inv_r);
 }
 
 }  // namespace dpdmi

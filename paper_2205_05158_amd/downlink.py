@@ -164,6 +164,20 @@ class Downlink:
         return g_s
 
 
+def symbol_mse(z, t):
+    """The library's symbol MSE (dpd_symbol_mse) of complex values z against targets t
+    (contiguous float32 [..][2] of one shape): (L = sum |z - t|^2 / n as a device scalar,
+    dL/dz = 2 (z - t) / n)."""
+    if z.shape != t.shape or z.shape[-1] != 2 or not (z.is_contiguous() and t.is_contiguous()):
+        raise ValueError("z and t must be contiguous [..][2] tensors of one shape")
+    n = z.numel() // 2
+    out = torch.empty(2, dtype=torch.float32, device=z.device)
+    grad = torch.empty_like(z)
+    ws = torch.empty(max(L.dpd_symbol_mse_workspace_size(n), 256), dtype=torch.uint8, device=z.device)
+    L.dpd_symbol_mse(n, z, t, out, grad, ws)
+    return out[0], grad
+
+
 def receiver_loss_grad(dl: Downlink, net: FdNn, s, tx, w, pt, alpha, pa_coef, g, h, sym_per_ch=1):
     """The supervised criterion of Sec. V-A-2 for the FD-NN, on the device: the UE symbols s
     through the FD-NN, guard-band ZF precoding (every subcarrier), the link (PAs, channel)
@@ -174,9 +188,8 @@ def receiver_loss_grad(dl: Downlink, net: FdNn, s, tx, w, pt, alpha, pa_coef, g,
     x = dl.precode(v, pt, alpha, sym_per_ch=sym_per_ch, all_bins=True)
     errors, r = dl.link(x, pa_coef, g, h, alpha, tx, sym_per_ch=sym_per_ch, want_r=True)
     bins = torch.as_tensor(_data_bins(dl.n_fft, dl.n_data), device=s.device)
-    e = r - s.index_select(2, bins)
-    loss = (e * e).sum() / n
-    g_x = dl.link_backward(x, pa_coef, g, h, alpha, ((2.0 / n) * e).contiguous(), sym_per_ch=sym_per_ch)
+    loss, g_r = symbol_mse(r, s.index_select(2, bins).contiguous())
+    g_x = dl.link_backward(x, pa_coef, g, h, alpha, g_r, sym_per_ch=sym_per_ch)
     g_v = dl.precode_backward(g_x, pt, alpha, sym_per_ch=sym_per_ch, all_bins=True)
     return loss, net.backward(s, w, g_v), errors
 
@@ -196,9 +209,8 @@ def receiver_loss_grad_fdcnn(dl: Downlink, net, s, tx, w, pt, alpha, pa_coef, g,
     v_full.index_copy_(2, bins, v)
     x = dl.precode(v_full, pt, alpha, sym_per_ch=sym_per_ch, all_bins=False)
     errors, r = dl.link(x, pa_coef, g, h, alpha, tx, sym_per_ch=sym_per_ch, want_r=True)
-    e = r - s_data
-    loss = (e * e).sum() / n
-    g_x = dl.link_backward(x, pa_coef, g, h, alpha, ((2.0 / n) * e).contiguous(), sym_per_ch=sym_per_ch)
+    loss, g_r = symbol_mse(r, s_data)
+    g_x = dl.link_backward(x, pa_coef, g, h, alpha, g_r, sym_per_ch=sym_per_ch)
     g_v = dl.precode_backward(g_x, pt, alpha, sym_per_ch=sym_per_ch, all_bins=False)
     g_items = g_v.index_select(2, bins).contiguous().view(n_sym * dl.users, dl.n_data, 2)
     return loss, net.backward(items, w, g_items), errors

@@ -48,16 +48,22 @@ class FdCnn:
         """`steps` Adam updates of w in place on L = sum |out - target|^2 / (items n_d).
         Returns the loss before each step (device [steps]) and the state (m, v, t)."""
         n = self._items(s)
+        if target.shape != s.shape or not target.is_contiguous():
+            raise ValueError("target must be a contiguous tensor shaped like s")
         m, v, t = (torch.zeros_like(w), torch.zeros_like(w), 0) if state is None else state
         losses = torch.empty(steps, dtype=torch.float32, device=self.device)
-        scale = 2.0 / (n * self.n_d)
+        nv = n * self.n_d
+        mse = torch.empty((steps, 2), dtype=torch.float32, device=self.device)
+        g_out = torch.empty_like(s)
+        ws = torch.empty(max(L.dpd_symbol_mse_workspace_size(nv), 256), dtype=torch.uint8,
+                         device=self.device)
         for i in range(steps):
             out = self.forward(s, w)
-            e = out - target
-            losses[i] = (e * e).sum() / (n * self.n_d)
-            dw = self.backward(s, w, (e * scale).contiguous())
+            L.dpd_symbol_mse(nv, out, target, mse[i], g_out, ws)
+            dw = self.backward(s, w, g_out)
             t += 1
             L.dpd_adam_step(dw, w, m, v, t, lr=lr)
+        losses.copy_(mse[:, 0])
         return losses, (m, v, t)
 
 

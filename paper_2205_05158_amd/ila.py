@@ -53,9 +53,9 @@ class GmpIla:
         y = torch.empty_like(x)
         L.pa_gmp_forward(self.dpd, self.batch, x, dpd_coef, u)
         L.pa_gmp_forward(self.pa_desc, self.batch, u, pa_coef, y)
-        nm = torch.empty(3 * (self.S + 1), dtype=torch.float32, device=self.device)
+        nm = torch.empty((self.S + 1, L.DPD_NMSE_FIELDS), dtype=torch.float32, device=self.device)
         L.cascade_nmse(self.batch, y, x, self.gain, nm, self.workspace)
-        return u, y, nm[-1]
+        return u, y, nm[-1, 2]
 
     def run(self, x, pa_coef, iters, ridge=0.0, dpd_coef=None):
         """`iters` ILA iterations from dpd_coef (default identity).  Returns the NMSE in dB

@@ -117,8 +117,47 @@ def test_acpr_arguments_rejected(dpdlib):
 
 
 def test_status_strings(dpdlib):
-    for code in range(-6, 1):
+    for code in range(-7, 1):
         assert D.status_string(code).startswith("DPD_")
+    assert "NONFINITE" in D.status_string(L.DPD_ERR_NONFINITE)
+
+
+def test_nmse_status_host(dpdlib):
+    """dpd_nmse_status reads host copies of the NMSE records (E, R, NMSE dB, count): a
+    record with a non-finite count, E, R or an NMSE of NaN / +inf is DPD_ERR_NONFINITE;
+    the exact match E = 0 (NMSE = -inf dB) is a finite result."""
+    assert L.DPD_NMSE_FIELDS == 4
+    good = np.array([[1.0, 2.0, -3.0103, 0.0], [0.0, 2.0, -np.inf, 0.0]], np.float32)
+    assert D.dpd_nmse_status(good) == L.DPD_OK
+    for bad_rec in ([1.0, 2.0, -3.0, 1.0], [np.nan, 2.0, np.nan, 0.0], [np.inf, 2.0, np.inf, 0.0],
+                    [1.0, np.inf, -np.inf, 0.0], [1.0, 0.0, np.inf, 0.0], [0.0, 0.0, np.nan, 0.0]):
+        recs = np.vstack([good, np.array(bad_rec, np.float32)])
+        assert D.dpd_nmse_status(recs) == L.DPD_ERR_NONFINITE, bad_rec
+    lib = L.lib()
+    assert lib.dpd_nmse_status(None, 1) == L.DPD_ERR_NULL
+    a = np.zeros(4, np.float32)
+    assert lib.dpd_nmse_status(a.ctypes.data_as(C.POINTER(C.c_float)), 0) == L.DPD_ERR_SHAPE
+    with pytest.raises(ValueError):
+        D.dpd_nmse_status(np.zeros(6, np.float32))
+
+
+def test_symbol_mse_arguments_rejected(dpdlib):
+    lib = L.lib()
+    ws = L.dpd_symbol_mse_workspace_size(10000)
+    assert ws >= 16 * 3
+    assert L.dpd_symbol_mse_workspace_size(10000) < L.dpd_symbol_mse_workspace_size(10 ** 7)
+    b = C.c_size_t(0)
+    assert lib.dpd_symbol_mse_workspace_size(0, C.byref(b)) == L.DPD_ERR_SHAPE
+    assert lib.dpd_symbol_mse_workspace_size(5, None) == L.DPD_ERR_NULL
+    mse = lib.dpd_symbol_mse
+    assert mse(0, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE
+    assert mse(10, None, FAKE, FAKE, None, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    assert mse(10, FAKE, FAKE, None, None, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
+    assert mse(10, FAKE, FAKE, FAKE, None, None, 1 << 40, None) == L.DPD_ERR_NULL
+    assert mse(10, C.c_void_p(0x100004), FAKE, FAKE, None, FAKE, 1 << 40, None) == L.DPD_ERR_ALIGN
+    assert mse(10, FAKE, FAKE, FAKE, None, C.c_void_p(0x100010), 1 << 40, None) == L.DPD_ERR_ALIGN
+    assert mse(10, FAKE, C.c_void_p(0x200000), FAKE, FAKE, FAKE, 1 << 40, None) == L.DPD_ERR_SHAPE  # grad == z
+    assert mse(10 ** 7, FAKE, FAKE, FAKE, None, FAKE, 256, None) == L.DPD_ERR_WORKSPACE
 
 
 def test_tune_table_host(dpdlib):
