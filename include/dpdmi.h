@@ -141,6 +141,23 @@ dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x,
                         float g_re, float g_im, float* out,
                         void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): cascade_nmse without a workspace.
+ * Same arguments, records and kernels as cascade_nmse; the per-tile partial sums live
+ * in a static device array of DPD_NOALLOC_NMSE_MAX_TILES records of 16 bytes (4 MiB;
+ * tiles of 256 samples, one tile count per stream rounded up, so up to about 2^26
+ * samples), held by each device the library runs on until the process ends.  A problem
+ * needing more tiles returns DPD_ERR_WORKSPACE before any HIP call.  The call allocates
+ * nothing and calls no allocating routine; the array's device address is looked up once
+ * per device (hipGetSymbolAddress, the device current) on the first call there.  Every
+ * call on one device shares the array: calls that may overlap on one device (other
+ * streams or host threads) race and must be serialised by the caller; the array keeps
+ * the last call's partials, and each call writes every partial it reads, so nothing
+ * needs clearing. */
+enum { DPD_NOALLOC_NMSE_MAX_TILES = 1 << 18 };
+dpd_status cascade_nmse_noalloc(const dpd_batch* batch, const float* y, const float* x,
+                                float g_re, float g_im, float* out, hipStream_t stream);
+
 /* Direct-learning gradient (Sec. V-A-2): runs DPD -> GMP -> NMSE and the reverse
  * mode through both, returning for each parameter set p the pooled loss
  * loss[p] = sum_{s in p} E_s / sum_{s in p} R_s and dw[p] = d loss[p] / d w_p

@@ -83,6 +83,7 @@ _SIGS = {
     "dpd_autotune": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
                                C.c_float, C.c_float, C.c_int32, _P, C.c_size_t, _P, C.POINTER(Tune)]),
     "dpd_nmse_status": (C.c_int, [C.POINTER(C.c_float), C.c_int64]),
+    "cascade_nmse_noalloc": (C.c_int, [C.POINTER(Batch), _P, _P, C.c_float, C.c_float, _P, _P]),
     "dpd_symbol_mse_workspace_size": (C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
     "dpd_symbol_mse": (C.c_int, [C.c_int64, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "dpd_adam_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int32, C.c_double, C.c_double,
@@ -236,6 +237,15 @@ def dpd_symbol_mse(n, z, t, out, grad, workspace, stream=None):
     _check(lib().dpd_symbol_mse(int(n), _ptr(z), _ptr(t), _ptr(out), _ptr(grad), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream)),
            "dpd_symbol_mse")
+
+
+DPD_NOALLOC_NMSE_MAX_TILES = 1 << 18
+
+
+def cascade_nmse_noalloc(batch, y, x, g, out, stream=None):
+    g = complex(g)
+    _check(lib().cascade_nmse_noalloc(C.byref(batch), _ptr(y), _ptr(x), g.real, g.imag, _ptr(out),
+                                      _stream(stream)), "cascade_nmse_noalloc")
 
 
 def dpd_backward(tdnn, gmp, batch, x, w, coef, g, dw, loss, workspace, stream=None):

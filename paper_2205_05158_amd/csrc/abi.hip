@@ -22,6 +22,13 @@ void launch_plain_finalize_sets(const float* acc, int taps, int n_hidden, int hi
 
 using namespace dpdmi;
 
+// Scratch of cascade_nmse_noalloc: the per-tile NMSE partials (E, R, non-finite count) of
+// problems of up to DPD_NOALLOC_NMSE_MAX_TILES tiles, in a static device array (each
+// device that runs the library holds its own copy until the process ends).  In host code
+// this name is only a stand-in for the symbol: kernels and runtime calls get the device
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float4 scratch[DPD_NOALLOC_NMSE_MAX_TILES];
+
 namespace {
 
 constexpr int kNmseTile = 256;        // tile of the stand-alone NMSE pass
@@ -470,6 +477,40 @@ dpd_status dpd_symbol_mse(int64_t n, const float* z, const float* t, float* out,
     DPD_PROF("symbol_mse");
     launch_mse(n, z, t, (float)(2.0 / (double)n), grad, static_cast<float4*>(workspace), out, stream);
   }
+  return launch_status();
+}
+
+// Device address of `scratch` on the current device, looked up once per device (with
+// that device current) and kept; null if the runtime reports an error.
+float4* noalloc_scratch_ptr() {
+  static std::mutex mu;
+  static float4* addr[64] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    addr[dev] = static_cast<float4*>(p);
+  }
+  return addr[dev];
+}
+
+dpd_status cascade_nmse_noalloc(const dpd_batch* batch, const float* y, const float* x, float g_re,
+                                float g_im, float* out, hipStream_t stream) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!y || !x || !out) return DPD_ERR_NULL;
+  if (!aligned(y, 8) || !aligned(x, 8) || !aligned(out, 4)) return DPD_ERR_ALIGN;
+  if (!isfinite(g_re) || !isfinite(g_im) || (g_re == 0.f && g_im == 0.f)) return DPD_ERR_SHAPE;
+  StreamTable tab = make_table(p, kNmseTile);
+  if (tab.n_tiles > DPD_NOALLOC_NMSE_MAX_TILES) return DPD_ERR_WORKSPACE;
+  float4* part = noalloc_scratch_ptr();
+  if (!part) return DPD_ERR_LAUNCH;
+  // every partial the final pass reads is written by the tile pass first: nothing to clear
+  { DPD_PROF("nmse_tiles"); launch_nmse_tiles(tab, y, x, g_re, g_im, part, stream); }
+  { DPD_PROF("nmse_final"); launch_nmse_final(tab, part, out, nullptr, nullptr, stream); }
   return launch_status();
 }
 

@@ -141,6 +141,23 @@ def test_nmse_status_host(dpdlib):
         D.dpd_nmse_status(np.zeros(6, np.float32))
 
 
+def test_noalloc_nmse_arguments_rejected(dpdlib):
+    """cascade_nmse_noalloc checks its arguments and the size of its static scratch
+    before any HIP call."""
+    lib = L.lib()
+    f = lib.cascade_nmse_noalloc
+    b = D.make_batch([0, 1000])
+    assert f(C.byref(b), None, FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_NULL
+    assert f(C.byref(b), FAKE, FAKE, 1.0, 0.0, None, None) == L.DPD_ERR_NULL
+    assert f(C.byref(b), C.c_void_p(0x100004), FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_ALIGN
+    assert f(C.byref(b), FAKE, FAKE, 0.0, 0.0, FAKE, None) == L.DPD_ERR_SHAPE
+    assert f(C.byref(D.make_batch([0, 0])), FAKE, FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_SHAPE
+    # tiles of 256 samples, one count per stream rounded up
+    cap = L.DPD_NOALLOC_NMSE_MAX_TILES * 256
+    too_big = D.make_batch([0, cap + 1])
+    assert f(C.byref(too_big), FAKE, FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_WORKSPACE
+
+
 def test_symbol_mse_arguments_rejected(dpdlib):
     lib = L.lib()
     ws = L.dpd_symbol_mse_workspace_size(10000)
