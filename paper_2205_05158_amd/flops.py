@@ -78,3 +78,65 @@ def gmp_train_flops(K: int, M: int, L: int) -> dict:
     as the multiplied sample and inside the envelope)."""
     f = gmp_flops_fig3(K, M, L)
     return {"fwd": f, "bwd": 2 * f, "total": 3 * f}
+
+
+# ---------------------------------------------------------------- executed counts
+# The kernels evaluate eq. (9) in the factorised form y[n] = sum_l u[n-l] Q_l(n-l), each
+# Q_l a polynomial in |u| at one position (and its neighbours for the b, c families)
+# evaluated by Horner's rule: one complex-by-real fused multiply-add (4 FLOPs) per
+# coefficient instead of the 8 FLOPs per complex coefficient that eq. (10) counts for the
+# direct sum of products.  These counts are what the kernels execute (a multiply-add is
+# 2 FLOPs), and what their vector-ALU roofline is taken against.
+
+def gmp_q_executed(K: int, M: int, L: int) -> int:
+    """FLOPs of all M + 1 polynomials Q_l at one position: the a family by Horner over
+    k = 0..K-1 (4 (K - 1)), per lag g the b and c families over k = 1..K-1 (4 (K - 2)
+    each) and their combination (8)."""
+    per_l = 4 * (K - 1)
+    if K > 1:
+        per_l += L * (2 * 4 * (K - 2) + 8)
+    return (M + 1) * per_l
+
+
+def gmp_y_executed(M: int) -> int:
+    """FLOPs of y[n] = sum_l u[n-l] Q_l(n-l): a complex product and accumulation per tap."""
+    return 8 * (M + 1)
+
+
+def gmp_grad_executed(K: int, M: int, L: int) -> int:
+    """FLOPs of the gather-form reverse mode at one sample: conj(Q_l) g_y per tap (8),
+    and per envelope term (the a family, and per lag the b and c families) the weight
+    conj(g_y) u (6), its products with C_1 (4) and with the Horner sum of k C_k r^(k-2)
+    (4 + 4 (K - 3)); 10 for the final combination."""
+    d2 = 4 * max(K - 3, 0)
+    per_l = 8
+    if K > 1:
+        env = 6 + 4 + d2 + 4
+        per_l += env + 2 * L * env
+    return (M + 1) * per_l + 10
+
+
+def gmp_bwd_executed(K: int, M: int, L: int, tile: int) -> float:
+    """Per sample of the TD reverse-mode GMP kernel with `tile`-sample tiles: Q on the tile
+    and a halo of M + L positions each side, y, error and gradient seed (8 more FLOPs)
+    on the tile plus L behind and M + L ahead, the gather-form gradient on the tile."""
+    q = gmp_q_executed(K, M, L) * (tile + 2 * (M + L)) / tile
+    y = (gmp_y_executed(M) + 8) * (tile + M + 2 * L) / tile
+    return q + y + gmp_grad_executed(K, M, L)
+
+
+def fft_nominal(n: int) -> float:
+    """Per-point FLOPs of one n-point complex FFT, the radix-2 nominal 5 log2 n."""
+    return 5 * math.log2(n)
+
+
+def link_pa_executed(K: int, M: int, L: int, n: int) -> float:
+    """Per sample of the cyclic PA kernel of the downlink (one antenna row): IDFT, Q and y
+    on every sample (cyclic: no halo), DFT."""
+    return gmp_q_executed(K, M, L) + gmp_y_executed(M) + 2 * fft_nominal(n)
+
+
+def link_pa_bwd_executed(K: int, M: int, L: int, n: int) -> float:
+    """Per sample of its reverse mode: IDFT of x and of the output gradient, Q, the
+    gather-form gradient, DFT."""
+    return gmp_q_executed(K, M, L) + gmp_grad_executed(K, M, L) + 3 * fft_nominal(n)

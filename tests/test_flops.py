@@ -36,3 +36,22 @@ def test_tdnn_counts():
     assert f["fwd_mma"] == 2 * (80 * 128 + 3 * 128 * 128)
     assert f["fwd_mma"] + f["out"] + f["bwd_mma"] + f["bwd_out"] == f["total"]
     assert F.gmp_coeffs(9, 7, 4) == 584
+
+
+def test_executed_gmp_counts_follow_the_coefficient_count():
+    """Horner evaluation costs 4 FLOPs (one complex-by-real multiply-add) per coefficient
+    beyond the leading one of each polynomial: (M + 1) polynomials of the a family and
+    2 L (M + 1) of the b and c families, plus 8 FLOPs per (l, g) to combine them; the
+    executed count is below eq. (10)'s 8 FLOPs per coefficient."""
+    for K in range(2, 10):
+        for M in range(0, 8):
+            for L in range(0, 5):
+                J = F.gmp_coeffs(K, M, L)
+                polys = (M + 1) * (1 + 2 * L)
+                assert F.gmp_q_executed(K, M, L) == 4 * (J - polys) + 8 * (M + 1) * L
+                assert F.gmp_q_executed(K, M, L) < F.gmp_flops_fig3(K, M, L)
+    assert F.gmp_q_executed(1, 0, 0) == 0 and F.gmp_y_executed(0) == 8
+    # the headline PA (9, 7, 4): about 5.4k FLOPs per sample for the whole reverse-mode
+    # kernel against 3 x 4836 = 14508 counted with eq. (10)
+    assert 5300 < F.gmp_bwd_executed(9, 7, 4, 256) < 5500
+    assert 3 * F.gmp_flops_fig3(9, 7, 4) == 14508
