@@ -100,6 +100,11 @@ struct Cfg {
   static constexpr int MT = X::MT, KS = X::KS, NR = X::NR, LG = X::LG;
   static constexpr int S = MT * kWaves;                // samples per workgroup tile
   static constexpr int KIN = 5 * T;
+  // bf16 tanh layers run on weights and biases pre-scaled by 2 log2 e (the MFMA then
+  // yields the exp2 argument of tanh_bf16_scaled directly; its accumulators start at the
+  // scaled bias), so the delta chain through them carries a factor WS per layer, which
+  // k_dw_finalize removes.  The output layer is not scaled.
+  static constexpr float WS = X::EPL == 8 ? kTanhScale : 1.0f;
   // Layer-1 K order: lane group g holds the features of its own taps [g*TPG, (g+1)*TPG):
   // element f = EPL*ks + e of its K-slices is feature f%5 of tap g*TPG + f/5 (zero when
   // f >= 5*TPG or the tap is >= T), so each lane computes only its own taps' features.
@@ -213,7 +218,7 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
         const int r = (int)(f % ((int64_t)C::HP * C::HP));
         const int o = r / C::HP, kk = r % C::HP;
         const float* Wi = ws + so.w[i - 1];
-        const float val = (o < H && kk < H) ? Wi[(int64_t)o * H + kk] : 0.f;
+        const float val = (o < H && kk < H) ? Wi[(int64_t)o * H + kk] * C::WS : 0.f;
         __bf16* dstw = reinterpret_cast<__bf16*>(ps + C::OFF_WH + (int64_t)(i - 2) * C::WH_LAYER);
         dstw[o * C::HP + 4 * ((kk / 4) ^ C::swz(o)) + kk % 4] = (__bf16)val;
       }
@@ -245,7 +250,7 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
             val = sec == 1 ? Wi[(int64_t)m * H + kk]           // forward: A[o][k] = W_i[o][k]
                            : Wi[(int64_t)kk * H + m];          // backward: A[k][o] = W_i[o][k]
         }
-        v[ee] = val;
+        v[ee] = val * C::WS;
       }
       if constexpr (EPL == 8) {
         bf16x8 a;
@@ -319,7 +324,7 @@ __device__ __forceinline__ void make_features(const float2* xw, int g, Ops<C, C:
       z = ok ? z : make_float2(0.f, 0.f);
     }
     const float m2 = z.x * z.x + z.y * z.y;
-    const float m = sqrtf(m2);
+    const float m = __builtin_amdgcn_sqrtf(m2);   // hardware square root (within 1 ulp)
     f[5 * t + 0] = z.x;
     f[5 * t + 1] = z.y;
     f[5 * t + 2] = m;
@@ -399,40 +404,62 @@ struct SharedBwdA {
   }
 };
 
-template <class C, int NKS, class LA, class BF, class EPI>
-__device__ __forceinline__ void dense_layer(LA&& la, BF&& bop, EPI&& epi) {
+// Accumulators of a block start at zero ...
+struct ZeroInit {
+  template <class Acc> __device__ Acc operator()(int, Acc* tag) const {
+    (void)tag;
+    Acc a;
+#pragma unroll
+    for (int j = 0; j < (int)(sizeof(Acc) / sizeof(float)); ++j) a[j] = 0.f;
+    return a;
+  }
+};
+// ... or at the lane's rows of a bias vector in accumulator order (the bf16 forward
+// layers: their scaled bias, read from LDS along with the block's weight operands).
+template <class C>
+struct BiasInit {
+  const float* bias;   // layer's bias block, rows in accumulator order
+  int g;
+  template <class Acc> __device__ Acc operator()(int mb, Acc* tag) const {
+    (void)tag;
+    return *reinterpret_cast<const Acc*>(bias + (mb * C::LG + g) * C::NR);
+  }
+};
+
+template <class C, int NKS, class LA, class BF, class EPI, class INIT = ZeroInit>
+__device__ __forceinline__ void dense_layer(LA&& la, BF&& bop, EPI&& epi, INIT&& init = INIT{}) {
   using A = typename C::A;
   using Acc = typename C::X::Acc;
+  Acc* const tag = nullptr;
   if constexpr (NKS <= 8) {
     A cur[NKS], nxt[NKS];
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) cur[ks] = la(0, ks);
+    Acc a_cur = init(0, tag), a_nxt;
     Acc prev;
 #pragma unroll
     for (int mb = 0; mb < C::NB; ++mb) {
       if (mb + 1 < C::NB) {
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) nxt[ks] = la(mb + 1, ks);
+        a_nxt = init(mb + 1, tag);
       }
       DPD_KEEP_LOADS_LOCAL();
-      Acc acc;
-#pragma unroll
-      for (int j = 0; j < C::NR; ++j) acc[j] = 0.f;
+      Acc acc = a_cur;
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) acc = C::X::mma(cur[ks], bop(ks), acc);
       if (mb > 0) epi(mb - 1, prev);
       prev = acc;
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) cur[ks] = nxt[ks];
+      a_cur = a_nxt;
     }
     epi(C::NB - 1, prev);
   } else {
 #pragma unroll
     for (int mb = 0; mb < C::NB; ++mb) {
       DPD_KEEP_LOADS_LOCAL();
-      Acc acc;
-#pragma unroll
-      for (int j = 0; j < C::NR; ++j) acc[j] = 0.f;
+      Acc acc = init(mb, tag);
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) acc = C::X::mma(la(mb, ks), bop(ks), acc);
       epi(mb, acc);
@@ -471,7 +498,8 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
       for (int j = 0; j < C::NR; ++j) {
         float v;
         if constexpr (C::X::EPL == 8) {
-          v = tanh_bf16_scaled(fmaf(acc[j], kTanhScale, bias[j]));
+          (void)bias;
+          v = tanh_bf16_scaled(acc[j]);          // accumulators started at the scaled bias
         } else {
           v = tanh_f32(acc[j] + bias[j]);
           if (i == NL - 1) {
@@ -482,18 +510,22 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
         set_elem<C>(hb[i][C::X::ks_of(mb, j)], C::X::e_of(mb, j), v);
       }
     };
+    using Init = std::conditional_t<C::X::EPL == 8, BiasInit<C>, ZeroInit>;
+    Init init;
+    if constexpr (C::X::EPL == 8) init = BiasInit<C>{vec + i * C::HP, g};
     if (i == 0) {
-      dense_layer<C, C::NKS1>(PackedA<C, C::NKS1>{wf, lane}, [&](int ks) { return feat[ks]; }, epi);
+      dense_layer<C, C::NKS1>(PackedA<C, C::NKS1>{wf, lane}, [&](int ks) { return feat[ks]; }, epi, init);
     } else if constexpr (C::SHARED_W) {
       if (wh) {
         dense_layer<C, C::NKSH>(SharedFwdA<C>{wh + (int64_t)(i - 1) * (C::WH_LAYER / 2), lane},
-                                [&](int ks) { return hb[i - 1][ks]; }, epi);
+                                [&](int ks) { return hb[i - 1][ks]; }, epi, init);
         continue;
       }
     }
     if (i > 0) {
       const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
-      dense_layer<C, C::NKSH>(PackedA<C, C::NKSH>{Ah, lane}, [&](int ks) { return hb[i - 1][ks]; }, epi);
+      dense_layer<C, C::NKSH>(PackedA<C, C::NKSH>{Ah, lane}, [&](int ks) { return hb[i - 1][ks]; }, epi,
+                              init);
     }
   }
   const float* bo = vec + NL * C::HP + 2 * C::HP;
@@ -530,7 +562,7 @@ __global__ __launch_bounds__(64 * FW) void k_tdnn_fwd(StreamTable st, const floa
   constexpr bool kLdsWeights = C::OFF_BWDH <= 144 * 1024;
   constexpr int NWF = kLdsWeights ? (int)(C::OFF_BWDH / 16) : 1;
   __shared__ float2 xw[XW];
-  __shared__ float vec[C::NVEC];
+  __shared__ __attribute__((aligned(16))) float vec[C::NVEC];
   __shared__ __attribute__((aligned(16))) uint4 wf[NWF];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int g = lane / C::MT, sl = lane % C::MT;
@@ -838,7 +870,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   using A = typename C::A;
   constexpr int S = C::S;
   __shared__ float2 xw[B::XW];
-  __shared__ float vec[C::NVEC];
+  __shared__ __attribute__((aligned(16))) float vec[C::NVEC];
   __shared__ float bacc[B::BIAS_N];
   __shared__ __attribute__((aligned(16))) char un[B::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint4 wlds[B::W_BYTES / 16];
@@ -1217,6 +1249,7 @@ __global__ void k_dw_finalize(StreamTable st, int G_wg, const float* __restrict_
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= P) return;
   int64_t nat = -1;
+  float lscale = 1.f;   // 1 / WS^(NL - 1 - li): the delta-chain scale of layer li
   {
     int64_t pos = 0;
     int din = C::KIN;
@@ -1233,6 +1266,8 @@ __global__ void k_dw_finalize(StreamTable st, int G_wg, const float* __restrict_
         const int o = (int)(j - pos - nw);
         nat = C::dw_off(li) + (int64_t)rows * cols + o;
       }
+      if (nat >= 0)
+        for (int q = li; q < NL - 1; ++q) lscale *= 1.0f / C::WS;
       pos += nw + dout;
       din = H;
     }
@@ -1244,7 +1279,7 @@ __global__ void k_dw_finalize(StreamTable st, int G_wg, const float* __restrict_
     const int g1 = wg_of_tile(st.tile0[s + 1] - 1, G_wg, st.n_tiles);
     for (int g = g0; g <= g1; ++g) acc += slots[(int64_t)(g + s) * C::SLOT + nat];
   }
-  dw[set * P + j] = acc * inv_r[set];
+  dw[set * P + j] = acc * (inv_r[set] * lscale);
 }
 
 SrcOff src_offsets(int T, int H, int NL) {

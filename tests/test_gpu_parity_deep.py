@@ -53,7 +53,7 @@ def test_bf16_gradient_2p20_against_oracle(bf16_slice, bwd_per_cu):
           + ", ".join(f"{k} {v:.1e}" for k, v in per_tensor.items()) + f"; output parity {op:.1f} dB",
           flush=True)
     H.check_cascade(inp, got, ref, "bf16")
-    assert max(per_tensor.values()) <= H.BF16_GRAD
+    assert max(per_tensor.values()) <= H.BF16_GRAD_LARGE
     assert op <= H.BF16_OUTPUT_PARITY_DB
 
 
