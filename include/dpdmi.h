@@ -184,7 +184,7 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
 /* Launch shapes of the tuned path.  The many-stream persistent launches (the
  * per-antenna DPDs of the paper's massive-MIMO setting, Sec. II and V) run with
  * tile shapes and grid sizes picked at run time among compiled variants:
- *   fwd_waves      waves per forward workgroup: 8 or 12 (tile = waves x 16 samples
+ *   fwd_waves      waves per forward workgroup: 8, 12 or 16 (tile = waves x 16 samples
  *                  in bf16, waves x 32 in fp32);
  *   fwd_wg_per_cu  forward workgroups per compute unit, 1..4 (capped by the tiles);
  *   bwd_wg_per_cu  backward (reverse-mode) workgroups per compute unit, 1..2
@@ -214,7 +214,7 @@ dpd_status dpd_tune_set(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                         const dpd_batch* batch, const dpd_tune* tune_host);
 
 /* Autotuner: on the given inputs, times reps (1..1000) back-to-back launches of every
- * candidate shape of each kernel (8 forward shapes, 2 GMP tiles, 2 backward grids;
+ * candidate shape of each kernel (12 forward shapes, 2 GMP tiles, 2 backward grids;
  * the kernels run one after another, so each is tuned on its own), installs the
  * fastest combination as this problem's entry (gmp key = gmp) and returns it.  It
  * enqueues that work on `stream`, records HIP events on it and waits for them (it

@@ -136,7 +136,7 @@ int device_cus() {
 // reverse-mode tile.  Defaults: the compiled default forward tile with as many
 // workgroups per CU as fit in LDS (at most 2), 2 backward workgroups per CU, 256-sample
 // GMP tiles.
-constexpr int kTuneFwdWaves[] = {8, 12};
+constexpr int kTuneFwdWaves[] = {8, 12, 16};
 constexpr int kTuneGmpTiles[] = {256, 512};
 constexpr int kTuneMaxFwdPerCu = 4, kTuneMaxBwdPerCu = 2;
 

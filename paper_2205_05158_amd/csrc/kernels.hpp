@@ -110,7 +110,7 @@ struct TdnnDims {
   int nksh;         // MFMA K steps of a hidden layer
   int tile;         // samples per workgroup tile of the tuned backward kernel
   int fwd_mt;       // samples per wave of the tuned forward kernel
-  int fwd_waves;    // default waves per forward workgroup (8 or 12 are compiled)
+  int fwd_waves;    // default waves per forward workgroup (8, 12 or 16 are compiled)
   int fwd_tile;     // default samples per forward tile (fwd_mt * fwd_waves)
   int64_t pack_bytes;  // bytes of one packed parameter set
   int64_t fwd_lds;     // LDS bytes of the forward kernel at the default tile
@@ -126,7 +126,7 @@ bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g);
 
 void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack,
                  hipStream_t s);
-// TDNN forward over the table's tiles (st.tile = td.fwd_mt * waves; waves 8 or 12).
+// TDNN forward over the table's tiles (st.tile = td.fwd_mt * waves; waves 8, 12 or 16).
 void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
                      float* u, int grid, int waves, hipStream_t s);
 // GMP forward over the table's tiles.
