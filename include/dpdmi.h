@@ -67,7 +67,12 @@ enum { DPD_MAX_STREAMS = 128, DPD_MAX_TAPS = 32, DPD_MAX_HIDDEN = 256, DPD_MAX_L
  * stream start), at input index 5t+j.  h_0 = features, h_i = tanh(W_i h_{i-1} + b_i),
  * (o0, o1) = W_o h_nl + b_o, u = o0 + j o1 (+ x[n] if residual).
  * Packed float32 weights (P = dpd_tdnn_param_count): W1[H][5T] b1[H]
- * (W_i[H][H] b_i[H]) for i = 2..nl, W_o[2][H] b_o[2]; rows are output neurons. */
+ * (W_i[H][H] b_i[H]) for i = 2..nl, W_o[2][H] b_o[2]; rows are output neurons.
+ * DPD_IMPL_TUNED runs every shape with T <= 32, H <= 128 and nl <= 4: the paper's three
+ * sizes (T, nl, H) = (4, 2, 20), (10, 3, 64), (16, 4, 128) on kernels compiled for them,
+ * the others on generic instantiations compiled for T rounded up to 8, 16 or 32 and H to
+ * 32, 64 or 128 (zero-padded weights, padding taps masked); larger shapes return
+ * DPD_ERR_UNSUPPORTED there (DPD_IMPL_PLAIN, float32, takes every valid shape). */
 typedef struct {
     int32_t taps;       /* T, 1..DPD_MAX_TAPS                               */
     int32_t n_hidden;   /* nl, 1..DPD_MAX_LAYERS                            */

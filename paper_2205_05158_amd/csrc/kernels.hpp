@@ -101,11 +101,26 @@ void launch_cnn_dwconv(const CnnDims& d, int64_t n_items, const float* s, const 
                        float* dw, hipStream_t st);
 
 // ------------------------------------------------------------------ tuned path
+struct TdnnDims;
+// Launchers of one compiled TDNN shape (tdnn_kernels.hpp): an exact shape, or a generic
+// instantiation whose tap count and width come at run time within its compiled bounds.
+struct TdnnKernels {
+  void (*dims)(TdnnDims* td);
+  void (*pack)(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack, hipStream_t s);
+  void (*fwd)(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack, float* u, int grid,
+              int waves, hipStream_t s);
+  void (*bwd)(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu, const void* pack,
+              float* slots, int grid, hipStream_t s);
+  void (*finalize)(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
+                   const float* inv_r_set, float* dw, hipStream_t s);
+};
 struct TdnnDims {
   int taps, n_hidden, hidden, residual, prec;
+  const TdnnKernels* k;   // the compiled shape that runs this model
+  bool generic;           // k is a generic instantiation (no exact shape matches)
   int kin;          // 5 * taps
-  int hp;           // hidden padded to a multiple of 32
-  int kin_p;        // kin padded to the MFMA K step
+  int hp;           // hidden padded to a multiple of 32 (generic: the compiled width)
+  int kin_p;        // layer-1 K padded to the MFMA K step
   int nks1;         // MFMA K steps of layer 1
   int nksh;         // MFMA K steps of a hidden layer
   int tile;         // samples per workgroup tile of the tuned backward kernel
@@ -114,12 +129,7 @@ struct TdnnDims {
   int fwd_tile;     // default samples per forward tile (fwd_mt * fwd_waves)
   int64_t pack_bytes;  // bytes of one packed parameter set
   int64_t fwd_lds;     // LDS bytes of the forward kernel at the default tile
-  // packed offsets (bytes) inside one set
-  int64_t off_fwd1, off_fwdh, off_bwdh, off_bias, off_wo, off_bo;
-  // natural-layout dW (floats) per slot: layer rows x cols, bias in the last used column
-  int dw_cols1, dw_colsh, dw_colso;    // columns of layer 1, hidden, output blocks
-  int64_t dw_off[DPD_MAX_LAYERS + 2];  // float offset of each layer (index nl = output)
-  int64_t dw_slot;                     // floats per slot
+  int64_t dw_slot;     // floats per dW slot (natural layout, padded rows and columns)
 };
 bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out);
 bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g);

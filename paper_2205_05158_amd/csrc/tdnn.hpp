@@ -149,30 +149,17 @@ struct Cfg {
   }
 };
 
-// Supported TDNN shapes of the tuned kernels.
-template <class F>
-bool tdnn_dispatch(int prec, int T, int H, int NL, F&& f) {
-#define DPD_CASE(P_, T_, H_, NL_) \
-  if (prec == P_ && T == T_ && H == H_ && NL == NL_) { f.template operator()<P_, T_, H_, NL_>(); return true; }
-  DPD_CASE(DPD_FP32, 4, 20, 2)
-  DPD_CASE(DPD_FP32, 10, 64, 3)
-  DPD_CASE(DPD_FP32, 16, 128, 4)
-  DPD_CASE(DPD_BF16, 4, 20, 2)
-  DPD_CASE(DPD_BF16, 10, 64, 3)
-  DPD_CASE(DPD_BF16, 16, 128, 4)
-#undef DPD_CASE
-  return false;
-}
-
 // ------------------------------------------------------------------ pack
 // Source offsets inside the packed float32 weight vector.
 struct SrcOff {
   int64_t w[DPD_MAX_LAYERS + 1], b[DPD_MAX_LAYERS + 1];
 };
 
+// Packs parameter set blockIdx.y of a model with tn taps and width hn (at most the
+// compiled T and padded width; the padding rows and columns are zero).
 template <int PREC, int T, int H, int NL>
 __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
-                       char* __restrict__ pack) {
+                       int tn, int hn, char* __restrict__ pack) {
   using C = Cfg<PREC, T, H, NL>;
   using X = typename C::X;
   constexpr int EPL = X::EPL;
@@ -195,7 +182,7 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
         bf16x8 a;
         for (int ee = 0; ee < 8; ++ee) {
           const int kk = C::hid_k(ks, g, ee);
-          a[ee] = (__bf16)((m < 2 && kk < H) ? ws[so.w[NL] + (int64_t)m * H + kk] : 0.f);
+          a[ee] = (__bf16)((m < 2 && kk < hn) ? ws[so.w[NL] + (int64_t)m * hn + kk] : 0.f);
         }
         reinterpret_cast<bf16x8*>(ps + C::OFF_WO)[f] = a;
       }
@@ -207,7 +194,7 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
         const int r = (int)(f % ((int64_t)C::HP * C::HP));
         const int o = r / C::HP, kk = r % C::HP;
         const float* Wi = ws + so.w[i - 1];
-        const float val = (o < H && kk < H) ? Wi[(int64_t)o * H + kk] * C::WS : 0.f;
+        const float val = (o < hn && kk < hn) ? Wi[(int64_t)o * hn + kk] * C::WS : 0.f;
         __bf16* dstw = reinterpret_cast<__bf16*>(ps + C::OFF_WH + (int64_t)(i - 2) * C::WH_LAYER);
         dstw[o * C::HP + 4 * ((kk / 4) ^ C::swz(o)) + kk % 4] = (__bf16)val;
       }
@@ -231,13 +218,13 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
         float val = 0.f;
         if (sec == 0) {
           const int k = C::feat_k(ks, g, ee);
-          if (m < H && k >= 0) val = ws[so.w[0] + (int64_t)m * C::KIN + k];
+          if (m < hn && k >= 0 && k < 5 * tn) val = ws[so.w[0] + (int64_t)m * (5 * tn) + k];
         } else {
           const int kk = C::hid_k(ks, g, ee);
-          const float* Wi = ws + so.w[layer - 1];             // W_i is [H][H]
-          if (m < H && kk < H)
-            val = sec == 1 ? Wi[(int64_t)m * H + kk]           // forward: A[o][k] = W_i[o][k]
-                           : Wi[(int64_t)kk * H + m];          // backward: A[k][o] = W_i[o][k]
+          const float* Wi = ws + so.w[layer - 1];             // W_i is [hn][hn]
+          if (m < hn && kk < hn)
+            val = sec == 1 ? Wi[(int64_t)m * hn + kk]           // forward: A[o][k] = W_i[o][k]
+                           : Wi[(int64_t)kk * hn + m];          // backward: A[k][o] = W_i[o][k]
         }
         v[ee] = val * C::WS;
       }
@@ -260,11 +247,11 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
       if (f < NL * C::HP) {
         // bf16 layers take their bias pre-scaled by 2 log2 e (see tanh_bf16_scaled)
         const int i = f / C::HP, o = neuron(f % C::HP);
-        if (o < H) val = ws[so.b[i] + o] * (EPL == 8 ? kTanhScale : 1.0f);
+        if (o < hn) val = ws[so.b[i] + o] * (EPL == 8 ? kTanhScale : 1.0f);
       } else if (f < NL * C::HP + 2 * C::HP) {
         const int r0 = f - NL * C::HP;
         const int c = r0 / C::HP, o = neuron(r0 % C::HP);
-        if (o < H) val = ws[so.w[NL] + (int64_t)c * H + o];
+        if (o < hn) val = ws[so.w[NL] + (int64_t)c * hn + o];
       } else {
         const int c = f - NL * C::HP - 2 * C::HP;
         if (c < 2) val = ws[so.b[NL] + c];
@@ -312,8 +299,10 @@ __device__ __forceinline__ float value_at(const Ops<C, NKS>& ops, int mb, int j)
 
 // Features (I, Q, |x|, |x|^2, |x|^3 per tap) of the lane's sample for the taps of its
 // lane group g (see Cfg::feat_k): xw points at x[n] in an LDS window (xw[-t] = x[n-t]).
-template <class C>
-__device__ __forceinline__ void make_features(const float2* xw, int g, Ops<C, C::NKS1>& feat) {
+// RT: the model has tn <= T taps; the features of taps >= tn are zero (their weights are
+// zero too, but a non-finite sample there must not reach the sum).
+template <class C, bool RT = false>
+__device__ __forceinline__ void make_features(const float2* xw, int g, Ops<C, C::NKS1>& feat, int tn = 0) {
   constexpr int T = C::KIN / 5, EPL = C::X::EPL;
   float f[C::NKS1 * EPL];
   const int tb = g * C::TPG;
@@ -327,6 +316,7 @@ __device__ __forceinline__ void make_features(const float2* xw, int g, Ops<C, C:
       z = xw[-(ok ? tb + t : T - 1)];
       z = ok ? z : make_float2(0.f, 0.f);
     }
+    if constexpr (RT) z = tb + t < tn ? z : make_float2(0.f, 0.f);
     const float m2 = z.x * z.x + z.y * z.y;
     const float m = __builtin_amdgcn_sqrtf(m2);   // hardware square root (within 1 ulp)
     f[5 * t + 0] = z.x;
@@ -483,14 +473,14 @@ __device__ __forceinline__ float lane_group_sum(float v) {
 // wf: forward weight operands (layer 1, then the hidden layers; global or LDS); when wh
 // is not null the hidden layers are read from the shared row-major copy there instead
 // (LDS, Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
-template <class C, int NL>
+template <class C, int NL, bool RT = false>
 __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const __bf16* wh,
                                               const typename C::A* __restrict__ wout,
                                               const float* vec, int lane, int g, const float2* xw,
-                                              Ops<C, C::NKSH> (&hb)[NL]) {
+                                              Ops<C, C::NKSH> (&hb)[NL], int tn = 0) {
   using A = typename C::A;
   Ops<C, C::NKS1> feat;
-  make_features<C>(xw, g, feat);
+  make_features<C, RT>(xw, g, feat, tn);
   const float* wo = vec + NL * C::HP;
   float o0 = 0.f, o1 = 0.f;
 #pragma unroll

@@ -60,7 +60,8 @@ def _fwd(tdnn, batch, x=FAKE, w=FAKE, u=FAKE, ws=FAKE, nbytes=1 << 40):
     (dict(residual=2), L.DPD_ERR_SHAPE), (dict(precision=7), L.DPD_ERR_SHAPE),
     (dict(impl=3), L.DPD_ERR_SHAPE),
     (dict(precision=L.DPD_BF16, impl=L.DPD_IMPL_PLAIN), L.DPD_ERR_UNSUPPORTED),
-    (dict(taps=3, hidden=7, n_hidden=1), L.DPD_ERR_UNSUPPORTED),   # no tuned kernel for this shape
+    (dict(hidden=129), L.DPD_ERR_UNSUPPORTED),     # wider than the tuned kernels
+    (dict(n_hidden=5), L.DPD_ERR_UNSUPPORTED),     # deeper than the tuned kernels
 ])
 def test_tdnn_descriptor_rejected(dpdlib, desc, code):
     base = dict(taps=10, n_hidden=3, hidden=64, residual=0, precision=0, impl=0)
@@ -188,6 +189,10 @@ def test_tune_table_host(dpdlib):
     assert d["fwd_waves"] == 8 and d["bwd_wg_per_cu"] == 2 and d["gmp_tile"] == 256
     assert 1 <= d["fwd_wg_per_cu"] <= 2
     assert D.dpd_tune_get(D.tdnn_desc(16, 4, 128, precision="bf16"), D.gmp_desc(9, 7, 4), b)["fwd_waves"] == 12
+    # generic shapes (the paper's FD-NN-sized core, odd sizes) have a tuned launch shape
+    for shape in [(4, 1, 15), (3, 1, 7), (32, 4, 128), (17, 2, 100)]:
+        for prec in ("fp32", "bf16"):
+            assert D.dpd_tune_get(D.tdnn_desc(*shape, precision=prec), g, b)["fwd_waves"] in (8, 12)
     mine = dict(fwd_waves=12, fwd_wg_per_cu=3, bwd_wg_per_cu=1, gmp_tile=512)
     try:
         D.dpd_tune_set(t, g, b, mine)
