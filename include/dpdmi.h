@@ -186,6 +186,28 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                        float* u, float* y, float* nmse, float* dw, float* loss,
                        void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Ideal linear-clipping PA, the minimum-distortion reference PA of the paper's SER
+ * comparison (Sec. V-B-2): unit gain up to the clipping level, constant envelope beyond
+ * it, phase kept, no memory:
+ *   y[n] = u[n]                          if |u[n]| <= a_clip,
+ *   y[n] = a_clip u[n] / |u[n]|          otherwise.
+ * u, y: device float[n][2], 8-byte aligned; y may equal u (in place).  a_clip finite
+ * and > 0, n >= 1 (DPD_ERR_SHAPE otherwise).  |u| is formed without overflow for every
+ * finite u; a NaN sample stays NaN, an infinite one becomes NaN. */
+dpd_status pa_clip_forward(int64_t n, const float* u, float a_clip, float* y, hipStream_t stream);
+
+/* The cascade DPD -> linear-clipping PA -> NMSE: dpd_cascade with the clipping PA above
+ * in place of the GMP PA.  Same outputs (u, y, NMSE records, and with dw the pooled loss
+ * per parameter set and its gradient), same argument rules; the workspace is
+ * dpd_workspace_size(tdnn, NULL, batch).  Reverse mode of the PA: g_u = g_y below the
+ * clip; beyond it only the phase of u moves y, g_u = (a_clip / |u|)(g_y - v Re(conj(v)
+ * g_y)) with v = u / |u|; at |u| = a_clip exactly the linear branch's derivative is
+ * taken. */
+dpd_status dpd_cascade_clip(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const float* x,
+                            const float* w, float a_clip, float g_re, float g_im,
+                            float* u, float* y, float* nmse, float* dw, float* loss,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* Launch shapes of the tuned path.  The many-stream persistent launches (the
  * per-antenna DPDs of the paper's massive-MIMO setting, Sec. II and V) run with
  * tile shapes and grid sizes picked at run time among compiled variants:

@@ -78,6 +78,9 @@ _SIGS = {
                                C.c_float, C.c_float, _P, _P, _P, C.c_size_t, _P]),
     "dpd_cascade": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
                               C.c_float, C.c_float, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "pa_clip_forward": (C.c_int, [C.c_int64, _P, C.c_float, _P, _P]),
+    "dpd_cascade_clip": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(Batch), _P, _P, C.c_float, C.c_float,
+                                   C.c_float, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
     "dpd_tune_get": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(Tune)]),
     "dpd_tune_set": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), C.POINTER(Tune)]),
     "dpd_autotune": (C.c_int, [C.POINTER(TdnnDesc), C.POINTER(GmpDesc), C.POINTER(Batch), _P, _P, _P,
@@ -263,6 +266,18 @@ def dpd_cascade(tdnn, gmp, batch, x, w, coef, g, u, y, nmse, dw, loss, workspace
                              _ptr(loss), _ptr(workspace),
                              workspace.numel() * workspace.element_size(), _stream(stream)),
            "dpd_cascade")
+
+
+def pa_clip_forward(n, u, a_clip, y, stream=None):
+    _check(lib().pa_clip_forward(int(n), _ptr(u), float(a_clip), _ptr(y), _stream(stream)), "pa_clip_forward")
+
+
+def dpd_cascade_clip(tdnn, batch, x, w, a_clip, g, u, y, nmse, dw, loss, workspace, stream=None):
+    g = complex(g)
+    _check(lib().dpd_cascade_clip(C.byref(tdnn), C.byref(batch), _ptr(x), _ptr(w), float(a_clip), g.real,
+                                  g.imag, _ptr(u), _ptr(y), _ptr(nmse), _ptr(dw), _ptr(loss), _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), _stream(stream)),
+           "dpd_cascade_clip")
 
 
 def _gref(gmp):

@@ -132,6 +132,66 @@ class Cascade:
         return loss, dw
 
 
+class ClipCascade:
+    """The cascade with the ideal linear-clipping PA (Sec. V-B-2) in place of the GMP:
+    DPD -> y = u below the clipping level a_clip, a_clip u / |u| above -> NMSE, with the
+    library's reverse mode (dpd_cascade_clip)."""
+
+    def __init__(self, taps, n_hidden, hidden, offsets, a_clip, per_stream_params=False, residual=False,
+                 precision="fp32", impl="tuned", gain=1.0 + 0.0j, device="cuda"):
+        self.tdnn = L.tdnn_desc(taps, n_hidden, hidden, residual, precision, impl)
+        self.offsets = np.asarray(offsets, dtype=np.int64)
+        self.batch = L.make_batch(self.offsets, per_stream_params)
+        self.S = int(self.offsets.size - 1)
+        self.n_sets = self.S if per_stream_params else 1
+        self.n_total = int(self.offsets[-1])
+        self.P = L.dpd_tdnn_param_count(self.tdnn)
+        self.a_clip = float(a_clip)
+        self.gain = complex(gain)
+        self.device = torch.device(device)
+        nbytes = L.dpd_workspace_size(self.tdnn, None, self.batch)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    _chk = Cascade._chk
+    _w_shape = Cascade._w_shape
+
+    def pa(self, u):
+        self._chk(u, (self.n_total, 2))
+        y = torch.empty_like(u)
+        L.pa_clip_forward(self.n_total, u, self.a_clip, y)
+        return y
+
+    def run(self, x, w, want_u=True, want_y=True, want_nmse=True, want_grad=True):
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape())
+        dev = self.device
+        u = torch.empty_like(x) if want_u else None
+        y = torch.empty_like(x) if want_y else None
+        nm = (torch.empty((self.S + 1, L.DPD_NMSE_FIELDS), dtype=torch.float32, device=dev)
+              if want_nmse else None)
+        dw = torch.empty(self._w_shape(), dtype=torch.float32, device=dev) if want_grad else None
+        loss = torch.empty(self.n_sets, dtype=torch.float32, device=dev) if want_grad else None
+        L.dpd_cascade_clip(self.tdnn, self.batch, x, w, self.a_clip, self.gain, u, y, nm, dw, loss,
+                           self.workspace)
+        return {"u": u, "y": y, "nmse": nm, "dw": dw, "loss": loss}
+
+    def backward(self, x, w):
+        out = self.run(x, w, want_u=False, want_y=False, want_nmse=False)
+        return out["loss"], out["dw"]
+
+    def train(self, x, w, steps, lr=1e-3):
+        """Direct learning through the clipping PA: gradient + Adam in place, `steps` times;
+        returns the loss before each step (device [steps][n_sets])."""
+        self._chk(x, (self.n_total, 2)); self._chk(w, self._w_shape())
+        m, v = torch.zeros_like(w), torch.zeros_like(w)
+        dw = torch.empty_like(w)
+        losses = torch.empty((steps, self.n_sets), dtype=torch.float32, device=self.device)
+        for i in range(steps):
+            L.dpd_cascade_clip(self.tdnn, self.batch, x, w, self.a_clip, self.gain, None, None, None, dw,
+                               losses[i], self.workspace)
+            L.dpd_adam_step(dw, w, m, v, i + 1, lr=lr)
+        return losses
+
+
 class CascadeFn(torch.autograd.Function):
     """loss[p] = pooled NMSE of parameter set p; differentiable w.r.t. the packed weights."""
 

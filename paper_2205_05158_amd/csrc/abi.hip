@@ -36,6 +36,7 @@ constexpr int kPlainChunk = 1 << 17;  // samples per chunk of the plain path
 constexpr int kPlainDwBlock = 2048;   // samples per split-K block of the plain dW
 constexpr int kMaxGrid = 512;         // persistent workgroups (sizes the dW slots)
 constexpr int kGmpTile = 128;         // table tile handed to the stand-alone GMP pass
+constexpr int kClipTile = 2048;       // tile of the clipping-PA cascade pass
 
 struct Problem {
   int S = 0, n_sets = 0, per_stream = 0;
@@ -321,16 +322,21 @@ void plain_gmp_forward(const dpd_gmp_desc& g, const Problem& p, const float* u, 
                          g.M, g.L, y, s);
 }
 
-void plain_backward(const dpd_tdnn_desc& d, const dpd_gmp_desc& g, const Problem& p,
+// g: the GMP PA whose reverse mode gives g_u; null when g_u is already in the workspace
+// (the clipping PA's cascade pass writes it there).
+void plain_backward(const dpd_tdnn_desc& d, const dpd_gmp_desc* g, const Problem& p,
                     const float* x, const float* w, const float* coef, float g_re, float g_im,
                     const float* u, const float* y, float* dw, const float* inv_r, const Ws& L,
                     void* ws, hipStream_t s) {
-  int64_t P = param_count(d), J = coeff_count(g);
+  int64_t P = param_count(d);
   int H = d.hidden, din = 5 * d.taps, nl = d.n_hidden;
   float* gu = at<float>(ws, L.gu_buf);
-  for (int st = 0; st < p.S; ++st)
-    launch_plain_gmp_bwd(u, y, x, p.off[st], p.off[st + 1], coef + (p.per_stream ? st * 2 * J : 0),
-                         g.K, g.M, g.L, g_re, g_im, gu, s);
+  if (g) {
+    const int64_t J = coeff_count(*g);
+    for (int st = 0; st < p.S; ++st)
+      launch_plain_gmp_bwd(u, y, x, p.off[st], p.off[st + 1], coef + (p.per_stream ? st * 2 * J : 0),
+                           g->K, g->M, g->L, g_re, g_im, gu, s);
+  }
   float* acc = at<float>(ws, L.acc);
   launch_fill(acc, (int64_t)p.n_sets * P, 0.f, s);
   float* act = at<float>(ws, L.act);
@@ -579,7 +585,7 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
     { DPD_PROF("nmse_final"); launch_nmse_final(tab, part, nmse, lossp, inv_r, stream); }
     if (dw) {
       DPD_PROF("plain_backward");
-      plain_backward(*tdnn, *gmp, p, x, w, coef, g_re, g_im, ubuf, ybuf, dw, inv_r, L, workspace,
+      plain_backward(*tdnn, gmp, p, x, w, coef, g_re, g_im, ubuf, ybuf, dw, inv_r, L, workspace,
                      stream);
     }
     return launch_status();
@@ -620,6 +626,68 @@ dpd_status dpd_backward(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
   if (!dw || !loss) return DPD_ERR_NULL;
   return dpd_cascade(tdnn, gmp, batch, x, w, coef, g_re, g_im, nullptr, nullptr, nullptr, dw, loss,
                      workspace, workspace_bytes, stream);
+}
+
+dpd_status pa_clip_forward(int64_t n, const float* u, float a_clip, float* y, hipStream_t stream) {
+  if (n < 1) return DPD_ERR_SHAPE;
+  if (!u || !y) return DPD_ERR_NULL;
+  if (!aligned(u, 8) || !aligned(y, 8)) return DPD_ERR_ALIGN;
+  if (!(a_clip > 0.f) || !isfinite(a_clip)) return DPD_ERR_SHAPE;
+  { DPD_PROF("clip_fwd"); launch_clip_fwd(n, u, a_clip, y, stream); }
+  return launch_status();
+}
+
+dpd_status dpd_cascade_clip(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const float* x,
+                            const float* w, float a_clip, float g_re, float g_im, float* u, float* y,
+                            float* nmse, float* dw, float* loss, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream) {
+  Problem p;
+  dpd_status st;
+  if ((st = check_tdnn(tdnn)) != DPD_OK) return st;
+  if ((st = check_batch(batch, &p)) != DPD_OK) return st;
+  if (!x || !w || !workspace) return DPD_ERR_NULL;
+  if (dw && !loss) return DPD_ERR_NULL;
+  if (!aligned(x, 8) || (u && !aligned(u, 8)) || (y && !aligned(y, 8)) || !aligned(w, 4) ||
+      (dw && !aligned(dw, 4)) || (loss && !aligned(loss, 4)) || (nmse && !aligned(nmse, 4)) ||
+      !aligned(workspace, 256))
+    return DPD_ERR_ALIGN;
+  if (!isfinite(g_re) || !isfinite(g_im) || (g_re == 0.f && g_im == 0.f)) return DPD_ERR_SHAPE;
+  if (!(a_clip > 0.f) || !isfinite(a_clip)) return DPD_ERR_SHAPE;
+  Ws L = ws_layout(tdnn, nullptr, p);
+  if (workspace_bytes < L.total) return DPD_ERR_WORKSPACE;
+  float* ubuf = u ? u : at<float>(workspace, L.u_buf);
+  float* inv_r = at<float>(workspace, L.inv_r);
+  float* lossp = loss ? loss : at<float>(workspace, L.loss_tmp);
+  float4* part = at<float4>(workspace, L.tile_part);
+  float* gub = dw ? at<float>(workspace, L.gu_buf) : nullptr;
+  StreamTable ct = make_table(p, kClipTile);
+  if (tdnn->impl == DPD_IMPL_PLAIN) {
+    { DPD_PROF("plain_forward"); plain_forward(*tdnn, p, x, w, ubuf, L, workspace, stream); }
+    { DPD_PROF("clip_tiles"); launch_clip_tiles(ct, x, ubuf, a_clip, g_re, g_im, part, gub, y, stream); }
+    { DPD_PROF("nmse_final"); launch_nmse_final(ct, part, nmse, lossp, inv_r, stream); }
+    if (dw) {
+      DPD_PROF("plain_backward");
+      plain_backward(*tdnn, nullptr, p, x, w, nullptr, g_re, g_im, ubuf, y, dw, inv_r, L, workspace, stream);
+    }
+    return launch_status();
+  }
+  TdnnDims td;
+  tdnn_dims(*tdnn, &td);
+  void* pack = at<void>(workspace, L.pack);
+  { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
+  const dpd_tune tn = lookup_tune(*tdnn, nullptr, p, td);
+  StreamTable ftab = make_table(p, td.fwd_mt * tn.fwd_waves);
+  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fwd_grid(tn, ftab), tn.fwd_waves, stream); }
+  { DPD_PROF("clip_tiles"); launch_clip_tiles(ct, x, ubuf, a_clip, g_re, g_im, part, gub, y, stream); }
+  { DPD_PROF("nmse_final"); launch_nmse_final(ct, part, nmse, lossp, inv_r, stream); }
+  if (dw) {
+    StreamTable tab = make_table(p, td.tile);
+    const int grid = bwd_grid(tn, tab);
+    float* slots = at<float>(workspace, L.slots);
+    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, stream); }
+    { DPD_PROF("dw_finalize"); launch_dw_finalize(td, tab, grid, slots, inv_r, dw, stream); }
+  }
+  return launch_status();
 }
 
 dpd_status dpd_tune_get(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const dpd_batch* batch,

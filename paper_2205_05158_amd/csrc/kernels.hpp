@@ -20,6 +20,12 @@ void launch_nmse_tiles(const StreamTable& st, const float* y, const float* x, fl
 // be null).
 void launch_nmse_final(const StreamTable& st, const float4* tile_part, float* rec, float* loss,
                        float* inv_r, hipStream_t s);
+// Ideal linear-clipping PA (y = u up to |u| = a, a u / |u| beyond): y of n samples
+// (y may equal u), and the cascade pass over the table's tiles: y (may be null), the
+// NMSE tile partials and, when gu is not null, g_u = J^T 2 (y - G x).
+void launch_clip_fwd(int64_t n, const float* u, float a, float* y, hipStream_t s);
+void launch_clip_tiles(const StreamTable& st, const float* x, const float* u, float a, float g_re,
+                       float g_im, float4* tile_part, float* gu, float* y, hipStream_t s);
 // Symbol MSE of n complex values: out[0] = sum |z - t|^2 / n, out[1] = non-finite count,
 // grad (may be null) = scale (z - t); part holds mse_tiles(n) tile partials.
 int mse_tiles(int64_t n);

@@ -2,7 +2,8 @@
 // and the count of samples whose |y - Gx|^2 or |Gx|^2 is not finite.  Per-tile
 // partials (one workgroup per tile, fixed tree) and a single-workgroup final pass
 // that sums each stream's tiles in a fixed order with Neumaier compensation, so
-// results are deterministic and accurate in float32.
+// results are deterministic and accurate in float32.  Also the memoryless ideal
+// linear-clipping PA, whose cascade pass is an NMSE tile pass that also writes y and g_u.
 #include "kernels.hpp"
 
 namespace dpdmi {
@@ -172,7 +173,95 @@ __global__ __launch_bounds__(kRedThreads) void k_mse_final(int n_tiles, int64_t 
   }
 }
 
+// ------------------------------------------------------------------ linear-clipping PA
+// The ideal linear-clipping PA of the paper's SER comparison (Sec. V-B-2): unit gain up
+// to the clipping level a, constant envelope a beyond it, phase kept:
+//   y = u if |u| <= a,   y = (a / |u|) u otherwise.
+// |u| without overflow for every finite u (the square is rescaled when it overflows);
+// a NaN sample takes the linear branch and stays NaN.
+__device__ __forceinline__ float clip_mag(float2 u) {
+  const float r2 = u.x * u.x + u.y * u.y;
+  if (r2 != INFINITY) return sqrtf(r2);                 // finite, or NaN
+  const float m = fmaxf(fabsf(u.x), fabsf(u.y));
+  if (m == INFINITY) return INFINITY;
+  const float p = u.x / m, q = u.y / m;
+  return m * sqrtf(p * p + q * q);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_clip_fwd(int64_t n, const float* __restrict__ u, float a,
+                                                          float* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    float2 v = ld2(u, i);
+    const float r = clip_mag(v);
+    if (r > a) {
+      const float sc = a / r;
+      v = make_float2(sc * v.x, sc * v.y);
+    }
+    st2(y, i, v);
+  }
+}
+
+// The clipping PA with the NMSE partials and its reverse mode over the table's tiles:
+// y (may be null), (E, R, non-finite count) per tile, and (when gu is not null)
+// g_u = J^T g_y with g_y = 2 (y - G x) (the loss's 1/R is applied with dW).  J = I on
+// the linear branch; beyond the clip J = (a / |u|)(I - v v^T), v = u / |u|: only the
+// phase of u moves y.  At |u| = a the linear branch's derivative is taken.
+__global__ __launch_bounds__(kRedThreads) void k_clip_tiles(StreamTable st, const float* __restrict__ x,
+                                                            const float* __restrict__ u, float a,
+                                                            float g_re, float g_im,
+                                                            float4* __restrict__ part,
+                                                            float* __restrict__ gu,
+                                                            float* __restrict__ y) {
+  __shared__ float sh[4 * kRedThreads];
+  __shared__ uint32_t shn[kRedThreads];
+  const int t = blockIdx.x;
+  const int s = stream_of_tile(st, t);
+  const int64_t lo = st.off[s], hi = st.off[s + 1];
+  const int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * st.tile;
+  const int64_t t1 = min(hi, t0 + st.tile);
+  Comp E, R;
+  uint32_t nf = 0;
+  for (int64_t n = t0 + threadIdx.x; n < t1; n += kRedThreads) {
+    const float2 uv = ld2(u, n), xv = ld2(x, n);
+    const float r = clip_mag(uv);
+    const bool clipped = r > a;
+    const float sc = clipped ? a / r : 1.f;
+    const float2 yv = make_float2(sc * uv.x, sc * uv.y);
+    const float tr = g_re * xv.x - g_im * xv.y, ti = g_re * xv.y + g_im * xv.x;
+    const float er = yv.x - tr, ei = yv.y - ti;
+    const float e2 = er * er + ei * ei, r2 = tr * tr + ti * ti;
+    nf += !isfinite(e2 + r2);
+    E.add(e2);
+    R.add(r2);
+    if (y) st2(y, n, yv);
+    if (gu) {
+      float gx = 2.f * er, gy = 2.f * ei;
+      if (clipped) {
+        const float vx = uv.x / r, vy = uv.y / r;
+        const float d = vx * gx + vy * gy;
+        gx = sc * (gx - d * vx);
+        gy = sc * (gy - d * vy);
+      }
+      st2(gu, n, make_float2(gx, gy));
+    }
+  }
+  block_reduce2(E, R, sh);
+  nf = block_sum_u32(nf, shn);
+  if (threadIdx.x == 0) part[t] = make_float4(E.value(), R.value(), (float)nf, 0.f);
+}
+
 }  // namespace
+
+void launch_clip_fwd(int64_t n, const float* u, float a, float* y, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(ceil_div64(n, kRedThreads), 8192);
+  k_clip_fwd<<<(unsigned)blocks, kRedThreads, 0, s>>>(n, u, a, y);
+}
+
+void launch_clip_tiles(const StreamTable& st, const float* x, const float* u, float a, float g_re,
+                       float g_im, float4* tile_part, float* gu, float* y, hipStream_t s) {
+  k_clip_tiles<<<st.n_tiles, kRedThreads, 0, s>>>(st, x, u, a, g_re, g_im, tile_part, gu, y);
+}
 
 int mse_tiles(int64_t n) { return (int)ceil_div64(n, kMseTile); }
 

@@ -338,3 +338,26 @@ def test_downlink_arguments_rejected(dpdlib):
     assert lib.ofdm_link_backward(C.byref(ok), 2, 1, FAKE, FAKE, C.c_float(1.0), C.c_float(0.0), FAKE, FAKE,
                                   None, OUT, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
     assert lib.ofdm_precode_backward(C.byref(ok), 2, 1, FAKE, FAKE, FAKE, 3, OUT, None) == L.DPD_ERR_SHAPE
+
+
+def test_clip_pa_arguments_rejected(dpdlib):
+    lib = L.lib()
+    Y = C.c_void_p(0x300000)
+    for n, a in [(0, 1.0), (-5, 1.0), (10, 0.0), (10, -1.0), (10, float("nan")), (10, float("inf"))]:
+        assert lib.pa_clip_forward(n, FAKE, a, Y, None) == L.DPD_ERR_SHAPE
+    assert lib.pa_clip_forward(10, None, 1.0, Y, None) == L.DPD_ERR_NULL
+    assert lib.pa_clip_forward(10, C.c_void_p(0x100004), 1.0, Y, None) == L.DPD_ERR_ALIGN
+    t = D.tdnn_desc(10, 3, 64)
+    b = D.make_batch([0, 100])
+
+    def casc(a=1.0, dw=None, loss=None, nbytes=1 << 40, tdnn=t, x=FAKE):
+        return lib.dpd_cascade_clip(C.byref(tdnn), C.byref(b), x, FAKE, a, 1.0, 0.0, None, None, None, dw,
+                                    loss, FAKE, nbytes, None)
+    assert casc(a=0.0) == L.DPD_ERR_SHAPE
+    assert casc(a=float("nan")) == L.DPD_ERR_SHAPE
+    assert casc(x=None) == L.DPD_ERR_NULL
+    assert casc(dw=FAKE) == L.DPD_ERR_NULL                 # gradient without a loss output
+    assert casc(nbytes=16) == L.DPD_ERR_WORKSPACE
+    assert casc(tdnn=D.tdnn_desc(10, 3, 200)) == L.DPD_ERR_UNSUPPORTED
+    # the clip cascade needs no GMP table: its workspace is the forward-only one
+    assert D.dpd_workspace_size(t, None, b) < D.dpd_workspace_size(t, D.gmp_desc(7, 5, 3), b)
