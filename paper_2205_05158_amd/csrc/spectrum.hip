@@ -1,17 +1,58 @@
 // Welch power spectral density of a PA output and its adjacent-channel power ratio
 // (the out-of-band metric named in Sec. I).  Segments of nfft samples, hop nfft/2,
-// periodic Hann window; each workgroup transforms a contiguous group of segments
-// with an in-LDS radix-2 decimation-in-time FFT and accumulates |X_k|^2 per bin;
-// a single-workgroup pass sums the group spectra in a fixed order (Neumaier) and
-// integrates the channel powers.
-#include "kernels.hpp"
+// periodic Hann window; each workgroup transforms a contiguous group of segments and
+// accumulates |X_k|^2 per bin: 4096-point segments with the radix-16 transform of
+// fft.hpp (samples windowed as they are loaded, each thread's 16 bins in registers),
+// other sizes with an in-LDS radix-2 decimation-in-time FFT.  A single-workgroup pass
+// sums the group spectra in a fixed order (Neumaier) and integrates the channel powers.
+#include "fft.hpp"
 
 namespace dpdmi {
 
 namespace {
 
-constexpr int kFftThreads = 256;
-constexpr int kMaxFft = 4096;
+constexpr int kMaxFft = kFftMax;
+
+// 4096-point segments: thread t holds the samples t + 256 r (r = 0..15) of a segment,
+// whose Hann weights are fixed, and after the three radix-16 passes the bins t + 256 r.
+__global__ __launch_bounds__(kFftThreads) void k_welch4096(const float* __restrict__ y, int nseg,
+                                                           float* __restrict__ part) {
+  __shared__ float2 buf[kF16Row];
+  __shared__ float2 tw[kFftMax / 2];
+  fft_twiddles(tw, kFftMax);
+  const int t = threadIdx.x;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int s0 = (int)(((int64_t)g * nseg) / G), s1 = (int)(((int64_t)(g + 1) * nseg) / G);
+  float win[16], acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    win[r] = 0.5f - 0.5f * cospif(2.0f * (float)(t + 256 * r) / (float)kFftMax);
+    acc[r] = 0.f;
+  }
+  const float2* y2 = reinterpret_cast<const float2*>(y);
+  for (int sg = s0; sg < s1; ++sg) {
+    const int64_t base = (int64_t)sg * (kFftMax / 2);
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float2 a = y2[base + t + 256 * r];
+      v[r] = make_float2(a.x * win[r], a.y * win[r]);
+    }
+    __syncthreads();                       // the previous segment's last-pass reads are done
+    f16_pass1(buf, v);
+    __syncthreads();
+    f16_pass2(buf, tw);
+    __syncthreads();
+    f16_pass3(buf, tw, v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float2 X = X16(v, r);
+      acc[r] += X.x * X.x + X.y * X.y;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part[(int64_t)g * kFftMax + t + 256 * r] = acc[r];
+}
 
 __global__ __launch_bounds__(kFftThreads) void k_welch(const float* __restrict__ y, int64_t n,
                                                        int nfft, int log2n, int nseg,
@@ -143,7 +184,8 @@ void launch_welch(const float* y, int64_t n, int nfft, float* seg_part, int n_gr
   int log2n = 0;
   while ((1 << log2n) < nfft) ++log2n;
   int nseg = (int)((n - nfft) / (nfft / 2) + 1);
-  k_welch<<<n_groups, kFftThreads, 0, s>>>(y, n, nfft, log2n, nseg, seg_part);
+  if (nfft == kFftMax) k_welch4096<<<n_groups, kFftThreads, 0, s>>>(y, nseg, seg_part);
+  else k_welch<<<n_groups, kFftThreads, 0, s>>>(y, n, nfft, log2n, nseg, seg_part);
 }
 
 void launch_welch_final(const float* seg_part, int n_groups, int nseg, int nfft, int half_bins,

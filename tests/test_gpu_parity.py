@@ -176,3 +176,25 @@ def test_acpr_matches_oracle_psd():
     ref_acpr = O.acpr_db(ref_psd, 512)
     print(f"  ACPR gpu {acpr.cpu().numpy()} oracle {ref_acpr}", flush=True)
     assert np.max(np.abs(acpr.cpu().numpy() - np.array(ref_acpr))) < 0.01
+
+
+@pytest.mark.parametrize("nfft", [256, 1024, 4096])
+def test_welch_sizes_against_oracle(nfft):
+    """Welch PSD and ACPR of one PA output at every transform path: the radix-16
+    4096-point kernel and the in-LDS radix-2 kernel of the other sizes."""
+    announce(f"Welch PSD nfft={nfft} on a 2^16-sample PA output")
+    import paper_2205_05158_amd as D
+    inp = S.make_workload("fwd_4m", max_len=1 << 16)
+    ref = H.oracle_for(inp, grad=False)
+    y = np.stack([ref.y.real, ref.y.imag], -1).astype(np.float32)
+    n = y.shape[0]
+    hb = nfft // 8 - 1
+    ws = torch.empty(D.dpd_acpr_workspace_size(n, nfft), dtype=torch.uint8, device="cuda")
+    psd = torch.empty(nfft, dtype=torch.float32, device="cuda")
+    acpr = torch.empty(3, dtype=torch.float32, device="cuda")
+    D.cascade_acpr(H.to_dev(y), n, nfft, hb, psd, acpr, ws)
+    torch.cuda.synchronize()
+    ref_psd = O.welch_psd(y[:, 0].astype(np.float64) + 1j * y[:, 1], nfft)
+    np.testing.assert_allclose(psd.cpu().numpy(), ref_psd, rtol=2e-4, atol=1e-7 * ref_psd.max())
+    ref_acpr = np.array(O.acpr_db(ref_psd, hb))
+    assert np.max(np.abs(acpr.cpu().numpy() - ref_acpr)) < 0.01
