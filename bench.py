@@ -61,11 +61,13 @@ CNN_WORKLOADS = {"fdcnn_8u": dict(items=8 * 1024, n_d=384, side=20, n_conv=2, kc
 
 
 def source_digest() -> str:
-    """Digest of everything the kernels are built from (sources, header, build flags)."""
+    """Digest of everything the library's kernels are built from (sources, header, build
+    flags); the unit-throughput probes (peaks.hip, a separate library) are not part of it."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_05158_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".hpp")))
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                   if f.endswith((".hip", ".hpp")) and f != "peaks.hip")
     files += [os.path.join(ROOT, "include", "dpdmi.h"),
               os.path.join(ROOT, "paper_2205_05158_amd", "build.py")]
     for f in files:
@@ -136,14 +138,18 @@ def copy_calibration():
 
 def measure_peaks(torch):
     """Unit throughputs measured on this GPU by libdpdpeaks.so (timed with HIP events on
-    torch's current stream, where the probes are launched): bf16 MFMA 16x16x32, non-packed
-    fp32 FMA, exp2+reciprocal pairs (the transcendental part of a tanh) and an HBM copy."""
+    torch's current stream, where the probes are launched): bf16 MFMA 32x32x16 and
+    16x16x32 with the shader clock they ran at (s_memtime against the 100 MHz real-time
+    counter), non-packed fp32 FMA, exp2+reciprocal pairs (the transcendental part of a
+    tanh) and an HBM copy (four non-temporal 16-byte loads in flight per thread)."""
     import ctypes as C
     from paper_2205_05158_amd import build as B
     lib = C.CDLL(B.PEAKS_LIB)
-    for name in ("peak_mfma_bf16", "peak_fma_f32", "peak_trans"):
+    for name in ("peak_fma_f32", "peak_trans"):
         getattr(lib, name).argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p]
         getattr(lib, name).restype = C.c_int
+    lib.peak_mfma_bf16.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p]
+    lib.peak_mfma_bf16.restype = C.c_int
     lib.peak_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p]
     lib.peak_copy.restype = C.c_int
     props = torch.cuda.get_device_properties(0)
@@ -170,8 +176,14 @@ def measure_peaks(torch):
             raise RuntimeError(f"peak probe launch failed: {rc}")
 
     it = 4096
-    t = timed(lambda: check(lib.peak_mfma_bf16(C.c_void_p(sink.data_ptr()), blocks, it, sh)))
-    mfma = blocks * 4 * it * 4 * (16 * 16 * 32 * 2) / t / 1e12      # 4 waves x 4 chains
+    clk = torch.empty(2 * blocks, dtype=torch.int64, device="cuda")
+    mfma, mclk = {}, {}
+    for big, shape, flop in ((0, "16x16x32", 16 * 16 * 32 * 2), (1, "32x32x16", 32 * 32 * 16 * 2)):
+        t = timed(lambda: check(lib.peak_mfma_bf16(C.c_void_p(sink.data_ptr()), C.c_void_p(clk.data_ptr()),
+                                                   blocks, it, big, sh)))
+        mfma[shape] = blocks * 4 * it * 4 * flop / t / 1e12      # 4 waves x 4 chains
+        c = clk.view(-1, 2).cpu().double()
+        mclk[shape] = float((c[:, 0] / c[:, 1]).median() * 100.0)   # shader clock in MHz
     t = timed(lambda: check(lib.peak_fma_f32(C.c_void_p(sink.data_ptr()), blocks, it, sh)))
     fma = blocks * 256 * it * 8 * 2 / t / 1e12
     t = timed(lambda: check(lib.peak_trans(C.c_void_p(sink.data_ptr()), blocks, it, sh)))
@@ -180,11 +192,12 @@ def measure_peaks(torch):
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     t = timed(lambda: check(lib.peak_copy(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
-                                          nbytes, 16 * cus, sh)))
+                                          nbytes, 64 * cus, sh)))
     hbm = 2 * nbytes / t / 1e9
     del a, b
-    return {"mfma_bf16_tflops": mfma, "valu_fp32_fma_tflops": fma,
-            "exp2_rcp_pairs_gps": trans, "hbm_copy_gbs": hbm}
+    return {"mfma_bf16_tflops": mfma["32x32x16"], "mfma_bf16_16x16x32_tflops": mfma["16x16x32"],
+            "mfma_clock_mhz": mclk["32x32x16"], "mfma_16x16x32_clock_mhz": mclk["16x16x32"],
+            "valu_fp32_fma_tflops": fma, "exp2_rcp_pairs_gps": trans, "hbm_copy_gbs": hbm}
 
 
 def cpu_baseline(wl_name, n_sample):
@@ -1019,7 +1032,8 @@ def main():
         mp = (peaks["mfma_bf16_tflops"] if roof["bound"] == "mfma" and prec == "bf16" else
               peaks["valu_fp32_fma_tflops"] if roof["bound"] == "alu" else None)
         roof["measured_peak_note"] = ("unit probe on this GPU under sustained load (see "
-                                      "peaks_measured); frac is against the published peak")
+                                      "peaks_measured: bf16 32x32x16 MFMA at the shader clock it ran "
+                                      "at); frac is against the published peak")
         roof["measured_peak"] = mp
         roof["frac_of_measured_peak"] = roof["achieved"] / mp if mp else None
     # whole-step composite bound: each unit's algorithmic work at its published peak
