@@ -148,11 +148,12 @@ dpd_status cascade_nmse(const dpd_batch* batch, const float* y, const float* x,
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): cascade_nmse without a workspace.
- * Same arguments, records and kernels as cascade_nmse; the per-tile partial sums live
- * in a static device array of DPD_NOALLOC_NMSE_MAX_TILES records of 16 bytes (4 MiB;
- * tiles of 256 samples, one tile count per stream rounded up, so up to about 2^26
- * samples), held by each device the library runs on until the process ends.  A problem
- * needing more tiles returns DPD_ERR_WORKSPACE before any HIP call.  The call allocates
+ * Same arguments, records and kernels as cascade_nmse; the partial sums (one record per
+ * tile of 256 samples, a tile count per stream rounded up, plus one per 256 tiles of
+ * each stream for the final pass) live in a static device array of
+ * DPD_NOALLOC_NMSE_MAX_TILES records of 16 bytes (4 MiB, up to about 2^26 samples), held
+ * by each device the library runs on until the process ends.  A problem needing more
+ * records returns DPD_ERR_WORKSPACE before any HIP call.  The call allocates
  * nothing and calls no allocating routine; the array's device address is looked up once
  * per device (hipGetSymbolAddress, the device current) on the first call there.  Every
  * call on one device shares the array: calls that may overlap on one device (other

@@ -22,8 +22,9 @@ void launch_plain_finalize_sets(const float* acc, int taps, int n_hidden, int hi
 
 using namespace dpdmi;
 
-// Scratch of cascade_nmse_noalloc: the per-tile NMSE partials (E, R, non-finite count) of
-// problems of up to DPD_NOALLOC_NMSE_MAX_TILES tiles, in a static device array (each
+// Scratch of cascade_nmse_noalloc: the per-tile NMSE partials (E, R, non-finite count) and
+// the final pass's per-chunk records, DPD_NOALLOC_NMSE_MAX_TILES records in all, in a
+// static device array (each
 // device that runs the library holds its own copy until the process ends).  In host code
 // this name is only a stand-in for the symbol: kernels and runtime calls get the device
 // address that hipGetSymbolAddress returns for the current device.
@@ -210,7 +211,8 @@ Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
   size_t pos = 0;
   auto take = [&](size_t bytes) { size_t at = pos; pos = align_up(pos + bytes); return at; };
   int64_t max_tiles = p.n_total / 32 + p.S + 1;   // any tile size >= 32
-  w.tile_part = take(sizeof(float4) * max_tiles);
+  int64_t max_chunks = max_tiles / kNmseChunk + p.S + 1;   // the final pass's first stage
+  w.tile_part = take(sizeof(float4) * (max_tiles + max_chunks));
   w.inv_r = take(sizeof(float) * p.n_sets);
   w.loss_tmp = take(sizeof(float) * p.n_sets);
   w.u_buf = take(sizeof(float2) * p.n_total);
@@ -511,7 +513,8 @@ dpd_status cascade_nmse_noalloc(const dpd_batch* batch, const float* y, const fl
   if (!aligned(y, 8) || !aligned(x, 8) || !aligned(out, 4)) return DPD_ERR_ALIGN;
   if (!isfinite(g_re) || !isfinite(g_im) || (g_re == 0.f && g_im == 0.f)) return DPD_ERR_SHAPE;
   StreamTable tab = make_table(p, kNmseTile);
-  if (tab.n_tiles > DPD_NOALLOC_NMSE_MAX_TILES) return DPD_ERR_WORKSPACE;
+  if ((int64_t)tab.n_tiles + nmse_chunk_table(tab).n_tiles > DPD_NOALLOC_NMSE_MAX_TILES)
+    return DPD_ERR_WORKSPACE;
   float4* part = noalloc_scratch_ptr();
   if (!part) return DPD_ERR_LAUNCH;
   // every partial the final pass reads is written by the tile pass first: nothing to clear

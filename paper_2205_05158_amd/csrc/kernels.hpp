@@ -17,9 +17,13 @@ void launch_nmse_tiles(const StreamTable& st, const float* y, const float* x, fl
                        float g_im, float4* tile_part, hipStream_t s);
 // Per-stream and pooled NMSE records (E, R, NMSE dB, non-finite count) from the tile
 // partials (rec may be null); optional per-set pooled loss and 1/R per set (inv_r may
-// be null).
-void launch_nmse_final(const StreamTable& st, const float4* tile_part, float* rec, float* loss,
-                       float* inv_r, hipStream_t s);
+// be null).  Two fixed-order stages: chunks of kNmseChunk tiles of one stream, then the
+// chunks of each stream; the chunk records go to tile_part[st.n_tiles ..
+// st.n_tiles + nmse_chunk_table(st).n_tiles), which the caller provides.
+constexpr int kNmseChunk = 256;
+StreamTable nmse_chunk_table(const StreamTable& st);
+void launch_nmse_final(const StreamTable& st, float4* tile_part, float* rec, float* loss, float* inv_r,
+                       hipStream_t s);
 // Ideal linear-clipping PA (y = u up to |u| = a, a u / |u| beyond): y of n samples
 // (y may equal u), and the cascade pass over the table's tiles: y (may be null), the
 // NMSE tile partials and, when gu is not null, g_u = J^T 2 (y - G x).

@@ -13,33 +13,36 @@ namespace {
 constexpr int kRedThreads = 256;
 constexpr int kMseTile = 4096;   // values per symbol-MSE tile
 
+// Two compensated sums over the NT threads of the workgroup (fixed tree); every thread
+// gets both totals.  sh: 4 * NT floats.
+template <int NT = kRedThreads>
 __device__ void block_reduce2(Comp& a, Comp& b, float* sh) {
-  // sh: 4 * kRedThreads floats
   int t = threadIdx.x;
-  sh[t] = a.s; sh[kRedThreads + t] = a.c;
-  sh[2 * kRedThreads + t] = b.s; sh[3 * kRedThreads + t] = b.c;
+  sh[t] = a.s; sh[NT + t] = a.c;
+  sh[2 * NT + t] = b.s; sh[3 * NT + t] = b.c;
   __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (t < w) {
-      Comp x{sh[t], sh[kRedThreads + t]}, y{sh[2 * kRedThreads + t], sh[3 * kRedThreads + t]};
-      x.add(sh[t + w]); x.add(sh[kRedThreads + t + w]);
-      y.add(sh[2 * kRedThreads + t + w]); y.add(sh[3 * kRedThreads + t + w]);
-      sh[t] = x.s; sh[kRedThreads + t] = x.c;
-      sh[2 * kRedThreads + t] = y.s; sh[3 * kRedThreads + t] = y.c;
+      Comp x{sh[t], sh[NT + t]}, y{sh[2 * NT + t], sh[3 * NT + t]};
+      x.add(sh[t + w]); x.add(sh[NT + t + w]);
+      y.add(sh[2 * NT + t + w]); y.add(sh[3 * NT + t + w]);
+      sh[t] = x.s; sh[NT + t] = x.c;
+      sh[2 * NT + t] = y.s; sh[3 * NT + t] = y.c;
     }
     __syncthreads();
   }
-  a = Comp{sh[0], sh[kRedThreads]};
-  b = Comp{sh[2 * kRedThreads], sh[3 * kRedThreads]};
+  a = Comp{sh[0], sh[NT]};
+  b = Comp{sh[2 * NT], sh[3 * NT]};
   __syncthreads();
 }
 
 // Sum of one unsigned count per thread (fixed tree); every thread gets the total.
+template <int NT = kRedThreads>
 __device__ uint32_t block_sum_u32(uint32_t v, uint32_t* sh) {
   const int t = threadIdx.x;
   sh[t] = v;
   __syncthreads();
-  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (t < w) sh[t] += sh[t + w];
     __syncthreads();
   }
@@ -74,27 +77,70 @@ __global__ __launch_bounds__(kRedThreads) void k_nmse_tiles(StreamTable st, cons
   if (threadIdx.x == 0) part[t] = make_float4(E.value(), R.value(), (float)nf, 0.f);
 }
 
-// Records of DPD_NMSE_FIELDS floats: (E, R, NMSE dB, non-finite count).
-__global__ __launch_bounds__(kRedThreads) void k_nmse_final(StreamTable st, const float4* __restrict__ part,
+// First stage of the final pass: workgroup b sums the tile partials of chunk b (up to
+// kNmseChunk consecutive tiles of one stream; chunks never cross streams) in a fixed tree
+// into one (E, R, non-finite count) record.  ct: the chunk table (ct.tile0[s] = first
+// chunk of stream s).
+__global__ __launch_bounds__(kRedThreads) void k_nmse_chunks(StreamTable st, StreamTable ct,
+                                                             const float4* __restrict__ part,
+                                                             float4* __restrict__ chunk_part) {
+  static_assert(kNmseChunk == kRedThreads, "one tile partial per thread");
+  __shared__ float sh[4 * kRedThreads];
+  __shared__ uint32_t shn[kRedThreads];
+  const int b = blockIdx.x;
+  const int s = stream_of_tile(ct, b);
+  const int t = st.tile0[s] + (b - ct.tile0[s]) * kNmseChunk + (int)threadIdx.x;
+  Comp E, R;
+  uint32_t nf = 0;
+  if (t < st.tile0[s + 1]) {
+    const float4 v = part[t];
+    E.add(v.x);
+    R.add(v.y);
+    nf = (uint32_t)v.z;
+  }
+  block_reduce2(E, R, sh);
+  nf = block_sum_u32(nf, shn);
+  if (threadIdx.x == 0) chunk_part[b] = make_float4(E.value(), R.value(), (float)nf, 0.f);
+}
+
+// Records of DPD_NMSE_FIELDS floats: (E, R, NMSE dB, non-finite count), from the chunk
+// records of the first stage (part, indexed by the chunk table st).
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void k_nmse_final(StreamTable st, const float4* __restrict__ part,
                                                             float* __restrict__ rec,
                                                             float* __restrict__ loss,
                                                             float* __restrict__ inv_r) {
   constexpr int F = DPD_NMSE_FIELDS;
-  __shared__ float sh[4 * kRedThreads];
-  __shared__ uint32_t shn[kRedThreads];
+  __shared__ float sh[4 * kFinThreads];
+  __shared__ uint32_t shn[kFinThreads];
   Comp Et, Rt;   // pooled over all streams
   uint32_t nft = 0;
   for (int s = 0; s < st.n; ++s) {
     Comp E, R;
     uint32_t nf = 0;
-    for (int t = st.tile0[s] + threadIdx.x; t < st.tile0[s + 1]; t += kRedThreads) {
-      float4 v = part[t];
+    // each thread sums its partials in stride order; eight loads are issued ahead of
+    // their (dependent, compensated) adds
+    const int t1 = st.tile0[s + 1];
+    int t = st.tile0[s] + threadIdx.x;
+    for (; t + 7 * kFinThreads < t1; t += 8 * kFinThreads) {
+      float4 v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[t + q * kFinThreads];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        E.add(v[q].x);
+        R.add(v[q].y);
+        nf += (uint32_t)v[q].z;
+      }
+    }
+    for (; t < t1; t += kFinThreads) {
+      const float4 v = part[t];
       E.add(v.x);
       R.add(v.y);
       nf += (uint32_t)v.z;
     }
-    block_reduce2(E, R, sh);
-    nf = block_sum_u32(nf, shn);
+    block_reduce2<kFinThreads>(E, R, sh);
+    nf = block_sum_u32<kFinThreads>(nf, shn);
     float e = E.value(), r = R.value();
     if (threadIdx.x == 0) {
       if (rec) {
@@ -277,9 +323,25 @@ void launch_nmse_tiles(const StreamTable& st, const float* y, const float* x, fl
   k_nmse_tiles<<<st.n_tiles, kRedThreads, 0, s>>>(st, y, x, g_re, g_im, tile_part);
 }
 
-void launch_nmse_final(const StreamTable& st, const float4* tile_part, float* rec, float* loss,
-                       float* inv_r, hipStream_t s) {
-  k_nmse_final<<<1, kRedThreads, 0, s>>>(st, tile_part, rec, loss, inv_r);
+StreamTable nmse_chunk_table(const StreamTable& st) {
+  StreamTable ct = st;
+  ct.tile = st.tile * kNmseChunk;
+  int32_t c = 0;
+  for (int i = 0; i < st.n; ++i) {
+    ct.tile0[i] = c;
+    c += (st.tile0[i + 1] - st.tile0[i] + kNmseChunk - 1) / kNmseChunk;
+  }
+  ct.tile0[st.n] = c;
+  ct.n_tiles = c;
+  return ct;
+}
+
+void launch_nmse_final(const StreamTable& st, float4* tile_part, float* rec, float* loss, float* inv_r,
+                       hipStream_t s) {
+  const StreamTable ct = nmse_chunk_table(st);
+  float4* chunk_part = tile_part + st.n_tiles;
+  k_nmse_chunks<<<ct.n_tiles, kRedThreads, 0, s>>>(st, ct, tile_part, chunk_part);
+  k_nmse_final<<<1, kFinThreads, 0, s>>>(ct, chunk_part, rec, loss, inv_r);
 }
 
 }  // namespace dpdmi

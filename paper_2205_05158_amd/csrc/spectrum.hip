@@ -125,7 +125,15 @@ __global__ __launch_bounds__(kFftThreads) void k_welch_sum(const float* __restri
   const int sp = blockIdx.y;
   const int g0 = (int)((int64_t)sp * G / splits), g1 = (int)((int64_t)(sp + 1) * G / splits);
   Comp s;
-  for (int g = g0; g < g1; ++g) s.add(part[(int64_t)g * nfft + k]);
+  int g = g0;
+  for (; g + 8 <= g1; g += 8) {          // eight loads ahead of their (ordered) adds
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(g + q) * nfft + k];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s.add(v[q]);
+  }
+  for (; g < g1; ++g) s.add(part[(int64_t)g * nfft + k]);
   sums[(int64_t)sp * nfft + k] = make_float2(s.s, s.c);
 }
 

@@ -387,13 +387,14 @@ struct SharedBwdA {
   int lane;
   __device__ bf16x8 operator()(int mb, int ks) const {
     const int l = lane % 16, g = lane / 16;
-    const int c = 4 * mb + l % 4;
-    const int o1 = 32 * ks + 4 * g + l / 4, o2 = o1 + 16;
+    // The swizzle sees only bits 0-3 of the row, i.e. the lane part 4 g + l / 4 of
+    // o1 = 32 ks + 4 g + l / 4 and o2 = o1 + 16: the K step's rows are then constant
+    // offsets from one lane address per row block (immediate offsets of the reads).
+    const int ol = 4 * g + l / 4;
+    const __bf16* p = w + ol * C::HP + 4 * ((4 * mb + l % 4) ^ C::swz(ol));
     typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
-    const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
-        (lds_bf16x4*)(w + o1 * C::HP + 4 * (c ^ C::swz(o1))));
-    const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16(
-        (lds_bf16x4*)(w + o2 * C::HP + 4 * (c ^ C::swz(o2))));
+    const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(p + 32 * ks * C::HP));
+    const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(p + (32 * ks + 16) * C::HP));
     return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
   }
 };

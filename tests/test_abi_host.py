@@ -153,10 +153,16 @@ def test_noalloc_nmse_arguments_rejected(dpdlib):
     assert f(C.byref(b), C.c_void_p(0x100004), FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_ALIGN
     assert f(C.byref(b), FAKE, FAKE, 0.0, 0.0, FAKE, None) == L.DPD_ERR_SHAPE
     assert f(C.byref(D.make_batch([0, 0])), FAKE, FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_SHAPE
-    # tiles of 256 samples, one count per stream rounded up
+    # tiles of 256 samples, one count per stream rounded up, plus one final-pass record per
+    # 256 tiles of a stream
     cap = L.DPD_NOALLOC_NMSE_MAX_TILES * 256
     too_big = D.make_batch([0, cap + 1])
     assert f(C.byref(too_big), FAKE, FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_WORKSPACE
+    m = L.DPD_NOALLOC_NMSE_MAX_TILES
+    tiles = m - m // 257 + 1                      # tiles + ceil(tiles / 256) = m + 2
+    assert tiles + -(-tiles // 256) > m
+    over = D.make_batch([0, tiles * 256])
+    assert f(C.byref(over), FAKE, FAKE, 1.0, 0.0, FAKE, None) == L.DPD_ERR_WORKSPACE
 
 
 def test_symbol_mse_arguments_rejected(dpdlib):
