@@ -166,17 +166,29 @@ __global__ __launch_bounds__(kFftThreads) void k_welch_final(const float* __rest
     else if (ks > half_bins && ks <= 3 * half_bins) up.add(v);
     else if (ks < -half_bins && ks >= -3 * half_bins) lo.add(v);
   }
-  sh[tid] = lo.s; sh[kFftThreads + tid] = lo.c;
-  sh[2 * kFftThreads + tid] = mn.s; sh[3 * kFftThreads + tid] = mn.c;
-  sh[4 * kFftThreads + tid] = up.s; sh[5 * kFftThreads + tid] = up.c;
+  // the three band sums over the threads, a fixed tree
+  Comp* band[3] = {&lo, &mn, &up};
+  for (int b = 0; b < 3; ++b) {
+    sh[2 * b * kFftThreads + tid] = band[b]->s;
+    sh[(2 * b + 1) * kFftThreads + tid] = band[b]->c;
+  }
   __syncthreads();
-  if (tid == 0) {
-    Comp L, Mn, U;
-    for (int i = 0; i < kFftThreads; ++i) {
-      L.add(sh[i]); L.add(sh[kFftThreads + i]);
-      Mn.add(sh[2 * kFftThreads + i]); Mn.add(sh[3 * kFftThreads + i]);
-      U.add(sh[4 * kFftThreads + i]); U.add(sh[5 * kFftThreads + i]);
+  for (int w = kFftThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        Comp x{sh[2 * b * kFftThreads + tid], sh[(2 * b + 1) * kFftThreads + tid]};
+        x.add(sh[2 * b * kFftThreads + tid + w]);
+        x.add(sh[(2 * b + 1) * kFftThreads + tid + w]);
+        sh[2 * b * kFftThreads + tid] = x.s;
+        sh[(2 * b + 1) * kFftThreads + tid] = x.c;
+      }
     }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const Comp L{sh[0], sh[kFftThreads]}, Mn{sh[2 * kFftThreads], sh[3 * kFftThreads]},
+        U{sh[4 * kFftThreads], sh[5 * kFftThreads]};
     float pm = Mn.value();
     float aL = 10.f * log10f(L.value() / pm), aU = 10.f * log10f(U.value() / pm);
     acpr[0] = aL;

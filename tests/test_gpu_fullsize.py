@@ -112,6 +112,67 @@ def test_bf16_16m_step_at_full_size():
     assert ge <= H.BF16_GRAD and ngap <= H.BF16_NMSE_DB
 
 
+def oracle_forward_chunked(inp, chunk=1 << 19):
+    """The oracle's u and y of a one-stream workload, chunk by chunk: chunk [a, b) is
+    evaluated on its input window x[a - M - L - (T - 1), b + L) (zero outside the stream),
+    whose first T - 1 DPD outputs lack their taps and are not used; u is zero outside the
+    stream.  Equal to the whole-stream evaluation (the windowed evaluation and the zero
+    prefix are pinned on the oracle side)."""
+    wl = inp.workload
+    x = H.cplx(inp.x)
+    N = x.size
+    layers = O.unpack_tdnn(np.asarray(inp.w, np.float64), wl.taps, wl.n_hidden, wl.hidden)
+    a_c, b_c, c_c = O.unpack_gmp(np.asarray(inp.coef, np.float64), wl.K, wl.M, wl.L)
+    back, ahead = wl.M + wl.L, wl.L
+    u_all = np.empty(N, np.complex128)
+    y_all = np.empty(N, np.complex128)
+    for a in range(0, N, chunk):
+        b = min(N, a + chunk)
+        lo = a - back - (wl.taps - 1)
+        hi = b + ahead
+        win = np.zeros(hi - lo, np.complex128)
+        s0, s1 = max(lo, 0), min(hi, N)
+        win[s0 - lo:s1 - lo] = x[s0:s1]
+        u_win, _ = O.tdnn_forward(win, layers)
+        pos = np.arange(lo, hi)
+        u_win[(pos < 0) | (pos >= N)] = 0.0
+        u_win = u_win[wl.taps - 1:]                    # positions [a - back, hi)
+        y_win = O.gmp_forward(u_win, a_c, b_c, c_c)
+        u_all[a:b] = u_win[back:back + (b - a)]
+        y_all[a:b] = y_win[back:back + (b - a)]
+    return u_all, y_all
+
+
+def test_bf16_16m_every_sample_against_oracle():
+    """The whole 2^24-sample BF16 step of the bench (dpd_cascade at the autotuned shape):
+    every sample of u and y, the output-parity NMSE and the NMSE record against the FP64
+    oracle's forward, evaluated chunk by chunk."""
+    import paper_2205_05158_amd as D
+    announce("bf16_16m: 2^24 samples, every u and y sample and the NMSE vs the oracle")
+    inp = S.make_workload("bf16_16m")
+    cas = H.cascade_for(inp)
+    x, w, c = H.to_dev(inp.x), H.to_dev(inp.w), H.to_dev(inp.coef)
+    cas.autotune(x, w, c, reps=2)
+    out = cas.run(x, w, c)
+    torch.cuda.synchronize()
+    got = {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+    cas.set_tune(None)
+    del x, w, c, out
+    ru, ry = oracle_forward_chunked(inp)
+    eu = H.per_sample_rel(got["u"], ru)
+    ey = H.per_sample_rel(got["y"], ry)
+    op = H.output_parity_db(got["y"], ry)
+    e = ry - H.cplx(inp.x)
+    nmse_ref = H.db(float(np.sum(e.real ** 2 + e.imag ** 2)) / float(np.sum(np.abs(H.cplx(inp.x)) ** 2)))
+    gap = abs(float(got["nmse"][-1, 2]) - nmse_ref)
+    print(f"  every sample: rel err u {eu:.2e} y {ey:.2e}; output parity {op:.1f} dB; NMSE gap {gap:.2e} dB",
+          flush=True)
+    assert eu <= H.BF16_SAMPLE and ey <= H.BF16_SAMPLE
+    assert op <= H.BF16_OUTPUT_PARITY_DB
+    assert gap <= H.BF16_NMSE_DB
+    assert D.dpd_nmse_status(got["nmse"]) == D.DPD_OK
+
+
 def test_train_frame_at_full_length():
     """One 131072-sample frame of the 8-frame training batch against the oracle, and
     the 8-frame launch's per-frame E/R for that frame against the one-frame launch."""
