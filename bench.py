@@ -888,24 +888,24 @@ def main():
     if args.workload in CNN_WORKLOADS:
         world = int(os.environ.get("WORLD_SIZE", "1"))
         if args.gpus != 1 or world != 1:
-            print(json.dumps({"error": "this build runs on one GPU only", "n_gpus": args.gpus}))
+            print(json.dumps({"error": "this benchmark runs on one GPU only", "n_gpus": args.gpus}))
             sys.exit(2)
         return bench_fdcnn(args)
     if args.workload in DL_WORKLOADS:
         world = int(os.environ.get("WORLD_SIZE", "1"))
         if args.gpus != 1 or world != 1:
-            print(json.dumps({"error": "this build runs on one GPU only", "n_gpus": args.gpus}))
+            print(json.dumps({"error": "this benchmark runs on one GPU only", "n_gpus": args.gpus}))
             sys.exit(2)
         return bench_downlink(args)
     if args.workload in ILA_WORKLOADS:
         world = int(os.environ.get("WORLD_SIZE", "1"))
         if args.gpus != 1 or world != 1:
-            print(json.dumps({"error": "this build runs on one GPU only", "n_gpus": args.gpus}))
+            print(json.dumps({"error": "this benchmark runs on one GPU only", "n_gpus": args.gpus}))
             sys.exit(2)
         return bench_ila(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the hot path shards by "
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the hot path shards by "
                                    "streams or time chunks across GPUs (see the design notes), "
                                    "but no multi-GPU run is implemented", "n_gpus": args.gpus}))
         sys.exit(2)

@@ -48,7 +48,7 @@ typedef enum {
     DPD_OK = 0,
     DPD_ERR_NULL = -1,         /* a required pointer is NULL                          */
     DPD_ERR_SHAPE = -2,        /* a size, offset table or descriptor value is invalid */
-    DPD_ERR_UNSUPPORTED = -3,  /* valid request this build does not implement        */
+    DPD_ERR_UNSUPPORTED = -3,  /* valid request the library does not implement      */
     DPD_ERR_WORKSPACE = -4,    /* workspace smaller than dpd_workspace_size() says    */
     DPD_ERR_LAUNCH = -5,       /* the HIP runtime reported an error                   */
     DPD_ERR_ALIGN = -6,        /* a pointer is not aligned as documented              */

@@ -10,7 +10,7 @@ blocking or fusion beyond the definitions written out below.
 Paper passages followed (arXiv 2205.05158):
   * TD DPD slot, causal window of the last L2+1 inputs ........ Sec. II-C, eq. (8)
   * tapped delay line, real/imag split, FC layers, 2 outputs ... Sec. III-C (FD-NN core)
-    (per tap this build feeds I, Q, |x|, |x|^2, |x|^3 and uses tanh)
+    (per tap the TDNN here takes I, Q, |x|, |x|^2, |x|^3 and uses tanh)
   * PA with memory, filled by the GMP ............................ Sec. II-B, eq. (7); eq. (9)
   * linear-PA target x_PA = gain * x ............................. Sec. II-B
   * training by MSE through the differentiable chain ............. Sec. V-A-2

@@ -1051,7 +1051,7 @@ const char* dpd_status_string(dpd_status status) {
     case DPD_OK: return "DPD_OK";
     case DPD_ERR_NULL: return "DPD_ERR_NULL: a required pointer is NULL";
     case DPD_ERR_SHAPE: return "DPD_ERR_SHAPE: invalid size, offset table or descriptor";
-    case DPD_ERR_UNSUPPORTED: return "DPD_ERR_UNSUPPORTED: request not implemented by this build";
+    case DPD_ERR_UNSUPPORTED: return "DPD_ERR_UNSUPPORTED: request not implemented by this library";
     case DPD_ERR_WORKSPACE: return "DPD_ERR_WORKSPACE: workspace too small";
     case DPD_ERR_LAUNCH: return "DPD_ERR_LAUNCH: the HIP runtime reported an error";
     case DPD_ERR_ALIGN: return "DPD_ERR_ALIGN: misaligned pointer";
