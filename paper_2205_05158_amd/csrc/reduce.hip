@@ -106,50 +106,64 @@ __global__ __launch_bounds__(kRedThreads) void k_nmse_chunks(StreamTable st, Str
 // Records of DPD_NMSE_FIELDS floats: (E, R, NMSE dB, non-finite count), from the chunk
 // records of the first stage (part, indexed by the chunk table st).
 constexpr int kFinThreads = 1024;
+constexpr int kFinWaves = kFinThreads / 64;
+
+// Sum of a compensated value over the 64 lanes of a wave (fixed butterfly order); lane 0
+// holds the result.
+__device__ __forceinline__ Comp wave_sum(Comp v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float os = __shfl_xor(v.s, off), oc = __shfl_xor(v.c, off);
+    v.add(os);
+    v.add(oc);
+  }
+  return v;
+}
+
+// One wave per stream (streams wave, wave + kFinWaves, ...): each lane sums its chunk
+// records in stride order, the wave combines them; then thread 0 writes the records and
+// pools the streams in stream order.
 __global__ __launch_bounds__(kFinThreads) void k_nmse_final(StreamTable st, const float4* __restrict__ part,
                                                             float* __restrict__ rec,
                                                             float* __restrict__ loss,
                                                             float* __restrict__ inv_r) {
   constexpr int F = DPD_NMSE_FIELDS;
-  __shared__ float sh[4 * kFinThreads];
-  __shared__ uint32_t shn[kFinThreads];
-  Comp Et, Rt;   // pooled over all streams
-  uint32_t nft = 0;
-  for (int s = 0; s < st.n; ++s) {
+  __shared__ float4 sums[DPD_MAX_STREAMS];       // E.s, E.c, R.s, R.c per stream
+  __shared__ uint32_t counts[DPD_MAX_STREAMS];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  for (int s = wave; s < st.n; s += kFinWaves) {
     Comp E, R;
     uint32_t nf = 0;
-    // each thread sums its partials in stride order; eight loads are issued ahead of
-    // their (dependent, compensated) adds
-    const int t1 = st.tile0[s + 1];
-    int t = st.tile0[s] + threadIdx.x;
-    for (; t + 7 * kFinThreads < t1; t += 8 * kFinThreads) {
-      float4 v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = part[t + q * kFinThreads];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        E.add(v[q].x);
-        R.add(v[q].y);
-        nf += (uint32_t)v[q].z;
-      }
-    }
-    for (; t < t1; t += kFinThreads) {
+    for (int t = st.tile0[s] + lane; t < st.tile0[s + 1]; t += 64) {
       const float4 v = part[t];
       E.add(v.x);
       R.add(v.y);
       nf += (uint32_t)v.z;
     }
-    block_reduce2<kFinThreads>(E, R, sh);
-    nf = block_sum_u32<kFinThreads>(nf, shn);
-    float e = E.value(), r = R.value();
-    if (threadIdx.x == 0) {
+    E = wave_sum(E);
+    R = wave_sum(R);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nf += __shfl_xor(nf, off);
+    if (lane == 0) {
+      sums[s] = make_float4(E.s, E.c, R.s, R.c);
+      counts[s] = nf;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Comp Et, Rt;   // pooled over all streams
+    uint32_t nft = 0;
+    for (int s = 0; s < st.n; ++s) {
+      const float4 v = sums[s];
+      const Comp E{v.x, v.y}, R{v.z, v.w};
+      const float e = E.value(), r = R.value();
       if (rec) {
         rec[F * s] = e;
         rec[F * s + 1] = r;
         rec[F * s + 2] = 10.f * log10f(e / r);
-        rec[F * s + 3] = (float)nf;
+        rec[F * s + 3] = (float)counts[s];
       }
-      nft += nf;
+      nft += counts[s];
       Et.add(E.s); Et.add(E.c);
       Rt.add(R.s); Rt.add(R.c);
       if (st.per_stream) {
@@ -157,9 +171,7 @@ __global__ __launch_bounds__(kFinThreads) void k_nmse_final(StreamTable st, cons
         if (inv_r) inv_r[s] = 1.f / r;
       }
     }
-  }
-  if (threadIdx.x == 0) {
-    float e = Et.value(), r = Rt.value();
+    const float e = Et.value(), r = Rt.value();
     if (rec) {
       rec[F * st.n] = e;
       rec[F * st.n + 1] = r;
