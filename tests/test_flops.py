@@ -55,3 +55,10 @@ def test_executed_gmp_counts_follow_the_coefficient_count():
     # kernel against 3 x 4836 = 14508 counted with eq. (10)
     assert 5300 < F.gmp_bwd_executed(9, 7, 4, 256) < 5500
     assert 3 * F.gmp_flops_fig3(9, 7, 4) == 14508
+    # the downlink's cyclic PA kernels (no halo): Q and y (forward) or the gather-form
+    # gradient (reverse) on every sample, plus two or three n-point transforms at 5 log2 n
+    for K, M, L in ((7, 3, 1), (9, 7, 4), (5, 3, 2)):
+        q = F.gmp_q_executed(K, M, L)
+        assert F.link_pa_executed(K, M, L, 4096) == q + F.gmp_y_executed(M) + 2 * 5 * 12
+        assert F.link_pa_bwd_executed(K, M, L, 4096) == q + F.gmp_grad_executed(K, M, L) + 3 * 5 * 12
+        assert F.link_pa_executed(K, M, L, 4096) < F.gmp_flops_fig3(K, M, L) + 2 * 5 * 12
