@@ -471,10 +471,10 @@ __device__ __forceinline__ float lane_group_sum(float v) {
 
 // Forward through all hidden layers one row block at a time.  hb[i] holds h_{i+1} in
 // operand form; returns the two linear outputs (valid in every lane group).
-// wf: forward weight operands (layer 1, then the hidden layers; global or LDS); when wh
-// is not null the hidden layers are read from the shared row-major copy there instead
-// (LDS, Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
-template <class C, int NL, bool RT = false>
+// wf: forward weight operands (layer 1, then the hidden layers; global or LDS); with WH
+// the hidden layers are read from the shared row-major copy at wh instead (LDS,
+// Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
+template <class C, int NL, bool RT = false, bool WH = false>
 __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const __bf16* wh,
                                               const typename C::A* __restrict__ wout,
                                               const float* vec, int lane, int g, const float2* xw,
@@ -510,13 +510,11 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
     if constexpr (C::X::EPL == 8) init = BiasInit<C>{vec + i * C::HP, g};
     if (i == 0) {
       dense_layer<C, C::NKS1>(PackedA<C, C::NKS1>{wf, lane}, [&](int ks) { return feat[ks]; }, epi, init);
-    } else if constexpr (C::SHARED_W) {
-      if (wh) {
-        dense_layer<C, C::NKSH>(SharedFwdA<C>{wh + (int64_t)(i - 1) * (C::WH_LAYER / 2), lane},
-                                [&](int ks) { return hb[i - 1][ks]; }, epi, init);
-        opaque_ops<C, C::NKSH>(hb[i]);
-        continue;
-      }
+    } else if constexpr (C::SHARED_W && WH) {
+      dense_layer<C, C::NKSH>(SharedFwdA<C>{wh + (int64_t)(i - 1) * (C::WH_LAYER / 2), lane},
+                              [&](int ks) { return hb[i - 1][ks]; }, epi, init);
+      opaque_ops<C, C::NKSH>(hb[i]);
+      continue;
     }
     if (i > 0) {
       const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
@@ -591,9 +589,12 @@ struct BwdLds {
   }
   static constexpr int STAGE_BYTES = SM ? 2 * S * RW * 2 : (C::HP + HROWS) * LD * 4;
   // bytes of static LDS besides the weight operands
-  static constexpr int BIAS_N = NL * C::HP + 32;  // bias-gradient accumulators
+  // bf16 layers with one delta row block per wave (BREG) keep their bias-gradient sums in
+  // registers (each wave the rows of its own block); the others accumulate them in LDS.
+  static constexpr bool BREG = SM && C::NBD == kWaves;
+  static constexpr int BIAS_N = BREG ? 0 : NL * C::HP + 32;  // LDS bias-gradient accumulators
   static constexpr int DSTO_BYTES = SM ? 2 * S * 2 : 0;   // bf16: output-layer delta, [2][S]
-  static constexpr int BASE_BYTES = XW * 8 + C::NVEC * 4 + BIAS_N * 4 + STAGE_BYTES + DSTO_BYTES;
+  static constexpr int BASE_BYTES = (SM ? 2 : 1) * XW * 8 + C::NVEC * 4 + BIAS_N * 4 + STAGE_BYTES + DSTO_BYTES;
   // Weight operands staged in LDS, the byte range [W_LO, W_HI) of the packed set: both
   // packs when they fit, else the backward (transposed) pack, whose short delta-chain
   // blocks hide global-memory latency worse than the tanh-heavy recompute blocks, else

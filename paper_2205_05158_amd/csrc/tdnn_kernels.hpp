@@ -96,9 +96,12 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   using E = typename C::E;
   using A = typename C::A;
   constexpr int S = C::S;
-  __shared__ float2 xw[B::XW];
+  // bf16: x windows of this tile and the next (buffer t % 2), stored at the end of the
+  // previous tile; fp32: one window, stored at the top of the tile
+  constexpr int NXB = B::SM ? 2 : 1;
+  __shared__ float2 xw[NXB][B::XW];
   __shared__ __attribute__((aligned(16))) float vec[C::NVEC];
-  __shared__ float bacc[B::BIAS_N];
+  __shared__ float bacc[B::BIAS_N > 0 ? B::BIAS_N : 1];
   __shared__ __attribute__((aligned(16))) char un[B::STAGE_BYTES];
   __shared__ __attribute__((aligned(16))) uint4 wlds[B::W_BYTES / 16];
   __shared__ __attribute__((aligned(16))) __bf16 dsto[B::SM ? 2 * S : 8];
@@ -127,6 +130,11 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   // output-layer dW: fp32, element (tid / HP, tid % HP); bf16, rows 0 and 1 at column
   // 32 wave + lane of the lanes lane < 32 of waves wave < HP / 32
   float dwo = 0.f, dwo1 = 0.f;
+  // BREG: bias-gradient sums of rows 32 wave + lane % 32 of each tanh layer (both lane
+  // halves hold them) and, in wave 0, of the two outputs (lanes 0 and 1)
+  float bsr[NL + 1];
+#pragma unroll
+  for (int li = 0; li <= NL; ++li) bsr[li] = 0.f;
   for (int i = tid; i < B::BIAS_N; i += kThreads) bacc[i] = 0.f;
 
   // Write this workgroup's partial dW of stream s (plain stores: each (workgroup,
@@ -163,6 +171,16 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       if (tid < 2 * C::HP) slot[C::dw_off(NL) + tid] = dwo;   // row tid / HP, column tid % HP
     }
     dwo = dwo1 = 0.f;
+    if constexpr (B::BREG) {
+      if (ln < 32) {
+#pragma unroll
+        for (int li = 0; li < NL; ++li)
+          slot[C::dw_off(li) + (int64_t)C::HP * (li == 0 ? C::C1 : C::HP) + 32 * wv + ln] = bsr[li];
+        if (wv == 0) slot[C::dw_off(NL) + 32 * C::HP + ln] = ln < 2 ? bsr[NL] : 0.f;
+      }
+#pragma unroll
+      for (int li = 0; li <= NL; ++li) bsr[li] = 0.f;
+    }
     for (int i = tid; i < B::BIAS_N; i += kThreads) {
       const int li = i / C::HP, o = i % C::HP;
       float* dstb = li < NL ? slot + C::dw_off(li) + (int64_t)C::HP * (li == 0 ? C::C1 : C::HP) + o
@@ -194,13 +212,10 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       dw_mma_bf16<C>(a0, b1, dwacc[q0 + 1]);
       dw_mma_bf16<C>(a1, b0, dwacc[q0 + 2]);
       dw_mma_bf16<C>(a1, b1, dwacc[q0 + 3]);
-      if (nb0 == 0) {
-        const float s0 = dw_rowsum_bf16(a0), s1 = dw_rowsum_bf16(a1);
-        if (h == 0) {
-          bl[32 * mb0 + r] += s0;
-          bl[32 * mb0 + 32 + r] += s1;
-        }
-      }
+      // the bias sums of the wave's own row block (mb0 + wave % 2 = wave)
+      if (wave_u % 2) bsr[li] += dw_rowsum_bf16(a1);
+      else bsr[li] += dw_rowsum_bf16(a0);
+      (void)bl; (void)h; (void)r;
       return;
     } else if constexpr (B::STRIP(nnb)) {
       // the wave's row block mb = wave against every activation column block; the next
@@ -215,8 +230,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
         DPD_KEEP_LOADS_LOCAL();
         dw_mma_bf16<C>(a, b[k & 1], dwacc[q0 + k]);
       }
-      const float sum = dw_rowsum_bf16(a);
-      if (h == 0) bl[32 * wave_u + r] += sum;
+      bsr[li] += dw_rowsum_bf16(a);
+      (void)bl; (void)h; (void)r;
       return;
     } else if constexpr (B::SM) {
       // the operands of the wave's next block are read while this block's MFMAs run
@@ -263,9 +278,10 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     }
   };
 
-  // the x window and g_u of the next tile are read one tile ahead, into registers
+  // the x window and g_u of the next tile are read one tile ahead, into registers, and the
+  // window is stored to its LDS buffer at the end of the current tile
   static_assert(B::XW <= kThreads, "one x-window element per thread");
-  float2 xpre = make_float2(0.f, 0.f), gpre = make_float2(0.f, 0.f);
+  float2 xpre = make_float2(0.f, 0.f), gpre = make_float2(0.f, 0.f), gcur = gpre;
   auto prefetch = [&](int tt) {
     const int s2 = stream_of_tile(st, tt);
     const int64_t lo2 = st.off[s2], hi2 = st.off[s2 + 1];
@@ -275,7 +291,13 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const int64_t n2 = t02 + C::MT * wave_u + (tid % 64) % C::MT;
     gpre = n2 < hi2 ? ld2(gu, n2) : make_float2(0.f, 0.f);
   };
-  if (t_begin < t_end) prefetch(t_begin);
+  if (t_begin < t_end) {
+    prefetch(t_begin);
+    if constexpr (NXB == 2) {
+      if (tid < B::XW) xw[t_begin % 2][tid] = xpre;
+      gcur = gpre;
+    }
+  }
 
   int cur_stream = -1;
   for (int t = t_begin; t < t_end; ++t) {
@@ -288,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const int g = lane / C::MT, sl = lane % C::MT;
     const int col = C::MT * wave_u + sl;
 
-    __syncthreads();   // previous tile finished with every LDS buffer and accumulator
+    __syncthreads();   // previous tile finished with every LDS buffer; this tile's x window stored
     if (s != cur_stream) {
       if (cur_stream >= 0) flush(cur_stream);
       // a new stream may bring a new parameter set: stage its vector block and weights
@@ -305,11 +327,16 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
         for (int i = tid; i < (int)(B::W_BYTES / 16); i += kThreads) wlds[i] = wsrc[i];
       }
       cur_stream = s;
+      if constexpr (NXB == 2) __syncthreads();
     }
-    if (tid < B::XW) xw[tid] = xpre;
-    const float2 gsum = gpre;          // g_u of this lane's sample (zero past the stream)
+    if constexpr (NXB == 1) {
+      if (tid < B::XW) xw[0][tid] = xpre;
+      gcur = gpre;
+    }
+    const float2 gsum = gcur;          // g_u of this lane's sample (zero past the stream)
     if (t + 1 < t_end) prefetch(t + 1);
-    __syncthreads();
+    if constexpr (NXB == 1) __syncthreads();
+    const float2* xwt = xw[t % NXB];
 
     // ---- TDNN: recompute this wave's samples, then the reverse mode
     const A* wfwd = (B::SHW || B::W_FWD) ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
@@ -318,8 +345,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const __bf16* wsh = B::SHW ? reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(wlds) + C::OFF_FWDH)
                                : nullptr;
     Ops<C, C::NKSH> hb[NL];
-    (void)mlp_forward<C, NL, RT>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
-                                 &xw[col + B::XB], hb, tn);
+    (void)mlp_forward<C, NL, RT, B::SHW>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
+                                 &xwt[col + B::XB], hb, tn);
     int lb[2];
     B::lane_bases(g, col, lb);
     // output layer: delta_o = (Re g_u, Im g_u) (bf16: its own [2][S] array; fp32: staging
@@ -361,7 +388,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
         }
         if (wave_u == 0) {        // output-layer bias: rows 0 and 1 summed over the samples
           const float sum = dw_rowsum_bf16(aop);
-          if (h == 0 && r < 2) bacc[NL * C::HP + r] += sum;
+          if constexpr (B::BREG) bsr[NL] += sum;
+          else if (h == 0 && r < 2) bacc[NL * C::HP + r] += sum;
         }
       }
     } else if (tid < 2 * C::HP) {
@@ -402,7 +430,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       } else {
         // features at their natural rows: lane group g holds rows [g*FPG, g*FPG + FPG)
         Ops<C, C::NKS1> feat;
-        make_features<C, RT>(&xw[col + B::XB], g, feat, tn);
+        make_features<C, RT>(&xwt[col + B::XB], g, feat, tn);
         if constexpr (B::SM && C::FPG % 4 == 0) {
           // 4 consecutive features per 8-byte write; chunks of the padding rows zeroed by
           // lane group 0
@@ -462,6 +490,10 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     if constexpr (NL >= 3) layer(std::integral_constant<int, 3>{});
     if constexpr (NL >= 2) layer(std::integral_constant<int, 2>{});
     layer(std::integral_constant<int, 1>{});
+    if (NXB == 2 && t + 1 < t_end) {   // the next tile's x window (its buffer was last read by tile t - 1)
+      if (tid < B::XW) xw[(t + 1) % NXB][tid] = xpre;
+      gcur = gpre;
+    }
   }
   __syncthreads();
   if (cur_stream >= 0) flush(cur_stream);
