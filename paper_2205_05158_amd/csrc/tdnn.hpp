@@ -110,20 +110,24 @@ struct Cfg {
   // float vector block: bias [NL][NB][LG][NR], wo [2][NB][LG][NR], bo[2] (+2 pad)
   static constexpr int NVEC = NL * HP + 2 * HP + 4;
   // bf16 models also carry a row-major copy of the hidden weights W_i (i = 2..NL), shared
-  // in LDS by the backward kernel's forward recompute (two 8-byte reads per operand) and
-  // its delta chain (two transposing 8-byte reads per operand): element (o, k) of a layer
-  // at o*HP + 4*((k/4) ^ swz(o)) + k%4.  gfx950 serves 8-byte LDS reads 32 lanes at a
-  // time from 64 banks.  With 128-wide rows (one 256-byte sweep of the banks per row) the
-  // swizzle 4 (o mod 8) + 2 ((o / 8) mod 2) puts the 32 lanes of both read patterns on 32
-  // distinct 8-byte chunk positions: the forward read's 16 rows x 2 lane groups (the
-  // swizzle's bits 1-4 separate the rows, the lane group is bit 0) and the transposing
-  // read's 8 rows x 4 chunks (bits 2-4 separate the rows).  Narrower rows swap the two
-  // 2-bit fields of o mod 16, which separates 16-lane groups.
+  // in LDS by the backward kernel's forward recompute and its delta chain (two
+  // transposing 8-byte reads per operand); chunk c of row o (its elements 4c .. 4c+3) sits
+  // at chunk position cpos(c, o).  With 128-wide rows (one 256-byte sweep of the 64 banks
+  // per row) each 32-element group stores its chunks in the order 0 4 1 5 2 6 3 7, so the
+  // forward operand of lane group g (chunks g and g + 4 of a K step) is one aligned
+  // 16-byte read, and the pair index is swizzled by 4 (o mod 4) + (o / 4) mod 4: the 16
+  // rows of a 16-lane forward read hit 16 distinct 16-byte bank groups, and the
+  // transposing read's 8 rows x 4 chunks per 32 lanes (all on the same half of their
+  // pairs) are two-way at worst.  Narrower rows keep the chunks in order and swap the two
+  // 2-bit fields of o mod 16 (two 8-byte reads per forward operand).
   static constexpr bool SHARED_W = X::EPL == 8;
   static constexpr int NCH = HP / 4;                    // 8-byte chunks per row
+  static constexpr bool PAIRED = NCH == 32;
   __host__ __device__ static constexpr int swz(int o) {
-    return NCH == 32 ? 4 * (o & 7) + 2 * ((o >> 3) & 1)
-                     : (((o & 3) << 2) | ((o >> 2) & 3)) & (NCH - 1);
+    return PAIRED ? 8 * (o & 3) + 2 * ((o >> 2) & 3) : (((o & 3) << 2) | ((o >> 2) & 3)) & (NCH - 1);
+  }
+  __host__ __device__ static constexpr int cpos(int c, int o) {
+    return (PAIRED ? 8 * (c / 8) + 2 * (c % 4) + (c % 8) / 4 : c) ^ swz(o);
   }
   static constexpr int64_t OFF_WH = OFF_VEC + (int64_t)NVEC * 4;
   static constexpr int64_t WH_LAYER = (int64_t)HP * HP * 2;
@@ -196,7 +200,7 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
         const float* Wi = ws + so.w[i - 1];
         const float val = (o < hn && kk < hn) ? Wi[(int64_t)o * hn + kk] * C::WS : 0.f;
         __bf16* dstw = reinterpret_cast<__bf16*>(ps + C::OFF_WH + (int64_t)(i - 2) * C::WH_LAYER);
-        dstw[o * C::HP + 4 * ((kk / 4) ^ C::swz(o)) + kk % 4] = (__bf16)val;
+        dstw[o * C::HP + 4 * C::cpos(kk / 4, o) + kk % 4] = (__bf16)val;
       }
     } else if (idx < n1 + 2 * nh) {
       const int lane = (int)(idx % 64);
@@ -363,7 +367,8 @@ struct PackedA {
 };
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // Row-major swizzled hidden weights (Cfg::OFF_WH) in LDS, forward operand: row o = 16 mb +
-// lane%16 of W_i, K elements 32 ks + 4 g + (0..3) and 32 ks + 16 + 4 g + (0..3).
+// lane%16 of W_i, K elements 32 ks + 4 g + (0..3) and 32 ks + 16 + 4 g + (0..3) (chunks
+// 8 ks + g and 8 ks + 4 + g: adjacent in 128-wide rows).
 template <class C>
 struct SharedFwdA {
   const __bf16* w;     // LDS copy of one layer
@@ -371,9 +376,13 @@ struct SharedFwdA {
   __device__ bf16x8 operator()(int mb, int ks) const {
     const int o = 16 * mb + lane % 16, g = lane / 16;
     const __bf16* row = w + o * C::HP;
-    const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row + 4 * ((8 * ks + g) ^ C::swz(o)));
-    const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 4 * ((8 * ks + 4 + g) ^ C::swz(o)));
-    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    if constexpr (C::PAIRED) {
+      return *reinterpret_cast<const bf16x8*>(row + 4 * C::cpos(8 * ks + g, o));
+    } else {
+      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row + 4 * C::cpos(8 * ks + g, o));
+      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 4 * C::cpos(8 * ks + 4 + g, o));
+      return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    }
   }
 };
 // The same copy read as the transposed (delta-chain) operand: row = input neuron
@@ -391,7 +400,7 @@ struct SharedBwdA {
     // o1 = 32 ks + 4 g + l / 4 and o2 = o1 + 16: the K step's rows are then constant
     // offsets from one lane address per row block (immediate offsets of the reads).
     const int ol = 4 * g + l / 4;
-    const __bf16* p = w + ol * C::HP + 4 * ((4 * mb + l % 4) ^ C::swz(ol));
+    const __bf16* p = w + ol * C::HP + 4 * C::cpos(4 * mb + l % 4, ol);
     typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
     const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(p + 32 * ks * C::HP));
     const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(p + (32 * ks + 16) * C::HP));
