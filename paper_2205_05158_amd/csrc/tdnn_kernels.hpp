@@ -282,10 +282,21 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
   // window is stored to its LDS buffer at the end of the current tile
   static_assert(B::XW <= kThreads, "one x-window element per thread");
   float2 xpre = make_float2(0.f, 0.f), gpre = make_float2(0.f, 0.f), gcur = gpre;
+  // stream of the last prefetched tile and its bounds, advanced only when a tile of a
+  // later stream is prefetched (no per-tile lookups in the stream table)
+  int ps = t_begin < t_end ? stream_of_tile(st, t_begin) : 0;
+  int64_t p_lo = st.off[ps], p_hi = st.off[ps + 1];
+  int p_t0 = st.tile0[ps], p_t1 = st.tile0[ps + 1];
   auto prefetch = [&](int tt) {
-    const int s2 = stream_of_tile(st, tt);
-    const int64_t lo2 = st.off[s2], hi2 = st.off[s2 + 1];
-    const int64_t t02 = lo2 + (int64_t)(tt - st.tile0[s2]) * S;
+    if (tt >= p_t1) {                  // tile0[n] = n_tiles > tt ends the scan
+      do { ++ps; } while (tt >= st.tile0[ps + 1]);
+      p_lo = st.off[ps];
+      p_hi = st.off[ps + 1];
+      p_t0 = st.tile0[ps];
+      p_t1 = st.tile0[ps + 1];
+    }
+    const int64_t lo2 = p_lo, hi2 = p_hi;
+    const int64_t t02 = lo2 + (int64_t)(tt - p_t0) * S;
     const int64_t p = t02 - B::XB + tid;
     xpre = (tid < B::XW && p >= lo2 && p < hi2) ? ld2(x, p) : make_float2(0.f, 0.f);
     const int64_t n2 = t02 + C::MT * wave_u + (tid % 64) % C::MT;
@@ -301,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
 
   int cur_stream = -1;
   for (int t = t_begin; t < t_end; ++t) {
-    const int s = stream_of_tile(st, t);
+    const int s = ps;                  // tile t was the last one prefetched
     const int set = st.per_stream ? s : 0;
     const char* pk = pack + set * C::PACK;
     int tq = tid;
