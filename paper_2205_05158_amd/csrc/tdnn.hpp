@@ -483,14 +483,19 @@ __device__ __forceinline__ float lane_group_sum(float v) {
 // wf: forward weight operands (layer 1, then the hidden layers; global or LDS); with WH
 // the hidden layers are read from the shared row-major copy at wh instead (LDS,
 // Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
+// feat_out (optional) receives the layer-1 features in operand form.
 template <class C, int NL, bool RT = false, bool WH = false>
 __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const __bf16* wh,
                                               const typename C::A* __restrict__ wout,
                                               const float* vec, int lane, int g, const float2* xw,
-                                              Ops<C, C::NKSH> (&hb)[NL], int tn = 0) {
+                                              Ops<C, C::NKSH> (&hb)[NL], int tn = 0,
+                                              Ops<C, C::NKS1>* feat_out = nullptr) {
   using A = typename C::A;
   Ops<C, C::NKS1> feat;
   make_features<C, RT>(xw, g, feat, tn);
+  if (feat_out)
+#pragma unroll
+    for (int ks = 0; ks < C::NKS1; ++ks) (*feat_out)[ks] = feat[ks];
   const float* wo = vec + NL * C::HP;
   float o0 = 0.f, o1 = 0.f;
 #pragma unroll

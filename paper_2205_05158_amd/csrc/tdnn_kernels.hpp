@@ -356,8 +356,9 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const __bf16* wsh = B::SHW ? reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(wlds) + C::OFF_FWDH)
                                : nullptr;
     Ops<C, C::NKSH> hb[NL];
+    Ops<C, C::NKS1> feat1;             // bf16: layer-1 features, kept for the layer-1 dW staging
     (void)mlp_forward<C, NL, RT, B::SHW>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
-                                 &xwt[col + B::XB], hb, tn);
+                                 &xwt[col + B::XB], hb, tn, B::SM ? &feat1 : nullptr);
     int lb[2];
     B::lane_bases(g, col, lb);
     // output layer: delta_o = (Re g_u, Im g_u) (bf16: its own [2][S] array; fp32: staging
@@ -441,7 +442,12 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       } else {
         // features at their natural rows: lane group g holds rows [g*FPG, g*FPG + FPG)
         Ops<C, C::NKS1> feat;
-        make_features<C, RT>(&xwt[col + B::XB], g, feat, tn);
+        if constexpr (B::SM) {
+#pragma unroll
+          for (int ks = 0; ks < C::NKS1; ++ks) feat[ks] = feat1[ks];
+        } else {
+          make_features<C, RT>(&xwt[col + B::XB], g, feat, tn);
+        }
         if constexpr (B::SM && C::FPG % 4 == 0) {
           // 4 consecutive features per 8-byte write; chunks of the padding rows zeroed by
           // lane group 0
