@@ -519,18 +519,24 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
 // ------------------------------------------------------------------ dW finalize
 // dw[set][packed j] = inv_r[set] * sum over (stream s of set, workgroup g touching s)
 // of slot[g + s] at the natural position of j (model of tn taps and width hn).  Fixed
-// order: s ascending, g ascending.
+// order: the (s ascending, g ascending) list of slots is cut into kFinChunks consecutive
+// chunks; each thread of a column sums one chunk in list order, and the chunk sums are
+// added in chunk order.  A workgroup covers kFinCols packed indices.
+constexpr int kFinCols = 32, kFinChunks = 8;
 template <int PREC, int T, int H, int NL>
-__global__ void k_dw_finalize(StreamTable st, int G_wg, const float* __restrict__ slots,
-                              const float* __restrict__ inv_r, int64_t P, int tn, int hn,
-                              float* __restrict__ dw) {
+__global__ __launch_bounds__(kFinCols * kFinChunks) void k_dw_finalize(StreamTable st, int G_wg,
+                                                                     const float* __restrict__ slots,
+                                                                     const float* __restrict__ inv_r,
+                                                                     int64_t P, int tn, int hn,
+                                                                     float* __restrict__ dw) {
   using C = Cfg<PREC, T, H, NL>;
+  __shared__ float part[kFinChunks][kFinCols];
   const int set = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= P) return;
+  const int e = threadIdx.x % kFinCols, c = threadIdx.x / kFinCols;
+  const int64_t j = (int64_t)blockIdx.x * kFinCols + e;
   int64_t nat = -1;
   float lscale = 1.f;   // 1 / WS^(NL - 1 - li): the delta-chain scale of layer li
-  {
+  if (j < P) {
     int64_t pos = 0;
     int din = 5 * tn;
     for (int li = 0; li <= NL && nat < 0; ++li) {
@@ -552,14 +558,34 @@ __global__ void k_dw_finalize(StreamTable st, int G_wg, const float* __restrict_
       din = hn;
     }
   }
-  float acc = 0.f;
+  // this thread's chunk [lo, hi) of the set's slot list
+  int64_t total = 0;
   for (int s = 0; s < st.n; ++s) {
     if ((st.per_stream ? s : 0) != set) continue;
-    const int g0 = wg_of_tile(st.tile0[s], G_wg, st.n_tiles);
-    const int g1 = wg_of_tile(st.tile0[s + 1] - 1, G_wg, st.n_tiles);
-    for (int g = g0; g <= g1; ++g) acc += slots[(int64_t)(g + s) * C::SLOT + nat];
+    total += wg_of_tile(st.tile0[s + 1] - 1, G_wg, st.n_tiles) - wg_of_tile(st.tile0[s], G_wg, st.n_tiles) + 1;
   }
-  dw[set * P + j] = acc * (inv_r[set] * lscale);
+  const int64_t lo = total * c / kFinChunks, hi = total * (c + 1) / kFinChunks;
+  float acc = 0.f;
+  if (nat >= 0) {
+    int64_t idx = 0;
+    for (int s = 0; s < st.n && idx < hi; ++s) {
+      if ((st.per_stream ? s : 0) != set) continue;
+      const int g0 = wg_of_tile(st.tile0[s], G_wg, st.n_tiles);
+      const int g1 = wg_of_tile(st.tile0[s + 1] - 1, G_wg, st.n_tiles);
+      const int64_t n = g1 - g0 + 1;
+      const int64_t a = lo > idx ? lo : idx, b = hi < idx + n ? hi : idx + n;
+      for (int64_t q = a; q < b; ++q) acc += slots[(int64_t)(g0 + (q - idx) + s) * C::SLOT + nat];
+      idx += n;
+    }
+  }
+  part[c][e] = acc;
+  __syncthreads();
+  if (c == 0 && j < P) {
+    float t = part[0][e];
+#pragma unroll
+    for (int c2 = 1; c2 < kFinChunks; ++c2) t += part[c2][e];
+    dw[set * P + j] = t * (inv_r[set] * lscale);
+  }
 }
 
 SrcOff src_offsets(int T, int H, int NL) {
@@ -626,8 +652,9 @@ struct TdnnShape {
     const int64_t P = (int64_t)td.hidden * (5 * td.taps) + td.hidden +
                       (int64_t)(NL - 1) * ((int64_t)td.hidden * td.hidden + td.hidden) + 2 * (int64_t)td.hidden + 2;
     const int n_sets = st.per_stream ? st.n : 1;
-    dim3 g2((unsigned)((P + 255) / 256), n_sets);
-    k_dw_finalize<PREC, T, H, NL><<<g2, 256, 0, s>>>(st, grid, slots, inv_r_set, P, td.taps, td.hidden, dw);
+    dim3 g2((unsigned)((P + kFinCols - 1) / kFinCols), n_sets);
+    k_dw_finalize<PREC, T, H, NL><<<g2, kFinCols * kFinChunks, 0, s>>>(st, grid, slots, inv_r_set, P, td.taps,
+                                                                     td.hidden, dw);
   }
 
   static constexpr TdnnKernels table{&dims, &pack, &fwd, &bwd, &finalize};
