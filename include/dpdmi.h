@@ -109,7 +109,10 @@ int64_t dpd_gmp_coeff_count(const dpd_gmp_desc* gmp);
 
 /* Bytes of device workspace every call below needs for this problem (an upper
  * bound over the launch shapes the library may choose).  The same workspace may
- * be reused by consecutive calls on one stream; concurrent calls need their own. */
+ * be reused by consecutive calls on one stream; concurrent calls need their own.
+ * Tuned BF16 models include the forward's stored hidden activations, which the
+ * reverse mode reads instead of recomputing them: n_hidden x padded width x 2 bytes
+ * per sample (1 KB per sample for 4 layers of 128; 17 GB for 2^24 samples). */
 dpd_status dpd_workspace_size(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                               const dpd_batch* batch, size_t* bytes_host);
 

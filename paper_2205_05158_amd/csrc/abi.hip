@@ -199,7 +199,7 @@ int bwd_grid(const dpd_tune& t, const StreamTable& tab) {
 // ------------------------------------------------------------ workspace layout
 struct Ws {
   size_t tile_part = 0, inv_r = 0, loss_tmp = 0, u_buf = 0, y_buf = 0, gu_buf = 0, gmp_tab = 0;
-  size_t act = 0, part = 0, acc = 0, pack = 0, slots = 0, total = 0;
+  size_t act = 0, part = 0, acc = 0, pack = 0, slots = 0, hact = 0, total = 0;
   int64_t act_floats_per_sample = 0;
 };
 
@@ -233,6 +233,9 @@ Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
     w.slots = take(sizeof(float) * (size_t)td.dw_slot * (kMaxGrid + p.S));
     w.gu_buf = take(sizeof(float2) * p.n_total);
     if (g) w.gmp_tab = take(sizeof(float2) * 2 * (size_t)coeff_count(*g) * p.n_sets);
+    // bf16: the forward's hidden activations for the reverse mode, 4 groups of 16 samples
+    // per 64-sample reverse-mode tile
+    if (td.act_group > 0) w.hact = take((size_t)td.act_group * 4 * (size_t)make_table(p, td.tile).n_tiles);
   }
   w.total = pos;
   return w;
@@ -446,7 +449,7 @@ dpd_status dpd_forward(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, const 
     { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
     const dpd_tune tn = lookup_tune(*tdnn, nullptr, p, td);
     StreamTable tab = make_table(p, td.fwd_mt * tn.fwd_waves);
-    { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, fwd_grid(tn, tab), tn.fwd_waves, stream); }
+    { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, tab, x, pack, u, fwd_grid(tn, tab), tn.fwd_waves, nullptr, stream); }
   }
   return launch_status();
 }
@@ -599,8 +602,10 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
   { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, P, pack, stream); }
   const dpd_tune tn = lookup_tune(*tdnn, gmp, p, td);
   StreamTable ftab = make_table(p, td.fwd_mt * tn.fwd_waves);
-  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fwd_grid(tn, ftab), tn.fwd_waves, stream); }
   StreamTable tab = make_table(p, td.tile);
+  set_act_groups(ftab, tab);
+  void* hact = at<void>(workspace, L.hact);
+  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fwd_grid(tn, ftab), tn.fwd_waves, dw ? hact : nullptr, stream); }
   if (dw) {
     // GMP forward + reverse mode (y, E/R tile partials, g_u), then the TDNN reverse mode
     StreamTable gt = make_table(p, tn.gmp_tile);
@@ -609,7 +614,7 @@ dpd_status dpd_cascade(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, const
     { DPD_PROF("gmp_bwd"); launch_gmp_bwd(*gmp, gt, x, ubuf, coef, gtab, g_re, g_im, part, gub, y, stream); }
     const int grid = bwd_grid(tn, tab);
     float* slots = at<float>(workspace, L.slots);
-    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, stream); }
+    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, hact, stream); }
     { DPD_PROF("nmse_final"); launch_nmse_final(gt, part, nmse, lossp, inv_r, stream); }
     { DPD_PROF("dw_finalize"); launch_dw_finalize(td, tab, grid, slots, inv_r, dw, stream); }
   } else {
@@ -680,14 +685,16 @@ dpd_status dpd_cascade_clip(const dpd_tdnn_desc* tdnn, const dpd_batch* batch, c
   { DPD_PROF("pack"); launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream); }
   const dpd_tune tn = lookup_tune(*tdnn, nullptr, p, td);
   StreamTable ftab = make_table(p, td.fwd_mt * tn.fwd_waves);
-  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fwd_grid(tn, ftab), tn.fwd_waves, stream); }
+  set_act_groups(ftab, make_table(p, td.tile));
+  void* hact = at<void>(workspace, L.hact);
+  { DPD_PROF("tdnn_fwd"); launch_tdnn_fwd(td, ftab, x, pack, ubuf, fwd_grid(tn, ftab), tn.fwd_waves, dw ? hact : nullptr, stream); }
   { DPD_PROF("clip_tiles"); launch_clip_tiles(ct, x, ubuf, a_clip, g_re, g_im, part, gub, y, stream); }
   { DPD_PROF("nmse_final"); launch_nmse_final(ct, part, nmse, lossp, inv_r, stream); }
   if (dw) {
     StreamTable tab = make_table(p, td.tile);
     const int grid = bwd_grid(tn, tab);
     float* slots = at<float>(workspace, L.slots);
-    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, stream); }
+    { DPD_PROF("tdnn_bwd"); launch_tdnn_bwd(td, tab, x, gub, pack, slots, grid, hact, stream); }
     { DPD_PROF("dw_finalize"); launch_dw_finalize(td, tab, grid, slots, inv_r, dw, stream); }
   }
   return launch_status();
@@ -748,6 +755,7 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
   float* slots = at<float>(workspace, L.slots);
   const dpd_tune def = default_tune(td);
   const StreamTable btab = make_table(p, td.tile);
+  void* hact = at<void>(workspace, L.hact);
 
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
@@ -774,7 +782,8 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
   launch_pack(td, w, p.n_sets, param_count(*tdnn), pack, stream);
   {
     StreamTable ft = make_table(p, td.fwd_mt * def.fwd_waves);
-    launch_tdnn_fwd(td, ft, x, pack, ubuf, fwd_grid(def, ft), def.fwd_waves, stream);
+    set_act_groups(ft, btab);
+    launch_tdnn_fwd(td, ft, x, pack, ubuf, fwd_grid(def, ft), def.fwd_waves, hact, stream);
     StreamTable gt = make_table(p, def.gmp_tile);
     launch_gmp_bwd(*gmp, gt, x, ubuf, coef, gtab, g_re, g_im, part, gub, nullptr, stream);
   }
@@ -786,8 +795,9 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
       c.fwd_waves = wv;
       c.fwd_wg_per_cu = pc;
       StreamTable ft = make_table(p, td.fwd_mt * wv);
+      set_act_groups(ft, btab);
       if (pc > 1 && (pc - 1) * device_cus() >= ft.n_tiles) continue;   // same grid as pc - 1
-      const float ms = time_ms([&] { launch_tdnn_fwd(td, ft, x, pack, ubuf, fwd_grid(c, ft), wv, stream); });
+      const float ms = time_ms([&] { launch_tdnn_fwd(td, ft, x, pack, ubuf, fwd_grid(c, ft), wv, hact, stream); });
       if (ms < best_ms) { best_ms = ms; best.fwd_waves = wv; best.fwd_wg_per_cu = pc; }
     }
   best_ms = 1e30f;
@@ -803,7 +813,7 @@ dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp, cons
     dpd_tune c = def;
     c.bwd_wg_per_cu = pc;
     if (pc > 1 && (pc - 1) * device_cus() >= btab.n_tiles) continue;
-    const float ms = time_ms([&] { launch_tdnn_bwd(td, btab, x, gub, pack, slots, bwd_grid(c, btab), stream); });
+    const float ms = time_ms([&] { launch_tdnn_bwd(td, btab, x, gub, pack, slots, bwd_grid(c, btab), hact, stream); });
     if (ms < best_ms) { best_ms = ms; best.bwd_wg_per_cu = pc; }
   }
   (void)hipEventDestroy(ev[0]);

@@ -25,6 +25,9 @@ __host__ __device__ constexpr int64_t ceil_div64(int64_t a, int64_t b) { return 
 struct StreamTable {
   int64_t off[DPD_MAX_STREAMS + 1];
   int32_t tile0[DPD_MAX_STREAMS + 1];
+  // bf16 TDNN forward feeding the reverse mode: first stored-activation group (16 samples)
+  // of each stream, 4 groups per 64-sample reverse-mode tile
+  int32_t grp0[DPD_MAX_STREAMS + 1];
   int32_t n;            // number of streams
   int32_t per_stream;   // parameter set = stream index when 1, else 0
   int32_t tile;         // samples per tile

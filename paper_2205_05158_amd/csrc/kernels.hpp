@@ -118,9 +118,9 @@ struct TdnnKernels {
   void (*dims)(TdnnDims* td);
   void (*pack)(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack, hipStream_t s);
   void (*fwd)(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack, float* u, int grid,
-              int waves, hipStream_t s);
+              int waves, void* act, hipStream_t s);
   void (*bwd)(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu, const void* pack,
-              float* slots, int grid, hipStream_t s);
+              float* slots, int grid, const void* act, hipStream_t s);
   void (*finalize)(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
                    const float* inv_r_set, float* dw, hipStream_t s);
 };
@@ -140,6 +140,7 @@ struct TdnnDims {
   int64_t pack_bytes;  // bytes of one packed parameter set
   int64_t fwd_lds;     // LDS bytes of the forward kernel at the default tile
   int64_t dw_slot;     // floats per dW slot (natural layout, padded rows and columns)
+  int64_t act_group;   // bf16: bytes of the stored activations of one 16-sample group (0: fp32)
 };
 bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out);
 bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g);
@@ -147,8 +148,13 @@ bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g);
 void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack,
                  hipStream_t s);
 // TDNN forward over the table's tiles (st.tile = td.fwd_mt * waves; waves 8, 12 or 16).
+// act (bf16, optional): the hidden activations are also stored per 16-sample group at
+// st.grp0 (set_act_groups) for the reverse mode.
 void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
-                     float* u, int grid, int waves, hipStream_t s);
+                     float* u, int grid, int waves, void* act, hipStream_t s);
+// Group bases of the stored activations of a forward table ft: 4 groups per 64-sample
+// tile of the reverse-mode table bt of the same batch.
+void set_act_groups(StreamTable& ft, const StreamTable& bt);
 // GMP forward over the table's tiles.
 void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,
                     float* y, hipStream_t s);
@@ -160,8 +166,9 @@ void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x
                     const float* coef, float2* tab, float g_re, float g_im, float4* tile_part,
                     float* gu, float* y, hipStream_t s);
 // TDNN recompute + reverse mode from g_u: dW partial slots per (workgroup, stream).
+// act (bf16: required): the forward's stored activations of the same batch.
 void launch_tdnn_bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu,
-                     const void* pack, float* slots, int grid, hipStream_t s);
+                     const void* pack, float* slots, int grid, const void* act, hipStream_t s);
 void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
                         const float* inv_r_set, float* dw, hipStream_t s);
 

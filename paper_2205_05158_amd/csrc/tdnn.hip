@@ -87,13 +87,17 @@ void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_strid
 }
 
 void launch_tdnn_fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pack,
-                     float* u, int grid, int waves, hipStream_t s) {
-  td.k->fwd(td, st, x, pack, u, grid, waves, s);
+                     float* u, int grid, int waves, void* act, hipStream_t s) {
+  td.k->fwd(td, st, x, pack, u, grid, waves, td.act_group > 0 ? act : nullptr, s);
+}
+
+void set_act_groups(StreamTable& ft, const StreamTable& bt) {
+  for (int s = 0; s <= bt.n; ++s) ft.grp0[s] = 4 * bt.tile0[s];
 }
 
 void launch_tdnn_bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu,
-                     const void* pack, float* slots, int grid, hipStream_t s) {
-  td.k->bwd(td, st, x, gu, pack, slots, grid, s);
+                     const void* pack, float* slots, int grid, const void* act, hipStream_t s) {
+  td.k->bwd(td, st, x, gu, pack, slots, grid, act, s);
 }
 
 void launch_dw_finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,

@@ -483,19 +483,18 @@ __device__ __forceinline__ float lane_group_sum(float v) {
 // wf: forward weight operands (layer 1, then the hidden layers; global or LDS); with WH
 // the hidden layers are read from the shared row-major copy at wh instead (LDS,
 // Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
-// feat_out (optional) receives the layer-1 features in operand form.
-template <class C, int NL, bool RT = false, bool WH = false>
+// sink(i, hb[i]) receives each hidden layer's activations as soon as they are formed.
+struct NoSink {
+  template <class O> __device__ void operator()(int, const O&) const {}
+};
+template <class C, int NL, bool RT = false, bool WH = false, class SINK = NoSink>
 __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const __bf16* wh,
                                               const typename C::A* __restrict__ wout,
                                               const float* vec, int lane, int g, const float2* xw,
-                                              Ops<C, C::NKSH> (&hb)[NL], int tn = 0,
-                                              Ops<C, C::NKS1>* feat_out = nullptr) {
+                                              Ops<C, C::NKSH> (&hb)[NL], int tn = 0, SINK&& sink = SINK{}) {
   using A = typename C::A;
   Ops<C, C::NKS1> feat;
   make_features<C, RT>(xw, g, feat, tn);
-  if (feat_out)
-#pragma unroll
-    for (int ks = 0; ks < C::NKS1; ++ks) (*feat_out)[ks] = feat[ks];
   const float* wo = vec + NL * C::HP;
   float o0 = 0.f, o1 = 0.f;
 #pragma unroll
@@ -528,6 +527,7 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
       dense_layer<C, C::NKSH>(SharedFwdA<C>{wh + (int64_t)(i - 1) * (C::WH_LAYER / 2), lane},
                               [&](int ks) { return hb[i - 1][ks]; }, epi, init);
       opaque_ops<C, C::NKSH>(hb[i]);
+      sink(i, hb[i]);
       continue;
     }
     if (i > 0) {
@@ -536,6 +536,7 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
                               init);
     }
     opaque_ops<C, C::NKSH>(hb[i]);
+    sink(i, hb[i]);
   }
   const float* bo = vec + NL * C::HP + 2 * C::HP;
   if constexpr (C::X::EPL == 8) {

@@ -8,6 +8,8 @@
 
 namespace dpdmi {
 
+typedef unsigned act_u32x4 __attribute__((ext_vector_type(4)));   // one stored operand register
+
 // Generic instantiations (tdnn_gen.hip, one unit per precision and padded width): the
 // shape compiled for tp taps (8, 16 or 32) and nl hidden layers (1..4).
 const TdnnKernels* tdnn_gen_bf16_32(int tp, int nl);
@@ -27,7 +29,8 @@ namespace {
 template <int PREC, int T, int H, int NL, int FW, bool RT>
 __global__ __launch_bounds__(64 * FW) void k_tdnn_fwd(StreamTable st, const float* __restrict__ x,
                                                           const char* __restrict__ pack, int residual,
-                                                          int tn, float* __restrict__ u) {
+                                                          int tn, float* __restrict__ u,
+                                                          act_u32x4* __restrict__ act) {
   using C = Cfg<PREC, T, H, NL>;
   using A = typename C::A;
   constexpr int kFwdThreads = 64 * FW;
@@ -67,8 +70,26 @@ __global__ __launch_bounds__(64 * FW) void k_tdnn_fwd(StreamTable st, const floa
     Ops<C, C::NKSH> hb[NL];
     const int col = C::MT * wave + sl;
     const A* wops = kLdsWeights ? reinterpret_cast<const A*>(wf) : reinterpret_cast<const A*>(pk);
+    // bf16 with a reverse mode to follow: each layer's activations of the wave (operand
+    // form, one 16-byte store per lane and operand) go to the stream's 16-sample group, for
+    // every group of the stream's reverse-mode tiles (those past the stream hold the zero
+    // input's)
+    static_assert(C::X::EPL != 8 || C::MT == 16, "16-sample activation groups");
+    const int64_t grp = (int64_t)(t - st.tile0[s]) * FW + wave;
+    act_u32x4* dsta = (C::X::EPL == 8 && act && grp < st.grp0[s + 1] - st.grp0[s])
+                          ? act + (st.grp0[s] + grp) * (NL * C::NKSH * 64) + lane
+                          : nullptr;
+    auto sink = [&](int i, const Ops<C, C::NKSH>& h) {
+      if constexpr (C::X::EPL == 8) {
+        if (dsta) {
+#pragma unroll
+          for (int ks = 0; ks < C::NKSH; ++ks)
+            __builtin_nontemporal_store(__builtin_bit_cast(act_u32x4, h[ks]), dsta + (i * C::NKSH + ks) * 64);
+        }
+      }
+    };
     float2 o = mlp_forward<C, NL, RT>(wops, nullptr, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane,
-                                      g, &xw[col + T - 1], hb, tn);
+                                      g, &xw[col + T - 1], hb, tn, sink);
     const int64_t n = t0 + col;
     if (g == 0 && n < hi) {
       if (residual) {
@@ -89,7 +110,8 @@ template <int PREC, int T, int H, int NL, bool RT>
 __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const float* __restrict__ x,
                                                        const float* __restrict__ gu,
                                                        const char* __restrict__ pack, int tn,
-                                                       float* __restrict__ slots) {
+                                                       float* __restrict__ slots,
+                                                       const act_u32x4* __restrict__ act) {
   using C = Cfg<PREC, T, H, NL>;
   using X = typename C::X;
   using B = BwdLds<PREC, T, H, NL>;
@@ -310,6 +332,24 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     }
   }
 
+  // bf16: the hidden activations come from the forward's store (group 4 t + wave of tile
+  // t) instead of a recompute; h_NL of the next tile is read as soon as its registers free
+  // up, the other layers at the top of the tile (they are needed a phase later)
+  constexpr bool kAct = B::SM;
+  Ops<C, C::NKSH> hb[NL];
+  auto load_hb = [&](int tt, int i) {
+    if constexpr (kAct) {
+      int ln = tid;
+      asm volatile("" : "+v"(ln));
+      const act_u32x4* srca = act + ((int64_t)tt * kWaves + wave_u) * (NL * C::NKSH * 64) + ln % 64 +
+                              (int64_t)i * C::NKSH * 64;
+#pragma unroll
+      for (int ks = 0; ks < C::NKSH; ++ks)
+        hb[i][ks] = __builtin_bit_cast(A, __builtin_nontemporal_load(srca + ks * 64));
+    }
+  };
+  if constexpr (kAct)
+    if (t_begin < t_end) load_hb(t_begin, NL - 1);
   int cur_stream = -1;
   for (int t = t_begin; t < t_end; ++t) {
     const int s = ps;                  // tile t was the last one prefetched
@@ -355,10 +395,14 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
                              : reinterpret_cast<const A*>(pk + C::OFF_BWDH);
     const __bf16* wsh = B::SHW ? reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(wlds) + C::OFF_FWDH)
                                : nullptr;
-    Ops<C, C::NKSH> hb[NL];
-    Ops<C, C::NKS1> feat1;             // bf16: layer-1 features, kept for the layer-1 dW staging
-    (void)mlp_forward<C, NL, RT, B::SHW>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
-                                 &xwt[col + B::XB], hb, tn, B::SM ? &feat1 : nullptr);
+    if constexpr (kAct) {
+#pragma unroll
+      for (int i = 0; i < NL - 1; ++i) load_hb(t, i);
+    } else {
+      (void)mlp_forward<C, NL, RT, B::SHW>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
+                                           &xwt[col + B::XB], hb, tn);
+    }
+    (void)wfwd; (void)wsh;
     int lb[2];
     B::lane_bases(g, col, lb);
     // output layer: delta_o = (Re g_u, Im g_u) (bf16: its own [2][S] array; fp32: staging
@@ -433,6 +477,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
         }
       opaque_ops<C, C::NKSH>(db);
     }
+    if constexpr (kAct)
+      if (t + 1 < t_end) load_hb(t + 1, NL - 1);
     auto layer = [&](auto i_c) {       // hidden layer i: delta_i in db, input h_{i-1}
       constexpr int i = decltype(i_c)::value;
       __syncthreads();                 // staging free
@@ -442,12 +488,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       } else {
         // features at their natural rows: lane group g holds rows [g*FPG, g*FPG + FPG)
         Ops<C, C::NKS1> feat;
-        if constexpr (B::SM) {
-#pragma unroll
-          for (int ks = 0; ks < C::NKS1; ++ks) feat[ks] = feat1[ks];
-        } else {
-          make_features<C, RT>(&xwt[col + B::XB], g, feat, tn);
-        }
+        make_features<C, RT>(&xwt[col + B::XB], g, feat, tn);
         if constexpr (B::SM && C::FPG % 4 == 0) {
           // 4 consecutive features per 8-byte write; chunks of the padding rows zeroed by
           // lane group 0
@@ -622,6 +663,7 @@ struct TdnnShape {
     td->pack_bytes = C::PACK;
     td->fwd_lds = (C::OFF_BWDH <= 144 * 1024 ? C::OFF_BWDH : 16) + 8 * (td->fwd_tile + T) + 4 * C::NVEC;
     td->dw_slot = C::SLOT;
+    td->act_group = PREC == DPD_BF16 ? (int64_t)NL * C::NKSH * 64 * 16 : 0;
   }
 
   static void pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pk, hipStream_t s) {
@@ -631,10 +673,12 @@ struct TdnnShape {
   }
 
   static void fwd(const TdnnDims& td, const StreamTable& st, const float* x, const void* pk, float* u,
-                  int grid, int waves, hipStream_t s) {
+                  int grid, int waves, void* act, hipStream_t s) {
     auto go = [&]<int FW>() {
+      static_assert(FW % 4 == 0, "forward tiles cover whole reverse-mode tiles");
       k_tdnn_fwd<PREC, T, H, NL, FW, RT><<<grid, 64 * FW, 0, s>>>(st, x, static_cast<const char*>(pk),
-                                                                  td.residual, td.taps, u);
+                                                                  td.residual, td.taps, u,
+                                                                  static_cast<act_u32x4*>(act));
     };
     if (waves == 16) go.template operator()<16>();
     else if (waves == 12) go.template operator()<12>();
@@ -642,9 +686,9 @@ struct TdnnShape {
   }
 
   static void bwd(const TdnnDims& td, const StreamTable& st, const float* x, const float* gu, const void* pk,
-                  float* slots, int grid, hipStream_t s) {
+                  float* slots, int grid, const void* act, hipStream_t s) {
     k_tdnn_bwd<PREC, T, H, NL, RT><<<grid, kThreads, 0, s>>>(st, x, gu, static_cast<const char*>(pk),
-                                                             td.taps, slots);
+                                                             td.taps, slots, static_cast<const act_u32x4*>(act));
   }
 
   static void finalize(const TdnnDims& td, const StreamTable& st, int grid, const float* slots,
