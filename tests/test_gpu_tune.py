@@ -75,3 +75,31 @@ def test_autotune_installs_and_uses_a_shape():
         H.check_cascade(inp, got, ref, "fp32")
     finally:
         cas.set_tune(None)
+
+
+@pytest.mark.parametrize("lens", [[7000, 63, 1, 4097, 2500], [65, 191, 193, 64]],
+                         ids=["ragged5", "tile_edges"])
+def test_bf16_gradient_independent_of_forward_tile(lens):
+    """bf16: the reverse mode reads the hidden activations the forward stored per 16-sample
+    group; with the backward grid fixed, dW (and the loss) are bitwise the same whatever
+    forward tile (8, 12 or 16 waves, 128/192/256 samples) wrote them, on ragged streams
+    whose lengths straddle the 64-sample reverse-mode tiles and the forward tiles."""
+    announce(f"bf16 gradient vs forward tile, streams {lens}")
+    inp = S.make_workload("batched_64s", n_streams=len(lens), max_len=max(lens))
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    x_np = np.concatenate([inp.x[inp.offsets[s]:inp.offsets[s] + n] for s, n in enumerate(lens)])
+    inp = S.Inputs(inp.workload, x_np, off, inp.w[:len(lens)], inp.coef[:len(lens)])
+    ref = H.oracle_for(inp)
+    cas = H.cascade_for(inp, precision="bf16")
+    x, w, c = _tensors(inp)
+    outs = []
+    try:
+        for fw in (8, 12, 16):
+            cas.set_tune(dict(fwd_waves=fw, fwd_wg_per_cu=1, bwd_wg_per_cu=1, gmp_tile=256))
+            outs.append(_host(cas.run(x, w, c)))
+            torch.cuda.synchronize()
+    finally:
+        cas.set_tune(None)
+    for o in outs[1:]:
+        assert np.array_equal(o["dw"], outs[0]["dw"]) and np.array_equal(o["loss"], outs[0]["loss"])
+    H.check_cascade(inp, outs[0], ref, "bf16")
