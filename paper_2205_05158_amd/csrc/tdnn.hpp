@@ -109,32 +109,11 @@ struct Cfg {
   static constexpr int64_t OFF_VEC = OFF_BWDH + (int64_t)(NL - 1) * NB * NKSH * 64 * ES;
   // float vector block: bias [NL][NB][LG][NR], wo [2][NB][LG][NR], bo[2] (+2 pad)
   static constexpr int NVEC = NL * HP + 2 * HP + 4;
-  // bf16 models also carry a row-major copy of the hidden weights W_i (i = 2..NL), shared
-  // in LDS by the backward kernel's forward recompute and its delta chain (two
-  // transposing 8-byte reads per operand); chunk c of row o (its elements 4c .. 4c+3) sits
-  // at chunk position cpos(c, o).  With 128-wide rows (one 256-byte sweep of the 64 banks
-  // per row) each 32-element group stores its chunks in the order 0 4 1 5 2 6 3 7, so the
-  // forward operand of lane group g (chunks g and g + 4 of a K step) is one aligned
-  // 16-byte read, and the pair index is swizzled by 4 (o mod 4) + (o / 4) mod 4: the 16
-  // rows of a 16-lane forward read hit 16 distinct 16-byte bank groups, and the
-  // transposing read's 8 rows x 4 chunks per 32 lanes (all on the same half of their
-  // pairs) are two-way at worst.  Narrower rows keep the chunks in order and swap the two
-  // 2-bit fields of o mod 16 (two 8-byte reads per forward operand).
-  static constexpr bool SHARED_W = X::EPL == 8;
-  static constexpr int NCH = HP / 4;                    // 8-byte chunks per row
-  static constexpr bool PAIRED = NCH == 32;
-  __host__ __device__ static constexpr int swz(int o) {
-    return PAIRED ? 8 * (o & 3) + 2 * ((o >> 2) & 3) : (((o & 3) << 2) | ((o >> 2) & 3)) & (NCH - 1);
-  }
-  __host__ __device__ static constexpr int cpos(int c, int o) {
-    return (PAIRED ? 8 * (c / 8) + 2 * (c % 4) + (c % 8) / 4 : c) ^ swz(o);
-  }
-  static constexpr int64_t OFF_WH = OFF_VEC + (int64_t)NVEC * 4;
-  static constexpr int64_t WH_LAYER = (int64_t)HP * HP * 2;
   // bf16 models: the output layer as one 16-row MFMA A block (rows 0, 1 = the two outputs,
   // K in the accumulator order of the last hidden layer), [K step][64 lanes]
-  static constexpr int64_t OFF_WO = OFF_WH + (SHARED_W ? (NL - 1) * WH_LAYER : 0);
-  static constexpr int64_t PACK = OFF_WO + (SHARED_W ? (int64_t)NKSH * 64 * 16 : 0);
+  static constexpr bool OUT_MMA = X::EPL == 8;
+  static constexpr int64_t OFF_WO = OFF_VEC + (int64_t)NVEC * 4;
+  static constexpr int64_t PACK = OFF_WO + (OUT_MMA ? (int64_t)NKSH * 64 * 16 : 0);
   // natural dW slot (floats): per layer W block [rows][cols] then bias [rows]
   static constexpr int64_t DW_L1 = (int64_t)HP * C1 + HP;
   static constexpr int64_t DW_H = (int64_t)HP * HP + HP;
@@ -172,15 +151,14 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
   char* ps = pack + set * C::PACK;
   const int64_t n1 = (int64_t)C::NB * C::NKS1 * 64;
   const int64_t nh = (int64_t)(NL - 1) * C::NB * C::NKSH * 64;
-  const int64_t nw = C::SHARED_W ? (int64_t)(NL - 1) * C::HP * C::HP : 0;
-  const int64_t no = C::SHARED_W ? (int64_t)C::NKSH * 64 : 0;
-  const int64_t total = n1 + 2 * nh + C::NVEC + nw + no;
+  const int64_t no = C::OUT_MMA ? (int64_t)C::NKSH * 64 : 0;
+  const int64_t total = n1 + 2 * nh + C::NVEC + no;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    if (idx >= n1 + 2 * nh + C::NVEC + nw) {
+    if (idx >= n1 + 2 * nh + C::NVEC) {
       // output-layer A block (bf16)
-      if constexpr (C::SHARED_W) {
-        const int64_t f = idx - (n1 + 2 * nh + C::NVEC + nw);
+      if constexpr (C::OUT_MMA) {
+        const int64_t f = idx - (n1 + 2 * nh + C::NVEC);
         const int lane = (int)(f % 64), ks = (int)(f / 64);
         const int m = lane % C::MT, g = lane / C::MT;
         bf16x8 a;
@@ -189,18 +167,6 @@ __global__ void k_pack(const float* __restrict__ w, int64_t w_stride, SrcOff so,
           a[ee] = (__bf16)((m < 2 && kk < hn) ? ws[so.w[NL] + (int64_t)m * hn + kk] : 0.f);
         }
         reinterpret_cast<bf16x8*>(ps + C::OFF_WO)[f] = a;
-      }
-    } else if (idx >= n1 + 2 * nh + C::NVEC) {
-      // row-major swizzled hidden weights (bf16)
-      if constexpr (C::SHARED_W) {
-        const int64_t f = idx - (n1 + 2 * nh + C::NVEC);
-        const int i = (int)(f / ((int64_t)C::HP * C::HP)) + 2;     // layer index 2..NL
-        const int r = (int)(f % ((int64_t)C::HP * C::HP));
-        const int o = r / C::HP, kk = r % C::HP;
-        const float* Wi = ws + so.w[i - 1];
-        const float val = (o < hn && kk < hn) ? Wi[(int64_t)o * hn + kk] * C::WS : 0.f;
-        __bf16* dstw = reinterpret_cast<__bf16*>(ps + C::OFF_WH + (int64_t)(i - 2) * C::WH_LAYER);
-        dstw[o * C::HP + 4 * C::cpos(kk / 4, o) + kk % 4] = (__bf16)val;
       }
     } else if (idx < n1 + 2 * nh) {
       const int lane = (int)(idx % 64);
@@ -366,47 +332,6 @@ struct PackedA {
   __device__ typename C::A operator()(int mb, int ks) const { return p[((int64_t)mb * NKS + ks) * 64 + lane]; }
 };
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-// Row-major swizzled hidden weights (Cfg::OFF_WH) in LDS, forward operand: row o = 16 mb +
-// lane%16 of W_i, K elements 32 ks + 4 g + (0..3) and 32 ks + 16 + 4 g + (0..3) (chunks
-// 8 ks + g and 8 ks + 4 + g: adjacent in 128-wide rows).
-template <class C>
-struct SharedFwdA {
-  const __bf16* w;     // LDS copy of one layer
-  int lane;
-  __device__ bf16x8 operator()(int mb, int ks) const {
-    const int o = 16 * mb + lane % 16, g = lane / 16;
-    const __bf16* row = w + o * C::HP;
-    if constexpr (C::PAIRED) {
-      return *reinterpret_cast<const bf16x8*>(row + 4 * C::cpos(8 * ks + g, o));
-    } else {
-      const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row + 4 * C::cpos(8 * ks + g, o));
-      const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 4 * C::cpos(8 * ks + 4 + g, o));
-      return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-    }
-  }
-};
-// The same copy read as the transposed (delta-chain) operand: row = input neuron
-// 16 mb + lane%16, K elements = output neurons 32 ks + 4 g + (0..3) and 32 ks + 16 + 4 g +
-// (0..3).  Each transposing read: lane l of a 16-lane group supplies the 8-byte chunk of
-// output neuron o0 + l/4 holding input neurons 16 mb + 4 (l%4) .. +3, and receives input
-// neuron 16 mb + l for output neurons o0 .. o0+3.
-template <class C>
-struct SharedBwdA {
-  const __bf16* w;
-  int lane;
-  __device__ bf16x8 operator()(int mb, int ks) const {
-    const int l = lane % 16, g = lane / 16;
-    // The swizzle sees only bits 0-3 of the row, i.e. the lane part 4 g + l / 4 of
-    // o1 = 32 ks + 4 g + l / 4 and o2 = o1 + 16: the K step's rows are then constant
-    // offsets from one lane address per row block (immediate offsets of the reads).
-    const int ol = 4 * g + l / 4;
-    const __bf16* p = w + ol * C::HP + 4 * C::cpos(4 * mb + l % 4, ol);
-    typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
-    const bf16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(p + 32 * ks * C::HP));
-    const bf16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(p + (32 * ks + 16) * C::HP));
-    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-  }
-};
 
 // Accumulators of a block start at zero ...
 struct ZeroInit {
@@ -480,15 +405,14 @@ __device__ __forceinline__ float lane_group_sum(float v) {
 
 // Forward through all hidden layers one row block at a time.  hb[i] holds h_{i+1} in
 // operand form; returns the two linear outputs (valid in every lane group).
-// wf: forward weight operands (layer 1, then the hidden layers; global or LDS); with WH
-// the hidden layers are read from the shared row-major copy at wh instead (LDS,
-// Cfg::OFF_WH layout).  vec: LDS copy of the float vector block (biases, output layer).
+// wf: forward weight operands (layer 1, then the hidden layers; global or LDS).  vec:
+// LDS copy of the float vector block (biases, output layer).
 // sink(i, hb[i]) receives each hidden layer's activations as soon as they are formed.
 struct NoSink {
   template <class O> __device__ void operator()(int, const O&) const {}
 };
-template <class C, int NL, bool RT = false, bool WH = false, class SINK = NoSink>
-__device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf, const __bf16* wh,
+template <class C, int NL, bool RT = false, class SINK = NoSink>
+__device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ wf,
                                               const typename C::A* __restrict__ wout,
                                               const float* vec, int lane, int g, const float2* xw,
                                               Ops<C, C::NKSH> (&hb)[NL], int tn = 0, SINK&& sink = SINK{}) {
@@ -523,12 +447,6 @@ __device__ __forceinline__ float2 mlp_forward(const typename C::A* __restrict__ 
     if constexpr (C::X::EPL == 8) init = BiasInit<C>{vec + i * C::HP, g};
     if (i == 0) {
       dense_layer<C, C::NKS1>(PackedA<C, C::NKS1>{wf, lane}, [&](int ks) { return feat[ks]; }, epi, init);
-    } else if constexpr (C::SHARED_W && WH) {
-      dense_layer<C, C::NKSH>(SharedFwdA<C>{wh + (int64_t)(i - 1) * (C::WH_LAYER / 2), lane},
-                              [&](int ks) { return hb[i - 1][ks]; }, epi, init);
-      opaque_ops<C, C::NKSH>(hb[i]);
-      sink(i, hb[i]);
-      continue;
     }
     if (i > 0) {
       const A* Ah = wf + (int64_t)C::NB * C::NKS1 * 64 + (int64_t)(i - 1) * C::NB * C::NKSH * 64;
@@ -615,9 +533,6 @@ struct BwdLds {
   // blocks hide global-memory latency worse than the tanh-heavy recompute blocks, else
   // the forward pack, else none.
   static constexpr int kLdsBudget = 160 * 1024;
-  // bf16: layer-1 operands + the shared row-major hidden weights, when they fit
-  static constexpr int64_t SH_BYTES = C::OFF_FWDH + (C::SHARED_W ? (NL - 1) * C::WH_LAYER : 0);
-  static constexpr bool SHW = C::SHARED_W && BASE_BYTES + SH_BYTES <= kLdsBudget;
   static constexpr bool FIT_ALL = BASE_BYTES + C::OFF_VEC <= kLdsBudget;
   static constexpr bool FIT_BWD = BASE_BYTES + (C::OFF_VEC - C::OFF_BWDH) <= kLdsBudget;
   static constexpr bool FIT_FWD = BASE_BYTES + C::OFF_BWDH <= kLdsBudget;
@@ -625,7 +540,7 @@ struct BwdLds {
   static constexpr int64_t W_HI = FIT_ALL ? C::OFF_VEC : (FIT_BWD ? C::OFF_VEC : (FIT_FWD ? C::OFF_BWDH : 0));
   static constexpr bool W_FWD = W_LO == 0 && W_HI >= C::OFF_BWDH;
   static constexpr bool W_BWD = W_LO <= C::OFF_BWDH && W_HI == C::OFF_VEC;
-  static constexpr int64_t W_BYTES = SHW ? SH_BYTES : (W_HI > W_LO ? W_HI - W_LO : 16);
+  static constexpr int64_t W_BYTES = W_HI > W_LO ? W_HI - W_LO : 16;
   // 32x32 dW blocks of the tanh layers (layer 1, then the hidden layers), dealt
   // round-robin over the waves: block bi is held by wave bi % kWaves in dwacc[bi / kWaves].
   // The output layer's 2 x HP dW is one register per thread instead (2*HP <= threads).

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64 * FW) void k_tdnn_fwd(StreamTable st, const floa
         }
       }
     };
-    float2 o = mlp_forward<C, NL, RT>(wops, nullptr, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane,
+    float2 o = mlp_forward<C, NL, RT>(wops, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane,
                                       g, &xw[col + T - 1], hb, tn, sink);
     const int64_t n = t0 + col;
     if (g == 0 && n < hi) {
@@ -367,13 +367,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
       // a new stream may bring a new parameter set: stage its vector block and weights
       const float* src = reinterpret_cast<const float*>(pk + C::OFF_VEC);
       for (int i = tid; i < C::NVEC; i += kThreads) vec[i] = src[i];
-      if constexpr (B::SHW) {
-        const uint4* w1 = reinterpret_cast<const uint4*>(pk);
-        for (int i = tid; i < (int)(C::OFF_FWDH / 16); i += kThreads) wlds[i] = w1[i];
-        const uint4* wh = reinterpret_cast<const uint4*>(pk + C::OFF_WH);
-        for (int i = tid; i < (int)((B::SH_BYTES - C::OFF_FWDH) / 16); i += kThreads)
-          wlds[C::OFF_FWDH / 16 + i] = wh[i];
-      } else if constexpr (B::W_HI > B::W_LO) {
+      if constexpr (B::W_HI > B::W_LO) {
         const uint4* wsrc = reinterpret_cast<const uint4*>(pk + B::W_LO);
         for (int i = tid; i < (int)(B::W_BYTES / 16); i += kThreads) wlds[i] = wsrc[i];
       }
@@ -390,19 +384,17 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     const float2* xwt = xw[t % NXB];
 
     // ---- TDNN: recompute this wave's samples, then the reverse mode
-    const A* wfwd = (B::SHW || B::W_FWD) ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
+    const A* wfwd = B::W_FWD ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
     const A* wbwd = B::W_BWD ? reinterpret_cast<const A*>(reinterpret_cast<const char*>(wlds) + (C::OFF_BWDH - B::W_LO))
                              : reinterpret_cast<const A*>(pk + C::OFF_BWDH);
-    const __bf16* wsh = B::SHW ? reinterpret_cast<const __bf16*>(reinterpret_cast<const char*>(wlds) + C::OFF_FWDH)
-                               : nullptr;
     if constexpr (kAct) {
 #pragma unroll
       for (int i = 0; i < NL - 1; ++i) load_hb(t, i);
     } else {
-      (void)mlp_forward<C, NL, RT, B::SHW>(wfwd, wsh, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
+      (void)mlp_forward<C, NL, RT>(wfwd, reinterpret_cast<const A*>(pk + C::OFF_WO), vec, lane, g,
                                            &xwt[col + B::XB], hb, tn);
     }
-    (void)wfwd; (void)wsh;
+    (void)wfwd;
     int lb[2];
     B::lane_bases(g, col, lb);
     // output layer: delta_o = (Re g_u, Im g_u) (bf16: its own [2][S] array; fp32: staging
@@ -527,13 +519,8 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
             set_elem<C>(dn[X::ks_of(mb, j)], X::e_of(mb, j), acc[j] * (1.f - hv * hv));
           }
         };
-        if constexpr (B::SHW) {
-          dense_layer<C, C::NKSH>(SharedBwdA<C>{wsh + (int64_t)(i - 2) * (C::WH_LAYER / 2), lane},
-                                  [&](int ks) { return db[ks]; }, epi);
-        } else {
-          const A* Ab = wbwd + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
-          dense_layer<C, C::NKSH>(PackedA<C, C::NKSH>{Ab, lane}, [&](int ks) { return db[ks]; }, epi);
-        }
+        const A* Ab = wbwd + (int64_t)(i - 2) * C::NB * C::NKSH * 64;
+        dense_layer<C, C::NKSH>(PackedA<C, C::NKSH>{Ab, lane}, [&](int ks) { return db[ks]; }, epi);
         opaque_ops<C, C::NKSH>(dn);
       }
       __syncthreads();
