@@ -1,4 +1,4 @@
-// Shared pieces of the tuned TDNN kernels (tdnn.hip, tdnn_pair.hip): MFMA geometry,
+// Common pieces of the tuned TDNN kernels (tdnn_kernels.hpp): MFMA geometry,
 // the packed parameter layout, the pack kernel, layer building blocks and the LDS
 // staging of the reverse mode.  See tdnn.hip for the formulation.
 #pragma once

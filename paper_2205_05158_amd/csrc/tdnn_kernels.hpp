@@ -103,9 +103,10 @@ __global__ __launch_bounds__(64 * FW) void k_tdnn_fwd(StreamTable st, const floa
 }
 
 // Reverse mode of the TDNN over the stream table's tiles, from g_u (= dL/du per sample,
-// zero-extended outside the streams): each workgroup owns a contiguous tile range,
-// recomputes the forward pass of its samples, runs the delta chain and accumulates
-// dW over its tiles in registers; one slot per (workgroup, stream) is written.
+// zero-extended outside the streams): each workgroup owns a contiguous tile range, takes
+// its samples' hidden activations from the forward's store (bf16) or recomputes them
+// (fp32), runs the delta chain and accumulates dW over its tiles in registers; one slot
+// per (workgroup, stream) is written.
 template <int PREC, int T, int H, int NL, bool RT>
 __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const float* __restrict__ x,
                                                        const float* __restrict__ gu,
@@ -383,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_tdnn_bwd(StreamTable st, const flo
     if constexpr (NXB == 1) __syncthreads();
     const float2* xwt = xw[t % NXB];
 
-    // ---- TDNN: recompute this wave's samples, then the reverse mode
+    // ---- TDNN: this wave's hidden activations (stored, or recomputed), then the reverse mode
     const A* wfwd = B::W_FWD ? reinterpret_cast<const A*>(wlds) : reinterpret_cast<const A*>(pk);
     const A* wbwd = B::W_BWD ? reinterpret_cast<const A*>(reinterpret_cast<const char*>(wlds) + (C::OFF_BWDH - B::W_LO))
                              : reinterpret_cast<const A*>(pk + C::OFF_BWDH);
