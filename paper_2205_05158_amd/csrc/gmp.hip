@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kGmpThreads) void k_gmp_fwd(StreamTable st, const f
   int64_t lo = st.off[s], hi = st.off[s + 1];
   int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
   const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
-  for (int j = threadIdx.x; j < G::J; j += S) cf[j] = make_float2(cs[2 * j], cs[2 * j + 1]);
+  for (int j = threadIdx.x; j < G::J; j += S) cf[G::tpos(j)] = make_float2(cs[2 * j], cs[2 * j + 1]);
   for (int i = threadIdx.x; i < UW; i += S) {
     int64_t p = t0 - UB + i;
     float2 v = (p >= lo && p < hi) ? ld2(u, p) : make_float2(0.f, 0.f);
@@ -62,8 +62,9 @@ __global__ __launch_bounds__(kGmpThreads) void k_gmp_fwd(StreamTable st, const f
   }
 }
 
-// Per parameter set, the coefficient table read by k_gmp_bwd: tab[set][j] = C_j and
-// tab[set][J + j] = order(j) * C_j (the coefficients of the envelope derivative).
+// Per parameter set, the coefficient table read by k_gmp_bwd, in the kernels' order
+// (Gmp::tpos): tab[set][tpos(j)] = C_j and tab[set][J + tpos(j)] = order(j) * C_j (the
+// coefficients of the envelope derivative).
 template <int K, int M, int L>
 __global__ void k_gmp_table(const float* __restrict__ coef, float2* __restrict__ tab) {
   using G = Gmp<K, M, L>;
@@ -73,8 +74,8 @@ __global__ void k_gmp_table(const float* __restrict__ coef, float2* __restrict__
   const float* cs = coef + (int64_t)set * 2 * G::J;
   const float2 c = make_float2(cs[2 * j], cs[2 * j + 1]);
   const float k = (float)G::order(j);
-  tab[(int64_t)set * 2 * G::J + j] = c;
-  tab[(int64_t)set * 2 * G::J + G::J + j] = make_float2(k * c.x, k * c.y);
+  tab[(int64_t)set * 2 * G::J + G::tpos(j)] = c;
+  tab[(int64_t)set * 2 * G::J + G::J + G::tpos(j)] = make_float2(k * c.x, k * c.y);
 }
 
 // GMP forward and reverse mode over tiles of S samples (one per thread), one workgroup per tile

@@ -33,6 +33,24 @@ struct Gmp {
   __host__ __device__ static constexpr int order(int j) {
     return j < KA ? j / (M + 1) : ((j - KA) % KB) / ((M + 1) * L) + 1;
   }
+  // The kernels' coefficient order: per memory tap l, the K coefficients of a_{.,l}, then
+  // per lag g the K - 1 coefficients of b_{.,l,g} and those of c_{.,l,g}, so that every
+  // Horner chain reads one contiguous run (a few wide scalar loads instead of one load
+  // per coefficient).
+  static constexpr int P = K + 2 * L * (K - 1);
+  __host__ __device__ static constexpr int ta(int k, int l) { return l * P + k; }
+  __host__ __device__ static constexpr int tb(int k, int l, int g) {
+    return l * P + K + 2 * (g - 1) * (K - 1) + (k - 1);
+  }
+  __host__ __device__ static constexpr int tc(int k, int l, int g) { return tb(k, l, g) + (K - 1); }
+  // position in the kernels' order of the coefficient at packed index j
+  __host__ __device__ static constexpr int tpos(int j) {
+    if (j < KA) return ta(j / (M + 1), j % (M + 1));
+    const bool fc = j >= KA + KB;
+    const int r = j - KA - (fc ? KB : 0);   // ((k - 1)(M + 1) + l) L + g - 1
+    const int g = r % L + 1, kl = r / L, l = kl % (M + 1), k = kl / (M + 1) + 1;
+    return fc ? tc(k, l, g) : tb(k, l, g);
+  }
 };
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -45,7 +63,8 @@ __device__ __forceinline__ float2 cfma_r(float2 acc, float r, float2 c) {   // a
   return make_float2(fmaf(acc.x, r, c.x), fmaf(acc.y, r, c.y));
 }
 
-// Q_l(p) for l = L0..L1-1 (default: all taps); rw points at r[p] inside a window that
+// Q_l(p) for l = L0..L1-1 (default: all taps); cf holds the coefficients in the kernels'
+// order (Gmp::tpos); rw points at r[p] inside a window that
 // covers p-L..p+L.
 template <int K, int M, int L, int L0 = 0, int L1 = M + 1>
 __device__ __forceinline__ void gmp_q(const float* rw, const float2* cf, float2 (&Q)[M + 1]) {
@@ -60,19 +79,19 @@ __device__ __forceinline__ void gmp_q(const float* rw, const float2* cf, float2 
 #pragma unroll
   for (int l = L0; l < L1; ++l) {
     DPD_KEEP_LOADS_LOCAL();
-    float2 acc = cf[G::ia(K - 1, l)];
+    float2 acc = cf[G::ta(K - 1, l)];
 #pragma unroll
-    for (int k = K - 2; k >= 0; --k) acc = cfma_r(acc, r0, cf[G::ia(k, l)]);
+    for (int k = K - 2; k >= 0; --k) acc = cfma_r(acc, r0, cf[G::ta(k, l)]);
     if (K > 1) {
 #pragma unroll
       for (int g = 1; g <= L; ++g) {
         DPD_KEEP_LOADS_LOCAL();
-        float2 hb = cf[G::ib(K - 1, l, g)];
+        float2 hb = cf[G::tb(K - 1, l, g)];
 #pragma unroll
-        for (int k = K - 2; k >= 1; --k) hb = cfma_r(hb, rl[g], cf[G::ib(k, l, g)]);
-        float2 hc = cf[G::ic(K - 1, l, g)];
+        for (int k = K - 2; k >= 1; --k) hb = cfma_r(hb, rl[g], cf[G::tb(k, l, g)]);
+        float2 hc = cf[G::tc(K - 1, l, g)];
 #pragma unroll
-        for (int k = K - 2; k >= 1; --k) hc = cfma_r(hc, rr[g], cf[G::ic(k, l, g)]);
+        for (int k = K - 2; k >= 1; --k) hc = cfma_r(hc, rr[g], cf[G::tc(k, l, g)]);
         acc.x = fmaf(hb.x, rl[g], fmaf(hc.x, rr[g], acc.x));
         acc.y = fmaf(hb.y, rl[g], fmaf(hc.y, rr[g], acc.y));
       }
@@ -85,7 +104,7 @@ __device__ __forceinline__ void gmp_q(const float* rw, const float2* cf, float2 
 template <int K, int M, int L, int FAM>
 __device__ __forceinline__ float2 gmp_d2(const float2* dcf, int l, int g, float r) {
   using G = Gmp<K, M, L>;
-  auto idx = [&](int k) { return FAM == 0 ? G::ia(k, l) : (FAM == 1 ? G::ib(k, l, g) : G::ic(k, l, g)); };
+  auto idx = [&](int k) { return FAM == 0 ? G::ta(k, l) : (FAM == 1 ? G::tb(k, l, g) : G::tc(k, l, g)); };
   float2 acc = make_float2(0.f, 0.f);
   if (K >= 3) {
     acc = dcf[idx(K - 1)];
@@ -120,7 +139,7 @@ __device__ __forceinline__ float2 gmp_grad(const float2* uw, const float* rw, co
     gu.y += t.y;
     if (K > 1) {
       float2 w = cmulc(gyl, um);                         // conj(g_y[m+l]) u[m]
-      float2 c1 = cf[G::ia(1, l)];
+      float2 c1 = cf[G::ta(1, l)];
       s1 += w.x * c1.x - w.y * c1.y;
       float2 d = gmp_d2<K, M, L, 0>(dcf, l, 0, r);
       s2 += w.x * d.x - w.y * d.y;
@@ -128,12 +147,12 @@ __device__ __forceinline__ float2 gmp_grad(const float2* uw, const float* rw, co
       for (int g = 1; g <= L; ++g) {
         DPD_KEEP_LOADS_LOCAL();
         float2 wb = cmulc(gyw[l + g], uw[g]);            // conj(g_y[m+l+g]) u[m+g]
-        float2 cb = cf[G::ib(1, l, g)];
+        float2 cb = cf[G::tb(1, l, g)];
         s1 += wb.x * cb.x - wb.y * cb.y;
         float2 db = gmp_d2<K, M, L, 1>(dcf, l, g, r);
         s2 += wb.x * db.x - wb.y * db.y;
         float2 wc = cmulc(gyw[l - g], uw[-g]);           // conj(g_y[m+l-g]) u[m-g]
-        float2 cc = cf[G::ic(1, l, g)];
+        float2 cc = cf[G::tc(1, l, g)];
         s1 += wc.x * cc.x - wc.y * cc.y;
         float2 dc = gmp_d2<K, M, L, 2>(dcf, l, g, r);
         s2 += wc.x * dc.x - wc.y * dc.y;
