@@ -87,7 +87,12 @@ typedef struct {
  *                                                 + c_{k,l,g} u[n-l] |u[n-l+g]|^k ),
  * u = 0 outside the stream.  Packed complex float32 coefficients
  * (J = dpd_gmp_coeff_count): a[K][M+1], b[K-1][M+1][L], c[K-1][M+1][L],
- * b and c indexed from k = 1 and g = 1. */
+ * b and c indexed from k = 1 and g = 1.  The tuned gradient path (dpd_backward,
+ * dpd_cascade with dW, dpd_autotune) takes K <= 9, M <= 7, L <= 4: the orders (5, 3, 2),
+ * (7, 5, 3), (9, 7, 4) and (7, 3, 1) on kernels compiled for them, the others on the
+ * (9, 7, 4) kernels with zero-padded coefficients (their reverse-mode table, and so the
+ * workspace, then has that order's size); larger orders return DPD_ERR_UNSUPPORTED there
+ * (DPD_IMPL_PLAIN takes every valid order). */
 typedef struct {
     int32_t K;          /* nonlinear order, 1..DPD_MAX_GMP_K   */
     int32_t M;          /* memory depth (paper L3), 0..DPD_MAX_GMP_M */
@@ -250,7 +255,8 @@ dpd_status dpd_tune_set(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
  * fastest combination as this problem's entry (gmp key = gmp) and returns it.  It
  * enqueues that work on `stream`, records HIP events on it and waits for them (it
  * blocks; not for the hot loop), and writes only workspace memory.  Tuned
- * implementation with supported GMP orders only (else DPD_ERR_UNSUPPORTED). */
+ * implementation with GMP orders of the tuned gradient path only (else
+ * DPD_ERR_UNSUPPORTED). */
 dpd_status dpd_autotune(const dpd_tdnn_desc* tdnn, const dpd_gmp_desc* gmp,
                         const dpd_batch* batch, const float* x, const float* w,
                         const float* coef, float g_re, float g_im, int32_t reps,

@@ -232,7 +232,7 @@ Ws ws_layout(const dpd_tdnn_desc* d, const dpd_gmp_desc* g, const Problem& p) {
     w.pack = take((size_t)td.pack_bytes * p.n_sets);
     w.slots = take(sizeof(float) * (size_t)td.dw_slot * (kMaxGrid + p.S));
     w.gu_buf = take(sizeof(float2) * p.n_total);
-    if (g) w.gmp_tab = take(sizeof(float2) * 2 * (size_t)coeff_count(*g) * p.n_sets);
+    if (g) w.gmp_tab = take(sizeof(float2) * 2 * (size_t)std::max<int64_t>(gmp_table_coeffs(*g), 1) * p.n_sets);
     // bf16: the forward's hidden activations for the reverse mode, 4 groups of 16 samples
     // per 64-sample reverse-mode tile
     if (td.act_group > 0) w.hact = take((size_t)td.act_group * 4 * (size_t)make_table(p, td.tile).n_tiles);

@@ -78,6 +78,37 @@ __global__ void k_gmp_table(const float* __restrict__ coef, float2* __restrict__
   tab[(int64_t)set * 2 * G::J + G::J + G::tpos(j)] = make_float2(k * c.x, k * c.y);
 }
 
+// The same table for a smaller order (K, M, L) run on the (KP, MP, LP) kernels: every
+// position of the padded table holds the coefficient of the same monomial, or zero where
+// the order has none.
+template <int KP, int MP, int LP>
+__global__ void k_gmp_table_pad(const float* __restrict__ coef, int K, int M, int L, float2* __restrict__ tab) {
+  using G = Gmp<KP, MP, LP>;
+  const int set = blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;   // position in the padded table
+  if (q >= G::J) return;
+  const int J = K * (M + 1) + 2 * (K - 1) * (M + 1) * L;
+  const int l = q / G::P, r = q % G::P;
+  int k, g = 0, fam = 0;
+  if (r < KP) {
+    k = r;
+  } else {
+    const int r2 = r - KP;
+    g = r2 / (2 * (KP - 1)) + 1;
+    fam = (r2 % (2 * (KP - 1))) < KP - 1 ? 1 : 2;
+    k = r2 % (KP - 1) + 1;
+  }
+  int j = -1;                                           // packed index in the order (K, M, L)
+  if (k < K && l <= M && (fam == 0 || g <= L)) {
+    const int KA = K * (M + 1), KB = (K - 1) * (M + 1) * L;
+    j = fam == 0 ? k * (M + 1) + l : KA + (fam == 2 ? KB : 0) + ((k - 1) * (M + 1) + l) * L + (g - 1);
+  }
+  const float* cs = coef + (int64_t)set * 2 * J;
+  const float2 c = j >= 0 ? make_float2(cs[2 * j], cs[2 * j + 1]) : make_float2(0.f, 0.f);
+  tab[(int64_t)set * 2 * G::J + q] = c;
+  tab[(int64_t)set * 2 * G::J + G::J + q] = make_float2((float)k * c.x, (float)k * c.y);
+}
+
 // GMP forward and reverse mode over tiles of S samples (one per thread), one workgroup per tile
 // (no persistent state, so it runs at the occupancy its registers allow).  The
 // coefficients are read from the table (wave-uniform addresses: scalar loads into
@@ -189,18 +220,35 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
 
 }  // namespace
 
+int64_t gmp_table_coeffs(const dpd_gmp_desc& g) {
+  int64_t J = 0;
+  if (!gmp_dispatch(g.K, g.M, g.L, [&]<int K, int M, int L>() { J = Gmp<K, M, L>::J; }) &&
+      gmp_pad_fits(g.K, g.M, g.L))
+    J = Gmp<kGmpPadK, kGmpPadM, kGmpPadL>::J;
+  return J;
+}
+
 void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
                     const float* coef, float2* tab, float g_re, float g_im, float4* tile_part,
                     float* gu, float* y, hipStream_t s) {
-  gmp_dispatch(g.K, g.M, g.L, [&]<int K, int M, int L>() {
-    const int n_sets = st.per_stream ? st.n : 1;
-    dim3 tg((Gmp<K, M, L>::J + 255) / 256, n_sets);
-    k_gmp_table<K, M, L><<<tg, 256, 0, s>>>(coef, tab);
+  const int n_sets = st.per_stream ? st.n : 1;
+  auto run = [&]<int K, int M, int L>() {
     if (st.tile == 512)
       k_gmp_bwd<K, M, L, 512><<<st.n_tiles, 512, 0, s>>>(st, x, u, tab, g_re, g_im, tile_part, gu, y);
     else
       k_gmp_bwd<K, M, L, 256><<<st.n_tiles, 256, 0, s>>>(st, x, u, tab, g_re, g_im, tile_part, gu, y);
+  };
+  const bool exact = gmp_dispatch(g.K, g.M, g.L, [&]<int K, int M, int L>() {
+    dim3 tg((Gmp<K, M, L>::J + 255) / 256, n_sets);
+    k_gmp_table<K, M, L><<<tg, 256, 0, s>>>(coef, tab);
+    run.template operator()<K, M, L>();
   });
+  if (!exact && gmp_pad_fits(g.K, g.M, g.L)) {
+    constexpr int KP = kGmpPadK, MP = kGmpPadM, LP = kGmpPadL;
+    dim3 tg((Gmp<KP, MP, LP>::J + 255) / 256, n_sets);
+    k_gmp_table_pad<KP, MP, LP><<<tg, 256, 0, s>>>(coef, g.K, g.M, g.L, tab);
+    run.template operator()<KP, MP, LP>();
+  }
 }
 
 void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u, const float* coef,

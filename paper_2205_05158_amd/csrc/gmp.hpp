@@ -164,6 +164,14 @@ __device__ __forceinline__ float2 gmp_grad(const float2* uw, const float* rw, co
   return gu;
 }
 
+// Orders with no instantiation of their own run on the (9, 7, 4) kernels with their
+// coefficients zero-padded to that order (a polynomial with zero leading coefficients,
+// taps and lags with zero coefficients change no value for finite inputs).
+constexpr int kGmpPadK = 9, kGmpPadM = 7, kGmpPadL = 4;
+__host__ inline bool gmp_pad_fits(int K, int M, int L) {
+  return K >= 1 && K <= kGmpPadK && M >= 0 && M <= kGmpPadM && L >= 0 && L <= kGmpPadL;
+}
+
 // Supported (K, M, L) for the tuned kernels; call f.template operator()<K,M,L>().
 template <class F>
 __host__ bool gmp_dispatch(int K, int M, int L, F&& f) {

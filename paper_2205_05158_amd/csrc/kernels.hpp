@@ -162,6 +162,9 @@ void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u
 // E/R tile partials and g_u = dL/du.  Supported (K, M, L) are those of gmp_dispatch.
 // tab: workspace of 2 * J float2 per parameter set (the coefficients and their
 // derivative-weighted copy, written first on the same stream).
+// Coefficients per parameter set of the reverse-mode kernels' table: J of the order, or of
+// the padded order an order without its own instantiation runs on (0: not supported).
+int64_t gmp_table_coeffs(const dpd_gmp_desc& g);
 void launch_gmp_bwd(const dpd_gmp_desc& g, const StreamTable& st, const float* x, const float* u,
                     const float* coef, float2* tab, float g_re, float g_im, float4* tile_part,
                     float* gu, float* y, hipStream_t s);

@@ -78,7 +78,7 @@ bool tdnn_dims(const dpd_tdnn_desc& d, TdnnDims* out) {
 bool tuned_supported(const dpd_tdnn_desc& d, const dpd_gmp_desc* g) {
   TdnnDims td;
   if (!tdnn_dims(d, &td)) return false;
-  return !g || gmp_dispatch(g->K, g->M, g->L, [&]<int K_, int M_, int L_>() {});
+  return !g || gmp_table_coeffs(*g) > 0;
 }
 
 void launch_pack(const TdnnDims& td, const float* w, int n_sets, int64_t w_stride, void* pack,

@@ -103,8 +103,8 @@ def test_null_and_alignment_and_workspace(dpdlib):
     # gradient without a loss output
     assert lib.dpd_cascade(C.byref(t), C.byref(g), C.byref(b), FAKE, FAKE, FAKE, 1.0, 0.0, None, None,
                            None, FAKE, None, FAKE, 1 << 40, None) == L.DPD_ERR_NULL
-    # GMP orders the tuned backward kernels are not built for (rejected before any launch)
-    g2 = D.gmp_desc(3, 2, 1)
+    # GMP orders beyond the tuned backward kernels' padded bound (rejected before any launch)
+    g2 = D.gmp_desc(10, 2, 1)
     assert lib.dpd_backward(C.byref(t), C.byref(g2), C.byref(b), FAKE, FAKE, FAKE, 1.0, 0.0, FAKE, FAKE,
                             FAKE, 1 << 40, None) == L.DPD_ERR_UNSUPPORTED
 
@@ -224,7 +224,7 @@ def test_tune_table_host(dpdlib):
     assert auto(out_=None) == L.DPD_ERR_NULL
     assert auto(x=None) == L.DPD_ERR_NULL
     assert auto(tdnn=plain) == L.DPD_ERR_UNSUPPORTED
-    assert auto(gmp=D.gmp_desc(3, 2, 1)) == L.DPD_ERR_UNSUPPORTED
+    assert auto(gmp=D.gmp_desc(10, 2, 1)) == L.DPD_ERR_UNSUPPORTED
     assert auto(nbytes=16) == L.DPD_ERR_WORKSPACE
 
 

@@ -109,3 +109,31 @@ def test_exact_and_generic_dispatch():
     for shape in [(4, 2, 20), (4, 2, 21), (10, 3, 64), (10, 3, 63), (16, 4, 128), (16, 4, 127)]:
         for prec in ("fp32", "bf16"):
             assert D.dpd_tune_get(D.tdnn_desc(*shape, precision=prec), g, b)["fwd_waves"] in (8, 12)
+
+
+# GMP orders without an instantiation of their own (run on the zero-padded (9, 7, 4)
+# kernels): the degenerate linear PA (K 1, no memory), memory only, cross terms only at
+# the padded bound, and mixed orders
+GMP_ORDERS = [(1, 0, 0), (3, 2, 1), (6, 4, 2), (9, 0, 4), (2, 7, 0), (8, 6, 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("order", GMP_ORDERS, ids=lambda o: "K%d_M%d_L%d" % o)
+def test_padded_gmp_order_against_oracle(order, prec):
+    """The cascade and its gradient with GMP orders that run on the zero-padded kernels,
+    three ragged streams with their own parameter sets, against the FP64 oracle."""
+    K, M, L = order
+    announce(f"padded GMP order K={K} M={M} L={L} prec={prec}, streams {LENS}")
+    wl = dataclasses.replace(S.WORKLOADS["parity_16k"], name=f"gmp_{K}_{M}_{L}", K=K, M=M, L=L,
+                             n_streams=len(LENS), per_stream_params=True)
+    xs, ws, cs = [], [], []
+    for s, n in enumerate(LENS):
+        xs.append(S.ofdm_signal(2048, 1200, -(-n // 2048), 64, np.random.default_rng(21 + s))[:n])
+        ws.append(S.xavier_tdnn(wl.taps, wl.n_hidden, wl.hidden, 500 + s))
+        cs.append(S.gmp_coefficients(K, M, L, 600 + s))
+    x = S.to_interleaved(np.concatenate(xs))
+    off = np.concatenate([[0], np.cumsum(LENS)]).astype(np.int64)
+    inp = Inputs(wl, x, off, np.stack(ws), np.stack(cs))
+    got = H.run_gpu(inp, precision=prec)
+    ref = H.oracle_for(inp)
+    H.check_cascade(inp, got, ref, prec)
