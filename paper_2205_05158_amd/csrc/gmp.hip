@@ -12,10 +12,12 @@ namespace {
 
 constexpr int kGmpThreads = 128;
 
-template <int K, int M, int L>
+// PAD: the coefficients are of the smaller order (ku, mu, lu), zero-padded into (K, M, L).
+template <int K, int M, int L, bool PAD = false>
 __global__ __launch_bounds__(kGmpThreads) void k_gmp_fwd(StreamTable st, const float* __restrict__ u,
                                                          const float* __restrict__ coef,
-                                                         float* __restrict__ y) {
+                                                         float* __restrict__ y, int ku = K, int mu = M,
+                                                         int lu = L) {
   using G = Gmp<K, M, L>;
   constexpr int S = kGmpThreads;        // samples per tile (st.tile == S)
   constexpr int UB = M + L;             // u halo behind the first output
@@ -30,8 +32,18 @@ __global__ __launch_bounds__(kGmpThreads) void k_gmp_fwd(StreamTable st, const f
   int s = stream_of_tile(st, t);
   int64_t lo = st.off[s], hi = st.off[s + 1];
   int64_t t0 = lo + (int64_t)(t - st.tile0[s]) * S;
-  const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
-  for (int j = threadIdx.x; j < G::J; j += S) cf[G::tpos(j)] = make_float2(cs[2 * j], cs[2 * j + 1]);
+  if constexpr (PAD) {
+    const int Ju = ku * (mu + 1) + 2 * (ku - 1) * (mu + 1) * lu;
+    const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * Ju : 0);
+    for (int q = threadIdx.x; q < G::J; q += S) {
+      int k;
+      const int j = gmp_pad_src<K, M, L>(q, ku, mu, lu, k);
+      cf[q] = j >= 0 ? make_float2(cs[2 * j], cs[2 * j + 1]) : make_float2(0.f, 0.f);
+    }
+  } else {
+    const float* cs = coef + (st.per_stream ? (int64_t)s * 2 * G::J : 0);
+    for (int j = threadIdx.x; j < G::J; j += S) cf[G::tpos(j)] = make_float2(cs[2 * j], cs[2 * j + 1]);
+  }
   for (int i = threadIdx.x; i < UW; i += S) {
     int64_t p = t0 - UB + i;
     float2 v = (p >= lo && p < hi) ? ld2(u, p) : make_float2(0.f, 0.f);
@@ -88,21 +100,8 @@ __global__ void k_gmp_table_pad(const float* __restrict__ coef, int K, int M, in
   const int q = blockIdx.x * blockDim.x + threadIdx.x;   // position in the padded table
   if (q >= G::J) return;
   const int J = K * (M + 1) + 2 * (K - 1) * (M + 1) * L;
-  const int l = q / G::P, r = q % G::P;
-  int k, g = 0, fam = 0;
-  if (r < KP) {
-    k = r;
-  } else {
-    const int r2 = r - KP;
-    g = r2 / (2 * (KP - 1)) + 1;
-    fam = (r2 % (2 * (KP - 1))) < KP - 1 ? 1 : 2;
-    k = r2 % (KP - 1) + 1;
-  }
-  int j = -1;                                           // packed index in the order (K, M, L)
-  if (k < K && l <= M && (fam == 0 || g <= L)) {
-    const int KA = K * (M + 1), KB = (K - 1) * (M + 1) * L;
-    j = fam == 0 ? k * (M + 1) + l : KA + (fam == 2 ? KB : 0) + ((k - 1) * (M + 1) + l) * L + (g - 1);
-  }
+  int k;
+  const int j = gmp_pad_src<KP, MP, LP>(q, K, M, L, k);
   const float* cs = coef + (int64_t)set * 2 * J;
   const float2 c = j >= 0 ? make_float2(cs[2 * j], cs[2 * j + 1]) : make_float2(0.f, 0.f);
   tab[(int64_t)set * 2 * G::J + q] = c;
@@ -266,6 +265,10 @@ void launch_gmp_fwd(const dpd_gmp_desc& g, const StreamTable& st, const float* u
   bool ok = gmp_dispatch(g.K, g.M, g.L, [&]<int K, int M, int L>() {
     k_gmp_fwd<K, M, L><<<t2.n_tiles, kGmpThreads, 0, s>>>(t2, u, coef, y);
   });
+  if (!ok && gmp_pad_fits(g.K, g.M, g.L)) {
+    k_gmp_fwd<kGmpPadK, kGmpPadM, kGmpPadL, true><<<t2.n_tiles, kGmpThreads, 0, s>>>(t2, u, coef, y, g.K, g.M, g.L);
+    ok = true;
+  }
   if (!ok) {
     int64_t J = (int64_t)g.K * (g.M + 1) + 2 * (int64_t)(g.K - 1) * (g.M + 1) * g.L;
     for (int i = 0; i < st.n; ++i)

@@ -172,6 +172,26 @@ __host__ inline bool gmp_pad_fits(int K, int M, int L) {
   return K >= 1 && K <= kGmpPadK && M >= 0 && M <= kGmpPadM && L >= 0 && L <= kGmpPadL;
 }
 
+// Packed index, in the order (K, M, L), of the monomial at position q of the padded
+// (KP, MP, LP) table in the kernels' order, and its power k; -1 where (K, M, L) has none.
+template <int KP, int MP, int LP>
+__device__ inline int gmp_pad_src(int q, int K, int M, int L, int& k) {
+  constexpr int P = Gmp<KP, MP, LP>::P;
+  const int l = q / P, r = q % P;
+  int g = 0, fam = 0;
+  if (r < KP) {
+    k = r;
+  } else {
+    const int r2 = r - KP;
+    g = r2 / (2 * (KP - 1)) + 1;
+    fam = (r2 % (2 * (KP - 1))) < KP - 1 ? 1 : 2;
+    k = r2 % (KP - 1) + 1;
+  }
+  if (k >= K || l > M || (fam != 0 && g > L)) return -1;
+  const int KA = K * (M + 1), KB = (K - 1) * (M + 1) * L;
+  return fam == 0 ? k * (M + 1) + l : KA + (fam == 2 ? KB : 0) + ((k - 1) * (M + 1) + l) * L + (g - 1);
+}
+
 // Supported (K, M, L) for the tuned kernels; call f.template operator()<K,M,L>().
 template <class F>
 __host__ bool gmp_dispatch(int K, int M, int L, F&& f) {

@@ -121,7 +121,8 @@ GMP_ORDERS = [(1, 0, 0), (3, 2, 1), (6, 4, 2), (9, 0, 4), (2, 7, 0), (8, 6, 3)]
 @pytest.mark.parametrize("order", GMP_ORDERS, ids=lambda o: "K%d_M%d_L%d" % o)
 def test_padded_gmp_order_against_oracle(order, prec):
     """The cascade and its gradient with GMP orders that run on the zero-padded kernels,
-    three ragged streams with their own parameter sets, against the FP64 oracle."""
+    three ragged streams with their own parameter sets, against the FP64 oracle; and the
+    forward-only cascade, whose GMP forward kernel pads the same way."""
     K, M, L = order
     announce(f"padded GMP order K={K} M={M} L={L} prec={prec}, streams {LENS}")
     wl = dataclasses.replace(S.WORKLOADS["parity_16k"], name=f"gmp_{K}_{M}_{L}", K=K, M=M, L=L,
@@ -137,3 +138,5 @@ def test_padded_gmp_order_against_oracle(order, prec):
     got = H.run_gpu(inp, precision=prec)
     ref = H.oracle_for(inp)
     H.check_cascade(inp, got, ref, prec)
+    fwd = H.run_gpu(inp, precision=prec, grad=False)
+    H.check_cascade(inp, fwd, ref, prec, grad=False)
