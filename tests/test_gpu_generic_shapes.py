@@ -117,6 +117,19 @@ def test_exact_and_generic_dispatch():
 GMP_ORDERS = [(1, 0, 0), (3, 2, 1), (6, 4, 2), (9, 0, 4), (2, 7, 0), (8, 6, 3)]
 
 
+def gmp_order_inputs(K, M, L, lens=LENS):
+    wl = dataclasses.replace(S.WORKLOADS["parity_16k"], name=f"gmp_{K}_{M}_{L}", K=K, M=M, L=L,
+                             n_streams=len(lens), per_stream_params=True)
+    xs, ws, cs = [], [], []
+    for s, n in enumerate(lens):
+        xs.append(S.ofdm_signal(2048, 1200, -(-n // 2048), 64, np.random.default_rng(21 + s))[:n])
+        ws.append(S.xavier_tdnn(wl.taps, wl.n_hidden, wl.hidden, 500 + s))
+        cs.append(S.gmp_coefficients(K, M, L, 600 + s))
+    x = S.to_interleaved(np.concatenate(xs))
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return Inputs(wl, x, off, np.stack(ws), np.stack(cs))
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("order", GMP_ORDERS, ids=lambda o: "K%d_M%d_L%d" % o)
 def test_padded_gmp_order_against_oracle(order, prec):
@@ -125,18 +138,27 @@ def test_padded_gmp_order_against_oracle(order, prec):
     forward-only cascade, whose GMP forward kernel pads the same way."""
     K, M, L = order
     announce(f"padded GMP order K={K} M={M} L={L} prec={prec}, streams {LENS}")
-    wl = dataclasses.replace(S.WORKLOADS["parity_16k"], name=f"gmp_{K}_{M}_{L}", K=K, M=M, L=L,
-                             n_streams=len(LENS), per_stream_params=True)
-    xs, ws, cs = [], [], []
-    for s, n in enumerate(LENS):
-        xs.append(S.ofdm_signal(2048, 1200, -(-n // 2048), 64, np.random.default_rng(21 + s))[:n])
-        ws.append(S.xavier_tdnn(wl.taps, wl.n_hidden, wl.hidden, 500 + s))
-        cs.append(S.gmp_coefficients(K, M, L, 600 + s))
-    x = S.to_interleaved(np.concatenate(xs))
-    off = np.concatenate([[0], np.cumsum(LENS)]).astype(np.int64)
-    inp = Inputs(wl, x, off, np.stack(ws), np.stack(cs))
+    inp = gmp_order_inputs(K, M, L)
     got = H.run_gpu(inp, precision=prec)
     ref = H.oracle_for(inp)
     H.check_cascade(inp, got, ref, prec)
     fwd = H.run_gpu(inp, precision=prec, grad=False)
     H.check_cascade(inp, fwd, ref, prec, grad=False)
+
+
+def test_padded_gmp_order_autotuned():
+    """The autotuner takes a GMP order without kernels of its own (it times the padded
+    kernels); the cascade at the picked shapes against the FP64 oracle."""
+    announce(f"padded GMP order (6, 4, 2) autotuned, streams {LENS}")
+    inp = gmp_order_inputs(6, 4, 2)
+    cas = H.cascade_for(inp, precision="bf16")
+    x, w, c = H.to_dev(inp.x), H.to_dev(inp.w), H.to_dev(inp.coef)
+    try:
+        pick = cas.autotune(x, w, c, reps=1)
+        print(f"  picked {pick}", flush=True)
+        out = cas.run(x, w, c)
+        torch.cuda.synchronize()
+        got = {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+    finally:
+        cas.set_tune(None)
+    H.check_cascade(inp, got, H.oracle_for(inp), "bf16")
