@@ -134,8 +134,11 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
   __shared__ float2 xw[YW];
   __shared__ float2 qw[QW][M + 1];
   __shared__ float2 gyw[YW];
-  __shared__ float red[4 * S];
-  __shared__ uint32_t redn[S];
+  // the E/R reduction tree runs after the reverse mode, in the Q window's memory (5 KB
+  // less LDS per workgroup: six workgroups per CU instead of five)
+  static_assert(sizeof(float2) * QW * (M + 1) >= 5 * sizeof(float) * S, "tree fits the Q window");
+  float* red = reinterpret_cast<float*>(&qw[0][0]);
+  uint32_t* redn = reinterpret_cast<uint32_t*>(red + 4 * S);
 
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
@@ -192,6 +195,17 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
     }
     gyw[i] = gyv;
   }
+  __syncthreads();
+  // g_u at the tile's own samples
+  const int64_t m = t0 + tid;
+  if (m < hi) {
+    float2 Qm[M + 1];
+#pragma unroll
+    for (int l = 0; l <= M; ++l) Qm[l] = qw[tid + QB][l];
+    const float2 gu = gmp_grad<K, M, L>(&uw[tid + UB], &rw[tid + UB], &gyw[tid + L], Qm, cf, dcf);
+    st2(gu_out, m, gu);
+  }
+  __syncthreads();                      // Q window free for the tree
   red[tid] = Ec.s; red[S + tid] = Ec.c; red[2 * S + tid] = Rc.s; red[3 * S + tid] = Rc.c;
   redn[tid] = nf;
   __syncthreads();
@@ -206,15 +220,6 @@ __global__ __launch_bounds__(S) void k_gmp_bwd(StreamTable st, const float* __re
     __syncthreads();
   }
   if (tid == 0) tile_part[t] = make_float4(red[0] + red[S], red[2 * S] + red[3 * S], (float)redn[0], 0.f);
-  // g_u at the tile's own samples
-  const int64_t m = t0 + tid;
-  if (m < hi) {
-    float2 Qm[M + 1];
-#pragma unroll
-    for (int l = 0; l <= M; ++l) Qm[l] = qw[tid + QB][l];
-    const float2 gu = gmp_grad<K, M, L>(&uw[tid + UB], &rw[tid + UB], &gyw[tid + L], Qm, cf, dcf);
-    st2(gu_out, m, gu);
-  }
 }
 
 }  // namespace
